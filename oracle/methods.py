@@ -1,0 +1,279 @@
+"""Sketched FOM and sketched GMRES approximants of f(A)b (plain FP64).
+
+Section 2 defines the sketched FOM approximant by the integral (sFOM) over the
+sketched Galerkin solutions (eq. ym_hat) and derives the closed forms (sFOM'),
+(sFOM'') and, after retrospective basis whitening SV_m = Q_m R_m, (sFOM''') --
+the form Algorithm 1 evaluates.  Section 3 defines the sketched GMRES
+approximant (sGMRES), evaluated by quadrature as in Algorithm 2 and Section 4.1.
+
+Functions f (the ``f`` argument):
+  "invsqrt"  f(z) = z^(-1/2)       (Stieltjes; principal branch)
+  "exp"      f(z) = exp(-tau z)    (``fparam`` = tau)
+  "inv"      f(z) = 1/z            (Stieltjes with a point mass at t = 0)
+  "poly"     f(z) = sum_i p[i] z^i (``poly`` = coefficients, lowest first)
+
+Readings (listed in the design notes):
+  * S b is taken as ||b|| * S v_1, the first column of SV_m (Section 4's
+    algorithm never sketches b itself).
+  * Whitened coordinates: c = Q^T S b, B = SAV R^-1, M = Q^T B.
+  * Quadrature uses the spectral scaling sigma = sqrt(|theta|_min |theta|_max)
+    over the eigenvalues theta of M (an exact identity for z^(-1/2)).
+  * An eigenvalue of M on (-inf, 0] makes z^(-1/2) undefined: BranchError.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+from . import quadrature as quad
+from .arnoldi import ArnoldiResult
+
+
+class BranchError(ArithmeticError):
+    """An eigenvalue of the projected matrix lies on f's branch cut."""
+
+
+class QuadratureError(ArithmeticError):
+    """Adaptive quadrature reached the maximum order without converging."""
+
+
+@dataclass
+class Whitened:
+    Q: np.ndarray
+    R: np.ndarray
+    B: np.ndarray     # SAV R^-1
+    M: np.ndarray     # Q^T SAV R^-1
+    c: np.ndarray     # Q^T S b
+    Sb: np.ndarray    # S b = beta * SV[:, 0]
+
+
+def whiten(arn: ArnoldiResult) -> Whitened:
+    """Thin QR of SV_m and the whitened quantities (Section 2.1, eq. sfom3)."""
+    Q, R = np.linalg.qr(arn.SV, mode="reduced")
+    # B = SAV R^-1  <=>  R^T B^T = SAV^T
+    B = sla.solve_triangular(R, arn.SAV.T, trans="T", lower=False).T
+    M = Q.T @ B
+    Sb = arn.beta * arn.SV[:, 0]
+    c = Q.T @ Sb
+    return Whitened(Q, R, B, M, c, Sb)
+
+
+# ---------------------------------------------------------------- f(M) c ---
+def check_branch(M: np.ndarray):
+    ev = np.linalg.eigvals(M)
+    bad = (np.abs(ev.imag) <= 1e-12 * np.max(np.abs(ev))) & (ev.real <= 0.0)
+    if np.any(bad):
+        raise BranchError("eigenvalue of the projected matrix on (-inf, 0]")
+    return ev
+
+
+def matfun_apply(M: np.ndarray, c: np.ndarray, f: str, fparam: float = 0.0,
+                 poly=None) -> np.ndarray:
+    """g = f(M) c with dense Schur-based routines (SciPy)."""
+    if f == "invsqrt":
+        check_branch(M)
+        X = sla.sqrtm(M)
+        g = np.linalg.solve(X, c)
+        return np.real_if_close(g, tol=1e6).real
+    if f == "exp":
+        return sla.expm(-fparam * M) @ c
+    if f == "inv":
+        return np.linalg.solve(M, c)
+    if f == "poly":
+        p = np.asarray(poly, dtype=np.float64)
+        g = p[-1] * c
+        for coef in p[-2::-1]:
+            g = M @ g + coef * c
+        return g
+    raise ValueError(f"unknown function {f!r}")
+
+
+def spectral_scale(M: np.ndarray) -> float:
+    ev = np.abs(np.linalg.eigvals(M))
+    return float(np.sqrt(ev.min() * ev.max()))
+
+
+# ------------------------------------------------------------ results -----
+@dataclass
+class SolveResult:
+    x: np.ndarray
+    y: np.ndarray             # coefficients in the (unwhitened) basis V_m
+    m_used: int
+    l_used: int = 0
+    info: dict = field(default_factory=dict)
+
+
+def _assemble(arn: ArnoldiResult, y: np.ndarray) -> np.ndarray:
+    """f_m = V_m y  (Algorithm 1, last step)."""
+    return arn.V @ y
+
+
+def _empty(arn: ArnoldiResult) -> SolveResult:
+    return SolveResult(np.zeros(arn.V.shape[0]), np.zeros(0), 0)
+
+
+def sfom_closed(arn: ArnoldiResult, f: str, fparam: float = 0.0, poly=None) -> SolveResult:
+    """Closed form (sFOM''') of Algorithm 1: V_m R^-1 f(Q^T SAV R^-1) Q^T S b."""
+    if arn.m_used == 0:
+        return _empty(arn)
+    w = whiten(arn)
+    g = matfun_apply(w.M, w.c, f, fparam, poly)
+    y = sla.solve_triangular(w.R, g, lower=False)
+    return SolveResult(_assemble(arn, y), y, arn.m_used,
+                       info=dict(rcond_R=1.0 / np.linalg.cond(w.R)))
+
+
+def _adaptive(eval_rule, tol: float, l1: int, l2: int, lmax: int):
+    """Adaptive order loop of Section 4.1 (relative test ||q1-q2|| <= tol ||q2||)."""
+    q1 = eval_rule(l1)
+    q2 = eval_rule(l2)
+    while np.linalg.norm(q1 - q2) > tol * np.linalg.norm(q2):
+        nxt = quad.next_order(l2)
+        if nxt > lmax:
+            raise QuadratureError(f"no convergence up to l = {l2}")
+        q1, l1, l2 = q2, l2, nxt
+        q2 = eval_rule(l2)
+    return q2, l2
+
+
+def sfom_quad(arn: ArnoldiResult, f: str = "invsqrt", tol: float = 1e-13,
+              l1: int = quad.L1_DEFAULT, l2: int = quad.L2_DEFAULT,
+              lmax: int = quad.LMAX_DEFAULT) -> SolveResult:
+    """Integral form (sFOM) in whitened coordinates: the sketched Galerkin
+    solutions of eq. (ym_hat) satisfy (t I + M) y_hat(t) = c, integrated by the
+    Gauss-Chebyshev rule."""
+    if arn.m_used == 0:
+        return _empty(arn)
+    w = whiten(arn)
+    m = w.M.shape[0]
+    if f == "inv":
+        g = np.linalg.solve(w.M, w.c)
+        y = sla.solve_triangular(w.R, g, lower=False)
+        return SolveResult(_assemble(arn, y), y, arn.m_used, 1)
+    if f != "invsqrt":
+        raise ValueError("quadrature forms support the Stieltjes functions invsqrt and inv")
+    check_branch(w.M)
+    sigma = spectral_scale(w.M)
+
+    def rule(l):
+        t, wt = quad.gauss_chebyshev_invsqrt(l)
+        acc = np.zeros(m)
+        for ti, wi in zip(t, wt):
+            acc += wi * np.linalg.solve(ti * np.eye(m) + w.M / sigma, w.c)
+        return acc / np.sqrt(sigma)
+
+    g, l_used = _adaptive(rule, tol, l1, l2, lmax)
+    y = sla.solve_triangular(w.R, g, lower=False)
+    return SolveResult(_assemble(arn, y), y, arn.m_used, l_used, info=dict(sigma=sigma))
+
+
+def sgmres(arn: ArnoldiResult, f: str = "invsqrt", tol: float = 1e-13,
+           l1: int = quad.L1_DEFAULT, l2: int = quad.L2_DEFAULT,
+           lmax: int = quad.LMAX_DEFAULT) -> SolveResult:
+    """Sketched GMRES approximant (sGMRES), Section 3 / Algorithm 2:
+    V_m R^-1 int (t Q + B)^+ dmu(t) S b, the pseudo-inverse applied by a
+    least-squares solve at every quadrature node (Section 4.1, eq.
+    quadrature_rule)."""
+    if arn.m_used == 0:
+        return _empty(arn)
+    w = whiten(arn)
+    if f == "inv":
+        # point mass at t = 0: the textbook sketched GMRES solution of A x = b
+        g = np.linalg.lstsq(w.B, w.Sb, rcond=None)[0]
+        y = sla.solve_triangular(w.R, g, lower=False)
+        return SolveResult(_assemble(arn, y), y, arn.m_used, 1)
+    if f != "invsqrt":
+        raise ValueError("sGMRES needs a Stieltjes function (invsqrt or inv)")
+    sigma = spectral_scale(w.M)
+
+    def rule(l):
+        t, wt = quad.gauss_chebyshev_invsqrt(l)
+        acc = np.zeros(w.M.shape[0])
+        for ti, wi in zip(t, wt):
+            acc += wi * np.linalg.lstsq(ti * w.Q + w.B / sigma, w.Sb, rcond=None)[0]
+        return acc / np.sqrt(sigma)
+
+    g, l_used = _adaptive(rule, tol, l1, l2, lmax)
+    y = sla.solve_triangular(w.R, g, lower=False)
+    return SolveResult(_assemble(arn, y), y, arn.m_used, l_used, info=dict(sigma=sigma))
+
+
+# ---------------------------------------------- equivalent forms (pins) ---
+def sfom_gram_form(arn: ArnoldiResult, f: str, fparam: float = 0.0, poly=None) -> np.ndarray:
+    """(sFOM'): V (V^H S^H S V)^-1 f(V^H S^H S A V (V^H S^H S V)^-1) (SV)^H (S b),
+    evaluated without any QR (Section 2.1)."""
+    G = arn.SV.T @ arn.SV
+    K = arn.SV.T @ arn.SAV
+    Kg = np.linalg.solve(G.T, K.T).T          # K G^-1
+    rhs = arn.SV.T @ (arn.beta * arn.SV[:, 0])
+    g = matfun_apply(Kg, rhs, f, fparam, poly)
+    return arn.V @ np.linalg.solve(G, g)
+
+
+def cortinovis_form(arn: ArnoldiResult, f: str, fparam: float = 0.0, poly=None) -> np.ndarray:
+    """Remark in Section 2.2: V f(H_m + h_{m+1,m} x_hat e_m^T) ||b|| e_1 with
+    x_hat = argmin ||S v_{m+1} - S V_m x||.  Needs ``extend=True`` Arnoldi."""
+    if arn.v_next is None:
+        raise ValueError("needs the extended basis (v_{m+1})")
+    m = arn.m_used
+    Hm = arn.H[:m, :m]
+    hlast = arn.H[m, m - 1]
+    Sv = _sketch_from(arn, arn.v_next)
+    xhat = np.linalg.lstsq(arn.SV, Sv, rcond=None)[0]
+    Hhat = Hm.copy()
+    Hhat[:, m - 1] += hlast * xhat
+    e1 = np.zeros(m)
+    e1[0] = arn.beta
+    return arn.V @ matfun_apply(Hhat, e1, f, fparam, poly)
+
+
+def _sketch_from(arn: ArnoldiResult, v: np.ndarray) -> np.ndarray:
+    if not hasattr(arn, "S") or arn.S is None:
+        raise ValueError("attach the sketch as arn.S to use this form")
+    return arn.S @ v
+
+
+def fom(arn_full: ArnoldiResult, f: str, fparam: float = 0.0, poly=None) -> np.ndarray:
+    """Standard FOM approximant (eq. FOM) ||b|| V_m f(H_m) e_1 from a fully
+    orthogonalised basis."""
+    m = arn_full.m_used
+    e1 = np.zeros(m)
+    e1[0] = arn_full.beta
+    return arn_full.V @ matfun_apply(arn_full.H[:m, :m], e1, f, fparam, poly)
+
+
+# ------------------------------------------------- monitoring (Section 4.3) ---
+def embedding_eps_estimate(arn: ArnoldiResult) -> float:
+    """max_j | ||S v_j||^2 - 1 |, the cheap epsilon monitor (Section 4.3)."""
+    return float(np.max(np.abs(np.sum(arn.SV ** 2, axis=0) - 1.0)))
+
+
+def sketched_difference(SV_big: np.ndarray, y_big: np.ndarray, y_small: np.ndarray) -> float:
+    """|| S V_{m+d} (y_{m+d} - [y_m; 0]) ||, eq. (sketched_err_est2)."""
+    d = np.zeros_like(y_big)
+    d[: y_small.size] = y_small
+    return float(np.linalg.norm(SV_big @ (y_big - d)))
+
+
+def stopping_estimate(SV_big, y_big, y_small, eps: float) -> float:
+    """Upper estimate of ||f_{m+d} - f_m||: the sketched difference / sqrt(1-eps)."""
+    return sketched_difference(SV_big, y_big, y_small) / np.sqrt(1.0 - eps)
+
+
+def solve(A, b, f: str, m: int, k: int, S, method: str = "sfom", fparam: float = 0.0,
+          poly=None, tol: float = 1e-13, extend: bool = False):
+    """Convenience driver: truncated Arnoldi + the chosen evaluation."""
+    from .arnoldi import truncated_arnoldi
+    arn = truncated_arnoldi(A, b, m, k, S, extend=extend)
+    arn.S = S
+    if method == "sfom":
+        res = sfom_closed(arn, f, fparam, poly)
+    elif method == "sfom_quad":
+        res = sfom_quad(arn, f, tol)
+    elif method == "sgmres":
+        res = sgmres(arn, f, tol)
+    else:
+        raise ValueError(method)
+    return res, arn
