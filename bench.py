@@ -1,0 +1,234 @@
+#!/usr/bin/env python3
+"""Benchmark: sketched-FOM f(A)b solves per second on one MI355X.
+
+Workload (default): 3D convection-diffusion on a 128^3 grid (N = 2,097,152,
+7-point upwind stencil, diffusion 1, convection (100,100,100), CSR FP64),
+f(z) = z^(-1/2), b ~ N(0,1) seed 0, m = 200, k = 2, s = 400 sparse-sign sketch
+with 8 nonzeros per column (seed 0), sketched FOM closed form.
+
+One timed step = one complete solve with the inputs already resident in HBM:
+the implicit sketch, m fused Arnoldi steps (SpMV + truncated Gram-Schmidt dots +
+both sketches), the extension vector, the sketch reduction, the whitening QR,
+the Hessenberg pencil, the adaptive quadrature and the assembly x = V_m y.
+
+The JSON line also carries
+  roofline:     the fused Arnoldi step kernel (dominant): algorithmic bytes per
+                launch / its mean duration, timed with HIP events recorded by the
+                library on the solve stream during the timed region, against
+                the 8 TB/s HBM peak;
+  cpu_baseline: the FP64 oracle on a bounded sample of the same workload on this
+                host's CPU, scaled to solves/s;
+  parity:       relative 2-norm error of the timed GPU result against the oracle
+                on the full workload (same sketch, m, k).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="convdiff3d_n128_m200")
+    ap.add_argument("--f", default="invsqrt", choices=["invsqrt", "inv"])
+    ap.add_argument("--method", default="sfom", choices=["sfom", "sfom_quad", "sgmres"])
+    ap.add_argument("--no-parity", action="store_true", help="skip the full-size oracle comparison")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-steps", type=int, default=30)
+    ap.add_argument("--no-timing-events", action="store_true")
+    return ap.parse_args()
+
+
+def step_kernel_bytes(N: int, nnz: int, k: int) -> int:
+    """Algorithmic HBM bytes of one fused Arnoldi step (FP64, int32 indices, implicit sketch):
+    A once (8 nnz values + 4 nnz columns + 4 (N+1) row pointers), the k window vectors and
+    A u_{j-1} read once (8 (k+1) N), u_j and A u_j written once (16 N)."""
+    return 12 * nnz + 4 * (N + 1) + 8 * (k + 1) * N + 16 * N
+
+
+def cpu_baseline(cfg, arrays, b, sample_steps):
+    """Time the oracle as it stands on a bounded sample: `sample_steps` of the m
+    truncated-Arnoldi steps on the full operator (per-step time scaled to m), the
+    oracle small problem + assembly at full m on the same-shape problem of a 32^3
+    grid, and the sketch construction."""
+    import numpy as np
+    import scipy.sparse as sp
+    from threadpoolctl import threadpool_limits
+
+    from oracle import arnoldi as oarn
+    from oracle import methods as ometh
+    from oracle import sketch as osk
+    from workloads import convdiff_csr, gaussian_rhs
+
+    rp, col, val = arrays
+    N = rp.size - 1
+    m, k, s, zeta = cfg["m"], cfg["k"], cfg["s"], cfg["zeta"]
+    with threadpool_limits(limits=1):
+        A = sp.csr_matrix((val, col, rp), shape=(N, N))
+        t0 = time.perf_counter()
+        S = osk.sparse_sign_matrix(N, s, zeta, cfg["sketch_seed"])
+        t_sketch = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        arn = oarn.truncated_arnoldi(A, b, sample_steps, k, S)
+        t_arn = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _ = arn.V @ np.ones(arn.m_used)
+        t_asm = time.perf_counter() - t0
+        # small problem at full m on a smaller operator of the same family
+        rp2, col2, val2 = convdiff_csr(32, cfg["dim"], cfg["diffusion"], cfg["convection"])
+        N2 = rp2.size - 1
+        A2 = sp.csr_matrix((val2, col2, rp2), shape=(N2, N2))
+        S2 = osk.sparse_sign_matrix(N2, s, zeta, 0)
+        arn2 = oarn.truncated_arnoldi(A2, gaussian_rhs(N2, 0), m, k, S2)
+        t0 = time.perf_counter()
+        w = ometh.whiten(arn2)
+        g = ometh.matfun_apply(w.M, w.c, "invsqrt")
+        _ = np.linalg.solve(w.R, g)
+        t_small = time.perf_counter() - t0
+    per_solve = t_sketch + t_arn / sample_steps * m + t_asm / sample_steps * m + t_small
+    sample = (f"oracle: sketch build + {sample_steps} of {m} truncated-Arnoldi steps on the full operator "
+              f"({t_arn:.1f} s, scaled to {m} steps) + assembly scaled likewise + small problem at m={m} "
+              f"({t_small:.2f} s); single thread")
+    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle", "sample": sample,
+            "sec_per_solve": per_solve}
+
+
+def oracle_parity(cfg, arrays, b, x_gpu, f, method):
+    import numpy as np
+    import scipy.sparse as sp
+
+    from oracle import arnoldi as oarn
+    from oracle import methods as ometh
+    from oracle import sketch as osk
+
+    rp, col, val = arrays
+    N = rp.size - 1
+    A = sp.csr_matrix((val, col, rp), shape=(N, N))
+    S = osk.sparse_sign_matrix(N, cfg["s"], cfg["zeta"], cfg["sketch_seed"])
+    arn = oarn.truncated_arnoldi(A, b, cfg["m"], cfg["k"], S)
+    if method == "sfom":
+        xr = ometh.sfom_closed(arn, f).x
+    elif method == "sgmres":
+        xr = ometh.sgmres(arn, f, tol=1e-13).x
+    else:
+        xr = ometh.sfom_quad(arn, f, tol=1e-13).x
+    return float(np.linalg.norm(x_gpu - xr) / np.linalg.norm(xr))
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2208_11447_amd import skfab as sk
+    from workloads import config, convdiff_csr, gaussian_rhs
+
+    cfg = config(args.workload)
+    rp, col, val = convdiff_csr(cfg["n"], cfg["dim"], cfg["diffusion"], cfg["convection"])
+    N = rp.size - 1
+    nnz = int(rp[-1])
+    b = gaussian_rhs(N, cfg["rhs_seed"])
+    dev = torch.device("cuda:0")
+    A = sk.CSR.from_numpy(rp, col, val, device=dev)
+    bd = torch.as_tensor(b, device=dev)
+    x = torch.empty_like(bd)
+    p = sk.make_params(f=args.f, m=cfg["m"], k=cfg["k"], s=cfg["s"], zeta=cfg["zeta"], seed=cfg["sketch_seed"],
+                       method=args.method, quad_tol=1e-13)
+    ws = sk.alloc_workspace(sk.skfab_workspace_bytes(A, p), device=dev)
+    ctx = sk.Context(0)
+    print(f"# workload {args.workload}: N={N} nnz={nnz} m={cfg['m']} k={cfg['k']} s={cfg['s']} "
+          f"f={args.f} method={args.method}", file=sys.stderr, flush=True)
+
+    info = sk.skfab_solve(ctx, A, bd, x, p, ws)
+    if info.status != 0:
+        raise RuntimeError(f"solve status {info.status}")
+    for _ in range(args.warmup):
+        sk.skfab_solve(ctx, A, bd, x, p, ws, want_info=False)
+    torch.cuda.synchronize()
+
+    timing = not args.no_timing_events
+    if timing:
+        sk.skfab_timing_enable(ctx, True)
+        sk.skfab_timing_read(ctx, 0)
+        sk.skfab_timing_read(ctx, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sk.skfab_solve(ctx, A, bd, x, p, ws, want_info=False)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    elapsed = t1 - t0
+    roof = None
+    if timing:
+        ms_step, n_step = sk.skfab_timing_read(ctx, 0)
+        ms_asm, n_asm = sk.skfab_timing_read(ctx, 1)
+        sk.skfab_timing_enable(ctx, False)
+        per_launch_s = ms_step / 1e3 / max(n_step, 1)
+        nbytes = step_kernel_bytes(N, nnz, cfg["k"])
+        achieved = nbytes / per_launch_s / 1e9
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "arnoldi_step_kernel", "bytes_per_launch": nbytes,
+                "mean_launch_us": round(per_launch_s * 1e6, 2), "launches": n_step,
+                "assembly_gbs": round((8 * N * cfg["m"] + 8 * N) / (ms_asm / 1e3 / max(n_asm, 1)) / 1e9, 1)
+                if n_asm else None}
+    x_host = x.cpu().numpy()
+    print(f"# timed {args.steps} solves in {elapsed:.3f} s; m_used={info.m_used} l_used={info.l_used} "
+          f"sigma={info.sigma:.4g} rcond={info.rcond_R:.3e} eps_est={info.eps_est:.3f} "
+          f"relres={info.arnoldi_relres:.2e}", file=sys.stderr, flush=True)
+
+    parity = None
+    if not args.no_parity:
+        t = time.perf_counter()
+        err = oracle_parity(cfg, (rp, col, val), b, x_host, args.f, args.method)
+        parity = {"rel_err_vs_oracle": err, "tol": 1e-10, "oracle_seconds": round(time.perf_counter() - t, 1)}
+        print(f"# parity vs oracle: {err:.3e}", file=sys.stderr, flush=True)
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(cfg, (rp, col, val), b, args.cpu_sample_steps)
+        print(f"# cpu baseline: {cpu['sec_per_solve']:.1f} s/solve", file=sys.stderr, flush=True)
+        cpu.pop("sec_per_solve")
+
+    value = args.steps / elapsed
+    out = {
+        "metric": "f(A)b solves/s and SpMV+sketch HBM GB/s at rel. err 1e-8 vs FP64 oracle",
+        "value": round(value, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}_{args.f}_{args.method}", "grid": f"{cfg['n']}^{cfg['dim']}",
+                   "N": N, "nnz": nnz, "m": cfg["m"], "k": cfg["k"], "s": cfg["s"], "zeta": cfg["zeta"],
+                   "f": args.f, "method": args.method, "parallelism": "single-gpu"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "parity": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

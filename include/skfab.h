@@ -1,0 +1,229 @@
+/*
+ * skfab.h - sketched Krylov approximation of f(A) b on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI of libskfab.so.  The library evaluates the sketched FOM and sketched
+ * GMRES approximants of Guettel & Schweitzer, "Randomized sketching for Krylov
+ * approximations of large-scale matrix functions" (arXiv 2208.11447):
+ *
+ *   Algorithm 1 (Section 2.2)  sketched FOM, closed form (sFOM''') of Section 2.1
+ *   Algorithm 2 (Section 4)    sketched GMRES with k-truncated Arnoldi and
+ *                              adaptive quadrature (Section 4.1)
+ *
+ * Problem statement (both algorithms' inputs): a sparse matrix A (N x N), a
+ * vector b, a function f, the Krylov dimension m, the truncation length k and
+ * the sketch size s with m < s << N.  Output: an approximation of f(A) b.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Memory: every pointer to N-sized data (CSR arrays, b, x, workspace, test
+ *    hook outputs) is a DEVICE pointer on the context's device, allocated and
+ *    owned by the caller.  Structs passed by pointer (skfab_csr, skfab_params,
+ *    skfab_info) are HOST memory.  The library never allocates or frees device
+ *    memory in these calls; all scratch lives in the caller's workspace.
+ *  - Streams: work is enqueued on the context's HIP stream and is asynchronous
+ *    unless stated otherwise.  Calls that fill a host skfab_info synchronise
+ *    the stream before returning.
+ *  - Errors: return codes only; no C++ exception crosses the ABI.  Argument and
+ *    shape errors are detected before anything is enqueued.  Numerical
+ *    failures detected on the device (rank deficiency, branch cut, quadrature
+ *    non-convergence) are reported through skfab_info.status, which requires a
+ *    synchronising call (info != NULL).
+ *  - Layouts: dense matrices are column-major with the stated leading
+ *    dimension.  CSR uses 0-based int32 row pointers and column indices.
+ *  - Precision: values are real; the default path computes in IEEE double.
+ */
+#ifndef SKFAB_H
+#define SKFAB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SKFAB_VERSION_MAJOR 0
+#define SKFAB_VERSION_MINOR 1
+
+typedef enum skfab_status {
+    SKFAB_OK = 0,
+    SKFAB_ERR_ARG = 1,      /* null pointer, unsupported option, bad enum value          */
+    SKFAB_ERR_SHAPE = 2,    /* violates 1 <= k <= min(m, 8), m < s <= N, zeta <= s ...   */
+    SKFAB_ERR_RANK = 3,     /* R_m of SV_m = Q_m R_m numerically singular (Section 2.1)  */
+    SKFAB_ERR_BRANCH = 4,   /* projected matrix has det < 0: an eigenvalue on the branch
+                               cut of z^(-1/2) (Section 2.3, sketched Ritz values)       */
+    SKFAB_ERR_QUAD = 5,     /* adaptive quadrature did not converge by lmax (Section 4.1) */
+    SKFAB_ERR_HIP = 6,      /* a HIP runtime call failed                                  */
+    SKFAB_ERR_WORKSPACE = 7 /* workspace pointer null or smaller than required            */
+} skfab_status;
+
+/* f in f(A) b.  INVSQRT and INV are Stieltjes functions (Section 1) and work with
+ * every method; EXP and POLY are evaluated in closed form (SFOM_CLOSED only). */
+typedef enum skfab_fun {
+    SKFAB_F_INVSQRT = 0,    /* z^(-1/2), principal branch                            */
+    SKFAB_F_EXP = 1,        /* exp(-fparam * z)  (rejected with SKFAB_ERR_ARG until the
+                               closed-form exponential kernel is available)           */
+    SKFAB_F_INV = 2,        /* 1/z (test function)                                   */
+    SKFAB_F_POLY = 3        /* sum_i poly[i] z^i, npoly coefficients (test function)  */
+} skfab_fun;
+
+typedef enum skfab_method {
+    SKFAB_SFOM_CLOSED = 0,  /* Algorithm 1, closed form (sFOM'''): f(M) evaluated to
+                               near machine precision                              */
+    SKFAB_SFOM_QUAD = 1,    /* (sFOM) integral form, adaptive quadrature, quad_tol   */
+    SKFAB_SGMRES_QUAD = 2   /* Algorithm 2, (sGMRES), adaptive quadrature, quad_tol   */
+} skfab_method;
+
+typedef enum skfab_prec {
+    SKFAB_PREC_FP64 = 0     /* A, basis and all arithmetic in IEEE double            */
+} skfab_prec;
+
+typedef enum skfab_valtype {
+    SKFAB_VAL_F64 = 0
+} skfab_valtype;
+
+/* Sparse matrix A in CSR form (device arrays, caller-owned, read-only). */
+typedef struct skfab_csr {
+    int64_t n;              /* N: rows = columns                                     */
+    int64_t nnz;            /* rowptr[n]                                             */
+    const int32_t *rowptr;  /* [n+1], non-decreasing, rowptr[0] = 0                  */
+    const int32_t *col;     /* [nnz], column indices in [0, n)                       */
+    const void *val;        /* [nnz], element type given by val_type                 */
+    int32_t val_type;       /* skfab_valtype                                         */
+} skfab_csr;
+
+/* Method parameters (Algorithm 1/2 inputs; host struct). */
+typedef struct skfab_params {
+    int32_t f;              /* skfab_fun                                             */
+    double fparam;          /* tau for SKFAB_F_EXP                                   */
+    const double *poly;     /* HOST array of npoly coefficients (lowest degree first) */
+    int32_t npoly;          /* 1 <= npoly <= m for SKFAB_F_POLY                       */
+    int32_t method;         /* skfab_method                                          */
+    int32_t m;              /* Krylov dimension, 1 <= m <= 256                       */
+    int32_t k;              /* truncation length, 1 <= k <= min(m, 8)                */
+    int32_t s;              /* sketch rows, m < s <= min(N, 1024)                    */
+    int32_t zeta;           /* nonzeros per sketch column: 8                         */
+    uint64_t seed;          /* sketch seed (SplitMix64 stream, see skfab_sketch_pattern) */
+    int32_t l1, l2;         /* starting quadrature orders, l1 < l2 (default 32, 45)  */
+    int32_t lmax;           /* largest quadrature order tried (default 1395)         */
+    double quad_tol;        /* relative tolerance of the quadrature test (Section 4.1) */
+    int32_t prec;           /* skfab_prec                                            */
+} skfab_params;
+
+/* Filled by synchronising calls (host struct). */
+typedef struct skfab_info {
+    int32_t status;         /* device-detected numerical status (skfab_status)       */
+    int32_t m_used;         /* Krylov dimension actually used (< m after breakdown)  */
+    int32_t l_used;         /* quadrature order accepted (0 if none)                 */
+    int32_t reserved;
+    double eps_est;         /* max_j | ||S v_j||^2 - 1 |  (Section 4.3 monitor)        */
+    double rcond_R;         /* min|R_jj| / max|R_jj| of the whitening factor         */
+    double sigma;           /* spectral scale used by the quadrature                 */
+    double beta;            /* ||b||_2                                               */
+    double arnoldi_relres;  /* ||S A V_m - [S V_m, S u_{m+1}] Hbar||_F / ||S A V_m||_F: the
+                               Arnoldi relation checked in the sketched space          */
+} skfab_info;
+
+typedef struct skfab_ctx skfab_ctx;
+
+/* Library version as MAJOR*100 + MINOR. */
+int32_t skfab_version(void);
+
+/* Human-readable name of a status code (static string, never NULL). */
+const char *skfab_status_string(int32_t status);
+
+/* Create a context bound to HIP device `device` and stream `hip_stream`
+ * (a hipStream_t; NULL = the default stream).  *ctx receives a host handle.
+ * Errors: SKFAB_ERR_ARG (ctx NULL, bad device), SKFAB_ERR_HIP. */
+skfab_status skfab_create(skfab_ctx **ctx, int32_t device, void *hip_stream);
+
+/* Rebind the context to another stream on the same device. */
+skfab_status skfab_set_stream(skfab_ctx *ctx, void *hip_stream);
+
+/* Destroy a context (does not synchronise; NULL is accepted). */
+skfab_status skfab_destroy(skfab_ctx *ctx);
+
+/* Bytes of device workspace skfab_solve / skfab_arnoldi need for this problem
+ * (host computation, no device work).  Errors: SKFAB_ERR_ARG, SKFAB_ERR_SHAPE. */
+skfab_status skfab_workspace_bytes(const skfab_csr *A, const skfab_params *p,
+                                   size_t *bytes);
+
+/* x <- approximation of f(A) b (Algorithm 1 for SFOM_*, Algorithm 2 for SGMRES).
+ *   b, x     device vectors of length N (may not alias)
+ *   ws       device workspace of at least skfab_workspace_bytes bytes, 256-byte aligned
+ *   info     optional host struct; if non-NULL the call synchronises the stream and
+ *            returns the device-detected status in info->status
+ * Steps (all on the device): draw S (implicit, hashed), k-truncated Arnoldi with the
+ * sketches S v_j and S A v_j formed on the fly, whitening QR of [SV_m | SAV_m], the
+ * projected matrix M = Q^T SAV R^-1, f(M) c or the quadrature of Section 4.1, the
+ * coefficients y = R^-1 (...), and the assembly x = V_m y.
+ * b = 0 gives x = 0.  Lucky breakdown (Section 4: division by ||w||) stops the
+ * recurrence early; info->m_used reports the dimension used. */
+skfab_status skfab_solve(skfab_ctx *ctx, const skfab_csr *A, const double *b, double *x,
+                         const skfab_params *p, void *ws, size_t ws_bytes,
+                         skfab_info *info);
+
+/* Test hook: run only the k-truncated Arnoldi recurrence with sketches
+ * (Algorithm 2, basis part) and export its state.
+ *   V    device, N x m column-major (ld = N), the unit basis vectors v_1..v_m
+ *   SV   device, s x m (ld = s), S v_j          SAV  device, s x m, S A v_j
+ *   H    device, (m+1) x m (ld = m+1), the truncated MGS coefficients h_ij
+ *        (zero outside the band of width k+1)
+ * Any of V, SV, SAV, H may be NULL.  info (optional, synchronising) receives
+ * m_used, beta and eps_est. */
+skfab_status skfab_arnoldi(skfab_ctx *ctx, const skfab_csr *A, const double *b,
+                           const skfab_params *p, double *V, double *SV, double *SAV,
+                           double *H, void *ws, size_t ws_bytes, skfab_info *info);
+
+/* Test hook: the small sketched problem alone, from Arnoldi data.
+ *   SVext  device, s x (m+1) (ld = s): columns 0..m-1 are S v_1..S v_m (unit basis
+ *          vectors), column m is S u_{m+1} = h_{m+1,m} S v_{m+1} (unnormalised)
+ *   Hbar   device, (m+1) x m (ld = m+1): the Arnoldi coefficients h_ij of
+ *          A v_j = sum_i h_ij v_i + u_{j+1}; row m is ignored (taken as e_m^T)
+ *   beta   ||b|| (host)
+ *   y      device, m: coefficients of the approximant V_m y (Sections 2.1, 3, 4.1)
+ * Uses the same device algorithm as skfab_solve after the basis is built. */
+skfab_status skfab_small_problem(skfab_ctx *ctx, const double *SVext, const double *Hbar,
+                                 double beta, const skfab_params *p, double *y,
+                                 void *ws, size_t ws_bytes, skfab_info *info);
+
+/* Workspace bytes for skfab_small_problem alone. */
+skfab_status skfab_small_workspace_bytes(const skfab_params *p, size_t *bytes);
+
+/* Test hook: the sparse-sign sketch pattern of columns [col0, col0 + ncols).
+ * rows  device int32 [ncols * zeta]: rows[i*zeta + q] is the row of entry q of
+ *       column col0 + i;  signs device int8 [ncols * zeta], +1 or -1.
+ * Definition (implemented independently of the CPU reference): SplitMix64
+ * (gamma 0x9E3779B97F4A7C15) seeded with `seed`; column i uses outputs
+ * 4*ceil(zeta/8)*i + 1 ... ; their 32-bit halves w_q give Floyd's sampling draws
+ * r = floor((w_q >> 1)(j+1) / 2^31), j = s - zeta + q (row j on a repeat) and the
+ * sign (+1 if bit 0 of w_q is 0).  Each column of S is sum_q sign_q e_row_q / sqrt(zeta).
+ * Errors: SKFAB_ERR_SHAPE unless 1 <= zeta <= s and zeta in {2, 4, 8, 16}. */
+skfab_status skfab_sketch_pattern(skfab_ctx *ctx, int64_t col0, int64_t ncols, int32_t s,
+                                  int32_t zeta, uint64_t seed, int32_t *rows, int8_t *signs);
+
+/* Test hook: Sv <- S v for a device vector v of length n (Sv device, length s).
+ * Deterministic (fixed reduction order).  Uses `ws` for per-block partial sums
+ * (at least skfab_sketch_ws_bytes(n, s) bytes). */
+skfab_status skfab_sketch_apply(skfab_ctx *ctx, int64_t n, int32_t s, int32_t zeta,
+                                uint64_t seed, const double *v, double *Sv,
+                                void *ws, size_t ws_bytes);
+size_t skfab_sketch_ws_bytes(int64_t n, int32_t s);
+
+/* Kernel timing with HIP events on the context's stream (benchmark support).
+ * While enabled, every launch of the timed kernel classes is bracketed by a pair
+ * of events; skfab_timing_read synchronises the stream and returns the summed
+ * event durations and the launch count since the last read (then resets).
+ *   kernel 0: the fused Arnoldi step kernel (SpMV + orthogonalisation dots +
+ *             sparse-sign sketches), kernel 1: the assembly x = V_m y.
+ * Events are host runtime objects created by skfab_timing_enable; no device
+ * memory is allocated. */
+skfab_status skfab_timing_enable(skfab_ctx *ctx, int32_t enable);
+skfab_status skfab_timing_read(skfab_ctx *ctx, int32_t kernel, double *total_ms,
+                               int64_t *launches);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SKFAB_H */

@@ -1,0 +1,575 @@
+// C ABI of libskfab: validation, workspace layout and the launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/skfab.h"
+#include "common.hpp"
+#include "device_state.hpp"
+
+namespace skfab {
+hipError_t launch_arnoldi_step(const StepArgs& a, int zeta, int block, hipStream_t st);
+hipError_t launch_sketch_reduce(const double* skpart, int G, int s, int m, int zeta, const DevCtrl* ctrl,
+                                const double* eta, double* SV, double* SAV, double* colnorm2, hipStream_t st);
+hipError_t launch_extension_finalize(const double* scal, int G, int m, DevCtrl* ctrl, double* eta, double* H,
+                                     hipStream_t st);
+hipError_t launch_arnoldi_check(const double* SV, const double* SAV, const double* H, int s, int m, int k,
+                                DevCtrl* ctrl, hipStream_t st);
+hipError_t launch_normalize_basis(const double* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl,
+                                  const double* eta, double* V, hipStream_t st);
+hipError_t launch_sketch_pattern(int64_t col0, int64_t ncols, int s, int zeta, uint64_t seed, int32_t* rows,
+                                 int8_t* signs, hipStream_t st);
+hipError_t launch_sketch_apply(int64_t n, int s, int zeta, uint64_t seed, const double* v, double* Sv,
+                               double* part, hipStream_t st);
+int sketch_apply_blocks(int64_t n);
+hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
+hipError_t launch_init_ctrl(DevCtrl* c, int m, hipStream_t st);
+hipError_t launch_qr(double* X, int s, int ncols_max, const DevCtrl* ctrl, double* Tws, hipStream_t st);
+hipError_t launch_pencil_setup(const double* X, int s, int m, int k, const DevCtrl* ctrl, const double* H,
+                               double* K0r, double* T1r, hipStream_t st);
+hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, const double* eta,
+                                 const double* T1r, const double* K0r, double* Ubuf, double* Urhs, double* y0,
+                                 int is_ls, int branch_check, hipStream_t st);
+hipError_t launch_quad_level(const DevCtrl* ctrl, const double* T1r, const double* K0r, double* Ubuf, double* Urhs,
+                             double* nodebuf, int m, int l, int is_ls, const double* X, int s, const double* eta,
+                             hipStream_t st);
+hipError_t launch_quad_reduce(DevCtrl* ctrl, const double* nodebuf, int m, int l, int first, double tol,
+                              const double* T1r, double* qprev, double* qcur, double* y, hipStream_t st);
+hipError_t launch_quad_fail(DevCtrl* ctrl, hipStream_t st);
+hipError_t launch_poly(const DevCtrl* ctrl, int m, const double* T1r, const double* K0r, const double* eta,
+                       const double* coef, int npoly, double* y, hipStream_t st);
+hipError_t launch_finish_coeffs(DevCtrl* ctrl, int m, const double* y, const double* eta, const double* colnorm2,
+                                double* ys, double* yout, hipStream_t st);
+hipError_t launch_assemble(const double* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl, const double* ys,
+                           double* x, hipStream_t st);
+constexpr int QR_NB_HOST = 16;
+constexpr int NODE_SLOTS_HOST = 256;
+}  // namespace skfab
+
+using namespace skfab;
+
+struct skfab_ctx {
+    int device;
+    hipStream_t stream;
+    // optional per-launch timing of kernel classes (0: Arnoldi step, 1: assembly)
+    bool timing = false;
+    std::vector<hipEvent_t> ev[2];  // start/stop pairs, flattened
+    size_t used[2] = {0, 0};
+    double acc_ms[2] = {0.0, 0.0};
+    int64_t count[2] = {0, 0};
+};
+
+namespace {
+constexpr size_t TIMING_PAIRS = 2048;
+
+// Sum the durations of the recorded pairs of class c and recycle them.
+hipError_t timing_flush(skfab_ctx* ctx, int c) {
+    if (ctx->used[c] == 0) return hipSuccess;
+    hipError_t e = hipEventSynchronize(ctx->ev[c][2 * ctx->used[c] - 1]);
+    if (e != hipSuccess) return e;
+    for (size_t i = 0; i < ctx->used[c]; ++i) {
+        float ms = 0.f;
+        e = hipEventElapsedTime(&ms, ctx->ev[c][2 * i], ctx->ev[c][2 * i + 1]);
+        if (e != hipSuccess) return e;
+        ctx->acc_ms[c] += ms;
+        ctx->count[c] += 1;
+    }
+    ctx->used[c] = 0;
+    return hipSuccess;
+}
+
+// Event pair for the next timed launch of class c (nullptr pair when disabled).
+hipError_t timing_begin(skfab_ctx* ctx, int c, hipStream_t st, hipEvent_t* stop) {
+    *stop = nullptr;
+    if (!ctx || !ctx->timing) return hipSuccess;
+    if (ctx->used[c] == TIMING_PAIRS) {
+        hipError_t e = timing_flush(ctx, c);
+        if (e != hipSuccess) return e;
+    }
+    const size_t i = ctx->used[c]++;
+    *stop = ctx->ev[c][2 * i + 1];
+    return hipEventRecord(ctx->ev[c][2 * i], st);
+}
+
+hipError_t timing_end(hipEvent_t stop, hipStream_t st) {
+    return stop ? hipEventRecord(stop, st) : hipSuccess;
+}
+}  // namespace
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+constexpr int GMAX_BLOCKS = 256;  // step-kernel blocks for large N (one per CU)
+
+size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+int next_order(int l) {
+    // floor(sqrt(2) * l) exactly: largest q with q*q <= 2*l*l
+    const int64_t t = 2LL * l * l;
+    int64_t q = (int64_t)std::sqrt((double)t);
+    while (q * q > t) --q;
+    while ((q + 1) * (q + 1) <= t) ++q;
+    return (int)q;
+}
+
+struct Launch {
+    int block;
+    int G;
+    int64_t rows_per_chunk;
+};
+
+Launch step_launch(int64_t N, int s) {
+    // largest block whose per-wave sketch bins fit in LDS (160 KiB, keep 4 KiB spare)
+    const size_t lds_budget = 156 * 1024;
+    int block = 1024;
+    while (block > 256 && (size_t)(block / 64) * 2 * s * sizeof(double) > lds_budget) block /= 2;
+    if (N < (int64_t)block * 256) block = 256;  // small problems: more, smaller blocks
+    int64_t tiles = (N + block - 1) / block;
+    int64_t G = tiles < GMAX_BLOCKS * (1024 / block) ? tiles : GMAX_BLOCKS * (1024 / block);
+    G = (G + 7) / 8 * 8;
+    Launch L;
+    L.block = block;
+    L.G = (int)G;
+    L.rows_per_chunk = (N + G - 1) / G;
+    return L;
+}
+
+struct Layout {
+    size_t ctrl, eta, wnorm, H, gram, colnorm2, scal, U, W, skpart, SV, SAV, Tws, K0r, T1r, Ubuf, Urhs, nodebuf,
+        qprev, qcur, y, ys, y0, poly, total;
+    int64_t ldU;
+    int lnodes;
+    Launch L;
+};
+
+int max_level_nodes(int l1, int l2, int lmax) {
+    int mx = l1 > l2 ? l1 : l2;
+    int l = l2;
+    while (true) {
+        int nx = next_order(l);
+        if (nx > lmax) break;
+        l = nx;
+        if (l > mx) mx = l;
+    }
+    return mx;
+}
+
+Layout make_layout(int64_t N, int m, int s, int l1, int l2, int lmax, int npoly, bool with_basis) {
+    Layout ly;
+    ly.L = step_launch(N > 0 ? N : 1, s);
+    ly.ldU = (N + 63) / 64 * 64;
+    ly.lnodes = max_level_nodes(l1, l2, lmax);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off = align_up(off + bytes);
+        return o;
+    };
+    const size_t d = sizeof(double);
+    const int G = ly.L.G;
+    ly.ctrl = take(sizeof(DevCtrl));
+    ly.eta = take((m + 2) * d);
+    ly.wnorm = take((m + 2) * d);
+    ly.H = take((size_t)(m + 1) * m * d);
+    ly.gram = take((size_t)(m + 1) * KMAX * d);
+    ly.colnorm2 = take((m + 1) * d);
+    ly.scal = take((size_t)2 * NSC_MAX * G * d);
+    ly.U = with_basis ? take((size_t)ly.ldU * m * d) : take(0);
+    ly.W = with_basis ? take((size_t)2 * ly.ldU * d) : take(0);
+    ly.skpart = with_basis ? take((size_t)(m + 1) * G * 2 * s * d) : take(0);
+    ly.SV = take((size_t)s * (m + 1) * d);
+    ly.SAV = take((size_t)s * m * d);
+    ly.Tws = take((size_t)QR_NB_HOST * QR_NB_HOST * d);
+    ly.K0r = take((size_t)(m + 1) * m * d);
+    ly.T1r = take((size_t)(m + 1) * m * d);
+    ly.Ubuf = take((size_t)NODE_SLOTS_HOST * m * m * d);
+    ly.Urhs = take((size_t)NODE_SLOTS_HOST * m * d);
+    ly.nodebuf = take((size_t)ly.lnodes * m * d);
+    ly.qprev = take(m * d);
+    ly.qcur = take(m * d);
+    ly.y = take(m * d);
+    ly.ys = take(m * d);
+    ly.y0 = take(m * d);
+    ly.poly = take((size_t)(npoly > 0 ? npoly : 1) * d);
+    ly.total = off;
+    return ly;
+}
+
+struct Ptrs {
+    DevCtrl* ctrl;
+    double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *U, *W, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Ubuf, *Urhs,
+        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly;
+};
+
+Ptrs carve(void* ws, const Layout& ly) {
+    char* b = static_cast<char*>(ws);
+    Ptrs p;
+    p.ctrl = reinterpret_cast<DevCtrl*>(b + ly.ctrl);
+    auto D = [&](size_t o) { return reinterpret_cast<double*>(b + o); };
+    p.eta = D(ly.eta); p.wnorm = D(ly.wnorm); p.H = D(ly.H); p.gram = D(ly.gram); p.colnorm2 = D(ly.colnorm2);
+    p.scal = D(ly.scal); p.U = D(ly.U); p.W = D(ly.W); p.skpart = D(ly.skpart); p.SV = D(ly.SV); p.SAV = D(ly.SAV);
+    p.Tws = D(ly.Tws); p.K0r = D(ly.K0r); p.T1r = D(ly.T1r); p.Ubuf = D(ly.Ubuf); p.Urhs = D(ly.Urhs);
+    p.nodebuf = D(ly.nodebuf); p.qprev = D(ly.qprev); p.qcur = D(ly.qcur); p.y = D(ly.y); p.ys = D(ly.ys);
+    p.y0 = D(ly.y0); p.poly = D(ly.poly);
+    return p;
+}
+
+void defaults(const skfab_params* p, int* l1, int* l2, int* lmax, double* tol) {
+    *l1 = p->l1 > 0 ? p->l1 : 32;
+    *l2 = p->l2 > 0 ? p->l2 : 45;
+    *lmax = p->lmax > 0 ? p->lmax : 1395;
+    *tol = p->quad_tol > 0.0 ? p->quad_tol : 1e-13;
+}
+
+bool zeta_ok(int z) { return z == 2 || z == 4 || z == 8 || z == 16; }
+
+skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matrix) {
+    if (!p) return SKFAB_ERR_ARG;
+    if (need_matrix) {
+        if (!A || !A->rowptr || !A->col || !A->val) return SKFAB_ERR_ARG;
+        if (A->val_type != SKFAB_VAL_F64) return SKFAB_ERR_ARG;
+        if (A->n <= 0 || A->nnz < 0 || A->nnz > INT32_MAX) return SKFAB_ERR_SHAPE;
+    }
+    if (p->f < 0 || p->f > 3 || p->method < 0 || p->method > 2 || p->prec != SKFAB_PREC_FP64) return SKFAB_ERR_ARG;
+    if (p->m < 1 || p->m > MMAX) return SKFAB_ERR_SHAPE;
+    if (p->k < 1 || p->k > KMAX || p->k > p->m) return SKFAB_ERR_SHAPE;
+    if (p->s <= p->m || p->s > SMAX) return SKFAB_ERR_SHAPE;
+    if (need_matrix && p->s > A->n) return SKFAB_ERR_SHAPE;
+    if (!zeta_ok(p->zeta) || p->zeta > p->s) return SKFAB_ERR_SHAPE;
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    if (l1 < 1 || l2 <= l1 || lmax < l2) return SKFAB_ERR_ARG;
+    if (p->f == SKFAB_F_POLY) {
+        if (!p->poly || p->npoly < 1 || p->npoly > p->m) return SKFAB_ERR_ARG;
+        if (p->method != SKFAB_SFOM_CLOSED) return SKFAB_ERR_ARG;
+    }
+    if (p->f == SKFAB_F_EXP) {
+        if (p->method != SKFAB_SFOM_CLOSED) return SKFAB_ERR_ARG;
+        return SKFAB_ERR_ARG;  // closed-form exponential not available in this build
+    }
+    return SKFAB_OK;
+}
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t _e = (expr);                         \
+        if (_e != hipSuccess) return SKFAB_ERR_HIP;     \
+    } while (0)
+
+// k-truncated Arnoldi with sketches, plus the extension vector u_m (Algorithm 2, basis part).
+skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, const skfab_params* p,
+                         const Layout& ly, const Ptrs& w, hipStream_t st) {
+    const int m = p->m, s = p->s;
+    HIP_TRY(launch_init_ctrl(w.ctrl, m, st));
+    StepArgs a;
+    std::memset(&a, 0, sizeof(a));
+    a.N = A->n;
+    a.rows_per_chunk = ly.L.rows_per_chunk;
+    a.ldU = ly.ldU;
+    a.rowptr = A->rowptr;
+    a.col = A->col;
+    a.val = static_cast<const double*>(A->val);
+    a.b = b;
+    a.U = w.U;
+    a.ctrl = w.ctrl;
+    a.eta = w.eta;
+    a.wnorm = w.wnorm;
+    a.H = w.H;
+    a.gram = w.gram;
+    a.seed = p->seed;
+    a.s = s;
+    a.k = p->k;
+    a.m = m;
+    a.G = ly.L.G;
+    HIP_TRY(launch_fill(w.H, (int64_t)(m + 1) * m, 0.0, st));
+    const int64_t nsc = (int64_t)NSC_MAX * ly.L.G;
+    for (int j = 0; j <= m; ++j) {
+        a.j = j;
+        a.extend = (j == m) ? 1 : 0;
+        a.Wcur = w.W + (int64_t)(j & 1) * ly.ldU;
+        a.Wprev = w.W + (int64_t)((j + 1) & 1) * ly.ldU;
+        a.scal_prev = w.scal + ((j + 1) & 1) * nsc;
+        a.scal_cur = w.scal + (j & 1) * nsc;
+        a.skpart = w.skpart + (int64_t)j * ly.L.G * 2 * s;
+        hipEvent_t stop;
+        const bool timed = j < m;  // the extension pass has no product with A
+        if (timed) HIP_TRY(timing_begin(ctx, 0, st, &stop));
+        HIP_TRY(launch_arnoldi_step(a, p->zeta, ly.L.block, st));
+        if (timed) HIP_TRY(timing_end(stop, st));
+    }
+    HIP_TRY(launch_extension_finalize(w.scal + (m & 1) * nsc, ly.L.G, m, w.ctrl, w.eta, w.H, st));
+    HIP_TRY(launch_sketch_reduce(w.skpart, ly.L.G, s, m, p->zeta, w.ctrl, w.eta, w.SV, w.SAV, w.colnorm2, st));
+    return SKFAB_OK;
+}
+
+// Small problem and coefficients y (unnormalised-basis coefficients in w.ys).
+skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, hipStream_t st) {
+    const int m = p->m, s = p->s;
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    if (p->method == SKFAB_SFOM_CLOSED) tol = 1e-13;
+    const bool ls = p->method == SKFAB_SGMRES_QUAD;
+    HIP_TRY(launch_arnoldi_check(w.SV, w.SAV, w.H, s, m, p->k, w.ctrl, st));
+    HIP_TRY(launch_qr(w.SV, s, m + 1, w.ctrl, w.Tws, st));
+    HIP_TRY(launch_pencil_setup(w.SV, s, m, p->k, w.ctrl, w.H, w.K0r, w.T1r, st));
+    const int branch = (p->f == SKFAB_F_INVSQRT && !ls) ? 1 : 0;
+    // square pencil at t = 0: sigma, rcond, branch check; for 1/z with sFOM also the solution
+    HIP_TRY(launch_pencil_scalars(m, s, w.SV, w.ctrl, w.eta, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.y0, 0, branch, st));
+    if (p->f == SKFAB_F_INV) {
+        if (ls) HIP_TRY(launch_pencil_scalars(m, s, w.SV, w.ctrl, w.eta, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.y0, 1, 0, st));
+        HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
+        return SKFAB_OK;
+    }
+    if (p->f == SKFAB_F_POLY) {
+        HIP_TRY(hipMemcpyAsync(w.poly, p->poly, sizeof(double) * p->npoly, hipMemcpyHostToDevice, st));
+        HIP_TRY(launch_poly(w.ctrl, m, w.T1r, w.K0r, w.eta, w.poly, p->npoly, w.y0, st));
+        HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
+        return SKFAB_OK;
+    }
+    // z^(-1/2): adaptive Gauss-Chebyshev (Section 4.1 / 5.1)
+    int la = l1, lb = l2;
+    HIP_TRY(launch_quad_level(w.ctrl, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.nodebuf, m, la, ls ? 1 : 0, w.SV, s, w.eta, st));
+    HIP_TRY(launch_quad_reduce(w.ctrl, w.nodebuf, m, la, 1, tol, w.T1r, w.qprev, w.qcur, w.y0, st));
+    while (true) {
+        HIP_TRY(launch_quad_level(w.ctrl, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.nodebuf, m, lb, ls ? 1 : 0, w.SV, s, w.eta,
+                                  st));
+        HIP_TRY(launch_quad_reduce(w.ctrl, w.nodebuf, m, lb, 0, tol, w.T1r, w.qprev, w.qcur, w.y0, st));
+        const int nx = next_order(lb);
+        if (nx > lmax) break;
+        lb = nx;
+    }
+    HIP_TRY(launch_quad_fail(w.ctrl, st));
+    HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
+    return SKFAB_OK;
+}
+
+skfab_status read_info(const Ptrs& w, hipStream_t st, skfab_info* info) {
+    if (!info) return SKFAB_OK;
+    DevCtrl c;
+    HIP_TRY(hipMemcpyAsync(&c, w.ctrl, sizeof(DevCtrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    info->status = c.status;
+    info->m_used = c.m_used;
+    info->l_used = c.l_used;
+    info->reserved = 0;
+    info->eps_est = c.eps_est;
+    info->rcond_R = c.rcond;
+    info->sigma = c.sigma;
+    info->beta = c.beta;
+    info->arnoldi_relres = c.relres;
+    return SKFAB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t skfab_version(void) { return SKFAB_VERSION_MAJOR * 100 + SKFAB_VERSION_MINOR; }
+
+const char* skfab_status_string(int32_t s) {
+    switch (s) {
+        case SKFAB_OK: return "ok";
+        case SKFAB_ERR_ARG: return "invalid argument";
+        case SKFAB_ERR_SHAPE: return "invalid shape (need 1 <= k <= min(m,8), m < s <= min(N,1024), m <= 256)";
+        case SKFAB_ERR_RANK: return "sketched basis numerically rank deficient";
+        case SKFAB_ERR_BRANCH: return "projected matrix has an eigenvalue on the branch cut";
+        case SKFAB_ERR_QUAD: return "adaptive quadrature did not converge";
+        case SKFAB_ERR_HIP: return "HIP runtime error";
+        case SKFAB_ERR_WORKSPACE: return "workspace missing or too small";
+        default: return "unknown status";
+    }
+}
+
+skfab_status skfab_create(skfab_ctx** ctx, int32_t device, void* hip_stream) {
+    if (!ctx) return SKFAB_ERR_ARG;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess) return SKFAB_ERR_HIP;
+    if (device < 0 || device >= n) return SKFAB_ERR_ARG;
+    if (hipSetDevice(device) != hipSuccess) return SKFAB_ERR_HIP;
+    skfab_ctx* c = new (std::nothrow) skfab_ctx;
+    if (!c) return SKFAB_ERR_ARG;
+    c->device = device;
+    c->stream = static_cast<hipStream_t>(hip_stream);
+    *ctx = c;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_set_stream(skfab_ctx* ctx, void* hip_stream) {
+    if (!ctx) return SKFAB_ERR_ARG;
+    ctx->stream = static_cast<hipStream_t>(hip_stream);
+    return SKFAB_OK;
+}
+
+skfab_status skfab_destroy(skfab_ctx* ctx) {
+    if (ctx) {
+        for (int c = 0; c < 2; ++c)
+            for (hipEvent_t e : ctx->ev[c]) (void)hipEventDestroy(e);
+    }
+    delete ctx;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_timing_enable(skfab_ctx* ctx, int32_t enable) {
+    if (!ctx) return SKFAB_ERR_ARG;
+    if (enable && ctx->ev[0].empty()) {
+        if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+        for (int c = 0; c < 2; ++c) {
+            ctx->ev[c].resize(2 * TIMING_PAIRS);
+            for (auto& e : ctx->ev[c]) HIP_TRY(hipEventCreate(&e));
+        }
+    }
+    if (!enable && ctx->timing) {
+        for (int c = 0; c < 2; ++c) HIP_TRY(timing_flush(ctx, c));
+    }
+    ctx->timing = enable != 0;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_timing_read(skfab_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches) {
+    if (!ctx || kernel < 0 || kernel > 1 || !total_ms || !launches) return SKFAB_ERR_ARG;
+    HIP_TRY(timing_flush(ctx, kernel));
+    *total_ms = ctx->acc_ms[kernel];
+    *launches = ctx->count[kernel];
+    ctx->acc_ms[kernel] = 0.0;
+    ctx->count[kernel] = 0;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_workspace_bytes(const skfab_csr* A, const skfab_params* p, size_t* bytes) {
+    if (!bytes || !A || !p) return SKFAB_ERR_ARG;
+    skfab_status v = validate(A, p, false);
+    if (v != SKFAB_OK) return v;
+    if (A->n <= 0) return SKFAB_ERR_SHAPE;
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    *bytes = make_layout(A->n, p->m, p->s, l1, l2, lmax, p->npoly, true).total;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_solve(skfab_ctx* ctx, const skfab_csr* A, const double* b, double* x, const skfab_params* p,
+                         void* ws, size_t ws_bytes, skfab_info* info) {
+    if (!ctx || !b || !x) return SKFAB_ERR_ARG;
+    skfab_status v = validate(A, p, true);
+    if (v != SKFAB_OK) return v;
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    const Layout ly = make_layout(A->n, p->m, p->s, l1, l2, lmax, p->npoly, true);
+    if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    const Ptrs w = carve(ws, ly);
+    hipStream_t st = ctx->stream;
+    skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st);
+    if (r != SKFAB_OK) return r;
+    r = run_small(p, ly, w, st);
+    if (r != SKFAB_OK) return r;
+    hipEvent_t stop;
+    HIP_TRY(timing_begin(ctx, 1, st, &stop));
+    HIP_TRY(launch_assemble(w.U, ly.ldU, A->n, p->m, w.ctrl, w.ys, x, st));
+    HIP_TRY(timing_end(stop, st));
+    return read_info(w, st, info);
+}
+
+skfab_status skfab_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, const skfab_params* p, double* V,
+                           double* SV, double* SAV, double* H, void* ws, size_t ws_bytes, skfab_info* info) {
+    if (!ctx || !b) return SKFAB_ERR_ARG;
+    skfab_status v = validate(A, p, true);
+    if (v == SKFAB_ERR_ARG && p && p->f == SKFAB_F_EXP) v = SKFAB_OK;  // the basis does not depend on f
+    if (v != SKFAB_OK) return v;
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    const Layout ly = make_layout(A->n, p->m, p->s, l1, l2, lmax, p->npoly, true);
+    if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    const Ptrs w = carve(ws, ly);
+    hipStream_t st = ctx->stream;
+    skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st);
+    if (r != SKFAB_OK) return r;
+    const int m = p->m, s = p->s;
+    if (V) HIP_TRY(launch_normalize_basis(w.U, ly.ldU, A->n, m, w.ctrl, w.eta, V, st));
+    if (SV) HIP_TRY(hipMemcpyAsync(SV, w.SV, sizeof(double) * s * m, hipMemcpyDeviceToDevice, st));
+    if (SAV) HIP_TRY(hipMemcpyAsync(SAV, w.SAV, sizeof(double) * s * m, hipMemcpyDeviceToDevice, st));
+    if (H) HIP_TRY(hipMemcpyAsync(H, w.H, sizeof(double) * (m + 1) * m, hipMemcpyDeviceToDevice, st));
+    if (info) {
+        HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y, w.eta, w.colnorm2, w.ys, nullptr, st));
+        return read_info(w, st, info);
+    }
+    return SKFAB_OK;
+}
+
+skfab_status skfab_small_workspace_bytes(const skfab_params* p, size_t* bytes) {
+    if (!bytes || !p) return SKFAB_ERR_ARG;
+    skfab_status v = validate(nullptr, p, false);
+    if (v != SKFAB_OK) return v;
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    *bytes = make_layout(0, p->m, p->s, l1, l2, lmax, p->npoly, false).total;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_small_problem(skfab_ctx* ctx, const double* SVext, const double* Hbar, double beta,
+                                 const skfab_params* p, double* y, void* ws, size_t ws_bytes, skfab_info* info) {
+    if (!ctx || !SVext || !Hbar || !y) return SKFAB_ERR_ARG;
+    skfab_status v = validate(nullptr, p, false);
+    if (v != SKFAB_OK) return v;
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    const Layout ly = make_layout(0, p->m, p->s, l1, l2, lmax, p->npoly, false);
+    if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    const Ptrs w = carve(ws, ly);
+    hipStream_t st = ctx->stream;
+    const int m = p->m, s = p->s;
+    HIP_TRY(launch_init_ctrl(w.ctrl, m, st));
+    // the caller's basis is normalised: eta = 1 except eta[0] = beta (used for S b = beta S v_1)
+    HIP_TRY(launch_fill(w.eta, m + 2, 1.0, st));
+    HIP_TRY(hipMemcpyAsync(w.eta, &beta, sizeof(double), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w.SV, SVext, sizeof(double) * s * (m + 1), hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(w.H, Hbar, sizeof(double) * (m + 1) * m, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_fill(w.colnorm2, m + 1, 1.0, st));
+    // SAV is not an input here: the Arnoldi-relation check is skipped (relres = 0)
+    HIP_TRY(launch_fill(w.SAV, (int64_t)s * m, 0.0, st));
+    skfab_params q = *p;
+    skfab_status r = run_small(&q, ly, w, st);
+    if (r != SKFAB_OK) return r;
+    // run_small leaves y / eta in ys; with eta_j = 1 for j >= 1 only ys[0] differs
+    HIP_TRY(hipMemcpyAsync(y, w.y, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
+    return read_info(w, st, info);
+}
+
+skfab_status skfab_sketch_pattern(skfab_ctx* ctx, int64_t col0, int64_t ncols, int32_t s, int32_t zeta,
+                                  uint64_t seed, int32_t* rows, int8_t* signs) {
+    if (!ctx || !rows || !signs || col0 < 0 || ncols < 0) return SKFAB_ERR_ARG;
+    if (!zeta_ok(zeta) || zeta > s || s < 1) return SKFAB_ERR_SHAPE;
+    if (ncols == 0) return SKFAB_OK;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    HIP_TRY(launch_sketch_pattern(col0, ncols, s, zeta, seed, rows, signs, ctx->stream));
+    return SKFAB_OK;
+}
+
+size_t skfab_sketch_ws_bytes(int64_t n, int32_t s) {
+    if (n <= 0 || s <= 0) return 0;
+    return (size_t)sketch_apply_blocks(n) * s * sizeof(double);
+}
+
+skfab_status skfab_sketch_apply(skfab_ctx* ctx, int64_t n, int32_t s, int32_t zeta, uint64_t seed, const double* v,
+                                double* Sv, void* ws, size_t ws_bytes) {
+    if (!ctx || !v || !Sv || n <= 0) return SKFAB_ERR_ARG;
+    if (!zeta_ok(zeta) || zeta > s || s < 1 || s > SMAX) return SKFAB_ERR_SHAPE;
+    if (!ws || ws_bytes < skfab_sketch_ws_bytes(n, s)) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    HIP_TRY(launch_sketch_apply(n, s, zeta, seed, v, Sv, static_cast<double*>(ws), ctx->stream));
+    return SKFAB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,202 @@
+"""Python binding of libskfab with the C ABI's names.
+
+PyTorch is used only to hold device memory and to name the HIP stream; every
+step of the method runs in the library's kernels.  Device arrays are torch CUDA
+(HIP) tensors; the functions marshal pointers and sizes and raise
+``SkfabError`` on a non-OK status.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _native as N
+
+FUNCS = {"invsqrt": N.SKFAB_F_INVSQRT, "exp": N.SKFAB_F_EXP, "inv": N.SKFAB_F_INV, "poly": N.SKFAB_F_POLY}
+METHODS = {"sfom": N.SKFAB_SFOM_CLOSED, "sfom_quad": N.SKFAB_SFOM_QUAD, "sgmres": N.SKFAB_SGMRES_QUAD}
+
+
+class SkfabError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        msg = N.lib().skfab_status_string(status).decode()
+        super().__init__(f"{where}: {msg} (status {status})")
+        self.status = status
+
+
+def _check(status: int, where: str):
+    if status != N.SKFAB_OK:
+        raise SkfabError(status, where)
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _require_device(t: torch.Tensor, dtype, name: str):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must have dtype {dtype}")
+    if not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous")
+
+
+@dataclass
+class CSR:
+    """Device CSR matrix (int32 indices, float64 values)."""
+    rowptr: torch.Tensor
+    col: torch.Tensor
+    val: torch.Tensor
+
+    @property
+    def n(self) -> int:
+        return self.rowptr.numel() - 1
+
+    def c_struct(self) -> N.skfab_csr:
+        _require_device(self.rowptr, torch.int32, "rowptr")
+        _require_device(self.col, torch.int32, "col")
+        _require_device(self.val, torch.float64, "val")
+        return N.skfab_csr(self.n, self.col.numel(), self.rowptr.data_ptr(), self.col.data_ptr(),
+                           self.val.data_ptr(), N.SKFAB_VAL_F64)
+
+    @staticmethod
+    def from_numpy(rowptr, col, val, device="cuda"):
+        return CSR(torch.as_tensor(rowptr, dtype=torch.int32, device=device),
+                   torch.as_tensor(col, dtype=torch.int32, device=device),
+                   torch.as_tensor(val, dtype=torch.float64, device=device))
+
+
+def make_params(f="invsqrt", m=50, k=2, s=200, zeta=8, seed=0, method="sfom", fparam=0.0, poly=None,
+                l1=32, l2=45, lmax=1395, quad_tol=1e-13) -> N.skfab_params:
+    p = N.skfab_params()
+    p.f = FUNCS[f] if isinstance(f, str) else int(f)
+    p.fparam = float(fparam)
+    p.method = METHODS[method] if isinstance(method, str) else int(method)
+    p.m, p.k, p.s, p.zeta, p.seed = int(m), int(k), int(s), int(zeta), int(seed)
+    p.l1, p.l2, p.lmax, p.quad_tol = int(l1), int(l2), int(lmax), float(quad_tol)
+    p.prec = N.SKFAB_PREC_FP64
+    if poly is not None:
+        arr = (C.c_double * len(poly))(*[float(c) for c in poly])
+        p.poly = C.cast(arr, C.POINTER(C.c_double))
+        p.npoly = len(poly)
+        p._poly_keepalive = arr
+    else:
+        p.poly = None
+        p.npoly = 0
+    return p
+
+
+class Context:
+    """skfab_create / skfab_destroy around a device and a torch stream."""
+
+    def __init__(self, device: int = 0, stream: torch.cuda.Stream | None = None):
+        self.device = device
+        self.stream = stream or torch.cuda.current_stream(device)
+        self.handle = C.c_void_p()
+        _check(N.lib().skfab_create(C.byref(self.handle), device, C.c_void_p(self.stream.cuda_stream)),
+               "skfab_create")
+
+    def set_stream(self, stream: torch.cuda.Stream):
+        self.stream = stream
+        _check(N.lib().skfab_set_stream(self.handle, C.c_void_p(stream.cuda_stream)), "skfab_set_stream")
+
+    def close(self):
+        if self.handle:
+            N.lib().skfab_destroy(self.handle)
+            self.handle = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def skfab_version() -> int:
+    return N.lib().skfab_version()
+
+
+def skfab_workspace_bytes(A: CSR | int, p: N.skfab_params) -> int:
+    if isinstance(A, CSR):
+        csr = N.skfab_csr(A.n, A.col.numel(), None, None, None, N.SKFAB_VAL_F64)
+    else:
+        csr = N.skfab_csr(int(A), 0, None, None, None, N.SKFAB_VAL_F64)
+    out = C.c_size_t()
+    _check(N.lib().skfab_workspace_bytes(C.byref(csr), C.byref(p), C.byref(out)), "skfab_workspace_bytes")
+    return out.value
+
+
+def alloc_workspace(nbytes: int, device=None) -> torch.Tensor:
+    """Device bytes for the library (torch caching allocator; 256-byte aligned)."""
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device or "cuda")
+
+
+def skfab_solve(ctx: Context, A: CSR, b: torch.Tensor, x: torch.Tensor, p: N.skfab_params,
+                ws: torch.Tensor, want_info: bool = True):
+    _require_device(b, torch.float64, "b")
+    _require_device(x, torch.float64, "x")
+    csr = A.c_struct()
+    info = N.skfab_info() if want_info else None
+    st = N.lib().skfab_solve(ctx.handle, C.byref(csr), _ptr(b), _ptr(x), C.byref(p), _ptr(ws), ws.numel(),
+                             C.byref(info) if info is not None else None)
+    _check(st, "skfab_solve")
+    return info
+
+
+def skfab_arnoldi(ctx: Context, A: CSR, b: torch.Tensor, p: N.skfab_params, V=None, SV=None, SAV=None, H=None,
+                  ws: torch.Tensor = None, want_info: bool = True):
+    csr = A.c_struct()
+    info = N.skfab_info() if want_info else None
+    st = N.lib().skfab_arnoldi(ctx.handle, C.byref(csr), _ptr(b), C.byref(p), _ptr(V), _ptr(SV), _ptr(SAV),
+                               _ptr(H), _ptr(ws), ws.numel(), C.byref(info) if info is not None else None)
+    _check(st, "skfab_arnoldi")
+    return info
+
+
+def skfab_small_workspace_bytes(p: N.skfab_params) -> int:
+    out = C.c_size_t()
+    _check(N.lib().skfab_small_workspace_bytes(C.byref(p), C.byref(out)), "skfab_small_workspace_bytes")
+    return out.value
+
+
+def skfab_small_problem(ctx: Context, SVext: torch.Tensor, Hbar: torch.Tensor, beta: float, p: N.skfab_params,
+                        y: torch.Tensor, ws: torch.Tensor):
+    info = N.skfab_info()
+    st = N.lib().skfab_small_problem(ctx.handle, _ptr(SVext), _ptr(Hbar), float(beta), C.byref(p), _ptr(y),
+                                     _ptr(ws), ws.numel(), C.byref(info))
+    _check(st, "skfab_small_problem")
+    return info
+
+
+def skfab_sketch_pattern(ctx: Context, col0: int, ncols: int, s: int, zeta: int, seed: int,
+                         rows: torch.Tensor, signs: torch.Tensor):
+    _require_device(rows, torch.int32, "rows")
+    _require_device(signs, torch.int8, "signs")
+    _check(N.lib().skfab_sketch_pattern(ctx.handle, col0, ncols, s, zeta, seed, _ptr(rows), _ptr(signs)),
+           "skfab_sketch_pattern")
+
+
+def skfab_sketch_ws_bytes(n: int, s: int) -> int:
+    return N.lib().skfab_sketch_ws_bytes(n, s)
+
+
+def skfab_sketch_apply(ctx: Context, n: int, s: int, zeta: int, seed: int, v: torch.Tensor, Sv: torch.Tensor,
+                       ws: torch.Tensor):
+    _require_device(v, torch.float64, "v")
+    _require_device(Sv, torch.float64, "Sv")
+    _check(N.lib().skfab_sketch_apply(ctx.handle, n, s, zeta, seed, _ptr(v), _ptr(Sv), _ptr(ws), ws.numel()),
+           "skfab_sketch_apply")
+
+
+def skfab_timing_enable(ctx: Context, enable: bool = True):
+    _check(N.lib().skfab_timing_enable(ctx.handle, 1 if enable else 0), "skfab_timing_enable")
+
+
+def skfab_timing_read(ctx: Context, kernel: int = 0):
+    """(total milliseconds, launches) of kernel class 0 (Arnoldi step) or 1 (assembly) since the last read."""
+    ms = C.c_double()
+    n = C.c_int64()
+    _check(N.lib().skfab_timing_read(ctx.handle, kernel, C.byref(ms), C.byref(n)), "skfab_timing_read")
+    return ms.value, n.value

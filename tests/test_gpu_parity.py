@@ -1,0 +1,165 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Tolerances: bit-exact for the sketch pattern (integer work); relative 2-norm
+1e-10 for FP64 solves (stated per config); basis vectors compared column by
+column with a tolerance that grows with the step index, since two correct
+implementations of the recurrence round differently and the truncated basis
+amplifies the difference (the approximant itself depends only on the span).
+"""
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import (ctx, problem, device_csr, dev, gpu_solve, gpu_arnoldi, oracle_run, rel, log)
+from oracle import methods as ometh
+from oracle import sketch as osk
+from paper_2208_11447_amd import skfab as sk
+
+pytestmark = pytest.mark.gpu
+
+FP64_TOL = 1e-10
+
+
+@pytest.mark.parametrize("N,s,zeta,seed,col0", [
+    (5000, 200, 8, 0, 0), (3000, 37, 8, 5, 0), (4000, 400, 16, 1, 0), (2000, 9, 4, 2, 0),
+    (1000, 600, 8, 7, (1 << 31) - 500),   # counters beyond 32 bits
+])
+def test_sketch_pattern_bit_exact(N, s, zeta, seed, col0):
+    log(f"sketch pattern N={N} s={s} zeta={zeta} seed={seed} col0={col0}")
+    rows = torch.empty(N * zeta, dtype=torch.int32, device="cuda")
+    signs = torch.empty(N * zeta, dtype=torch.int8, device="cuda")
+    sk.skfab_sketch_pattern(ctx(), col0, N, s, zeta, seed, rows, signs)
+    r_or, s_or = osk.sparse_sign_pattern(col0 + N, s, zeta, seed, cols=np.arange(col0, col0 + N))
+    assert np.array_equal(rows.cpu().numpy().reshape(N, zeta), r_or.astype(np.int32))
+    assert np.array_equal(signs.cpu().numpy().reshape(N, zeta), s_or)
+
+
+@pytest.mark.parametrize("N,s", [(1000, 50), (123457, 400), (10000, 1024)])
+def test_sketch_apply(N, s):
+    log(f"sketch apply N={N} s={s}")
+    v = np.random.default_rng(N).standard_normal(N)
+    S = osk.sparse_sign_matrix(N, s, 8, 3)
+    ws = sk.alloc_workspace(sk.skfab_sketch_ws_bytes(N, s))
+    out = torch.empty(s, dtype=torch.float64, device="cuda")
+    sk.skfab_sketch_apply(ctx(), N, s, 8, 3, dev(v), out, ws)
+    assert rel(out.cpu().numpy(), S @ v) < 1e-14
+
+
+@pytest.mark.parametrize("n,m,k,s", [(30, 20, 2, 80), (37, 25, 3, 100), (40, 16, 1, 64), (33, 12, 4, 60)])
+def test_arnoldi_state_parity(n, m, k, s):
+    """V, SV, S A V and the truncated Hessenberg entries against the oracle; ragged N."""
+    log(f"arnoldi parity n={n} m={m} k={k} s={s}")
+    A, b, arrs = problem(n)
+    V, SV, SAV, H, info = gpu_arnoldi(arrs, b, m, k, s)
+    arn, _ = oracle_run(A, b, m, k, s, extend=True)
+    assert info.m_used == m
+    assert abs(info.beta - np.linalg.norm(b)) <= 1e-14 * np.linalg.norm(b)
+    for j in range(m):
+        tol = 1e-13 * 4.0 ** j
+        tol = min(tol, 1e-6)
+        assert rel(V[:, j], arn.V[:, j]) < tol, j
+        assert rel(SV[:, j], arn.SV[:, j]) < tol, j
+        assert rel(SAV[:, j], arn.SAV[:, j]) < tol, j
+    Ho = arn.H[:m + 1, :m]
+    assert np.max(np.abs(H - Ho)) < 1e-8 * np.max(np.abs(Ho))
+    assert np.allclose(np.tril(H, -2), 0)
+    # first columns must agree to rounding
+    assert rel(V[:, :3], arn.V[:, :3]) < 1e-13
+
+
+CASES_C1 = [
+    ("sfom", "invsqrt"), ("sgmres", "invsqrt"), ("sfom_quad", "invsqrt"),
+    ("sfom", "inv"), ("sgmres", "inv"),
+]
+
+
+@pytest.mark.parametrize("method,f", CASES_C1)
+def test_solve_parity_convdiff2d_n100(method, f):
+    """2D convection-diffusion, 100x100 grid, m=50, k=2, s=200, zeta=8."""
+    log(f"solve parity 2D n=100 method={method} f={f}")
+    A, b, arrs = problem(100)
+    x, info = gpu_solve(arrs, b, f=f, m=50, k=2, s=200, method=method, quad_tol=1e-13)
+    assert info.status == 0 and info.m_used == 50
+    arn, _ = oracle_run(A, b, 50, 2, 200)
+    ref = {"sfom": ometh.sfom_closed, "sgmres": ometh.sgmres, "sfom_quad": ometh.sfom_quad}[method]
+    xr = (ref(arn, f) if method == "sfom" else ref(arn, f, tol=1e-13)).x
+    err = rel(x, xr)
+    log(f"  rel err {err:.3e}  l_used={info.l_used} sigma={info.sigma:.4g} rcond={info.rcond_R:.3e} "
+        f"relres={info.arnoldi_relres:.2e}")
+    assert err < FP64_TOL
+    assert info.arnoldi_relres < 1e-12
+
+
+def test_polynomial_exactness_gpu():
+    """Interpolation corollary on the GPU: deg p <= m-1 gives p(A) b exactly."""
+    log("polynomial exactness n=60")
+    A, b, arrs = problem(60)
+    p = [0.5, -1e-4, 3e-9, -2e-14]
+    x, info = gpu_solve(arrs, b, f="poly", poly=p, m=10, k=2, s=40)
+    ref = p[-1] * b
+    for c in p[-2::-1]:
+        ref = A @ ref + c * b
+    assert rel(x, ref) < 1e-10
+
+
+def test_small_problem_hook_parity():
+    """The small problem alone, fed the oracle's Arnoldi data."""
+    log("small problem hook")
+    A, b, arrs = problem(50)
+    m, k, s = 30, 2, 120
+    arn, S = oracle_run(A, b, m, k, s, extend=True)
+    hlast = arn.H[m, m - 1]
+    SVext = np.column_stack([arn.SV, hlast * (S @ arn.v_next)])
+    for method in ("sfom", "sgmres"):
+        p = sk.make_params(f="invsqrt", m=m, k=k, s=s, method=method, quad_tol=1e-13)
+        ws = sk.alloc_workspace(sk.skfab_small_workspace_bytes(p))
+        y = torch.empty(m, dtype=torch.float64, device="cuda")
+        info = sk.skfab_small_problem(ctx(), dev(SVext.T.copy()), dev(arn.H[:m + 1, :m].T.copy()),
+                                      arn.beta, p, y, ws)
+        ref = (ometh.sfom_closed(arn, "invsqrt") if method == "sfom" else ometh.sgmres(arn, "invsqrt", tol=1e-13))
+        assert info.status == 0
+        assert rel(arn.V @ y.cpu().numpy(), ref.x) < 1e-11
+
+
+def test_zero_rhs_gives_zero():
+    log("zero rhs")
+    _, b, arrs = problem(20)
+    x, info = gpu_solve(arrs, np.zeros_like(b), m=10, k=2, s=40)
+    assert info.m_used == 0 and np.all(x == 0)
+
+
+def test_lucky_breakdown():
+    """b in an A-invariant subspace of dimension 3 with k = 3: m_used = 3, exact result."""
+    log("breakdown")
+    import scipy.sparse as sp
+    rng = np.random.default_rng(0)
+    blk = np.diag([2.0, 5.0, 9.0]) + 0.5 * rng.standard_normal((3, 3))
+    rest = sp.diags(np.linspace(1.0, 9.0, 197))
+    A = sp.block_diag([blk, rest]).tocsr()
+    A.sort_indices()
+    b = np.zeros(200)
+    b[:3] = rng.standard_normal(3)
+    arrs = (A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data)
+    x, info = gpu_solve(arrs, b, f="invsqrt", m=8, k=3, s=40)
+    import scipy.linalg as sla
+    truth = np.zeros(200)
+    truth[:3] = np.real(np.linalg.solve(sla.sqrtm(blk), b[:3]))
+    assert info.m_used == 3
+    assert rel(x, truth) < 1e-10
+
+
+def test_run_to_run_bitwise_identical():
+    log("determinism")
+    _, b, arrs = problem(64)
+    x1, _ = gpu_solve(arrs, b, m=30, k=2, s=100)
+    x2, _ = gpu_solve(arrs, b, m=30, k=2, s=100)
+    assert np.array_equal(x1, x2)
+
+
+def test_seed_matters_and_zeta():
+    log("seed/zeta")
+    A, b, arrs = problem(40)
+    for zeta, seed in ((4, 3), (16, 1)):
+        x, info = gpu_solve(arrs, b, m=20, k=2, s=80, zeta=zeta, seed=seed)
+        arn, _ = oracle_run(A, b, 20, 2, 80, zeta=zeta, seed=seed)
+        assert rel(x, ometh.sfom_closed(arn, "invsqrt").x) < FP64_TOL

@@ -1,0 +1,80 @@
+"""CPU checks of the C ABI: the library loads, exports every declared symbol,
+and rejects bad shapes on the host (no device work)."""
+import ctypes as C
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_2208_11447_amd import _native as N
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "skfab.h")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(skfab_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_binding_names():
+    assert sorted(N.EXPORTED) == declared_functions()
+
+
+def test_library_exports_every_symbol():
+    lib = N.lib()
+    out = subprocess.run(["nm", "-D", "--defined-only", N.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r"\sT\s(skfab_\w+)", out))
+    for name in declared_functions():
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def _params(**kw):
+    p = N.skfab_params()
+    p.f, p.method, p.m, p.k, p.s, p.zeta, p.seed = 0, 0, 50, 2, 200, 8, 0
+    p.l1, p.l2, p.lmax, p.quad_tol, p.prec = 32, 45, 1395, 1e-13, 0
+    for k, v in kw.items():
+        setattr(p, k, v)
+    return p
+
+
+def _ws(n, **kw):
+    csr = N.skfab_csr(n, 5 * n, None, None, None, 0)
+    out = C.c_size_t()
+    st = N.lib().skfab_workspace_bytes(C.byref(csr), C.byref(_params(**kw)), C.byref(out))
+    return st, out.value
+
+
+def test_workspace_sizes_grow_with_problem():
+    st1, a = _ws(10_000)
+    st2, b = _ws(2_097_152, m=200, s=400)
+    assert st1 == st2 == N.SKFAB_OK
+    assert b > a > 0
+    # the basis dominates: N * m doubles
+    assert b >= 2_097_152 * 200 * 8
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(m=200, s=200), N.SKFAB_ERR_SHAPE),   # m < s violated
+    (dict(k=0), N.SKFAB_ERR_SHAPE),
+    (dict(k=9, m=50), N.SKFAB_ERR_SHAPE),      # k above the fused-kernel limit
+    (dict(m=300, s=600), N.SKFAB_ERR_SHAPE),   # m above the small-problem limit
+    (dict(s=2000), N.SKFAB_ERR_SHAPE),
+    (dict(zeta=3), N.SKFAB_ERR_SHAPE),
+    (dict(f=7), N.SKFAB_ERR_ARG),
+    (dict(method=1, f=3), N.SKFAB_ERR_ARG),    # polynomial needs the closed form
+    (dict(l1=45, l2=32), N.SKFAB_ERR_ARG),
+])
+def test_host_validation(kw, status):
+    st, _ = _ws(10_000, **kw)
+    assert st == status
+
+
+def test_status_strings():
+    lib = N.lib()
+    for s in range(8):
+        assert lib.skfab_status_string(s)
+    assert lib.skfab_status_string(99) == b"unknown status"
