@@ -60,8 +60,8 @@ def step_kernel_bytes(N: int, nnz: int, k: int) -> int:
 def cpu_baseline(cfg, arrays, b, sample_steps):
     """Time the oracle as it stands on a bounded sample: `sample_steps` of the m
     truncated-Arnoldi steps on the full operator (per-step time scaled to m), the
-    oracle small problem + assembly at full m on the same-shape problem of a 32^3
-    grid, and the sketch construction."""
+    oracle small problem at full m and s (its cost does not depend on N) on the
+    same family's 64^3 grid, and the sketch construction."""
     import numpy as np
     import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
@@ -86,7 +86,7 @@ def cpu_baseline(cfg, arrays, b, sample_steps):
         _ = arn.V @ np.ones(arn.m_used)
         t_asm = time.perf_counter() - t0
         # small problem at full m on a smaller operator of the same family
-        rp2, col2, val2 = convdiff_csr(32, cfg["dim"], cfg["diffusion"], cfg["convection"])
+        rp2, col2, val2 = convdiff_csr(64, cfg["dim"], cfg["diffusion"], cfg["convection"])
         N2 = rp2.size - 1
         A2 = sp.csr_matrix((val2, col2, rp2), shape=(N2, N2))
         S2 = osk.sparse_sign_matrix(N2, s, zeta, 0)
@@ -99,7 +99,7 @@ def cpu_baseline(cfg, arrays, b, sample_steps):
     per_solve = t_sketch + t_arn / sample_steps * m + t_asm / sample_steps * m + t_small
     sample = (f"oracle: sketch build + {sample_steps} of {m} truncated-Arnoldi steps on the full operator "
               f"({t_arn:.1f} s, scaled to {m} steps) + assembly scaled likewise + small problem at m={m} "
-              f"({t_small:.2f} s); single thread")
+              f"({t_small:.2f} s, 64^3 grid); single thread")
     return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle", "sample": sample,
             "sec_per_solve": per_solve}
 

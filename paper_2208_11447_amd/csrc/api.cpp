@@ -46,6 +46,16 @@ hipError_t launch_finish_coeffs(DevCtrl* ctrl, int m, const double* y, const dou
                                 double* ys, double* yout, hipStream_t st);
 hipError_t launch_assemble(const double* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl, const double* ys,
                            double* x, hipStream_t st);
+hipError_t launch_hhat(const DevCtrl* ctrl, int m, const double* T1r, const double* X, int s, const double* H,
+                       double tau, double* Ahat, double* norm1, hipStream_t st);
+hipError_t launch_combine(const DevCtrl* ctrl, int m, double a, const double* P, double b, const double* Q,
+                          double c, const double* R, double d, double* D, hipStream_t st);
+hipError_t launch_dgemm(const DevCtrl* ctrl, int m, const double* A, const double* B, double beta, double* C,
+                        hipStream_t st);
+hipError_t launch_lu(DevCtrl* ctrl, int m, double* Q, int* piv, hipStream_t st);
+hipError_t launch_lu_solve_cols(const DevCtrl* ctrl, int m, const double* LU, const int* piv, double* P,
+                                hipStream_t st);
+hipError_t launch_first_column(const DevCtrl* ctrl, const double* X, const double* eta, double* y, hipStream_t st);
 constexpr int QR_NB_HOST = 16;
 constexpr int NODE_SLOTS_HOST = 256;
 }  // namespace skfab
@@ -103,6 +113,7 @@ hipError_t timing_end(hipEvent_t stop, hipStream_t st) {
 namespace {
 
 constexpr size_t ALIGN = 256;
+constexpr int EXP_BUFS = 10;  // dense m x m work matrices of the exponential
 constexpr int GMAX_BLOCKS = 256;  // step-kernel blocks for large N (one per CU)
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -140,7 +151,7 @@ Launch step_launch(int64_t N, int s) {
 
 struct Layout {
     size_t ctrl, eta, wnorm, H, gram, colnorm2, scal, U, W, skpart, SV, SAV, Tws, K0r, T1r, Ubuf, Urhs, nodebuf,
-        qprev, qcur, y, ys, y0, poly, total;
+        qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, total;
     int64_t ldU;
     int lnodes;
     Launch L;
@@ -195,6 +206,9 @@ Layout make_layout(int64_t N, int m, int s, int l1, int l2, int lmax, int npoly,
     ly.ys = take(m * d);
     ly.y0 = take(m * d);
     ly.poly = take((size_t)(npoly > 0 ? npoly : 1) * d);
+    ly.expbuf = take((size_t)EXP_BUFS * m * m * d);
+    ly.piv = take((size_t)m * sizeof(int));
+    ly.norm1 = take(d);
     ly.total = off;
     return ly;
 }
@@ -202,7 +216,8 @@ Layout make_layout(int64_t N, int m, int s, int l1, int l2, int lmax, int npoly,
 struct Ptrs {
     DevCtrl* ctrl;
     double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *U, *W, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Ubuf, *Urhs,
-        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly;
+        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1;
+    int* piv;
 };
 
 Ptrs carve(void* ws, const Layout& ly) {
@@ -214,7 +229,8 @@ Ptrs carve(void* ws, const Layout& ly) {
     p.scal = D(ly.scal); p.U = D(ly.U); p.W = D(ly.W); p.skpart = D(ly.skpart); p.SV = D(ly.SV); p.SAV = D(ly.SAV);
     p.Tws = D(ly.Tws); p.K0r = D(ly.K0r); p.T1r = D(ly.T1r); p.Ubuf = D(ly.Ubuf); p.Urhs = D(ly.Urhs);
     p.nodebuf = D(ly.nodebuf); p.qprev = D(ly.qprev); p.qcur = D(ly.qcur); p.y = D(ly.y); p.ys = D(ly.ys);
-    p.y0 = D(ly.y0); p.poly = D(ly.poly);
+    p.y0 = D(ly.y0); p.poly = D(ly.poly); p.expbuf = D(ly.expbuf); p.norm1 = D(ly.norm1);
+    p.piv = reinterpret_cast<int*>(b + ly.piv);
     return p;
 }
 
@@ -250,7 +266,7 @@ skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matri
     }
     if (p->f == SKFAB_F_EXP) {
         if (p->method != SKFAB_SFOM_CLOSED) return SKFAB_ERR_ARG;
-        return SKFAB_ERR_ARG;  // closed-form exponential not available in this build
+        if (!(p->fparam >= 0.0)) return SKFAB_ERR_ARG;
     }
     return SKFAB_OK;
 }
@@ -307,6 +323,59 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
     return SKFAB_OK;
 }
 
+// y0 = exp(-tau H_hat) beta e_1 by [13/13] Pade scaling and squaring.  Reads ||A||_1
+// back to the host once to choose the number of squarings.
+skfab_status run_expm(const skfab_params* p, const Ptrs& w, hipStream_t st) {
+    const int m = p->m, s = p->s;
+    double* B[EXP_BUFS];
+    for (int i = 0; i < EXP_BUFS; ++i) B[i] = w.expbuf + (size_t)i * m * m;
+    double *A = B[0], *A2 = B[1], *A4 = B[2], *A6 = B[3], *T = B[4], *W1 = B[5], *U = B[6], *V = B[7], *Q = B[8],
+           *X2 = B[9];
+    HIP_TRY(launch_fill(w.norm1, 1, 0.0, st));
+    HIP_TRY(launch_fill(w.y0, m, 0.0, st));
+    HIP_TRY(launch_hhat(w.ctrl, m, w.T1r, w.SV, s, w.H, p->fparam, A, w.norm1, st));
+    double nrm = 0.0;
+    HIP_TRY(hipMemcpyAsync(&nrm, w.norm1, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double theta13 = 5.371920351148152;  // Higham (2005), Table 2.3
+    int sq = 0;
+    if (std::isfinite(nrm) && nrm > theta13) sq = (int)std::ceil(std::log2(nrm / theta13));
+    if (!std::isfinite(nrm)) return SKFAB_OK;  // m_used == 0 or overflow: y0 stays as initialised
+    if (sq > 0) HIP_TRY(launch_combine(w.ctrl, m, std::ldexp(1.0, -sq), A, 0, nullptr, 0, nullptr, 0.0, A, st));
+    double c[14];
+    c[0] = 1.0;
+    for (int j = 0; j < 13; ++j) c[j + 1] = c[j] * (13.0 - j) / ((26.0 - j) * (j + 1.0));
+    HIP_TRY(launch_dgemm(w.ctrl, m, A, A, 0.0, A2, st));
+    HIP_TRY(launch_dgemm(w.ctrl, m, A2, A2, 0.0, A4, st));
+    HIP_TRY(launch_dgemm(w.ctrl, m, A4, A2, 0.0, A6, st));
+    // U = A (A6 (c13 A6 + c11 A4 + c9 A2) + c7 A6 + c5 A4 + c3 A2 + c1 I)
+    HIP_TRY(launch_combine(w.ctrl, m, c[13], A6, c[11], A4, c[9], A2, 0.0, T, st));
+    HIP_TRY(launch_dgemm(w.ctrl, m, A6, T, 0.0, W1, st));
+    HIP_TRY(launch_combine(w.ctrl, m, 1.0, W1, c[7], A6, c[5], A4, 0.0, W1, st));
+    HIP_TRY(launch_combine(w.ctrl, m, 1.0, W1, c[3], A2, 0, nullptr, c[1], W1, st));
+    HIP_TRY(launch_dgemm(w.ctrl, m, A, W1, 0.0, U, st));
+    // V = A6 (c12 A6 + c10 A4 + c8 A2) + c6 A6 + c4 A4 + c2 A2 + c0 I
+    HIP_TRY(launch_combine(w.ctrl, m, c[12], A6, c[10], A4, c[8], A2, 0.0, T, st));
+    HIP_TRY(launch_dgemm(w.ctrl, m, A6, T, 0.0, V, st));
+    HIP_TRY(launch_combine(w.ctrl, m, 1.0, V, c[6], A6, c[4], A4, 0.0, V, st));
+    HIP_TRY(launch_combine(w.ctrl, m, 1.0, V, c[2], A2, 0, nullptr, c[0], V, st));
+    // Q = V - U, P = V + U (into T); X = Q^-1 P
+    HIP_TRY(launch_combine(w.ctrl, m, 1.0, V, -1.0, U, 0, nullptr, 0.0, Q, st));
+    HIP_TRY(launch_combine(w.ctrl, m, 1.0, V, 1.0, U, 0, nullptr, 0.0, T, st));
+    HIP_TRY(launch_lu(w.ctrl, m, Q, w.piv, st));
+    HIP_TRY(launch_lu_solve_cols(w.ctrl, m, Q, w.piv, T, st));
+    double* cur = T;
+    double* nxt = X2;
+    for (int i = 0; i < sq; ++i) {
+        HIP_TRY(launch_dgemm(w.ctrl, m, cur, cur, 0.0, nxt, st));
+        double* t = cur;
+        cur = nxt;
+        nxt = t;
+    }
+    HIP_TRY(launch_first_column(w.ctrl, cur, w.eta, w.y0, st));
+    return SKFAB_OK;
+}
+
 // Small problem and coefficients y (unnormalised-basis coefficients in w.ys).
 skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, hipStream_t st) {
     const int m = p->m, s = p->s;
@@ -329,6 +398,12 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     if (p->f == SKFAB_F_POLY) {
         HIP_TRY(hipMemcpyAsync(w.poly, p->poly, sizeof(double) * p->npoly, hipMemcpyHostToDevice, st));
         HIP_TRY(launch_poly(w.ctrl, m, w.T1r, w.K0r, w.eta, w.poly, p->npoly, w.y0, st));
+        HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
+        return SKFAB_OK;
+    }
+    if (p->f == SKFAB_F_EXP) {
+        skfab_status r = run_expm(p, w, st);
+        if (r != SKFAB_OK) return r;
         HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
         return SKFAB_OK;
     }

@@ -90,6 +90,20 @@ def test_solve_parity_convdiff2d_n100(method, f):
     assert info.arnoldi_relres < 1e-12
 
 
+@pytest.mark.parametrize("tau", [1e-3, 1e-2])
+def test_solve_parity_exp_convdiff2d_n100(tau):
+    """f(z) = exp(-tau z), closed form, 2D 100x100 grid, m=50, k=2, s=200."""
+    log(f"solve parity exp tau={tau}")
+    A, b, arrs = problem(100)
+    x, info = gpu_solve(arrs, b, f="exp", fparam=tau, m=50, k=2, s=200, method="sfom")
+    arn, _ = oracle_run(A, b, 50, 2, 200)
+    xr = ometh.sfom_closed(arn, "exp", tau).x
+    err = rel(x, xr)
+    log(f"  rel err {err:.3e} |x|={np.linalg.norm(xr):.3e}")
+    assert info.status == 0
+    assert err < FP64_TOL
+
+
 def test_polynomial_exactness_gpu():
     """Interpolation corollary on the GPU: deg p <= m-1 gives p(A) b exactly."""
     log("polynomial exactness n=60")
