@@ -13,12 +13,13 @@
 
 namespace skfab {
 hipError_t launch_arnoldi_step(const StepArgs& a, int zeta, int block, hipStream_t st);
-hipError_t launch_sketch_reduce(const double* skpart, int G, int s, int m, int zeta, const DevCtrl* ctrl,
-                                const double* eta, double* SV, double* SAV, double* colnorm2, hipStream_t st);
-hipError_t launch_extension_finalize(const double* scal, int G, int m, DevCtrl* ctrl, double* eta, double* H,
-                                     hipStream_t st);
+hipError_t launch_arnoldi_tail(const StepArgs& a, double* colnorm2, hipStream_t st);
 hipError_t launch_arnoldi_check(const double* SV, const double* SAV, const double* H, int s, int m, int k,
-                                DevCtrl* ctrl, hipStream_t st);
+                                DevCtrl* ctrl, double* part, hipStream_t st);
+int64_t sell_scan_blocks(int64_t nslices);
+hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const double* val, int64_t N,
+                               int64_t nslices, int64_t capacity, DevCtrl* ctrl, int32_t* sl_len, int64_t* sl_ptr,
+                               int64_t* bsum, int32_t* sl_col, double* sl_val, hipStream_t st);
 hipError_t launch_normalize_basis(const double* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl,
                                   const double* eta, double* V, hipStream_t st);
 hipError_t launch_sketch_pattern(int64_t col0, int64_t ncols, int s, int zeta, uint64_t seed, int32_t* rows,
@@ -34,11 +35,11 @@ hipError_t launch_pencil_setup(const double* X, int s, int m, int k, const DevCt
 hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, const double* eta,
                                  const double* T1r, const double* K0r, double* Ubuf, double* Urhs, double* y0,
                                  int is_ls, int branch_check, hipStream_t st);
-hipError_t launch_quad_level(const DevCtrl* ctrl, const double* T1r, const double* K0r, double* Ubuf, double* Urhs,
-                             double* nodebuf, int m, int l, int is_ls, const double* X, int s, const double* eta,
-                             hipStream_t st);
-hipError_t launch_quad_reduce(DevCtrl* ctrl, const double* nodebuf, int m, int l, int first, double tol,
-                              const double* T1r, double* qprev, double* qcur, double* y, hipStream_t st);
+hipError_t launch_quad_group(const DevCtrl* ctrl, const QuadGroup& g, const double* T1r, const double* K0r,
+                             double* Ubuf, double* Urhs, double* nodebuf, int m, int is_ls, const double* X,
+                             const double* eta, hipStream_t st);
+hipError_t launch_quad_reduce(DevCtrl* ctrl, const QuadGroup& g, const double* nodebuf, int m, double tol,
+                              const double* T1r, double* qprev, double* y, hipStream_t st);
 hipError_t launch_quad_fail(DevCtrl* ctrl, hipStream_t st);
 hipError_t launch_poly(const DevCtrl* ctrl, int m, const double* T1r, const double* K0r, const double* eta,
                        const double* coef, int npoly, double* y, hipStream_t st);
@@ -57,7 +58,7 @@ hipError_t launch_lu_solve_cols(const DevCtrl* ctrl, int m, const double* LU, co
                                 hipStream_t st);
 hipError_t launch_first_column(const DevCtrl* ctrl, const double* X, const double* eta, double* y, hipStream_t st);
 constexpr int QR_NB_HOST = 16;
-constexpr int NODE_SLOTS_HOST = 256;
+constexpr int NODE_SLOTS_HOST = 1024;
 }  // namespace skfab
 
 using namespace skfab;
@@ -130,6 +131,8 @@ int next_order(int l) {
 struct Launch {
     int block;
     int G;
+    int64_t nslices;
+    int64_t slices_per_chunk;
     int64_t rows_per_chunk;
 };
 
@@ -137,39 +140,74 @@ Launch step_launch(int64_t N, int s) {
     // largest block whose per-wave sketch bins fit in LDS (160 KiB, keep 4 KiB spare)
     const size_t lds_budget = 156 * 1024;
     int block = 1024;
-    while (block > 256 && (size_t)(block / 64) * 2 * s * sizeof(double) > lds_budget) block /= 2;
+    auto lds_of = [&](int bl) {
+        const size_t bins = (size_t)(bl / 64) * 2 * s, red = (size_t)(2 * KMAX + 1) * (bl + 72);
+        return (bins > red ? bins : red) * sizeof(double);
+    };
+    while (block > 256 && lds_of(block) > lds_budget) block /= 2;
     if (N < (int64_t)block * 256) block = 256;  // small problems: more, smaller blocks
-    int64_t tiles = (N + block - 1) / block;
-    int64_t G = tiles < GMAX_BLOCKS * (1024 / block) ? tiles : GMAX_BLOCKS * (1024 / block);
-    G = (G + 7) / 8 * 8;
     Launch L;
     L.block = block;
+    L.nslices = (N + 63) / 64;
+    const int waves = block / 64;
+    int64_t G = (L.nslices + waves - 1) / waves;
+    const int64_t gmax = (int64_t)GMAX_BLOCKS * (1024 / block);
+    if (G > gmax) G = gmax;
+    G = (G + 7) / 8 * 8;
     L.G = (int)G;
+    L.slices_per_chunk = (L.nslices + G - 1) / G;
     L.rows_per_chunk = (N + G - 1) / G;
     return L;
 }
 
 struct Layout {
     size_t ctrl, eta, wnorm, H, gram, colnorm2, scal, U, W, skpart, SV, SAV, Tws, K0r, T1r, Ubuf, Urhs, nodebuf,
-        qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, total;
+        qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, chk, sl_len, sl_ptr, bsum, sl_col, sl_val, total;
     int64_t ldU;
+    int64_t sell_capacity;
     int lnodes;
     Launch L;
 };
 
-int max_level_nodes(int l1, int l2, int lmax) {
-    int mx = l1 > l2 ? l1 : l2;
-    int l = l2;
+std::vector<int> order_sequence(int l1, int l2, int lmax) {
+    std::vector<int> seq{l1, l2};
     while (true) {
-        int nx = next_order(l);
+        const int nx = next_order(seq.back());
         if (nx > lmax) break;
-        l = nx;
-        if (l > mx) mx = l;
+        seq.push_back(nx);
     }
+    return seq;
+}
+
+// Consecutive orders packed into launches of at most NODE_SLOTS nodes (a single
+// order larger than that forms its own group).
+std::vector<QuadGroup> quad_groups(int l1, int l2, int lmax) {
+    const std::vector<int> seq = order_sequence(l1, l2, lmax);
+    std::vector<QuadGroup> out;
+    QuadGroup g;
+    std::memset(&g, 0, sizeof(g));
+    g.first = 1;
+    for (int l : seq) {
+        if (g.nlev > 0 && (g.total + l > NODE_SLOTS_HOST || g.nlev == MAX_GROUP_LEVELS)) {
+            out.push_back(g);
+            std::memset(&g, 0, sizeof(g));
+        }
+        g.lev_l[g.nlev] = l;
+        g.lev_off[g.nlev] = g.total;
+        g.total += l;
+        g.nlev += 1;
+    }
+    if (g.nlev > 0) out.push_back(g);
+    return out;
+}
+
+int max_level_nodes(int l1, int l2, int lmax) {
+    int mx = 0;
+    for (const QuadGroup& g : quad_groups(l1, l2, lmax)) mx = g.total > mx ? g.total : mx;
     return mx;
 }
 
-Layout make_layout(int64_t N, int m, int s, int l1, int l2, int lmax, int npoly, bool with_basis) {
+Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lmax, int npoly, bool with_basis) {
     Layout ly;
     ly.L = step_launch(N > 0 ? N : 1, s);
     ly.ldU = (N + 63) / 64 * 64;
@@ -191,7 +229,15 @@ Layout make_layout(int64_t N, int m, int s, int l1, int l2, int lmax, int npoly,
     ly.scal = take((size_t)2 * NSC_MAX * G * d);
     ly.U = with_basis ? take((size_t)ly.ldU * m * d) : take(0);
     ly.W = with_basis ? take((size_t)2 * ly.ldU * d) : take(0);
-    ly.skpart = with_basis ? take((size_t)(m + 1) * G * 2 * s * d) : take(0);
+    ly.skpart = with_basis ? take((size_t)2 * G * 2 * s * d) : take(0);
+    // SELL-64 copy of A: room for 25% more entries than nnz plus one padded row per slice
+    ly.sell_capacity = with_basis ? nnz + nnz / 4 + 64 * ly.L.nslices : 0;
+    ly.sl_len = with_basis ? take((size_t)ly.L.nslices * sizeof(int32_t)) : take(0);
+    ly.sl_ptr = with_basis ? take((size_t)ly.L.nslices * sizeof(int64_t)) : take(0);
+    ly.bsum = with_basis ? take((size_t)sell_scan_blocks(ly.L.nslices) * sizeof(int64_t)) : take(0);
+    ly.sl_col = with_basis ? take((size_t)ly.sell_capacity * sizeof(int32_t)) : take(0);
+    ly.sl_val = with_basis ? take((size_t)ly.sell_capacity * d) : take(0);
+    ly.chk = take((size_t)2 * m * d);
     ly.SV = take((size_t)s * (m + 1) * d);
     ly.SAV = take((size_t)s * m * d);
     ly.Tws = take((size_t)QR_NB_HOST * QR_NB_HOST * d);
@@ -216,8 +262,10 @@ Layout make_layout(int64_t N, int m, int s, int l1, int l2, int lmax, int npoly,
 struct Ptrs {
     DevCtrl* ctrl;
     double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *U, *W, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Ubuf, *Urhs,
-        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1;
+        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1, *chk, *sl_val;
     int* piv;
+    int32_t *sl_len, *sl_col;
+    int64_t *sl_ptr, *bsum;
 };
 
 Ptrs carve(void* ws, const Layout& ly) {
@@ -231,6 +279,12 @@ Ptrs carve(void* ws, const Layout& ly) {
     p.nodebuf = D(ly.nodebuf); p.qprev = D(ly.qprev); p.qcur = D(ly.qcur); p.y = D(ly.y); p.ys = D(ly.ys);
     p.y0 = D(ly.y0); p.poly = D(ly.poly); p.expbuf = D(ly.expbuf); p.norm1 = D(ly.norm1);
     p.piv = reinterpret_cast<int*>(b + ly.piv);
+    p.chk = D(ly.chk);
+    p.sl_val = D(ly.sl_val);
+    p.sl_len = reinterpret_cast<int32_t*>(b + ly.sl_len);
+    p.sl_col = reinterpret_cast<int32_t*>(b + ly.sl_col);
+    p.sl_ptr = reinterpret_cast<int64_t*>(b + ly.sl_ptr);
+    p.bsum = reinterpret_cast<int64_t*>(b + ly.bsum);
     return p;
 }
 
@@ -282,28 +336,40 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
                          const Layout& ly, const Ptrs& w, hipStream_t st) {
     const int m = p->m, s = p->s;
     HIP_TRY(launch_init_ctrl(w.ctrl, m, st));
+    HIP_TRY(launch_sell_convert(A->rowptr, A->col, static_cast<const double*>(A->val), A->n, ly.L.nslices,
+                                ly.sell_capacity, w.ctrl, w.sl_len, w.sl_ptr, w.bsum, w.sl_col, w.sl_val, st));
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.N = A->n;
-    a.rows_per_chunk = ly.L.rows_per_chunk;
     a.ldU = ly.ldU;
     a.rowptr = A->rowptr;
     a.col = A->col;
     a.val = static_cast<const double*>(A->val);
+    a.sl_ptr = w.sl_ptr;
+    a.sl_len = w.sl_len;
+    a.sl_col = w.sl_col;
+    a.sl_val = w.sl_val;
+    a.nslices = ly.L.nslices;
+    a.slices_per_chunk = ly.L.slices_per_chunk;
+    a.rows_per_chunk = ly.L.rows_per_chunk;
     a.b = b;
     a.U = w.U;
+    a.SV = w.SV;
+    a.SAV = w.SAV;
     a.ctrl = w.ctrl;
     a.eta = w.eta;
     a.wnorm = w.wnorm;
     a.H = w.H;
     a.gram = w.gram;
     a.seed = p->seed;
+    a.inv_sqrt_zeta = 1.0 / std::sqrt((double)p->zeta);
     a.s = s;
     a.k = p->k;
     a.m = m;
     a.G = ly.L.G;
     HIP_TRY(launch_fill(w.H, (int64_t)(m + 1) * m, 0.0, st));
     const int64_t nsc = (int64_t)NSC_MAX * ly.L.G;
+    const int64_t nsk = (int64_t)2 * s * ly.L.G;
     for (int j = 0; j <= m; ++j) {
         a.j = j;
         a.extend = (j == m) ? 1 : 0;
@@ -311,15 +377,18 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
         a.Wprev = w.W + (int64_t)((j + 1) & 1) * ly.ldU;
         a.scal_prev = w.scal + ((j + 1) & 1) * nsc;
         a.scal_cur = w.scal + (j & 1) * nsc;
-        a.skpart = w.skpart + (int64_t)j * ly.L.G * 2 * s;
+        a.skp_prev = w.skpart + ((j + 1) & 1) * nsk;
+        a.skp_cur = w.skpart + (j & 1) * nsk;
         hipEvent_t stop;
         const bool timed = j < m;  // the extension pass has no product with A
         if (timed) HIP_TRY(timing_begin(ctx, 0, st, &stop));
         HIP_TRY(launch_arnoldi_step(a, p->zeta, ly.L.block, st));
         if (timed) HIP_TRY(timing_end(stop, st));
     }
-    HIP_TRY(launch_extension_finalize(w.scal + (m & 1) * nsc, ly.L.G, m, w.ctrl, w.eta, w.H, st));
-    HIP_TRY(launch_sketch_reduce(w.skpart, ly.L.G, s, m, p->zeta, w.ctrl, w.eta, w.SV, w.SAV, w.colnorm2, st));
+    // tail: the extension step's partials
+    a.scal_prev = w.scal + (m & 1) * nsc;
+    a.skp_prev = w.skpart + (m & 1) * nsk;
+    HIP_TRY(launch_arnoldi_tail(a, w.colnorm2, st));
     return SKFAB_OK;
 }
 
@@ -384,7 +453,7 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     defaults(p, &l1, &l2, &lmax, &tol);
     if (p->method == SKFAB_SFOM_CLOSED) tol = 1e-13;
     const bool ls = p->method == SKFAB_SGMRES_QUAD;
-    HIP_TRY(launch_arnoldi_check(w.SV, w.SAV, w.H, s, m, p->k, w.ctrl, st));
+    HIP_TRY(launch_arnoldi_check(w.SV, w.SAV, w.H, s, m, p->k, w.ctrl, w.chk, st));
     HIP_TRY(launch_qr(w.SV, s, m + 1, w.ctrl, w.Tws, st));
     HIP_TRY(launch_pencil_setup(w.SV, s, m, p->k, w.ctrl, w.H, w.K0r, w.T1r, st));
     const int branch = (p->f == SKFAB_F_INVSQRT && !ls) ? 1 : 0;
@@ -407,17 +476,10 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
         HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
         return SKFAB_OK;
     }
-    // z^(-1/2): adaptive Gauss-Chebyshev (Section 4.1 / 5.1)
-    int la = l1, lb = l2;
-    HIP_TRY(launch_quad_level(w.ctrl, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.nodebuf, m, la, ls ? 1 : 0, w.SV, s, w.eta, st));
-    HIP_TRY(launch_quad_reduce(w.ctrl, w.nodebuf, m, la, 1, tol, w.T1r, w.qprev, w.qcur, w.y0, st));
-    while (true) {
-        HIP_TRY(launch_quad_level(w.ctrl, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.nodebuf, m, lb, ls ? 1 : 0, w.SV, s, w.eta,
-                                  st));
-        HIP_TRY(launch_quad_reduce(w.ctrl, w.nodebuf, m, lb, 0, tol, w.T1r, w.qprev, w.qcur, w.y0, st));
-        const int nx = next_order(lb);
-        if (nx > lmax) break;
-        lb = nx;
+    // z^(-1/2): adaptive Gauss-Chebyshev (Section 4.1 / 5.1), orders evaluated in groups
+    for (const QuadGroup& g : quad_groups(l1, l2, lmax)) {
+        HIP_TRY(launch_quad_group(w.ctrl, g, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.nodebuf, m, ls ? 1 : 0, w.SV, w.eta, st));
+        HIP_TRY(launch_quad_reduce(w.ctrl, g, w.nodebuf, m, tol, w.T1r, w.qprev, w.y0, st));
     }
     HIP_TRY(launch_quad_fail(w.ctrl, st));
     HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
@@ -524,7 +586,7 @@ skfab_status skfab_workspace_bytes(const skfab_csr* A, const skfab_params* p, si
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    *bytes = make_layout(A->n, p->m, p->s, l1, l2, lmax, p->npoly, true).total;
+    *bytes = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true).total;
     return SKFAB_OK;
 }
 
@@ -536,7 +598,7 @@ skfab_status skfab_solve(skfab_ctx* ctx, const skfab_csr* A, const double* b, do
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    const Layout ly = make_layout(A->n, p->m, p->s, l1, l2, lmax, p->npoly, true);
+    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true);
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);
@@ -561,7 +623,7 @@ skfab_status skfab_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, 
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    const Layout ly = make_layout(A->n, p->m, p->s, l1, l2, lmax, p->npoly, true);
+    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true);
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);
@@ -587,7 +649,7 @@ skfab_status skfab_small_workspace_bytes(const skfab_params* p, size_t* bytes) {
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    *bytes = make_layout(0, p->m, p->s, l1, l2, lmax, p->npoly, false).total;
+    *bytes = make_layout(0, 0, p->m, p->s, l1, l2, lmax, p->npoly, false).total;
     return SKFAB_OK;
 }
 
@@ -599,7 +661,7 @@ skfab_status skfab_small_problem(skfab_ctx* ctx, const double* SVext, const doub
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    const Layout ly = make_layout(0, p->m, p->s, l1, l2, lmax, p->npoly, false);
+    const Layout ly = make_layout(0, 0, p->m, p->s, l1, l2, lmax, p->npoly, false);
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);

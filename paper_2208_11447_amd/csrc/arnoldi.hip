@@ -11,8 +11,7 @@
 //   coefficients: ||u_j||^2, <u_j, W_j>, ||W_j||^2, <U_l, W_j>, <u_j, U_l>
 //   for the k-1 previous vectors l of the window.
 //
-// The stored basis is U (v_j = u_j / eta_j with eta_j = ||u_j||); the sketches are
-// rescaled by 1/eta_j when the per-block partial sums are reduced.  The truncated
+// The stored basis is U (v_j = u_j / eta_j with eta_j = ||u_j||).  The truncated
 // modified Gram-Schmidt coefficients are obtained from the dot products and the
 // Gram entries of the window (h_i = <v_i, w> - sum_{l<i} h_l <v_i, v_l>), which
 // equals sequential MGS for the stored vectors.  Entries of u_j needed by the
@@ -20,8 +19,17 @@
 // same fused multiply-add sequence, so the SpMV input equals the stored U_j bit
 // for bit.
 //
-// Determinism: every sum has a fixed order (per-wave LDS bins, fixed block trees,
-// partial arrays reduced in block order).
+// Layout and mapping: A is copied once per solve into SELL-64 (slices of 64 rows
+// = one wavefront, entries of a slice interleaved so every load of the column
+// indices and values is coalesced); each wavefront owns one slice at a time and
+// every lane one row.  Blocks own contiguous ranges of slices, assigned so that
+// the blocks of one XCD own neighbouring rows (shared L2 for the gathers).
+//
+// Sketches: per-wave LDS bins (64-lane FP64 LDS atomics, deterministic within a
+// wavefront), combined in wave order per block and written bin-major into a
+// [2s][G] partial array; the next step's blocks reduce it in slot order and
+// write S v_j and S A v_j (scaled by 1/eta_j) into SV, SAV.  Every sum has a
+// fixed order: results are bitwise reproducible run to run.
 #include "common.hpp"
 #include "device_state.hpp"
 
@@ -42,6 +50,7 @@ __device__ bool step_coefficients(const double* red, int p, int k, int m, bool w
     } else {
         ok = eta_p > BREAKDOWN_TOL * a.wnorm[p - 1];
     }
+    if (coef) coef[KMAX + 1] = eta_p;
     if (!ok) {
         if (writer) {
             a.ctrl->m_used = p;
@@ -113,32 +122,111 @@ __device__ void reduce_prev_scalars(const double* scal_prev, int G, double* red,
     __syncthreads();
 }
 
+// Bins [c0, c1) of the reduction of step p's sketch partials (slots summed in
+// fixed order), one wavefront per bin; used only when a block owns more bins than
+// it has wavefronts.  Bin i < s goes to SV[:, p] (scale_v), bin s + i to SAV[:, p]
+// (scale_av, skipped when write_av is false).
+template <int BLOCK>
+__device__ void reduce_prev_sketch_tail(const double* skp, int G, int s, int p, int c0, int c1, double scale_v,
+                                        double scale_av, bool write_av, double* SV, double* SAV) {
+    const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
+    constexpr int NW = BLOCK / WAVE;
+    for (int bin = c0 + wid; bin < c1; bin += NW) {
+        if (bin >= s && !write_av) continue;
+        const double* src = skp + (int64_t)bin * G;
+        double t = 0.0;
+        for (int g = lane; g < G; g += WAVE) t += src[g];
+        t = wave_sum(t);
+        if (lane == 0) {
+            if (bin < s) SV[(int64_t)p * s + bin] = t * scale_v;
+            else SAV[(int64_t)p * s + (bin - s)] = t * scale_av;
+        }
+    }
+}
+
+// u_j at row/column c: alpha * base[c] + sum_o cf[o] U_o[c] (fixed fma order)
+template <int KW>
+__device__ __forceinline__ double form_u(const double* __restrict__ base, const double* const (&Uo)[KW],
+                                         double alpha, const double (&cf)[KW], int nwin, int64_t c) {
+    double x = alpha * base[c];
+#pragma unroll
+    for (int o = 0; o < KW; ++o)
+        if (o < nwin) x = fma(cf[o], Uo[o][c], x);
+    return x;
+}
+
 // ------------------------------------------------------------- step kernel
+// SELL entries per load batch (fewer for wide windows to bound register use)
+template <int KW> struct SellBatch { static constexpr int value = KW <= 2 ? 8 : (KW <= 4 ? 4 : 1); };
+
 template <int KW, int ZETA, int BLOCK>
 __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
     extern __shared__ double bins[];  // [BLOCK/64][2s]
     __shared__ double red[NSC_MAX];
-    __shared__ double coef[KMAX + 1];
+    __shared__ double coef[KMAX + 2];
     __shared__ double scratch[BLOCK / WAVE];
     __shared__ int s_ok;
 
-    if (a.ctrl->stop) return;
+    // a breakdown detected by an earlier step ends the recurrence (the step that
+    // detects it still runs its prologue to write the extension column)
+    if (a.ctrl->stop && a.ctrl->m_used < a.j - 1) return;
     constexpr int NSC = 2 * KW + 1;
+    constexpr int NW = BLOCK / WAVE;
     const int j = a.j, k = a.k, s = a.s, G = a.G;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
 
     if (j > 0) {
-        reduce_prev_scalars<KW, BLOCK>(a.scal_prev, G, red, scratch);
+        // issue every load of the prologue before any reduction: the partial scalars
+        // of step j-1 (G per scalar), this block's share of its sketch partials, and
+        // the window's eta / Gram entries used by the coefficients
+        constexpr int PER = (NSC * 256 + BLOCK - 1) / BLOCK;  // G <= 256 * (1024 / BLOCK)
+        double sv[NSC];
+#pragma unroll
+        for (int sc = 0; sc < NSC; ++sc) {
+            double t = 0.0;
+            for (int g = tid; g < G; g += BLOCK) t += a.scal_prev[(int64_t)sc * G + g];
+            sv[sc] = t;
+        }
+        (void)PER;
+        const int nb = 2 * s;
+        const int b0 = (int)(((int64_t)blockIdx.x * nb) / gridDim.x);
+        const int b1 = (int)(((int64_t)(blockIdx.x + 1) * nb) / gridDim.x);
+        // sketch partial sums of this block's bins (one wavefront per bin)
+        double skv = 0.0;
+        int mybin = -1;
+        if (b0 + wid < b1) {
+            mybin = b0 + wid;
+            const double* src = a.skp_prev + (int64_t)mybin * G;
+            double t0 = 0.0, t1 = 0.0;
+            int g = lane;
+            for (; g + WAVE < G; g += 2 * WAVE) { t0 += src[g]; t1 += src[g + WAVE]; }
+            if (g < G) t0 += src[g];
+            skv = t0 + t1;
+        }
+        // every thread's scalar partials reduced in a fixed tree through the (not yet
+        // used) sketch-bin region of LDS
+        block_reduce_multi<NSC, BLOCK>(sv, bins, red);
         if (tid == 0) s_ok = step_coefficients<KW>(red, j - 1, k, a.m, blockIdx.x == 0, a, coef) ? 1 : 0;
+        skv = wave_sum(skv);
         __syncthreads();
-        if (!s_ok) return;
+        // S v_{j-1}, S A v_{j-1}; after a breakdown, S u_{j-1} unnormalised (extension column)
+        const double eta_p = coef[KMAX + 1];
+        const bool ok = s_ok != 0;
+        if (mybin >= 0 && lane == 0) {
+            if (mybin < s) a.SV[(int64_t)(j - 1) * s + mybin] = skv * (ok ? a.inv_sqrt_zeta / eta_p : a.inv_sqrt_zeta);
+            else if (ok) a.SAV[(int64_t)(j - 1) * s + (mybin - s)] = skv * (a.inv_sqrt_zeta / eta_p);
+        }
+        // bins beyond one per wave (only when 2s > 16 G): fall back to the generic loop
+        if (b1 - b0 > NW)
+            reduce_prev_sketch_tail<BLOCK>(a.skp_prev, G, s, j - 1, b0 + NW, b1,
+                                           ok ? a.inv_sqrt_zeta / eta_p : a.inv_sqrt_zeta,
+                                           a.inv_sqrt_zeta / eta_p, ok, a.SV, a.SAV);
+        if (!ok) return;
     } else if (tid == 0) {
         coef[0] = 1.0;
         for (int o = 0; o < KW; ++o) coef[1 + o] = 0.0;
     }
-    // zero the per-wave sketch bins
-    const int nwaves = BLOCK / WAVE;
-    for (int i = tid; i < nwaves * 2 * s; i += BLOCK) bins[i] = 0.0;
+    for (int i = tid; i < NW * 2 * s; i += BLOCK) bins[i] = 0.0;
     __syncthreads();
 
     const int nwin = (j == 0) ? 0 : min(k, j);   // vectors j-1 .. j-nwin form u_j
@@ -153,7 +241,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
 #pragma unroll
     for (int o = 0; o < KW; ++o) Uo[o] = a.U + (int64_t)((o < nwin) ? (j - 1 - o) : 0) * a.ldU;
     double* __restrict__ Uj = a.U + (int64_t)(a.extend ? 0 : j) * a.ldU;
-    double* binV = bins + (tid / WAVE) * 2 * s;
+    double* binV = bins + wid * 2 * s;
     double* binAV = binV + s;
 
     double acc_uu = 0.0, acc_uw = 0.0, acc_ww = 0.0;
@@ -162,40 +250,75 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
     for (int o = 0; o < KW; ++o) { acc_lw[o] = 0.0; acc_ul[o] = 0.0; }
 
     const int chunk = xcd_chunk(blockIdx.x, G);
-    const int64_t r_begin = (int64_t)chunk * a.rows_per_chunk;
-    const int64_t r_end = min(a.N, r_begin + a.rows_per_chunk);
-
-    for (int64_t r0 = r_begin; r0 < r_end; r0 += BLOCK) {
-        const int64_t r = r0 + tid;
-        if (r < r_end) {
-            double uo[KW];
-            double u = alpha * base[r];
+    const bool sell = a.ctrl->sell_ok != 0;
+    // rows of this block: SELL slices [sl0, sl1) or CSR rows [r_begin, r_end)
+    int64_t it0, it1, step;
+    if (sell) {
+        it0 = (int64_t)chunk * a.slices_per_chunk + wid;
+        it1 = min(a.nslices, (int64_t)(chunk + 1) * a.slices_per_chunk);
+        step = NW;
+    } else {
+        const int64_t r_begin = (int64_t)chunk * a.rows_per_chunk;
+        it0 = r_begin + tid;
+        it1 = min(a.N, r_begin + a.rows_per_chunk);
+        step = BLOCK;
+    }
+    for (int64_t it = it0; it < it1; it += step) {
+        const int64_t r = sell ? it * WAVE + lane : it;
+        const bool valid = r < a.N;
+        double uo[KW];
+        double u = 0.0;
+        if (valid) {
+            u = alpha * base[r];
 #pragma unroll
             for (int o = 0; o < KW; ++o) {
                 uo[o] = (o < nwin) ? Uo[o][r] : 0.0;
                 if (o < nwin) u = fma(cf[o], uo[o], u);
             }
-            if (a.extend) {
-                acc_uu = fma(u, u, acc_uu);
-                int rows[ZETA];
-                double sg[ZETA];
-                sketch_column<ZETA>(a.seed, (uint64_t)r, s, rows, sg);
+        } else {
 #pragma unroll
-                for (int q = 0; q < ZETA; ++q) lds_add(binV + rows[q], sg[q] * u);
-                continue;
-            }
-            Uj[r] = u;
-            const int e0 = a.rowptr[r], e1 = a.rowptr[r + 1];
-            double w = 0.0;
-            for (int e = e0; e < e1; ++e) {
-                const int c = a.col[e];
-                double x = alpha * base[c];
+            for (int o = 0; o < KW; ++o) uo[o] = 0.0;
+        }
+        double w = 0.0;
+        if (!a.extend) {
+            if (valid) Uj[r] = u;
+            if (sell) {
+                // entries in batches of SB: all index and value loads of a batch, then all
+                // gathers, then the products -- one memory round trip per batch
+                const int len = a.sl_len[it];
+                const int64_t e0 = a.sl_ptr[it] + lane;
+                constexpr int SB = SellBatch<KW>::value;
+                for (int q0 = 0; q0 < len; q0 += SB) {
+                    int cc[SB];
+                    double vv[SB], xb[SB], xu[SB][KW];
 #pragma unroll
-                for (int o = 0; o < KW; ++o)
-                    if (o < nwin) x = fma(cf[o], Uo[o][c], x);
-                w = fma(a.val[e], x, w);
+                    for (int q = 0; q < SB; ++q) {
+                        const bool in = q0 + q < len;
+                        cc[q] = in ? a.sl_col[e0 + (int64_t)(q0 + q) * WAVE] : 0;
+                        vv[q] = in ? a.sl_val[e0 + (int64_t)(q0 + q) * WAVE] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < SB; ++q) {
+                        xb[q] = base[cc[q]];
+#pragma unroll
+                        for (int o = 0; o < KW; ++o) xu[q][o] = (o < nwin) ? Uo[o][cc[q]] : 0.0;
+                    }
+#pragma unroll
+                    for (int q = 0; q < SB; ++q) {
+                        double x = alpha * xb[q];
+#pragma unroll
+                        for (int o = 0; o < KW; ++o)
+                            if (o < nwin) x = fma(cf[o], xu[q][o], x);
+                        w = fma(vv[q], x, w);
+                    }
+                }
+            } else if (valid) {
+                const int e0 = a.rowptr[r], e1 = a.rowptr[r + 1];
+                for (int e = e0; e < e1; ++e) w = fma(a.val[e], form_u<KW>(base, Uo, alpha, cf, nwin, a.col[e]), w);
             }
-            a.Wcur[r] = w;
+            if (valid) a.Wcur[r] = w;
+        }
+        if (valid) {
             acc_uu = fma(u, u, acc_uu);
             acc_uw = fma(u, w, acc_uw);
             acc_ww = fma(w, w, acc_ww);
@@ -210,104 +333,108 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
             double sg[ZETA];
             sketch_column<ZETA>(a.seed, (uint64_t)r, s, rows, sg);
 #pragma unroll
-            for (int q = 0; q < ZETA; ++q) {
-                lds_add(binV + rows[q], sg[q] * u);
-                lds_add(binAV + rows[q], sg[q] * w);
+            for (int q = 0; q < ZETA; ++q) lds_add(binV + rows[q], sg[q] * u);
+            if (!a.extend) {
+#pragma unroll
+                for (int q = 0; q < ZETA; ++q) lds_add(binAV + rows[q], sg[q] * w);
             }
         }
     }
 
-    // partial scalars of this block
+    // partial sketches, bin-major; slot = chunk keeps one XCD's slots contiguous
+    __syncthreads();
+    for (int i = tid; i < 2 * s; i += BLOCK) {
+        double t = 0.0;
+        for (int wv = 0; wv < NW; ++wv) t += bins[wv * 2 * s + i];
+        a.skp_cur[(int64_t)i * G + chunk] = t;
+    }
+    // partial scalars of this block, reduced through the (now free) bin region
     double vals[NSC];
     vals[0] = acc_uu; vals[1] = acc_uw; vals[2] = acc_ww;
 #pragma unroll
     for (int o = 0; o < KW - 1; ++o) { vals[3 + o] = acc_lw[o]; vals[3 + (KW - 1) + o] = acc_ul[o]; }
-#pragma unroll
-    for (int sc = 0; sc < NSC; ++sc) {
-        const double t = block_sum(vals[sc], scratch);
-        if (tid == 0) a.scal_cur[(int64_t)sc * G + blockIdx.x] = t;
-    }
     __syncthreads();
-    double* dst = a.skpart + (int64_t)blockIdx.x * 2 * s;
-    for (int i = tid; i < 2 * s; i += BLOCK) {
-        double t = 0.0;
-        for (int wv = 0; wv < nwaves; ++wv) t += bins[wv * 2 * s + i];
-        dst[i] = t;
-    }
+    block_reduce_multi<NSC, BLOCK>(vals, bins, red);
+    if (tid < NSC) a.scal_cur[(int64_t)tid * G + blockIdx.x] = red[tid];
 }
 
-// Coefficients of the last step (eta_{m-1}, h_{., m-1}) and breakdown check.
-template <int KW>
-__global__ __launch_bounds__(256) void arnoldi_finalize_kernel(StepArgs a) {
-    __shared__ double red[NSC_MAX];
-    __shared__ double scratch[256 / WAVE];
+// After the extension step m: S u_m (unnormalised) into SV[:, m_used], eta_m and
+// h_{m+1,m} (unless the recurrence broke down earlier, in which case the step
+// that detected it already wrote the extension column), then ||S v_j||^2 for the
+// epsilon monitor.  One wavefront per sketch bin in the first ceil(s/4) blocks.
+__global__ __launch_bounds__(256) void arnoldi_tail_kernel(StepArgs a) {
+    const int m = a.m, s = a.s, G = a.G;
+    const int lane = threadIdx.x & 63;
+    const int bin = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (a.ctrl->stop) return;
-    reduce_prev_scalars<KW, 256>(a.scal_prev, a.G, red, scratch);
-    if (threadIdx.x == 0) step_coefficients<KW>(red, a.j - 1, a.k, a.m, true, a, nullptr);
-}
-
-// SV[:, j] = inv_sqrt_zeta / eta_j * sum_g part_j[g][0:s], SAV likewise from [s:2s]
-// for j < m_used; column m_used of SV receives S u_{m_used} unnormalised (the
-// extension vector of the Arnoldi relation).  One block per column j = 0..m.
-__global__ __launch_bounds__(256) void sketch_reduce_kernel(const double* skpart, int G, int s, int m,
-                                                           double inv_sqrt_zeta, const DevCtrl* ctrl,
-                                                           const double* eta, double* SV, double* SAV,
-                                                           double* colnorm2) {
-    __shared__ double scratch[4];
-    const int j = blockIdx.x;
-    const int m_used = ctrl->m_used;
-    const bool valid = j <= m_used && m_used > 0;
-    const double scale = (j < m_used) ? inv_sqrt_zeta / eta[j] : inv_sqrt_zeta;
-    const double* src = skpart + (int64_t)j * G * 2 * s;
-    double nrm = 0.0;
-    for (int i = threadIdx.x; i < 2 * s; i += 256) {
-        double t = 0.0;
-        if (valid && (i < s || j < m_used))
-            for (int g = 0; g < G; ++g) t += src[(int64_t)g * 2 * s + i];
-        t *= scale;
-        if (i < s) {
-            SV[(int64_t)j * s + i] = t;
-            nrm = fma(t, t, nrm);
-        } else if (j < m) {
-            SAV[(int64_t)j * s + (i - s)] = (j < m_used) ? t : 0.0;
+    if (blockIdx.x == 0 && threadIdx.x < 64) {
+        double v = 0.0;
+        for (int g = lane; g < G; g += 64) v += a.scal_prev[g];
+        v = wave_sum_fast(v);
+        if (lane == 0) {
+            a.eta[m] = sqrt(v);
+            a.H[m + (int64_t)(m + 1) * (m - 1)] = sqrt(v);
         }
     }
-    nrm = block_sum(nrm, scratch);
-    if (threadIdx.x == 0 && j < m) colnorm2[j] = (j < m_used) ? nrm : 1.0;
+    if (bin < s) {
+        const double* src = a.skp_prev + (int64_t)bin * G;
+        double t0 = 0.0, t1 = 0.0;
+        int g = lane;
+        for (; g + 64 < G; g += 128) { t0 += src[g]; t1 += src[g + 64]; }
+        if (g < G) t0 += src[g];
+        const double t = wave_sum_fast(t0 + t1);
+        if (lane == 0) a.SV[(int64_t)m * s + bin] = t * a.inv_sqrt_zeta;
+    }
 }
 
-// eta_m and h_{m+1,m} from the extension step's partial ||u_m||^2.
-__global__ __launch_bounds__(256) void extension_finalize_kernel(const double* scal, int G, int m, DevCtrl* ctrl,
-                                                                 double* eta, double* H) {
-    __shared__ double scratch[4];
-    if (ctrl->stop) return;
-    double v = 0.0;
-    for (int g = threadIdx.x; g < G; g += 256) v += scal[g];
-    v = block_sum(v, scratch);
-    if (threadIdx.x == 0) {
-        eta[m] = sqrt(v);
-        H[m + (int64_t)(m + 1) * (m - 1)] = sqrt(v);
-    }
+// ||S v_j||^2 for the epsilon monitor, one wavefront per column.
+__global__ __launch_bounds__(256) void colnorm_kernel(const double* SV, int s, int m, const DevCtrl* ctrl,
+                                                      double* colnorm2) {
+    const int lane = threadIdx.x & 63;
+    const int jj = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (jj >= m) return;
+    const int mu = ctrl->m_used;
+    double t = 0.0;
+    if (jj < mu)
+        for (int i = lane; i < s; i += 64) {
+            const double x = SV[(int64_t)jj * s + i];
+            t = fma(x, x, t);
+        }
+    t = wave_sum_fast(t);
+    if (lane == 0) colnorm2[jj] = (jj < mu) ? t : 1.0;
 }
 
 // relres = ||SAV - [SV, S u] Hbar1||_F / ||SAV||_F over the first m_used columns,
-// Hbar1 = [H; e_mu^T] (Arnoldi relation in the sketched space).  One block.
+// Hbar1 = [H; e_mu^T] (Arnoldi relation in the sketched space).  One block per
+// column, partial sums in part[2 m]; the last block to finish would need an
+// atomic, so the final sum is taken by the small-problem kernels instead.
 __global__ __launch_bounds__(256) void arnoldi_check_kernel(const double* SV, const double* SAV, const double* H,
-                                                           int s, int m, int k, DevCtrl* ctrl) {
+                                                           int s, int m, int k, const DevCtrl* ctrl, double* part) {
     __shared__ double scratch[4];
     const int mu = ctrl->m_used;
+    const int jj = blockIdx.x;
     double num = 0.0, den = 0.0;
-    for (int idx = threadIdx.x; idx < s * mu; idx += 256) {
-        const int jj = idx / s, i = idx - jj * s;
-        double t = SAV[(int64_t)jj * s + i];
-        den = fma(t, t, den);
-        for (int l = max(0, jj - k + 1); l <= jj + 1; ++l) {
-            const double hb = (l == jj + 1) ? ((jj == mu - 1) ? 1.0 : H[(jj + 1) + (int64_t)(m + 1) * jj])
-                                            : H[l + (int64_t)(m + 1) * jj];
-            t = fma(-SV[(int64_t)l * s + i], hb, t);
+    if (jj < mu) {
+        for (int i = threadIdx.x; i < s; i += 256) {
+            double t = SAV[(int64_t)jj * s + i];
+            den = fma(t, t, den);
+            for (int l = max(0, jj - k + 1); l <= jj + 1; ++l) {
+                const double hb = (l == jj + 1) ? ((jj == mu - 1) ? 1.0 : H[(jj + 1) + (int64_t)(m + 1) * jj])
+                                                : H[l + (int64_t)(m + 1) * jj];
+                t = fma(-SV[(int64_t)l * s + i], hb, t);
+            }
+            num = fma(t, t, num);
         }
-        num = fma(t, t, num);
     }
+    num = block_sum(num, scratch);
+    den = block_sum(den, scratch);
+    if (threadIdx.x == 0) { part[jj] = num; part[m + jj] = den; }
+}
+
+__global__ __launch_bounds__(256) void arnoldi_check_finish_kernel(const double* part, int m, DevCtrl* ctrl) {
+    __shared__ double scratch[4];
+    double num = 0.0, den = 0.0;
+    for (int i = threadIdx.x; i < m; i += 256) { num += part[i]; den += part[m + i]; }
     num = block_sum(num, scratch);
     den = block_sum(den, scratch);
     if (threadIdx.x == 0) ctrl->relres = (den > 0.0) ? sqrt(num / den) : 0.0;
@@ -323,10 +450,121 @@ __global__ void normalize_basis_kernel(const double* U, int64_t ldU, int64_t N, 
         V[(int64_t)j * N + r] = (j < m_used) ? U[(int64_t)j * ldU + r] * sc : 0.0;
 }
 
+// ------------------------------------------------------ SELL-64 conversion
+// sl_len[sl] = max row length in slice sl (one wavefront per slice).
+__global__ __launch_bounds__(256) void sell_len_kernel(const int32_t* rowptr, int64_t N, int64_t nslices,
+                                                       int32_t* sl_len) {
+    const int lane = threadIdx.x & 63;
+    for (int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sl < nslices; sl += (int64_t)gridDim.x * 4) {
+        const int64_t r = sl * 64 + lane;
+        int len = (r < N) ? rowptr[r + 1] - rowptr[r] : 0;
+        for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
+        if (lane == 0) sl_len[sl] = len;
+    }
+}
+
+constexpr int SCAN_CH = 4096;  // slices per scan block
+
+// per-block sums of 64 * sl_len
+__global__ __launch_bounds__(1024) void sell_scan_sums_kernel(const int32_t* sl_len, int64_t nslices, int64_t* bsum) {
+    __shared__ double scratch[16];
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CH;
+    double t = 0.0;  // exact for totals below 2^53
+    for (int i = threadIdx.x; i < SCAN_CH; i += 1024)
+        if (base + i < nslices) t += 64.0 * sl_len[base + i];
+    t = block_sum(t, scratch);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (int64_t)t;
+}
+
+// exclusive scan of the block sums (one block, sequential per thread then across)
+__global__ __launch_bounds__(1024) void sell_scan_top_kernel(int64_t* bsum, int64_t nb, int64_t capacity,
+                                                             DevCtrl* ctrl) {
+    __shared__ int64_t part[1024];
+    const int64_t per = (nb + 1023) / 1024;
+    const int64_t i0 = threadIdx.x * per, i1 = min(nb, i0 + per);
+    int64_t t = 0;
+    for (int64_t i = i0; i < i1; ++i) t += bsum[i];
+    part[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = 0;
+        for (int i = 0; i < 1024; ++i) { const int64_t v = part[i]; part[i] = run; run += v; }
+        ctrl->sell_total = run;
+        ctrl->sell_ok = (run <= capacity) ? 1 : 0;
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int64_t i = i0; i < i1; ++i) { const int64_t v = bsum[i]; bsum[i] = run; run += v; }
+}
+
+// sl_ptr = exclusive prefix of 64 * sl_len (block-local scan plus block offset)
+__global__ __launch_bounds__(1024) void sell_scan_apply_kernel(const int32_t* sl_len, int64_t nslices,
+                                                               const int64_t* boff, int64_t* sl_ptr) {
+    __shared__ int64_t part[1024];
+    constexpr int PER = SCAN_CH / 1024;
+    const int64_t base = (int64_t)blockIdx.x * SCAN_CH + (int64_t)threadIdx.x * PER;
+    int64_t loc[PER];
+    int64_t t = 0;
+    for (int i = 0; i < PER; ++i) {
+        loc[i] = (base + i < nslices) ? 64 * (int64_t)sl_len[base + i] : 0;
+        t += loc[i];
+    }
+    part[threadIdx.x] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t run = boff[blockIdx.x];
+        for (int i = 0; i < 1024; ++i) { const int64_t v = part[i]; part[i] = run; run += v; }
+    }
+    __syncthreads();
+    int64_t run = part[threadIdx.x];
+    for (int i = 0; i < PER; ++i) {
+        if (base + i < nslices) sl_ptr[base + i] = run;
+        run += loc[i];
+    }
+}
+
+// interleaved copy; padding entries have value 0 and their own row as column
+__global__ __launch_bounds__(256) void sell_fill_kernel(const int32_t* rowptr, const int32_t* col, const double* val,
+                                                        int64_t N, int64_t nslices, const DevCtrl* ctrl,
+                                                        const int64_t* sl_ptr, const int32_t* sl_len,
+                                                        int32_t* sl_col, double* sl_val) {
+    if (!ctrl->sell_ok) return;
+    const int lane = threadIdx.x & 63;
+    for (int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sl < nslices; sl += (int64_t)gridDim.x * 4) {
+        const int64_t r = sl * 64 + lane;
+        const int len = sl_len[sl];
+        const int e0 = (r < N) ? rowptr[r] : 0;
+        const int rl = (r < N) ? rowptr[r + 1] - e0 : 0;
+        const int32_t self = (r < N) ? (int32_t)r : 0;
+        const int64_t o = sl_ptr[sl] + lane;
+        for (int q0 = 0; q0 < len; q0 += 8) {
+            int cb[8];
+            double vb[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool real = q0 + q < rl;
+                cb[q] = real ? col[e0 + q0 + q] : self;
+                vb[q] = real ? val[e0 + q0 + q] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (q0 + q < len) {
+                    sl_col[o + (int64_t)(q0 + q) * 64] = cb[q];
+                    sl_val[o + (int64_t)(q0 + q) * 64] = vb[q];
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 template <int KW, int ZETA>
 static hipError_t launch_step_t(const StepArgs& a, int block, hipStream_t st) {
-    const size_t lds = (size_t)(block / WAVE) * 2 * a.s * sizeof(double);
+    // the dynamic region holds the per-wave sketch bins, and in the prologue and
+    // epilogue the scratch of the (2 KW + 1)-value block reduction
+    const size_t bins = (size_t)(block / WAVE) * 2 * a.s;
+    const size_t red = (size_t)(2 * KW + 1) * (block + 72);
+    const size_t lds = (bins > red ? bins : red) * sizeof(double);
     if (block == 1024) {
         hipLaunchKernelGGL((arnoldi_step_kernel<KW, ZETA, 1024>), dim3(a.G), dim3(1024), lds, st, a);
     } else if (block == 512) {
@@ -357,33 +595,20 @@ hipError_t launch_arnoldi_step(const StepArgs& a, int zeta, int block, hipStream
     }
 }
 
-hipError_t launch_arnoldi_finalize(const StepArgs& a, hipStream_t st) {
-    switch (a.k) {
-        case 1: hipLaunchKernelGGL((arnoldi_finalize_kernel<1>), dim3(1), dim3(256), 0, st, a); break;
-        case 2: hipLaunchKernelGGL((arnoldi_finalize_kernel<2>), dim3(1), dim3(256), 0, st, a); break;
-        case 3: hipLaunchKernelGGL((arnoldi_finalize_kernel<3>), dim3(1), dim3(256), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((arnoldi_finalize_kernel<4>), dim3(1), dim3(256), 0, st, a); break;
-        default: hipLaunchKernelGGL((arnoldi_finalize_kernel<8>), dim3(1), dim3(256), 0, st, a); break;
-    }
-    return hipGetLastError();
-}
-
-hipError_t launch_sketch_reduce(const double* skpart, int G, int s, int m, int zeta, const DevCtrl* ctrl,
-                                const double* eta, double* SV, double* SAV, double* colnorm2, hipStream_t st) {
-    hipLaunchKernelGGL(sketch_reduce_kernel, dim3(m + 1), dim3(256), 0, st, skpart, G, s, m,
-                       1.0 / sqrt((double)zeta), ctrl, eta, SV, SAV, colnorm2);
-    return hipGetLastError();
-}
-
-hipError_t launch_extension_finalize(const double* scal, int G, int m, DevCtrl* ctrl, double* eta, double* H,
-                                     hipStream_t st) {
-    hipLaunchKernelGGL(extension_finalize_kernel, dim3(1), dim3(256), 0, st, scal, G, m, ctrl, eta, H);
+hipError_t launch_arnoldi_tail(const StepArgs& a, double* colnorm2, hipStream_t st) {
+    hipLaunchKernelGGL(arnoldi_tail_kernel, dim3((a.s + 3) / 4), dim3(256), 0, st, a);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colnorm_kernel, dim3((a.m + 3) / 4), dim3(256), 0, st, a.SV, a.s, a.m, a.ctrl, colnorm2);
     return hipGetLastError();
 }
 
 hipError_t launch_arnoldi_check(const double* SV, const double* SAV, const double* H, int s, int m, int k,
-                                DevCtrl* ctrl, hipStream_t st) {
-    hipLaunchKernelGGL(arnoldi_check_kernel, dim3(1), dim3(256), 0, st, SV, SAV, H, s, m, k, ctrl);
+                                DevCtrl* ctrl, double* part, hipStream_t st) {
+    hipLaunchKernelGGL(arnoldi_check_kernel, dim3(m), dim3(256), 0, st, SV, SAV, H, s, m, k, ctrl, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(arnoldi_check_finish_kernel, dim3(1), dim3(256), 0, st, part, m, ctrl);
     return hipGetLastError();
 }
 
@@ -392,6 +617,23 @@ hipError_t launch_normalize_basis(const double* U, int64_t ldU, int64_t N, int m
     int64_t gx64 = (N + 255) / 256;
     int gx = (int)(gx64 < 1024 ? gx64 : 1024);
     hipLaunchKernelGGL(normalize_basis_kernel, dim3(gx, m), dim3(256), 0, st, U, ldU, N, m, ctrl, eta, V);
+    return hipGetLastError();
+}
+
+int64_t sell_scan_blocks(int64_t nslices) { return (nslices + SCAN_CH - 1) / SCAN_CH; }
+
+hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const double* val, int64_t N,
+                               int64_t nslices, int64_t capacity, DevCtrl* ctrl, int32_t* sl_len, int64_t* sl_ptr,
+                               int64_t* bsum, int32_t* sl_col, double* sl_val, hipStream_t st) {
+    const int64_t g64 = (nslices + 3) / 4;
+    const unsigned g = (unsigned)(g64 < 65536 ? g64 : 65536);
+    hipLaunchKernelGGL(sell_len_kernel, dim3(g), dim3(256), 0, st, rowptr, N, nslices, sl_len);
+    const int64_t nb = sell_scan_blocks(nslices);
+    hipLaunchKernelGGL(sell_scan_sums_kernel, dim3((unsigned)nb), dim3(1024), 0, st, sl_len, nslices, bsum);
+    hipLaunchKernelGGL(sell_scan_top_kernel, dim3(1), dim3(1024), 0, st, bsum, nb, capacity, ctrl);
+    hipLaunchKernelGGL(sell_scan_apply_kernel, dim3((unsigned)nb), dim3(1024), 0, st, sl_len, nslices, bsum, sl_ptr);
+    hipLaunchKernelGGL(sell_fill_kernel, dim3(g), dim3(256), 0, st, rowptr, col, val, N, nslices, ctrl, sl_ptr,
+                       sl_len, sl_col, sl_val);
     return hipGetLastError();
 }
 

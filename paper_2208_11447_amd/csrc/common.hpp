@@ -57,6 +57,35 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
+// Broadcast of a double from a wave-uniform lane through two scalar reads
+// (no LDS crossbar round trip).
+__device__ __forceinline__ double bcast_lane(double v, int src_lane) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src_lane);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src_lane);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Lane permutation within rows of 16 lanes by a DPP control (quad_perm / mirror).
+template <int CTRL>
+__device__ __forceinline__ double dpp_perm(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Wave sum with short latency: DPP butterflies inside each row of 16 lanes
+// (quad_perm [1,0,3,2], [2,3,0,1], row_half_mirror, row_mirror), then the four row
+// sums read through scalar registers.  Fixed order; every lane gets the total.
+__device__ __forceinline__ double wave_sum_fast(double v) {
+    v += dpp_perm<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_perm<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_perm<0x141>(v);  // row_half_mirror
+    v += dpp_perm<0x140>(v);  // row_mirror
+    return (bcast_lane(v, 0) + bcast_lane(v, 16)) + (bcast_lane(v, 32) + bcast_lane(v, 48));
+}
+
 __device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
     for (int off = WAVE / 2; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, WAVE));
@@ -89,6 +118,41 @@ __device__ __forceinline__ double block_max(double v, double* scratch) {
     double t = scratch[0];
     for (int i = 1; i < nw; ++i) t = fmax(t, scratch[i]);
     return t;
+}
+
+// Deterministic sum of NV values per thread over the block, through LDS: a fixed
+// three-level tree (BLOCK -> 64 -> 8 -> 1 per value).  `sc` must hold
+// NV * (BLOCK + 72) doubles; the totals are returned in out[0..NV) (LDS), visible
+// to every thread on return.  Far shorter dependency chains than per-value
+// shuffle reductions.
+template <int NV, int BLOCK>
+__device__ void block_reduce_multi(const double (&v)[NV], double* sc, double* out) {
+    static_assert(BLOCK % 64 == 0, "block of whole wavefronts");
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) sc[i * BLOCK + tid] = v[i];
+    __syncthreads();
+    double* s1 = sc + NV * BLOCK;
+    for (int t = tid; t < NV * 64; t += BLOCK) {
+        const int i = t >> 6, l = t & 63;
+        double a0 = 0.0, a1 = 0.0;
+        int q = l;
+        for (; q + 64 < BLOCK; q += 128) { a0 += sc[i * BLOCK + q]; a1 += sc[i * BLOCK + q + 64]; }
+        if (q < BLOCK) a0 += sc[i * BLOCK + q];
+        s1[t] = a0 + a1;
+    }
+    __syncthreads();
+    double* s2 = s1 + NV * 64;
+    for (int t = tid; t < NV * 8; t += BLOCK) {
+        const double* p = s1 + (t >> 3) * 64 + (t & 7) * 8;
+        s2[t] = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+    }
+    __syncthreads();
+    for (int t = tid; t < NV; t += BLOCK) {
+        const double* p = s2 + t * 8;
+        out[t] = ((p[0] + p[1]) + (p[2] + p[3])) + ((p[4] + p[5]) + (p[6] + p[7]));
+    }
+    __syncthreads();
 }
 
 __device__ __forceinline__ void lds_add(double* p, double v) {

@@ -22,32 +22,56 @@ struct DevCtrl {
     double logdet;      // log |det H_hat|
     double relres;      // ||S A V - [S V, S u_{m+1}] Hbar||_F / ||S A V||_F (Arnoldi relation check)
     double pad2[2];
+    int64_t sell_total; // entries of the SELL-64 copy of A (padded)
+    int32_t sell_ok;    // 1: the SELL-64 copy fits the workspace and is used
+    int32_t pad3;
 };
 
 // Arguments of the fused Arnoldi step kernel.
 struct StepArgs {
     int64_t N;
-    int64_t rows_per_chunk;
     int64_t ldU;
+    // CSR (fallback) and its SELL-64 copy: slice sl holds rows 64 sl .. 64 sl + 63,
+    // entry q of row 64 sl + l at sl_ptr[sl] + 64 q + l, sl_len[sl] entries per row.
     const int32_t* rowptr;
     const int32_t* col;
     const double* val;
+    const int64_t* sl_ptr;
+    const int32_t* sl_len;
+    const int32_t* sl_col;
+    const double* sl_val;
+    int64_t nslices;
+    int64_t slices_per_chunk;
+    int64_t rows_per_chunk;
     const double* b;
     double* U;            // ldU x m, unnormalised basis u_j (v_j = u_j / eta_j)
     double* Wcur;         // A u_j (this step)
     const double* Wprev;  // A u_{j-1}
     const double* scal_prev;  // [NSC_MAX][G] partial scalars of step j-1
     double* scal_cur;         // [NSC_MAX][G] partial scalars of step j
-    double* skpart;           // [G][2s] partial sketches of step j (S u_j | S A u_j)
+    const double* skp_prev;   // [2s][G] partial sketches of step j-1 (bin-major, XCD slot order)
+    double* skp_cur;          // [2s][G] partial sketches of step j (S u_j | S A u_j)
+    double* SV;               // s x (m+1): S v_0 .. S v_{m-1}, then S u_m unnormalised
+    double* SAV;              // s x m
     DevCtrl* ctrl;
-    double* eta;    // [m]   ||u_j||
+    double* eta;    // [m+2] ||u_j||
     double* wnorm;  // [m]   ||A v_j||
     double* H;      // [(m+1) x m] truncated MGS coefficients
     double* gram;   // [m][KMAX] <v_j, v_{j-1-q}>
     uint64_t seed;
+    double inv_sqrt_zeta;
     int32_t s, k, j, m, G;
     int32_t extend;   // 1: form u_m and its sketch only (no product with A)
-    int32_t pad;
+};
+
+// A group of consecutive quadrature orders evaluated by one launch.
+constexpr int MAX_GROUP_LEVELS = 16;
+struct QuadGroup {
+    int32_t nlev;
+    int32_t total;                       // nodes in the group
+    int32_t lev_l[MAX_GROUP_LEVELS];     // order of each level
+    int32_t lev_off[MAX_GROUP_LEVELS];   // first node of each level
+    int32_t first;                       // 1: the group starts the sequence (its first level seeds qprev)
 };
 
 }  // namespace skfab

@@ -23,7 +23,7 @@
 namespace skfab {
 
 constexpr int QR_NB = 16;        // Householder panel width
-constexpr int NODE_SLOTS = 256;  // concurrent quadrature nodes (scratch slots)
+constexpr int NODE_SLOTS = 1024;  // concurrent quadrature nodes (scratch slots)
 
 // ------------------------------------------------------------ utilities
 __global__ void fill_kernel(double* p, int64_t n, double v) {
@@ -42,117 +42,132 @@ __global__ void init_ctrl_kernel(DevCtrl* c, int m) {
 // Panel factorisation of columns [c0, c0+nb) of X (s x ncols, ld s), rows c0..s-1,
 // in LDS.  Householder vectors are stored below the diagonal (unit diagonal
 // implied), R on and above it; T (nb x nb, upper) is the compact-WY factor.
-__global__ __launch_bounds__(1024) void qr_panel_kernel(double* X, int s, int c0, const DevCtrl* ctrl,
-                                                        double* Tws) {
+// Rows are owned by threads (r = tid + 256 i), so each column costs one block
+// reduction of the squared norm and the dot products with the later columns.
+constexpr int QR_NT = 256;
+
+__global__ __launch_bounds__(QR_NT) void qr_panel_kernel(double* X, int s, int c0, const DevCtrl* ctrl,
+                                                          double* Tws) {
     extern __shared__ double P[];  // [QR_NB][nrows]
-    __shared__ double red[16][QR_NB];
-    __shared__ double wv[QR_NB];
+    __shared__ double red[2][QR_NT / WAVE][QR_NB + 1];
     __shared__ double tau[QR_NB];
     __shared__ double G[QR_NB][QR_NB];
-    __shared__ double sc[3];
+    __shared__ double Ts[QR_NB][QR_NB];
     const int ncols = ctrl->m_used + 1;
     if (ctrl->m_used == 0 || c0 >= ncols) return;
     const int pc = min(QR_NB, ncols - c0);
     const int nrows = s - c0;
-    const int tid = threadIdx.x, nt = blockDim.x;
-    const int lane = tid & 63, wid = tid >> 6, nw = nt >> 6;
-    for (int idx = tid; idx < pc * nrows; idx += nt) {
-        const int cc = idx / nrows, r = idx - cc * nrows;
-        P[idx] = X[(int64_t)(c0 + r) + (int64_t)s * (c0 + cc)];
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NW = QR_NT / WAVE;
+    {
+        // every load of the panel issued before the first use (s <= SMAX rows)
+        constexpr int RPT = SMAX / QR_NT;
+        double ld[QR_NB][RPT];
+#pragma unroll
+        for (int cc = 0; cc < QR_NB; ++cc)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = tid + QR_NT * i;
+                ld[cc][i] = (cc < pc && r < nrows) ? X[(int64_t)(c0 + r) + (int64_t)s * (c0 + cc)] : 0.0;
+            }
+#pragma unroll
+        for (int cc = 0; cc < QR_NB; ++cc)
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = tid + QR_NT * i;
+                if (cc < pc && r < nrows) P[cc * nrows + r] = ld[cc][i];
+            }
     }
     __syncthreads();
     for (int cc = 0; cc < pc; ++cc) {
-        double* pcol = P + cc * nrows;
-        double part = 0.0;
-        for (int r = cc + 1 + tid; r < nrows; r += nt) part = fma(pcol[r], pcol[r], part);
-        part = wave_sum(part);
-        if (lane == 0) red[wid][0] = part;
-        __syncthreads();
-        if (tid == 0) {
-            double sig2 = 0.0;
-            for (int i = 0; i < nw; ++i) sig2 += red[i][0];
-            const double alpha = pcol[cc];
-            if (sig2 == 0.0) {
-                tau[cc] = 0.0; sc[0] = 0.0; sc[1] = alpha;
-            } else {
-                const double nrm = sqrt(alpha * alpha + sig2);
-                const double beta = (alpha >= 0.0) ? -nrm : nrm;
-                tau[cc] = (beta - alpha) / beta;
-                sc[0] = 1.0 / (alpha - beta);
-                sc[1] = beta;
-            }
-        }
-        __syncthreads();
-        const double scale = sc[0], tcc = tau[cc];
-        for (int r = cc + 1 + tid; r < nrows; r += nt) pcol[r] *= scale;
-        __syncthreads();
-        if (tid == 0) pcol[cc] = sc[1];
-        // w_{c2} = v^T P[:, c2] for the remaining panel columns
-        double acc[QR_NB];
+        const int buf = cc & 1;
+        double* xc = P + cc * nrows;
+        // partial sums over own rows below the diagonal: index 0 = sigma^2, 1 + c2 = x^T P[:, c2]
+        double acc[QR_NB + 1];
 #pragma unroll
-        for (int c2 = 0; c2 < QR_NB; ++c2) acc[c2] = 0.0;
-        for (int r = cc + tid; r < nrows; r += nt) {
-            const double vr = (r == cc) ? 1.0 : pcol[r];
+        for (int i = 0; i <= QR_NB; ++i) acc[i] = 0.0;
+        for (int r = cc + 1 + tid; r < nrows; r += QR_NT) {
+            const double x = xc[r];
+            acc[0] = fma(x, x, acc[0]);
 #pragma unroll
             for (int c2 = 0; c2 < QR_NB; ++c2)
-                if (c2 > cc && c2 < pc) acc[c2] = fma(vr, P[c2 * nrows + r], acc[c2]);
+                if (c2 > cc && c2 < pc) acc[1 + c2] = fma(x, P[c2 * nrows + r], acc[1 + c2]);
         }
+        // all sums unconditionally: the independent DPP chains interleave
+#pragma unroll
+        for (int i = 0; i <= QR_NB; ++i) acc[i] = wave_sum_fast(acc[i]);
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i <= QR_NB; ++i) red[buf][wid][i] = acc[i];
+        }
+        __syncthreads();
+        double sig2 = 0.0;
+        for (int w = 0; w < NW; ++w) sig2 += red[buf][w][0];
+        const double alpha = xc[cc];
+        double beta, tc, scale;
+        if (sig2 == 0.0) {
+            beta = alpha; tc = 0.0; scale = 0.0;
+        } else {
+            const double nrm = sqrt(alpha * alpha + sig2);
+            beta = (alpha >= 0.0) ? -nrm : nrm;
+            tc = (beta - alpha) / beta;
+            scale = 1.0 / (alpha - beta);
+        }
+        double wv[QR_NB];
 #pragma unroll
         for (int c2 = 0; c2 < QR_NB; ++c2) {
+            wv[c2] = 0.0;
             if (c2 > cc && c2 < pc) {
-                const double t = wave_sum(acc[c2]);
-                if (lane == 0) red[wid][c2] = t;
+                double d = 0.0;
+                for (int w = 0; w < NW; ++w) d += red[buf][w][1 + c2];
+                wv[c2] = tc * (P[c2 * nrows + cc] + scale * d);   // tau * v^T P[:, c2]
             }
         }
-        __syncthreads();
-        if (tid < QR_NB && tid > cc && tid < pc) {
-            double t = 0.0;
-            for (int i = 0; i < nw; ++i) t += red[i][tid];
-            wv[tid] = t;
+        __syncthreads();  // every thread has read row cc before its owner updates it
+        for (int r = cc + tid; r < nrows; r += QR_NT) {
+            const double v = (r == cc) ? 1.0 : scale * xc[r];
+            if (r == cc) xc[r] = beta;
+            else xc[r] = v;
+#pragma unroll
+            for (int c2 = 0; c2 < QR_NB; ++c2)
+                if (c2 > cc && c2 < pc) P[c2 * nrows + r] = fma(-wv[c2], v, P[c2 * nrows + r]);
         }
-        __syncthreads();
-        for (int idx = tid; idx < (pc - cc - 1) * (nrows - cc); idx += nt) {
-            const int c2 = cc + 1 + idx / (nrows - cc);
-            const int r = cc + idx % (nrows - cc);
-            const double vr = (r == cc) ? 1.0 : pcol[r];
-            P[c2 * nrows + r] -= tcc * wv[c2] * vr;
-        }
-        __syncthreads();
-    }
-    // Gram of the Householder vectors (unit diagonal, zero above) for T
-    for (int pair = wid; pair < pc * pc; pair += nw) {
-        const int i = pair / pc, l = pair % pc;
-        if (l < i) {
-            double t = 0.0;
-            for (int r = i + lane; r < nrows; r += 64) {
-                const double yi = (r == i) ? 1.0 : P[i * nrows + r];
-                const double yl = P[l * nrows + r];  // r >= i > l: strictly below diag
-                t = fma(yi, yl, t);
-            }
-            t = wave_sum(t);
-            if (lane == 0) G[l][i] = t;
-        }
+        if (tid == 0) tau[cc] = tc;
     }
     __syncthreads();
-    if (tid == 0) {
-        double T[QR_NB][QR_NB];
-        for (int i = 0; i < QR_NB; ++i)
-            for (int l = 0; l < QR_NB; ++l) T[i][l] = 0.0;
-        for (int i = 0; i < pc; ++i) {
-            T[i][i] = tau[i];
-            for (int l = 0; l < i; ++l) {
-                double t = 0.0;
-                for (int q = l; q < i; ++q) t += T[l][q] * G[q][i];
-                T[l][i] = -tau[i] * t;
+    // Gram of the Householder vectors (unit diagonal, zero above) for T: one
+    // thread per pair (l < i), four partial sums over the rows
+    if (tid < QR_NB * QR_NB) {
+        const int i = tid / QR_NB, l = tid % QR_NB;
+        if (l < i && i < pc) {
+            double t0 = P[l * nrows + i], t1 = 0.0, t2 = 0.0, t3 = 0.0;  // row i: y_i = 1
+            int r = i + 1;
+            for (; r + 3 < nrows; r += 4) {
+                t0 = fma(P[i * nrows + r], P[l * nrows + r], t0);
+                t1 = fma(P[i * nrows + r + 1], P[l * nrows + r + 1], t1);
+                t2 = fma(P[i * nrows + r + 2], P[l * nrows + r + 2], t2);
+                t3 = fma(P[i * nrows + r + 3], P[l * nrows + r + 3], t3);
             }
+            for (; r < nrows; ++r) t0 = fma(P[i * nrows + r], P[l * nrows + r], t0);
+            G[l][i] = (t0 + t1) + (t2 + t3);
         }
-        for (int i = 0; i < QR_NB; ++i)
-            for (int l = 0; l < QR_NB; ++l) Tws[i * QR_NB + l] = T[i][l];
     }
-    for (int idx = tid; idx < pc * nrows; idx += nt) {
-        const int cc = idx / nrows, r = idx - cc * nrows;
-        X[(int64_t)(c0 + r) + (int64_t)s * (c0 + cc)] = P[idx];
+    if (tid < QR_NB * QR_NB) Ts[tid / QR_NB][tid % QR_NB] = 0.0;
+    __syncthreads();
+    // compact-WY factor, column by column: T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
+    for (int i = 0; i < pc; ++i) {
+        if (tid < i) {
+            double t = 0.0;
+            for (int q = tid; q < i; ++q) t += Ts[tid][q] * G[q][i];
+            Ts[tid][i] = -tau[i] * t;
+        } else if (tid == i) {
+            Ts[i][i] = tau[i];
+        }
+        __syncthreads();
     }
+    if (tid < QR_NB * QR_NB) Tws[tid] = Ts[tid / QR_NB][tid % QR_NB];
+    for (int cc = 0; cc < pc; ++cc)
+        for (int r = tid; r < nrows; r += QR_NT) X[(int64_t)(c0 + r) + (int64_t)s * (c0 + cc)] = P[cc * nrows + r];
 }
 
 // Trailing update C <- (I - Y T Y^T)^T C for columns c0+nb .. ncols-1, one block per column.
@@ -169,23 +184,28 @@ __global__ __launch_bounds__(256) void qr_update_kernel(double* X, int s, int c0
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     const double* Y = X + (int64_t)c0 + (int64_t)s * c0;  // Y[r + s*i]
     double* C = X + (int64_t)c0 + (int64_t)s * d;
+    constexpr int RPT = SMAX / 256;
+    double cv[RPT], yv[RPT][QR_NB];
+    // all loads first (one memory round trip)
+#pragma unroll
+    for (int k = 0; k < RPT; ++k) {
+        const int r = tid + 256 * k;
+        cv[k] = (r < nrows) ? C[r] : 0.0;
+#pragma unroll
+        for (int i = 0; i < QR_NB; ++i)
+            yv[k][i] = (r < nrows && i < pc && r > i) ? Y[r + (int64_t)s * i] : ((r == i && i < pc) ? 1.0 : 0.0);
+    }
     double acc[QR_NB];
 #pragma unroll
-    for (int i = 0; i < QR_NB; ++i) acc[i] = 0.0;
-    for (int r = tid; r < nrows; r += 256) {
-        const double cr = C[r];
-#pragma unroll
-        for (int i = 0; i < QR_NB; ++i) {
-            if (i < pc && r >= i) {
-                const double yi = (r == i) ? 1.0 : Y[r + (int64_t)s * i];
-                acc[i] = fma(yi, cr, acc[i]);
-            }
-        }
-    }
-#pragma unroll
     for (int i = 0; i < QR_NB; ++i) {
-        const double t = wave_sum(acc[i]);
-        if (lane == 0) red[wid][i] = t;
+        double t = 0.0;
+#pragma unroll
+        for (int k = 0; k < RPT; ++k) t = fma(yv[k][i], cv[k], t);
+        acc[i] = wave_sum_fast(t);
+    }
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < QR_NB; ++i) red[wid][i] = acc[i];
     }
     __syncthreads();
     if (tid < QR_NB) W[tid] = red[0][tid] + red[1][tid] + red[2][tid] + red[3][tid];
@@ -196,16 +216,15 @@ __global__ __launch_bounds__(256) void qr_update_kernel(double* X, int s, int c0
         Z[tid] = (tid < pc) ? t : 0.0;
     }
     __syncthreads();
-    for (int r = tid; r < nrows; r += 256) {
-        double t = 0.0;
 #pragma unroll
-        for (int i = 0; i < QR_NB; ++i) {
-            if (i < pc && r >= i) {
-                const double yi = (r == i) ? 1.0 : Y[r + (int64_t)s * i];
-                t = fma(yi, Z[i], t);
-            }
+    for (int k = 0; k < RPT; ++k) {
+        const int r = tid + 256 * k;
+        if (r < nrows) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < QR_NB; ++i) t = fma(yv[k][i], Z[i], t);
+            C[r] = cv[k] - t;
         }
-        C[r] -= t;
     }
 }
 
@@ -242,117 +261,190 @@ __global__ void pencil_setup_kernel(const double* X, int s, int m, int k, const 
 // Returns log|det| and the sign of det(P[:mu]) for the square case in *logdet / *sgn.
 constexpr int QMAX = MMAX / WAVE;
 
-template <bool LS>
-__device__ void pencil_solve_wave(int mu, int m, double a, const double* __restrict__ T1r,
-                                  const double* __restrict__ K0r, double rhs0, double* __restrict__ Ubuf,
-                                  double* __restrict__ Urhs, double* __restrict__ y, double* logdet, double* sgn) {
+// raw entries of row kk of T1 and K0, columns >= c0 (zero elsewhere); combined into
+// P(a) = a T1 + K0 only when the row is used, so the loads stay in flight
+struct PRow {
+    double t[QMAX], k[QMAX];
+};
+
+__device__ __forceinline__ void load_pencil_row(PRow& row, int kk, int c0, int mu, int m,
+                                                const double* __restrict__ T1r, const double* __restrict__ K0r) {
     const int lane = threadIdx.x & 63;
-    double carry[QMAX], next[QMAX];
+    const double* t1 = T1r + (int64_t)kk * m;
+    const double* k0 = K0r + (int64_t)kk * m;
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
         const int jj = lane + WAVE * q;
-        carry[q] = (jj < mu) ? fma(a, T1r[jj], K0r[jj]) : 0.0;
+        const bool in = jj >= c0 && jj < mu;
+        row.t[q] = in ? t1[jj] : 0.0;
+        row.k[q] = in ? k0[jj] : 0.0;
     }
-    double rc = rhs0, rn = 0.0;
-    double ld = 0.0, sg = 1.0;
-    const int last = LS ? mu : mu - 1;  // number of eliminations
+}
+
+__device__ __forceinline__ void combine_row(double (&row)[QMAX], const PRow& r, double a) {
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) row[q] = fma(a, r.t[q], r.k[q]);
+}
+
+constexpr int PF = 4;  // rows of the pencil in flight ahead of the elimination
+
+// value of the distributed vector v at index i (wave-uniform i)
+__device__ __forceinline__ double dist_get(const double (&v)[QMAX], int i) {
+    double t = 0.0;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q)
+        if (q == i / WAVE) t = v[q];
+    return bcast_lane(t, i % WAVE);
+}
+
+__device__ __forceinline__ void dist_set(double (&v)[QMAX], int i, double x) {
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q)
+        if (q == i / WAVE && lane == i % WAVE) v[q] = x;
+}
+
+// Solves with P(a) = a T1 + K0 (upper Hessenberg), right-hand side rhs0 e_1.
+//   LS = false: square system P[:mu] y = rhs0 e_1 (Gaussian elimination with
+//               partial pivoting between the two candidate rows of each column)
+//   LS = true:  least squares min || rhs0 e_1 - P y || over the (mu+1) x mu pencil
+//               (Givens rotations)
+// One wavefront; vectors are distributed as index lane + 64 q.  The triangular
+// factor goes column-major into Ucol (column jj at jj * m), read back column by
+// column by the (reduction-free) back substitution.  With DET the sign of
+// det(P[:mu]) is returned in *sgn (row swaps times the signs of the pivots) and
+// the pivots are left on the diagonal of Ucol for the caller.
+template <bool LS, bool DET>
+__device__ void pencil_solve_wave(int mu, int m, double a, const double* __restrict__ T1r,
+                                  const double* __restrict__ K0r, double rhs0, double* __restrict__ Ucol,
+                                  double* __restrict__ unused, double* __restrict__ y, double* logdet, double* sgn) {
+    (void)unused;
+    const int lane = threadIdx.x & 63;
+    double carry[QMAX], next[QMAX];
+    PRow pref[PF];
+    double rv[QMAX], ud[QMAX];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) { rv[q] = 0.0; ud[q] = 1.0; }
+    {
+        PRow r0;
+        load_pencil_row(r0, 0, 0, mu, m, T1r, K0r);
+        combine_row(carry, r0, a);
+    }
+    const int last = LS ? mu : mu - 1;  // number of eliminations; rows 1..last are read
+#pragma unroll
+    for (int f = 0; f < PF; ++f)
+        if (1 + f <= last) load_pencil_row(pref[f], 1 + f, f, mu, m, T1r, K0r);
+    double rc = rhs0;
+    double sg = 1.0;
     for (int kk = 0; kk < last; ++kk) {
-        const double* t1 = T1r + (int64_t)(kk + 1) * m;
-        const double* k0 = K0r + (int64_t)(kk + 1) * m;
+        combine_row(next, pref[0], a);
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
-            const int jj = lane + WAVE * q;
-            next[q] = (jj >= kk && jj < mu) ? fma(a, t1[jj], k0[jj]) : 0.0;
-        }
-        rn = 0.0;
-        const int ql = kk / WAVE, ll = kk % WAVE;
-        double pk = 0.0, nk = 0.0;
-#pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
-            if (q == ql) { pk = __shfl(carry[q], ll, WAVE); nk = __shfl(next[q], ll, WAVE); }
-        }
-        double* urow = Ubuf + (int64_t)kk * m;
+        for (int f = 0; f + 1 < PF; ++f) pref[f] = pref[f + 1];
+        // keep PF rows in flight while this column is eliminated
+        if (kk + 1 + PF <= last) load_pencil_row(pref[PF - 1], kk + 1 + PF, kk + PF, mu, m, T1r, K0r);
+        double rn = 0.0;
+        double pk = dist_get(carry, kk);
+        double nk = dist_get(next, kk);
+        double* ucol = Ucol + kk;  // row kk of U: element (kk, jj) at jj * m + kk
         if (!LS) {
-            const bool swp = fabs(nk) > fabs(pk);
-            if (swp) {
+            if (fabs(nk) > fabs(pk)) {
 #pragma unroll
                 for (int q = 0; q < QMAX; ++q) { const double t = carry[q]; carry[q] = next[q]; next[q] = t; }
-                const double t = rc; rc = rn; rn = t;
+                rn = rc; rc = 0.0;
                 const double tp = pk; pk = nk; nk = tp;
-                sg = -sg;
+                if (DET) sg = -sg;
             }
             const double l = (pk != 0.0) ? nk / pk : 0.0;
 #pragma unroll
             for (int q = 0; q < QMAX; ++q) {
                 const int jj = lane + WAVE * q;
-                if (jj >= kk && jj < mu) urow[jj] = carry[q];
+                if (jj >= kk && jj < mu) ucol[(int64_t)jj * m] = carry[q];
                 next[q] = fma(-l, carry[q], next[q]);
             }
-            if (lane == 0) Urhs[kk] = rc;
+            dist_set(rv, kk, rc);
+            dist_set(ud, kk, pk);
             rn = fma(-l, rc, rn);
-            ld += log(fabs(pk));
-            if (pk < 0.0) sg = -sg;
         } else {
-            const double r = hypot(pk, nk);
-            const double c = (r != 0.0) ? pk / r : 1.0;
-            const double sn = (r != 0.0) ? nk / r : 0.0;
+            const double r = sqrt(fma(pk, pk, nk * nk));
+            const double rinv = (r != 0.0) ? 1.0 / r : 0.0;
+            const double c = (r != 0.0) ? pk * rinv : 1.0;
+            const double sn = nk * rinv;
 #pragma unroll
             for (int q = 0; q < QMAX; ++q) {
                 const int jj = lane + WAVE * q;
                 const double top = fma(c, carry[q], sn * next[q]);
                 const double bot = fma(-sn, carry[q], c * next[q]);
-                if (jj >= kk && jj < mu) urow[jj] = top;
+                if (jj >= kk && jj < mu) ucol[(int64_t)jj * m] = top;
                 next[q] = bot;
             }
-            const double rtop = fma(c, rc, sn * rn);
-            const double rbot = fma(-sn, rc, c * rn);
-            if (lane == 0) Urhs[kk] = rtop;
-            rn = rbot;
+            dist_set(rv, kk, c * rc);
+            dist_set(ud, kk, r);
+            rn = -sn * rc;
         }
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) carry[q] = next[q];
         rc = rn;
     }
     if (!LS) {
-        // last row of U
+        // last diagonal entry
         const int kk = mu - 1;
-        const int ql = kk / WAVE, ll = kk % WAVE;
-        double pk = 0.0;
+        const double pk = dist_get(carry, kk);
+        if (lane == kk % WAVE) Ucol[(int64_t)kk * m + kk] = pk;
+        dist_set(rv, kk, rc);
+        dist_set(ud, kk, pk);
+    }
+    if (DET) {
+        double neg = 0.0;
 #pragma unroll
         for (int q = 0; q < QMAX; ++q)
-            if (q == ql) pk = __shfl(carry[q], ll, WAVE);
-        if (lane == ll) Ubuf[(int64_t)kk * m + kk] = pk;
-        if (lane == 0) Urhs[kk] = rc;
-        ld += log(fabs(pk));
-        if (pk < 0.0) sg = -sg;
+            if (lane + WAVE * q < mu && ud[q] < 0.0) neg += 1.0;
+        neg = wave_sum_fast(neg);
+        if (((int)neg) & 1) sg = -sg;
     }
-    __threadfence_block();  // Ubuf / Urhs written by this wave become visible to all of its lanes
-    // back substitution, y distributed: y[lane + 64 q]
-    double yv[QMAX];
+    // reciprocals of the diagonal, all at once
+    double dinv[QMAX];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) dinv[q] = (lane + WAVE * q < mu) ? 1.0 / ud[q] : 0.0;
+    __threadfence_block();  // Ucol written by this wave becomes visible to all of its lanes
+    // column-oriented back substitution: y_k = r_k / U_kk, then r_i -= U_ik y_k (i < k)
+    constexpr int BF = 4;  // columns of U in flight
+    double yv[QMAX], cbuf[BF][QMAX];
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) yv[q] = 0.0;
-    for (int kk = mu - 1; kk >= 0; --kk) {
-        const double* urow = Ubuf + (int64_t)kk * m;
-        double part = 0.0;
+#pragma unroll
+    for (int f = 0; f < BF; ++f) {
+        const int col = mu - 1 - f;
 #pragma unroll
         for (int q = 0; q < QMAX; ++q) {
-            const int jj = lane + WAVE * q;
-            if (jj > kk && jj < mu) part = fma(urow[jj], yv[q], part);
+            const int i = lane + WAVE * q;
+            cbuf[f][q] = (col >= 0 && i < col) ? Ucol[(int64_t)col * m + i] : 0.0;
         }
-        part = wave_sum(part);
-        const double ukk = urow[kk];
-        const double yk = (Urhs[kk] - part) / ukk;
-        const int ql = kk / WAVE, ll = kk % WAVE;
+    }
+    for (int kk = mu - 1; kk >= 0; --kk) {
+        const double yk = dist_get(rv, kk) * dist_get(dinv, kk);
+        dist_set(yv, kk, yk);
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q)
-            if (q == ql && lane == ll) yv[q] = yk;
+        for (int q = 0; q < QMAX; ++q) {
+            const int i = lane + WAVE * q;
+            if (i < kk) rv[q] = fma(-cbuf[0][q], yk, rv[q]);
+        }
+#pragma unroll
+        for (int f = 0; f + 1 < BF; ++f)
+#pragma unroll
+            for (int q = 0; q < QMAX; ++q) cbuf[f][q] = cbuf[f + 1][q];
+        const int col = kk - BF;
+#pragma unroll
+        for (int q = 0; q < QMAX; ++q) {
+            const int i = lane + WAVE * q;
+            cbuf[BF - 1][q] = (col >= 0 && i < col) ? Ucol[(int64_t)col * m + i] : 0.0;
+        }
     }
 #pragma unroll
     for (int q = 0; q < QMAX; ++q) {
         const int jj = lane + WAVE * q;
         if (jj < mu) y[jj] = yv[q];
     }
-    if (logdet) *logdet = ld;
+    if (logdet) *logdet = 0.0;
     if (sgn) *sgn = sg;
 }
 
@@ -369,12 +461,21 @@ __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, 
     const int lane = threadIdx.x;
     // R diagonal statistics
     double lr = 0.0, rmin = 1e308, rmax = 0.0, rs = 1.0;
-    for (int j = lane; j < mu; j += 64) {
-        const double d = X[j + (int64_t)s * j];
-        lr += log(fabs(d));
-        rmin = fmin(rmin, fabs(d));
-        rmax = fmax(rmax, fabs(d));
-        if (d < 0.0) rs = -rs;
+    double dg[QMAX];
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+        const int j = lane + 64 * q;
+        dg[q] = (j < mu) ? X[j + (int64_t)s * j] : 1.0;
+    }
+#pragma unroll
+    for (int q = 0; q < QMAX; ++q) {
+        if (lane + 64 * q < mu) {
+            const double d = dg[q];
+            lr += log(fabs(d));
+            rmin = fmin(rmin, fabs(d));
+            rmax = fmax(rmax, fabs(d));
+            if (d < 0.0) rs = -rs;
+        }
     }
     lr = wave_sum(lr);
     rmax = wave_max(rmax);
@@ -385,10 +486,15 @@ __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, 
     const double beta = eta[0];
     const double rhs0 = beta * X[0];
     double ld = 0.0, sg = 1.0;
-    if (is_ls)
-        pencil_solve_wave<true>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, nullptr, nullptr);
-    else
-        pencil_solve_wave<false>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, &ld, &sg);
+    if (is_ls) {
+        pencil_solve_wave<true, false>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, nullptr, nullptr);
+    } else {
+        pencil_solve_wave<false, true>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, nullptr, &sg);
+        // log|det| = sum log|U_kk| (sg already holds the sign: row swaps and pivot signs)
+        double lu = 0.0;
+        for (int kk = lane; kk < mu; kk += 64) lu += log(fabs(Ubuf[(int64_t)kk * m + kk]));
+        ld = wave_sum_fast(lu);
+    }
     if (lane == 0) {
         ctrl->beta = beta;
         ctrl->rcond = (rmax > 0.0) ? rmin / rmax : 0.0;
@@ -409,92 +515,114 @@ __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, 
 // (Called before the LS setup kernel; see host sequence.)
 
 // ------------------------------------------------ quadrature levels
-struct QuadArgs {
-    const DevCtrl* ctrl;
-    const double* T1r;
-    const double* K0r;
-    double* Ubuf;     // [NODE_SLOTS][m*m]
-    double* Urhs;     // [NODE_SLOTS][m]
-    double* nodebuf;  // [l][m] weighted node solutions
-    int m, l, is_ls;
-    double rhs0_unused;
-};
-
-__global__ __launch_bounds__(256) void quad_level_kernel(QuadArgs qa, const double* X, int s, const double* eta) {
-    if (qa.ctrl->converged || qa.ctrl->status != 0) return;
-    const int mu = qa.ctrl->m_used;
+// One launch evaluates every node of a group of consecutive orders (the nodes
+// are independent, Section 5.3); the reduction then applies the acceptance test
+// of Section 4.1 to the orders in sequence.
+__global__ __launch_bounds__(256) void quad_level_kernel(const DevCtrl* ctrl, QuadGroup grp, const double* T1r,
+                                                         const double* K0r, double* Ubuf, double* Urhs,
+                                                         double* nodebuf, int m, int is_ls, const double* X,
+                                                         const double* eta) {
+    if (ctrl->converged || ctrl->status != 0) return;
+    const int mu = ctrl->m_used;
     if (mu == 0) return;
-    const double sigma = qa.ctrl->sigma;
+    const double sigma = ctrl->sigma;
     const double rhs0 = eta[0] * X[0];
     const int wave = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     const int nwaves_total = gridDim.x * (blockDim.x / WAVE);
-    const int slot = wave;  // < NODE_SLOTS by construction of the grid
-    double* U = qa.Ubuf + (int64_t)slot * qa.m * qa.m;
-    double* Ur = qa.Urhs + (int64_t)slot * qa.m;
-    const int l = qa.l;
-    for (int i = wave; i < l; i += nwaves_total) {
-        const double x = cos((2.0 * i + 1.0) * M_PI / (2.0 * l));
+    double* U = Ubuf + (int64_t)wave * m * m;   // slot = global wave index < NODE_SLOTS
+    double* Ur = Urhs + (int64_t)wave * m;
+    for (int i = wave; i < grp.total; i += nwaves_total) {
+        int lev = 0;
+        while (lev + 1 < grp.nlev && i >= grp.lev_off[lev + 1]) ++lev;
+        const int l = grp.lev_l[lev];
+        const int ii = i - grp.lev_off[lev];
+        const double x = cos((2.0 * ii + 1.0) * M_PI / (2.0 * l));
         const double t = (1.0 - x) / (1.0 + x);
         const double w = (2.0 / l) / (1.0 + x);
-        double* yi = qa.nodebuf + (int64_t)i * qa.m;
-        if (qa.is_ls)
-            pencil_solve_wave<true>(mu, qa.m, t * sigma, qa.T1r, qa.K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
+        double* yi = nodebuf + (int64_t)i * m;
+        if (is_ls)
+            pencil_solve_wave<true, false>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
         else
-            pencil_solve_wave<false>(mu, qa.m, t * sigma, qa.T1r, qa.K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
+            pencil_solve_wave<false, false>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
     }
 }
 
-// q_l = sqrt(sigma) * sum_i nodebuf[i] (fixed order); on the first level store it,
-// afterwards compare with the previous rule in the whitened norm ||R_e[:mu,:mu] (.)||
-// (Section 4.1 acceptance test) and either accept or keep the new rule.
-__global__ __launch_bounds__(256) void quad_reduce_kernel(DevCtrl* ctrl, const double* nodebuf, int m, int l,
-                                                          int first, double tol, const double* T1r,
-                                                          double* qprev, double* qcur, double* y) {
-    __shared__ double scratch[4];
-    __shared__ double diff[MMAX];
-    __shared__ double cur[MMAX];
+// For each level of the group: q_l = sqrt(sigma) sum_i nodebuf[i] (fixed order), and
+// the whitened norms ||R q_l||, ||R (q_l - q_{l-1})|| (R = R_e[:mu,:mu]); levels are
+// summed in parallel (one wavefront each), then the acceptance test of Section 4.1
+// is applied in sequence: the sequence's first level only seeds qprev; accept q_l
+// when ||R (q_l - q_prev)|| <= tol ||R q_l||.
+__global__ __launch_bounds__(1024) void quad_reduce_kernel(DevCtrl* ctrl, QuadGroup grp, const double* nodebuf, int m,
+                                                           double tol, const double* T1r, double* qprev, double* y,
+                                                           double* qlev) {
+    __shared__ double nd[MAX_GROUP_LEVELS], nc[MAX_GROUP_LEVELS];
+    __shared__ double qs[MAX_GROUP_LEVELS + 1][MMAX];
     if (ctrl->converged || ctrl->status != 0) return;
     const int mu = ctrl->m_used;
     if (mu == 0) return;
     const double sq = sqrt(ctrl->sigma);
-    for (int jj = threadIdx.x; jj < mu; jj += 256) {
-        double t = 0.0;
-        for (int i = 0; i < l; ++i) t += nodebuf[(int64_t)i * m + jj];
-        t *= sq;
-        cur[jj] = t;
-        diff[jj] = t - qprev[jj];
-        qcur[jj] = t;
-    }
-    __syncthreads();
-    if (first) {
-        for (int jj = threadIdx.x; jj < mu; jj += 256) qprev[jj] = cur[jj];
-        if (threadIdx.x == 0) ctrl->l_prev = l;
-        return;
-    }
-    // whitened norms: R = T1[:mu, :mu] (upper triangular, row-major)
-    double nd = 0.0, nc = 0.0;
-    for (int i = threadIdx.x; i < mu; i += 256) {
-        double td = 0.0, tc = 0.0;
-        for (int jj = i; jj < mu; ++jj) {
-            const double r = T1r[(int64_t)i * m + jj];
-            td = fma(r, diff[jj], td);
-            tc = fma(r, cur[jj], tc);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    // q of every level (row 0 of qs holds the previous group's last rule)
+    for (int jj = threadIdx.x; jj < mu; jj += 1024) qs[0][jj] = qprev[jj];
+    for (int lev = wid; lev < grp.nlev; lev += 16) {
+        const int l = grp.lev_l[lev], off = grp.lev_off[lev];
+        for (int jj = lane; jj < mu; jj += 64) {
+            double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+            int i = 0;
+            for (; i + 3 < l; i += 4) {
+                a0 += nodebuf[(int64_t)(off + i) * m + jj];
+                a1 += nodebuf[(int64_t)(off + i + 1) * m + jj];
+                a2 += nodebuf[(int64_t)(off + i + 2) * m + jj];
+                a3 += nodebuf[(int64_t)(off + i + 3) * m + jj];
+            }
+            for (; i < l; ++i) a0 += nodebuf[(int64_t)(off + i) * m + jj];
+            qs[lev + 1][jj] = ((a0 + a1) + (a2 + a3)) * sq;
         }
-        nd = fma(td, td, nd);
-        nc = fma(tc, tc, nc);
     }
-    nd = block_sum(nd, scratch);
-    nc = block_sum(nc, scratch);
-    const bool ok = sqrt(nd) <= tol * sqrt(nc);
     __syncthreads();
-    for (int jj = threadIdx.x; jj < mu; jj += 256) {
-        if (ok) y[jj] = cur[jj];
-        else qprev[jj] = cur[jj];
+    // whitened norms, one wavefront per level: rows of R spread over lanes
+    for (int lev = wid; lev < grp.nlev; lev += 16) {
+        double td_all = 0.0, tc_all = 0.0;
+        for (int i = lane; i < mu; i += 64) {
+            double d0 = 0.0, d1 = 0.0, c0 = 0.0, c1 = 0.0;
+            int jj = i;
+            for (; jj + 1 < mu; jj += 2) {
+                const double r0 = T1r[(int64_t)i * m + jj], r1 = T1r[(int64_t)i * m + jj + 1];
+                d0 = fma(r0, qs[lev + 1][jj] - qs[lev][jj], d0);
+                d1 = fma(r1, qs[lev + 1][jj + 1] - qs[lev][jj + 1], d1);
+                c0 = fma(r0, qs[lev + 1][jj], c0);
+                c1 = fma(r1, qs[lev + 1][jj + 1], c1);
+            }
+            if (jj < mu) {
+                const double r0 = T1r[(int64_t)i * m + jj];
+                d0 = fma(r0, qs[lev + 1][jj] - qs[lev][jj], d0);
+                c0 = fma(r0, qs[lev + 1][jj], c0);
+            }
+            td_all = fma(d0 + d1, d0 + d1, td_all);
+            tc_all = fma(c0 + c1, c0 + c1, tc_all);
+        }
+        td_all = wave_sum(td_all);
+        tc_all = wave_sum(tc_all);
+        if (lane == 0) { nd[lev] = td_all; nc[lev] = tc_all; }
+    }
+    __syncthreads();
+    int acc_lev = -1;
+    int last = grp.nlev - 1;
+    bool bad = false;
+    for (int lev = 0; lev < grp.nlev; ++lev) {
+        if (grp.first && lev == 0) continue;
+        if (!isfinite(nd[lev]) || !isfinite(nc[lev])) { bad = true; last = lev; break; }
+        if (sqrt(nd[lev]) <= tol * sqrt(nc[lev])) { acc_lev = lev; break; }
+    }
+    if (acc_lev >= 0) {
+        for (int jj = threadIdx.x; jj < mu; jj += 1024) y[jj] = qs[acc_lev + 1][jj];
+    } else {
+        for (int jj = threadIdx.x; jj < mu; jj += 1024) qprev[jj] = qs[last + 1][jj];
     }
     if (threadIdx.x == 0) {
-        if (ok) { ctrl->converged = 1; ctrl->l_used = l; }
-        else ctrl->l_prev = l;
-        if (!isfinite(nd) || !isfinite(nc)) ctrl->status = 5;
+        if (acc_lev >= 0) { ctrl->converged = 1; ctrl->l_used = grp.lev_l[acc_lev]; }
+        else ctrl->l_prev = grp.lev_l[last];
+        if (bad) ctrl->status = 5;
     }
 }
 
@@ -591,7 +719,7 @@ hipError_t launch_init_ctrl(DevCtrl* c, int m, hipStream_t st) {
 hipError_t launch_qr(double* X, int s, int ncols_max, const DevCtrl* ctrl, double* Tws, hipStream_t st) {
     for (int c0 = 0; c0 < ncols_max; c0 += QR_NB) {
         const size_t lds = (size_t)QR_NB * (s - c0) * sizeof(double);
-        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(1024), lds, st, X, s, c0, ctrl, Tws);
+        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(QR_NT), lds, st, X, s, c0, ctrl, Tws);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const int rest = ncols_max - c0 - QR_NB;
@@ -619,20 +747,20 @@ hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, c
     return hipGetLastError();
 }
 
-hipError_t launch_quad_level(const DevCtrl* ctrl, const double* T1r, const double* K0r, double* Ubuf, double* Urhs,
-                             double* nodebuf, int m, int l, int is_ls, const double* X, int s, const double* eta,
-                             hipStream_t st) {
-    QuadArgs qa{ctrl, T1r, K0r, Ubuf, Urhs, nodebuf, m, l, is_ls, 0.0};
-    int waves = l < NODE_SLOTS ? l : NODE_SLOTS;
-    int blocks = (waves + 3) / 4;
-    hipLaunchKernelGGL(quad_level_kernel, dim3(blocks), dim3(256), 0, st, qa, X, s, eta);
+hipError_t launch_quad_group(const DevCtrl* ctrl, const QuadGroup& g, const double* T1r, const double* K0r,
+                             double* Ubuf, double* Urhs, double* nodebuf, int m, int is_ls, const double* X,
+                             const double* eta, hipStream_t st) {
+    const int waves = g.total < NODE_SLOTS ? g.total : NODE_SLOTS;
+    const int blocks = (waves + 3) / 4;
+    hipLaunchKernelGGL(quad_level_kernel, dim3(blocks), dim3(256), 0, st, ctrl, g, T1r, K0r, Ubuf, Urhs, nodebuf, m,
+                       is_ls, X, eta);
     return hipGetLastError();
 }
 
-hipError_t launch_quad_reduce(DevCtrl* ctrl, const double* nodebuf, int m, int l, int first, double tol,
-                              const double* T1r, double* qprev, double* qcur, double* y, hipStream_t st) {
-    hipLaunchKernelGGL(quad_reduce_kernel, dim3(1), dim3(256), 0, st, ctrl, nodebuf, m, l, first, tol, T1r, qprev,
-                       qcur, y);
+hipError_t launch_quad_reduce(DevCtrl* ctrl, const QuadGroup& g, const double* nodebuf, int m, double tol,
+                              const double* T1r, double* qprev, double* y, hipStream_t st) {
+    hipLaunchKernelGGL(quad_reduce_kernel, dim3(1), dim3(1024), 0, st, ctrl, g, nodebuf, m, tol, T1r, qprev, y,
+                       nullptr);
     return hipGetLastError();
 }
 
