@@ -74,8 +74,18 @@ typedef enum skfab_method {
     SKFAB_SGMRES_QUAD = 2   /* Algorithm 2, (sGMRES), adaptive quadrature, quad_tol   */
 } skfab_method;
 
+/* Precision of the Krylov recurrence (spec precision extension).  In every
+ * mode the sketches are accumulated in FP64, the dot products of the recurrence
+ * are accumulated in FP64 per thread and reduced in FP64, and the small sketched
+ * problem (QR, quadrature / f evaluation) and the assembly x = V_m y (FP64
+ * accumulation) stay FP64.  Reduced precisions need zeta = 8 and k <= 4. */
 typedef enum skfab_prec {
-    SKFAB_PREC_FP64 = 0     /* A, basis and all arithmetic in IEEE double            */
+    SKFAB_PREC_FP64 = 0,           /* A, basis and all arithmetic in IEEE double       */
+    SKFAB_PREC_FP32 = 1,           /* A values, basis V_m and A V_m stored in FP32; SpMV
+                                      and the basis update in FP32                      */
+    SKFAB_PREC_FP32_BF16BASIS = 2  /* as FP32, but V_m stored in bfloat16 (rounded to
+                                      nearest even); the rounded vector is the one
+                                      multiplied by A and sketched                      */
 } skfab_prec;
 
 typedef enum skfab_valtype {
@@ -99,7 +109,7 @@ typedef struct skfab_params {
     const double *poly;     /* HOST array of npoly coefficients (lowest degree first) */
     int32_t npoly;          /* 1 <= npoly <= m for SKFAB_F_POLY                       */
     int32_t method;         /* skfab_method                                          */
-    int32_t m;              /* Krylov dimension, 1 <= m <= 256                       */
+    int32_t m;              /* Krylov dimension, 1 <= m <= 512                       */
     int32_t k;              /* truncation length, 1 <= k <= min(m, 8)                */
     int32_t s;              /* sketch rows, m < s <= min(N, 1024)                    */
     int32_t zeta;           /* nonzeros per sketch column: 8                         */

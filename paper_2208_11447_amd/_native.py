@@ -16,7 +16,7 @@ SKFAB_OK, SKFAB_ERR_ARG, SKFAB_ERR_SHAPE, SKFAB_ERR_RANK, SKFAB_ERR_BRANCH, SKFA
     SKFAB_ERR_HIP, SKFAB_ERR_WORKSPACE = range(8)
 SKFAB_F_INVSQRT, SKFAB_F_EXP, SKFAB_F_INV, SKFAB_F_POLY = range(4)
 SKFAB_SFOM_CLOSED, SKFAB_SFOM_QUAD, SKFAB_SGMRES_QUAD = range(3)
-SKFAB_PREC_FP64 = 0
+SKFAB_PREC_FP64, SKFAB_PREC_FP32, SKFAB_PREC_FP32_BF16BASIS = range(3)
 SKFAB_VAL_F64 = 0
 
 EXPORTED = [

@@ -12,16 +12,16 @@
 #include "device_state.hpp"
 
 namespace skfab {
-hipError_t launch_arnoldi_step(const StepArgs& a, int zeta, int block, hipStream_t st);
+hipError_t launch_arnoldi_step(const StepArgs& a, int zeta, int block, int prec, hipStream_t st);
 hipError_t launch_arnoldi_tail(const StepArgs& a, double* colnorm2, hipStream_t st);
 hipError_t launch_arnoldi_check(const double* SV, const double* SAV, const double* H, int s, int m, int k,
                                 DevCtrl* ctrl, double* part, hipStream_t st);
 int64_t sell_scan_blocks(int64_t nslices);
 hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const double* val, int64_t N,
                                int64_t nslices, int64_t capacity, DevCtrl* ctrl, int32_t* sl_len, int64_t* sl_ptr,
-                               int64_t* bsum, int32_t* sl_col, double* sl_val, hipStream_t st);
-hipError_t launch_normalize_basis(const double* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl,
-                                  const double* eta, double* V, hipStream_t st);
+                               int64_t* bsum, int32_t* sl_col, void* sl_val, int prec, hipStream_t st);
+hipError_t launch_normalize_basis(const void* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl,
+                                  const double* eta, double* V, int prec, hipStream_t st);
 hipError_t launch_sketch_pattern(int64_t col0, int64_t ncols, int s, int zeta, uint64_t seed, int32_t* rows,
                                  int8_t* signs, hipStream_t st);
 hipError_t launch_sketch_apply(int64_t n, int s, int zeta, uint64_t seed, const double* v, double* Sv,
@@ -45,8 +45,8 @@ hipError_t launch_poly(const DevCtrl* ctrl, int m, const double* T1r, const doub
                        const double* coef, int npoly, double* y, hipStream_t st);
 hipError_t launch_finish_coeffs(DevCtrl* ctrl, int m, const double* y, const double* eta, const double* colnorm2,
                                 double* ys, double* yout, hipStream_t st);
-hipError_t launch_assemble(const double* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl, const double* ys,
-                           double* x, hipStream_t st);
+hipError_t launch_assemble(const void* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl, const double* ys,
+                           double* x, int prec, hipStream_t st);
 hipError_t launch_hhat(const DevCtrl* ctrl, int m, const double* T1r, const double* X, int s, const double* H,
                        double tau, double* Ahat, double* norm1, hipStream_t st);
 hipError_t launch_combine(const DevCtrl* ctrl, int m, double a, const double* P, double b, const double* Q,
@@ -207,7 +207,12 @@ int max_level_nodes(int l1, int l2, int lmax) {
     return mx;
 }
 
-Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lmax, int npoly, bool with_basis) {
+// bytes of the basis (V), SpMV (W) and matrix-value (A) element types of a precision
+size_t vbytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
+size_t wbytes(int prec) { return prec == 0 ? 8 : 4; }
+
+Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lmax, int npoly, bool with_basis,
+                   int prec) {
     Layout ly;
     ly.L = step_launch(N > 0 ? N : 1, s);
     ly.ldU = (N + 63) / 64 * 64;
@@ -227,8 +232,8 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
     ly.gram = take((size_t)(m + 1) * KMAX * d);
     ly.colnorm2 = take((m + 1) * d);
     ly.scal = take((size_t)2 * NSC_MAX * G * d);
-    ly.U = with_basis ? take((size_t)ly.ldU * m * d) : take(0);
-    ly.W = with_basis ? take((size_t)2 * ly.ldU * d) : take(0);
+    ly.U = with_basis ? take((size_t)ly.ldU * m * vbytes(prec)) : take(0);
+    ly.W = with_basis ? take((size_t)2 * ly.ldU * wbytes(prec)) : take(0);
     ly.skpart = with_basis ? take((size_t)2 * G * 2 * s * d) : take(0);
     // SELL-64 copy of A: room for 25% more entries than nnz plus one padded row per slice
     ly.sell_capacity = with_basis ? nnz + nnz / 4 + 64 * ly.L.nslices : 0;
@@ -236,7 +241,7 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
     ly.sl_ptr = with_basis ? take((size_t)ly.L.nslices * sizeof(int64_t)) : take(0);
     ly.bsum = with_basis ? take((size_t)sell_scan_blocks(ly.L.nslices) * sizeof(int64_t)) : take(0);
     ly.sl_col = with_basis ? take((size_t)ly.sell_capacity * sizeof(int32_t)) : take(0);
-    ly.sl_val = with_basis ? take((size_t)ly.sell_capacity * d) : take(0);
+    ly.sl_val = with_basis ? take((size_t)ly.sell_capacity * wbytes(prec)) : take(0);
     ly.chk = take((size_t)2 * m * d);
     ly.SV = take((size_t)s * (m + 1) * d);
     ly.SAV = take((size_t)s * m * d);
@@ -261,8 +266,10 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
 
 struct Ptrs {
     DevCtrl* ctrl;
-    double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *U, *W, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Ubuf, *Urhs,
-        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1, *chk, *sl_val;
+    void *U, *W;
+    double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Ubuf, *Urhs,
+        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1, *chk;
+    void* sl_val;
     int* piv;
     int32_t *sl_len, *sl_col;
     int64_t *sl_ptr, *bsum;
@@ -274,13 +281,13 @@ Ptrs carve(void* ws, const Layout& ly) {
     p.ctrl = reinterpret_cast<DevCtrl*>(b + ly.ctrl);
     auto D = [&](size_t o) { return reinterpret_cast<double*>(b + o); };
     p.eta = D(ly.eta); p.wnorm = D(ly.wnorm); p.H = D(ly.H); p.gram = D(ly.gram); p.colnorm2 = D(ly.colnorm2);
-    p.scal = D(ly.scal); p.U = D(ly.U); p.W = D(ly.W); p.skpart = D(ly.skpart); p.SV = D(ly.SV); p.SAV = D(ly.SAV);
+    p.scal = D(ly.scal); p.U = b + ly.U; p.W = b + ly.W; p.skpart = D(ly.skpart); p.SV = D(ly.SV); p.SAV = D(ly.SAV);
     p.Tws = D(ly.Tws); p.K0r = D(ly.K0r); p.T1r = D(ly.T1r); p.Ubuf = D(ly.Ubuf); p.Urhs = D(ly.Urhs);
     p.nodebuf = D(ly.nodebuf); p.qprev = D(ly.qprev); p.qcur = D(ly.qcur); p.y = D(ly.y); p.ys = D(ly.ys);
     p.y0 = D(ly.y0); p.poly = D(ly.poly); p.expbuf = D(ly.expbuf); p.norm1 = D(ly.norm1);
     p.piv = reinterpret_cast<int*>(b + ly.piv);
     p.chk = D(ly.chk);
-    p.sl_val = D(ly.sl_val);
+    p.sl_val = b + ly.sl_val;
     p.sl_len = reinterpret_cast<int32_t*>(b + ly.sl_len);
     p.sl_col = reinterpret_cast<int32_t*>(b + ly.sl_col);
     p.sl_ptr = reinterpret_cast<int64_t*>(b + ly.sl_ptr);
@@ -304,7 +311,10 @@ skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matri
         if (A->val_type != SKFAB_VAL_F64) return SKFAB_ERR_ARG;
         if (A->n <= 0 || A->nnz < 0 || A->nnz > INT32_MAX) return SKFAB_ERR_SHAPE;
     }
-    if (p->f < 0 || p->f > 3 || p->method < 0 || p->method > 2 || p->prec != SKFAB_PREC_FP64) return SKFAB_ERR_ARG;
+    if (p->f < 0 || p->f > 3 || p->method < 0 || p->method > 2) return SKFAB_ERR_ARG;
+    if (p->prec < SKFAB_PREC_FP64 || p->prec > SKFAB_PREC_FP32_BF16BASIS) return SKFAB_ERR_ARG;
+    // reduced precisions are built for the default sketch density and k <= 4
+    if (p->prec != SKFAB_PREC_FP64 && (p->zeta != 8 || p->k > 4)) return SKFAB_ERR_ARG;
     if (p->m < 1 || p->m > MMAX) return SKFAB_ERR_SHAPE;
     if (p->k < 1 || p->k > KMAX || p->k > p->m) return SKFAB_ERR_SHAPE;
     if (p->s <= p->m || p->s > SMAX) return SKFAB_ERR_SHAPE;
@@ -337,7 +347,7 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
     const int m = p->m, s = p->s;
     HIP_TRY(launch_init_ctrl(w.ctrl, m, st));
     HIP_TRY(launch_sell_convert(A->rowptr, A->col, static_cast<const double*>(A->val), A->n, ly.L.nslices,
-                                ly.sell_capacity, w.ctrl, w.sl_len, w.sl_ptr, w.bsum, w.sl_col, w.sl_val, st));
+                                ly.sell_capacity, w.ctrl, w.sl_len, w.sl_ptr, w.bsum, w.sl_col, w.sl_val, p->prec, st));
     StepArgs a;
     std::memset(&a, 0, sizeof(a));
     a.N = A->n;
@@ -373,8 +383,8 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
     for (int j = 0; j <= m; ++j) {
         a.j = j;
         a.extend = (j == m) ? 1 : 0;
-        a.Wcur = w.W + (int64_t)(j & 1) * ly.ldU;
-        a.Wprev = w.W + (int64_t)((j + 1) & 1) * ly.ldU;
+        a.Wcur = static_cast<char*>(w.W) + (int64_t)(j & 1) * ly.ldU * wbytes(p->prec);
+        a.Wprev = static_cast<char*>(w.W) + (int64_t)((j + 1) & 1) * ly.ldU * wbytes(p->prec);
         a.scal_prev = w.scal + ((j + 1) & 1) * nsc;
         a.scal_cur = w.scal + (j & 1) * nsc;
         a.skp_prev = w.skpart + ((j + 1) & 1) * nsk;
@@ -382,7 +392,7 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
         hipEvent_t stop;
         const bool timed = j < m;  // the extension pass has no product with A
         if (timed) HIP_TRY(timing_begin(ctx, 0, st, &stop));
-        HIP_TRY(launch_arnoldi_step(a, p->zeta, ly.L.block, st));
+        HIP_TRY(launch_arnoldi_step(a, p->zeta, ly.L.block, p->prec, st));
         if (timed) HIP_TRY(timing_end(stop, st));
     }
     // tail: the extension step's partials
@@ -513,7 +523,7 @@ const char* skfab_status_string(int32_t s) {
     switch (s) {
         case SKFAB_OK: return "ok";
         case SKFAB_ERR_ARG: return "invalid argument";
-        case SKFAB_ERR_SHAPE: return "invalid shape (need 1 <= k <= min(m,8), m < s <= min(N,1024), m <= 256)";
+        case SKFAB_ERR_SHAPE: return "invalid shape (need 1 <= k <= min(m,8), m < s <= min(N,1024), m <= 512)";
         case SKFAB_ERR_RANK: return "sketched basis numerically rank deficient";
         case SKFAB_ERR_BRANCH: return "projected matrix has an eigenvalue on the branch cut";
         case SKFAB_ERR_QUAD: return "adaptive quadrature did not converge";
@@ -586,7 +596,7 @@ skfab_status skfab_workspace_bytes(const skfab_csr* A, const skfab_params* p, si
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    *bytes = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true).total;
+    *bytes = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec).total;
     return SKFAB_OK;
 }
 
@@ -598,7 +608,7 @@ skfab_status skfab_solve(skfab_ctx* ctx, const skfab_csr* A, const double* b, do
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true);
+    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec);
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);
@@ -609,7 +619,7 @@ skfab_status skfab_solve(skfab_ctx* ctx, const skfab_csr* A, const double* b, do
     if (r != SKFAB_OK) return r;
     hipEvent_t stop;
     HIP_TRY(timing_begin(ctx, 1, st, &stop));
-    HIP_TRY(launch_assemble(w.U, ly.ldU, A->n, p->m, w.ctrl, w.ys, x, st));
+    HIP_TRY(launch_assemble(w.U, ly.ldU, A->n, p->m, w.ctrl, w.ys, x, p->prec, st));
     HIP_TRY(timing_end(stop, st));
     return read_info(w, st, info);
 }
@@ -623,7 +633,7 @@ skfab_status skfab_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, 
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true);
+    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec);
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);
@@ -631,7 +641,7 @@ skfab_status skfab_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, 
     skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st);
     if (r != SKFAB_OK) return r;
     const int m = p->m, s = p->s;
-    if (V) HIP_TRY(launch_normalize_basis(w.U, ly.ldU, A->n, m, w.ctrl, w.eta, V, st));
+    if (V) HIP_TRY(launch_normalize_basis(w.U, ly.ldU, A->n, m, w.ctrl, w.eta, V, p->prec, st));
     if (SV) HIP_TRY(hipMemcpyAsync(SV, w.SV, sizeof(double) * s * m, hipMemcpyDeviceToDevice, st));
     if (SAV) HIP_TRY(hipMemcpyAsync(SAV, w.SAV, sizeof(double) * s * m, hipMemcpyDeviceToDevice, st));
     if (H) HIP_TRY(hipMemcpyAsync(H, w.H, sizeof(double) * (m + 1) * m, hipMemcpyDeviceToDevice, st));
@@ -649,7 +659,7 @@ skfab_status skfab_small_workspace_bytes(const skfab_params* p, size_t* bytes) {
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    *bytes = make_layout(0, 0, p->m, p->s, l1, l2, lmax, p->npoly, false).total;
+    *bytes = make_layout(0, 0, p->m, p->s, l1, l2, lmax, p->npoly, false, 0).total;
     return SKFAB_OK;
 }
 
@@ -661,7 +671,7 @@ skfab_status skfab_small_problem(skfab_ctx* ctx, const double* SVext, const doub
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    const Layout ly = make_layout(0, 0, p->m, p->s, l1, l2, lmax, p->npoly, false);
+    const Layout ly = make_layout(0, 0, p->m, p->s, l1, l2, lmax, p->npoly, false, 0);
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);

@@ -109,19 +109,6 @@ __device__ bool step_coefficients(const double* red, int p, int k, int m, bool w
     return true;
 }
 
-// Reduce the [NSC][G] partial scalars of the previous step (fixed order).
-template <int KW, int BLOCK>
-__device__ void reduce_prev_scalars(const double* scal_prev, int G, double* red, double* scratch) {
-    constexpr int NSC = 2 * KW + 1;
-    for (int sc = 0; sc < NSC; ++sc) {
-        double v = 0.0;
-        for (int g = threadIdx.x; g < G; g += BLOCK) v += scal_prev[(int64_t)sc * G + g];
-        v = block_sum(v, scratch);
-        if (threadIdx.x == 0) red[sc] = v;
-    }
-    __syncthreads();
-}
-
 // Bins [c0, c1) of the reduction of step p's sketch partials (slots summed in
 // fixed order), one wavefront per bin; used only when a block owns more bins than
 // it has wavefronts.  Bin i < s goes to SV[:, p] (scale_v), bin s + i to SAV[:, p]
@@ -144,23 +131,20 @@ __device__ void reduce_prev_sketch_tail(const double* skp, int G, int s, int p, 
     }
 }
 
-// u_j at row/column c: alpha * base[c] + sum_o cf[o] U_o[c] (fixed fma order)
-template <int KW>
-__device__ __forceinline__ double form_u(const double* __restrict__ base, const double* const (&Uo)[KW],
-                                         double alpha, const double (&cf)[KW], int nwin, int64_t c) {
-    double x = alpha * base[c];
-#pragma unroll
-    for (int o = 0; o < KW; ++o)
-        if (o < nwin) x = fma(cf[o], Uo[o][c], x);
-    return x;
-}
-
 // ------------------------------------------------------------- step kernel
 // SELL entries per load batch (fewer for wide windows to bound register use)
 template <int KW> struct SellBatch { static constexpr int value = KW <= 2 ? 8 : (KW <= 4 ? 4 : 1); };
 
-template <int KW, int ZETA, int BLOCK>
+// P: storage/arithmetic policy (PrecF64, PrecF32, PrecBF16).  The basis u_j is
+// formed in the SpMV type W, rounded to the basis type V for storage, and the
+// rounded value is what enters the product with A, the sketch and the dots (so
+// the stored basis, its sketch and its image under A stay consistent).  Dot
+// products and sketch bins accumulate in FP64.
+template <int KW, int ZETA, int BLOCK, typename P>
 __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
+    using VT = typename P::V;
+    using WT = typename P::W;
+    using AT = typename P::A;
     extern __shared__ double bins[];  // [BLOCK/64][2s]
     __shared__ double red[NSC_MAX];
     __shared__ double coef[KMAX + 2];
@@ -236,11 +220,19 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
 #pragma unroll
     for (int o = 0; o < KW; ++o) cf[o] = coef[1 + o];
 
-    const double* __restrict__ base = (j == 0) ? a.b : a.Wprev;
-    const double* Uo[KW];
+    const WT* __restrict__ Wp = static_cast<const WT*>(a.Wprev);
+    const double* __restrict__ b0p = a.b;
+    const bool first = (j == 0);
+    const VT* Uo[KW];
 #pragma unroll
-    for (int o = 0; o < KW; ++o) Uo[o] = a.U + (int64_t)((o < nwin) ? (j - 1 - o) : 0) * a.ldU;
-    double* __restrict__ Uj = a.U + (int64_t)(a.extend ? 0 : j) * a.ldU;
+    for (int o = 0; o < KW; ++o) Uo[o] = static_cast<const VT*>(a.U) + (int64_t)((o < nwin) ? (j - 1 - o) : 0) * a.ldU;
+    VT* __restrict__ Uj = static_cast<VT*>(a.U) + (int64_t)(a.extend ? 0 : j) * a.ldU;
+    WT* __restrict__ Wc = static_cast<WT*>(a.Wcur);
+    const AT* __restrict__ slv = static_cast<const AT*>(a.sl_val);
+    const WT alpha_w = (WT)alpha;
+    WT cf_w[KW];
+#pragma unroll
+    for (int o = 0; o < KW; ++o) cf_w[o] = (WT)cf[o];
     double* binV = bins + wid * 2 * s;
     double* binAV = binV + s;
 
@@ -266,22 +258,24 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
     for (int64_t it = it0; it < it1; it += step) {
         const int64_t r = sell ? it * WAVE + lane : it;
         const bool valid = r < a.N;
-        double uo[KW];
-        double u = 0.0;
+        WT uo[KW];
+        WT u = (WT)0;
         if (valid) {
-            u = alpha * base[r];
+            u = alpha_w * (first ? (WT)b0p[r] : Wp[r]);
 #pragma unroll
             for (int o = 0; o < KW; ++o) {
-                uo[o] = (o < nwin) ? Uo[o][r] : 0.0;
-                if (o < nwin) u = fma(cf[o], uo[o], u);
+                uo[o] = (o < nwin) ? to_w<WT>(Uo[o][r]) : (WT)0;
+                if (o < nwin) u = fma(cf_w[o], uo[o], u);
             }
         } else {
 #pragma unroll
-            for (int o = 0; o < KW; ++o) uo[o] = 0.0;
+            for (int o = 0; o < KW; ++o) uo[o] = (WT)0;
         }
-        double w = 0.0;
+        const VT us = Store<VT>::put(u);
+        u = to_w<WT>(us);  // the stored value is the one used everywhere
+        WT w = (WT)0;
         if (!a.extend) {
-            if (valid) Uj[r] = u;
+            if (valid) Uj[r] = us;
             if (sell) {
                 // entries in batches of SB: all index and value loads of a batch, then all
                 // gathers, then the products -- one memory round trip per batch
@@ -290,53 +284,63 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
                 constexpr int SB = SellBatch<KW>::value;
                 for (int q0 = 0; q0 < len; q0 += SB) {
                     int cc[SB];
-                    double vv[SB], xb[SB], xu[SB][KW];
+                    WT vv[SB], xb[SB], xu[SB][KW];
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
                         const bool in = q0 + q < len;
                         cc[q] = in ? a.sl_col[e0 + (int64_t)(q0 + q) * WAVE] : 0;
-                        vv[q] = in ? a.sl_val[e0 + (int64_t)(q0 + q) * WAVE] : 0.0;
+                        vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
                     }
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
-                        xb[q] = base[cc[q]];
+                        xb[q] = first ? (WT)b0p[cc[q]] : Wp[cc[q]];
 #pragma unroll
-                        for (int o = 0; o < KW; ++o) xu[q][o] = (o < nwin) ? Uo[o][cc[q]] : 0.0;
+                        for (int o = 0; o < KW; ++o) xu[q][o] = (o < nwin) ? to_w<WT>(Uo[o][cc[q]]) : (WT)0;
                     }
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
-                        double x = alpha * xb[q];
+                        WT x = alpha_w * xb[q];
 #pragma unroll
                         for (int o = 0; o < KW; ++o)
-                            if (o < nwin) x = fma(cf[o], xu[q][o], x);
+                            if (o < nwin) x = fma(cf_w[o], xu[q][o], x);
+                        x = to_w<WT>(Store<VT>::put(x));
                         w = fma(vv[q], x, w);
                     }
                 }
             } else if (valid) {
                 const int e0 = a.rowptr[r], e1 = a.rowptr[r + 1];
-                for (int e = e0; e < e1; ++e) w = fma(a.val[e], form_u<KW>(base, Uo, alpha, cf, nwin, a.col[e]), w);
+                for (int e = e0; e < e1; ++e) {
+                    const int c = a.col[e];
+                    WT x = alpha_w * (first ? (WT)b0p[c] : Wp[c]);
+#pragma unroll
+                    for (int o = 0; o < KW; ++o)
+                        if (o < nwin) x = fma(cf_w[o], to_w<WT>(Uo[o][c]), x);
+                    x = to_w<WT>(Store<VT>::put(x));
+                    w = fma((WT)a.val[e], x, w);
+                }
             }
-            if (valid) a.Wcur[r] = w;
+            if (valid) Wc[r] = w;
         }
         if (valid) {
-            acc_uu = fma(u, u, acc_uu);
-            acc_uw = fma(u, w, acc_uw);
-            acc_ww = fma(w, w, acc_ww);
+            const double ud = (double)u, wd = (double)w;
+            acc_uu = fma(ud, ud, acc_uu);
+            acc_uw = fma(ud, wd, acc_uw);
+            acc_ww = fma(wd, wd, acc_ww);
 #pragma unroll
             for (int o = 0; o < KW - 1; ++o) {
                 if (o < ndot) {
-                    acc_lw[o] = fma(uo[o], w, acc_lw[o]);
-                    acc_ul[o] = fma(u, uo[o], acc_ul[o]);
+                    acc_lw[o] = fma((double)uo[o], wd, acc_lw[o]);
+                    acc_ul[o] = fma(ud, (double)uo[o], acc_ul[o]);
                 }
             }
             int rows[ZETA];
             double sg[ZETA];
             sketch_column<ZETA>(a.seed, (uint64_t)r, s, rows, sg);
 #pragma unroll
-            for (int q = 0; q < ZETA; ++q) lds_add(binV + rows[q], sg[q] * u);
+            for (int q = 0; q < ZETA; ++q) lds_add(binV + rows[q], sg[q] * ud);
             if (!a.extend) {
 #pragma unroll
-                for (int q = 0; q < ZETA; ++q) lds_add(binAV + rows[q], sg[q] * w);
+                for (int q = 0; q < ZETA; ++q) lds_add(binAV + rows[q], sg[q] * wd);
             }
         }
     }
@@ -441,13 +445,14 @@ __global__ __launch_bounds__(256) void arnoldi_check_finish_kernel(const double*
 }
 
 // V[:, j] = U[:, j] / eta_j (zero beyond m_used); test hook only.
-__global__ void normalize_basis_kernel(const double* U, int64_t ldU, int64_t N, int m,
+template <typename VT>
+__global__ void normalize_basis_kernel(const VT* U, int64_t ldU, int64_t N, int m,
                                        const DevCtrl* ctrl, const double* eta, double* V) {
     const int j = blockIdx.y;
     const int m_used = ctrl->m_used;
     const double sc = (j < m_used) ? 1.0 / eta[j] : 0.0;
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x)
-        V[(int64_t)j * N + r] = (j < m_used) ? U[(int64_t)j * ldU + r] * sc : 0.0;
+        V[(int64_t)j * N + r] = (j < m_used) ? to_w<double>(U[(int64_t)j * ldU + r]) * sc : 0.0;
 }
 
 // ------------------------------------------------------ SELL-64 conversion
@@ -524,10 +529,11 @@ __global__ __launch_bounds__(1024) void sell_scan_apply_kernel(const int32_t* sl
 }
 
 // interleaved copy; padding entries have value 0 and their own row as column
+template <typename AT>
 __global__ __launch_bounds__(256) void sell_fill_kernel(const int32_t* rowptr, const int32_t* col, const double* val,
                                                         int64_t N, int64_t nslices, const DevCtrl* ctrl,
                                                         const int64_t* sl_ptr, const int32_t* sl_len,
-                                                        int32_t* sl_col, double* sl_val) {
+                                                        int32_t* sl_col, AT* sl_val) {
     if (!ctrl->sell_ok) return;
     const int lane = threadIdx.x & 63;
     for (int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sl < nslices; sl += (int64_t)gridDim.x * 4) {
@@ -550,7 +556,7 @@ __global__ __launch_bounds__(256) void sell_fill_kernel(const int32_t* rowptr, c
             for (int q = 0; q < 8; ++q) {
                 if (q0 + q < len) {
                     sl_col[o + (int64_t)(q0 + q) * 64] = cb[q];
-                    sl_val[o + (int64_t)(q0 + q) * 64] = vb[q];
+                    sl_val[o + (int64_t)(q0 + q) * 64] = (AT)vb[q];
                 }
             }
         }
@@ -558,7 +564,7 @@ __global__ __launch_bounds__(256) void sell_fill_kernel(const int32_t* rowptr, c
 }
 
 // ---------------------------------------------------------------- launchers
-template <int KW, int ZETA>
+template <int KW, int ZETA, typename P>
 static hipError_t launch_step_t(const StepArgs& a, int block, hipStream_t st) {
     // the dynamic region holds the per-wave sketch bins, and in the prologue and
     // epilogue the scratch of the (2 KW + 1)-value block reduction
@@ -566,11 +572,11 @@ static hipError_t launch_step_t(const StepArgs& a, int block, hipStream_t st) {
     const size_t red = (size_t)(2 * KW + 1) * (block + 72);
     const size_t lds = (bins > red ? bins : red) * sizeof(double);
     if (block == 1024) {
-        hipLaunchKernelGGL((arnoldi_step_kernel<KW, ZETA, 1024>), dim3(a.G), dim3(1024), lds, st, a);
+        hipLaunchKernelGGL((arnoldi_step_kernel<KW, ZETA, 1024, P>), dim3(a.G), dim3(1024), lds, st, a);
     } else if (block == 512) {
-        hipLaunchKernelGGL((arnoldi_step_kernel<KW, ZETA, 512>), dim3(a.G), dim3(512), lds, st, a);
+        hipLaunchKernelGGL((arnoldi_step_kernel<KW, ZETA, 512, P>), dim3(a.G), dim3(512), lds, st, a);
     } else {
-        hipLaunchKernelGGL((arnoldi_step_kernel<KW, ZETA, 256>), dim3(a.G), dim3(256), lds, st, a);
+        hipLaunchKernelGGL((arnoldi_step_kernel<KW, ZETA, 256, P>), dim3(a.G), dim3(256), lds, st, a);
     }
     return hipGetLastError();
 }
@@ -578,15 +584,28 @@ static hipError_t launch_step_t(const StepArgs& a, int block, hipStream_t st) {
 template <int ZETA>
 static hipError_t launch_step_z(const StepArgs& a, int block, hipStream_t st) {
     switch (a.k) {
-        case 1: return launch_step_t<1, ZETA>(a, block, st);
-        case 2: return launch_step_t<2, ZETA>(a, block, st);
-        case 3: return launch_step_t<3, ZETA>(a, block, st);
-        case 4: return launch_step_t<4, ZETA>(a, block, st);
-        default: return launch_step_t<8, ZETA>(a, block, st);
+        case 1: return launch_step_t<1, ZETA, PrecF64>(a, block, st);
+        case 2: return launch_step_t<2, ZETA, PrecF64>(a, block, st);
+        case 3: return launch_step_t<3, ZETA, PrecF64>(a, block, st);
+        case 4: return launch_step_t<4, ZETA, PrecF64>(a, block, st);
+        default: return launch_step_t<8, ZETA, PrecF64>(a, block, st);
     }
 }
 
-hipError_t launch_arnoldi_step(const StepArgs& a, int zeta, int block, hipStream_t st) {
+// reduced precision: zeta = 8, k <= 4
+template <typename P>
+static hipError_t launch_step_p(const StepArgs& a, int block, hipStream_t st) {
+    switch (a.k) {
+        case 1: return launch_step_t<1, 8, P>(a, block, st);
+        case 2: return launch_step_t<2, 8, P>(a, block, st);
+        case 3: return launch_step_t<3, 8, P>(a, block, st);
+        default: return launch_step_t<4, 8, P>(a, block, st);
+    }
+}
+
+hipError_t launch_arnoldi_step(const StepArgs& a, int zeta, int block, int prec, hipStream_t st) {
+    if (prec == 1) return launch_step_p<PrecF32>(a, block, st);
+    if (prec == 2) return launch_step_p<PrecBF16>(a, block, st);
     switch (zeta) {
         case 2: return launch_step_z<2>(a, block, st);
         case 4: return launch_step_z<4>(a, block, st);
@@ -612,11 +631,19 @@ hipError_t launch_arnoldi_check(const double* SV, const double* SAV, const doubl
     return hipGetLastError();
 }
 
-hipError_t launch_normalize_basis(const double* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl,
-                                  const double* eta, double* V, hipStream_t st) {
+hipError_t launch_normalize_basis(const void* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl,
+                                  const double* eta, double* V, int prec, hipStream_t st) {
     int64_t gx64 = (N + 255) / 256;
     int gx = (int)(gx64 < 1024 ? gx64 : 1024);
-    hipLaunchKernelGGL(normalize_basis_kernel, dim3(gx, m), dim3(256), 0, st, U, ldU, N, m, ctrl, eta, V);
+    if (prec == 1)
+        hipLaunchKernelGGL(normalize_basis_kernel<float>, dim3(gx, m), dim3(256), 0, st, static_cast<const float*>(U),
+                           ldU, N, m, ctrl, eta, V);
+    else if (prec == 2)
+        hipLaunchKernelGGL(normalize_basis_kernel<bf16s>, dim3(gx, m), dim3(256), 0, st, static_cast<const bf16s*>(U),
+                           ldU, N, m, ctrl, eta, V);
+    else
+        hipLaunchKernelGGL(normalize_basis_kernel<double>, dim3(gx, m), dim3(256), 0, st,
+                           static_cast<const double*>(U), ldU, N, m, ctrl, eta, V);
     return hipGetLastError();
 }
 
@@ -624,7 +651,7 @@ int64_t sell_scan_blocks(int64_t nslices) { return (nslices + SCAN_CH - 1) / SCA
 
 hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const double* val, int64_t N,
                                int64_t nslices, int64_t capacity, DevCtrl* ctrl, int32_t* sl_len, int64_t* sl_ptr,
-                               int64_t* bsum, int32_t* sl_col, double* sl_val, hipStream_t st) {
+                               int64_t* bsum, int32_t* sl_col, void* sl_val, int prec, hipStream_t st) {
     const int64_t g64 = (nslices + 3) / 4;
     const unsigned g = (unsigned)(g64 < 65536 ? g64 : 65536);
     hipLaunchKernelGGL(sell_len_kernel, dim3(g), dim3(256), 0, st, rowptr, N, nslices, sl_len);
@@ -632,8 +659,12 @@ hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const 
     hipLaunchKernelGGL(sell_scan_sums_kernel, dim3((unsigned)nb), dim3(1024), 0, st, sl_len, nslices, bsum);
     hipLaunchKernelGGL(sell_scan_top_kernel, dim3(1), dim3(1024), 0, st, bsum, nb, capacity, ctrl);
     hipLaunchKernelGGL(sell_scan_apply_kernel, dim3((unsigned)nb), dim3(1024), 0, st, sl_len, nslices, bsum, sl_ptr);
-    hipLaunchKernelGGL(sell_fill_kernel, dim3(g), dim3(256), 0, st, rowptr, col, val, N, nslices, ctrl, sl_ptr,
-                       sl_len, sl_col, sl_val);
+    if (prec == 0)
+        hipLaunchKernelGGL(sell_fill_kernel<double>, dim3(g), dim3(256), 0, st, rowptr, col, val, N, nslices, ctrl,
+                           sl_ptr, sl_len, sl_col, static_cast<double*>(sl_val));
+    else
+        hipLaunchKernelGGL(sell_fill_kernel<float>, dim3(g), dim3(256), 0, st, rowptr, col, val, N, nslices, ctrl,
+                           sl_ptr, sl_len, sl_col, static_cast<float*>(sl_val));
     return hipGetLastError();
 }
 

@@ -8,9 +8,41 @@ namespace skfab {
 constexpr int WAVE = 64;
 constexpr int KMAX = 8;                 // largest truncation length of the fused step
 constexpr int NSC_MAX = 2 * KMAX + 1;   // partial scalars per Arnoldi step
-constexpr int MMAX = 256;               // largest Krylov dimension (register-resident small problem)
+constexpr int MMAX = 512;               // largest Krylov dimension
 constexpr int SMAX = 1024;              // largest sketch size
 constexpr double BREAKDOWN_TOL = 1e-14; // lucky-breakdown threshold on h_{j+1,j} / ||A v_j||
+
+// ------------------------------------------------------------ precisions
+// Storage/arithmetic policies of the Krylov recurrence:
+//   V = basis storage, W = SpMV arithmetic and A u storage, A = matrix values.
+struct bf16s { uint16_t bits; };
+
+__device__ __forceinline__ float bf16_to_f32(bf16s h) { return __uint_as_float((uint32_t)h.bits << 16); }
+__device__ __forceinline__ bf16s f32_to_bf16(float f) {  // round to nearest even
+    const uint32_t u = __float_as_uint(f);
+    const uint32_t r = u + 0x7FFFu + ((u >> 16) & 1u);
+    return bf16s{(uint16_t)(r >> 16)};
+}
+
+struct PrecF64 { using V = double; using W = double; using A = double; };
+struct PrecF32 { using V = float; using W = float; using A = float; };
+struct PrecBF16 { using V = bf16s; using W = float; using A = float; };
+
+template <typename W> __device__ __forceinline__ W to_w(double x) { return (W)x; }
+template <typename W> __device__ __forceinline__ W to_w(float x) { return (W)x; }
+template <typename W> __device__ __forceinline__ W to_w(bf16s x) { return (W)bf16_to_f32(x); }
+
+template <typename V> struct Store;
+template <> struct Store<double> {
+    __device__ static double put(double x) { return x; }
+};
+template <> struct Store<float> {
+    __device__ static float put(float x) { return x; }
+    __device__ static float put(double x) { return (float)x; }
+};
+template <> struct Store<bf16s> {
+    __device__ static bf16s put(float x) { return f32_to_bf16(x); }
+};
 
 // ---------------------------------------------------------------- sketch hash
 // SplitMix64 (Steele, Lea & Flood 2014): n-th output of the generator seeded with

@@ -39,14 +39,14 @@ struct StepArgs {
     const int64_t* sl_ptr;
     const int32_t* sl_len;
     const int32_t* sl_col;
-    const double* sl_val;
+    const void* sl_val;   // values in the precision's matrix type
     int64_t nslices;
     int64_t slices_per_chunk;
     int64_t rows_per_chunk;
     const double* b;
-    double* U;            // ldU x m, unnormalised basis u_j (v_j = u_j / eta_j)
-    double* Wcur;         // A u_j (this step)
-    const double* Wprev;  // A u_{j-1}
+    void* U;              // ldU x m, unnormalised basis u_j (v_j = u_j / eta_j), basis storage type
+    void* Wcur;           // A u_j (this step), SpMV type
+    const void* Wprev;    // A u_{j-1}
     const double* scal_prev;  // [NSC_MAX][G] partial scalars of step j-1
     double* scal_cur;         // [NSC_MAX][G] partial scalars of step j
     const double* skp_prev;   // [2s][G] partial sketches of step j-1 (bin-major, XCD slot order)

@@ -259,21 +259,22 @@ __global__ void pencil_setup_kernel(const double* X, int s, int m, int k, const 
 // The triangular factor is written row-major into Ubuf (mu x mu, ld = m) and read
 // back by the back substitution.  One wavefront; columns j = lane + 64 q.
 // Returns log|det| and the sign of det(P[:mu]) for the square case in *logdet / *sgn.
-constexpr int QMAX = MMAX / WAVE;
 
 // raw entries of row kk of T1 and K0, columns >= c0 (zero elsewhere); combined into
 // P(a) = a T1 + K0 only when the row is used, so the loads stay in flight
+template <int QM>
 struct PRow {
-    double t[QMAX], k[QMAX];
+    double t[QM], k[QM];
 };
 
-__device__ __forceinline__ void load_pencil_row(PRow& row, int kk, int c0, int mu, int m,
+template <int QM>
+__device__ __forceinline__ void load_pencil_row(PRow<QM>& row, int kk, int c0, int mu, int m,
                                                 const double* __restrict__ T1r, const double* __restrict__ K0r) {
     const int lane = threadIdx.x & 63;
     const double* t1 = T1r + (int64_t)kk * m;
     const double* k0 = K0r + (int64_t)kk * m;
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
+    for (int q = 0; q < QM; ++q) {
         const int jj = lane + WAVE * q;
         const bool in = jj >= c0 && jj < mu;
         row.t[q] = in ? t1[jj] : 0.0;
@@ -281,26 +282,28 @@ __device__ __forceinline__ void load_pencil_row(PRow& row, int kk, int c0, int m
     }
 }
 
-__device__ __forceinline__ void combine_row(double (&row)[QMAX], const PRow& r, double a) {
+template <int QM>
+__device__ __forceinline__ void combine_row(double (&row)[QM], const PRow<QM>& r, double a) {
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) row[q] = fma(a, r.t[q], r.k[q]);
+    for (int q = 0; q < QM; ++q) row[q] = fma(a, r.t[q], r.k[q]);
 }
 
-constexpr int PF = 4;  // rows of the pencil in flight ahead of the elimination
 
 // value of the distributed vector v at index i (wave-uniform i)
-__device__ __forceinline__ double dist_get(const double (&v)[QMAX], int i) {
+template <int QM>
+__device__ __forceinline__ double dist_get(const double (&v)[QM], int i) {
     double t = 0.0;
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q)
+    for (int q = 0; q < QM; ++q)
         if (q == i / WAVE) t = v[q];
     return bcast_lane(t, i % WAVE);
 }
 
-__device__ __forceinline__ void dist_set(double (&v)[QMAX], int i, double x) {
+template <int QM>
+__device__ __forceinline__ void dist_set(double (&v)[QM], int i, double x) {
     const int lane = threadIdx.x & 63;
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q)
+    for (int q = 0; q < QM; ++q)
         if (q == i / WAVE && lane == i % WAVE) v[q] = x;
 }
 
@@ -314,19 +317,20 @@ __device__ __forceinline__ void dist_set(double (&v)[QMAX], int i, double x) {
 // column by the (reduction-free) back substitution.  With DET the sign of
 // det(P[:mu]) is returned in *sgn (row swaps times the signs of the pivots) and
 // the pivots are left on the diagonal of Ucol for the caller.
-template <bool LS, bool DET>
+template <bool LS, bool DET, int QM>
 __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restrict__ T1r,
                                   const double* __restrict__ K0r, double rhs0, double* __restrict__ Ucol,
                                   double* __restrict__ unused, double* __restrict__ y, double* logdet, double* sgn) {
     (void)unused;
     const int lane = threadIdx.x & 63;
-    double carry[QMAX], next[QMAX];
-    PRow pref[PF];
-    double rv[QMAX], ud[QMAX];
+    constexpr int PF = QM <= 4 ? 4 : 2;  // rows of the pencil in flight ahead of the elimination
+    double carry[QM], next[QM];
+    PRow<QM> pref[PF];
+    double rv[QM], ud[QM];
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) { rv[q] = 0.0; ud[q] = 1.0; }
+    for (int q = 0; q < QM; ++q) { rv[q] = 0.0; ud[q] = 1.0; }
     {
-        PRow r0;
+        PRow<QM> r0;
         load_pencil_row(r0, 0, 0, mu, m, T1r, K0r);
         combine_row(carry, r0, a);
     }
@@ -349,14 +353,14 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
         if (!LS) {
             if (fabs(nk) > fabs(pk)) {
 #pragma unroll
-                for (int q = 0; q < QMAX; ++q) { const double t = carry[q]; carry[q] = next[q]; next[q] = t; }
+                for (int q = 0; q < QM; ++q) { const double t = carry[q]; carry[q] = next[q]; next[q] = t; }
                 rn = rc; rc = 0.0;
                 const double tp = pk; pk = nk; nk = tp;
                 if (DET) sg = -sg;
             }
             const double l = (pk != 0.0) ? nk / pk : 0.0;
 #pragma unroll
-            for (int q = 0; q < QMAX; ++q) {
+            for (int q = 0; q < QM; ++q) {
                 const int jj = lane + WAVE * q;
                 if (jj >= kk && jj < mu) ucol[(int64_t)jj * m] = carry[q];
                 next[q] = fma(-l, carry[q], next[q]);
@@ -370,7 +374,7 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
             const double c = (r != 0.0) ? pk * rinv : 1.0;
             const double sn = nk * rinv;
 #pragma unroll
-            for (int q = 0; q < QMAX; ++q) {
+            for (int q = 0; q < QM; ++q) {
                 const int jj = lane + WAVE * q;
                 const double top = fma(c, carry[q], sn * next[q]);
                 const double bot = fma(-sn, carry[q], c * next[q]);
@@ -382,7 +386,7 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
             rn = -sn * rc;
         }
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) carry[q] = next[q];
+        for (int q = 0; q < QM; ++q) carry[q] = next[q];
         rc = rn;
     }
     if (!LS) {
@@ -396,26 +400,26 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
     if (DET) {
         double neg = 0.0;
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q)
+        for (int q = 0; q < QM; ++q)
             if (lane + WAVE * q < mu && ud[q] < 0.0) neg += 1.0;
         neg = wave_sum_fast(neg);
         if (((int)neg) & 1) sg = -sg;
     }
     // reciprocals of the diagonal, all at once
-    double dinv[QMAX];
+    double dinv[QM];
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) dinv[q] = (lane + WAVE * q < mu) ? 1.0 / ud[q] : 0.0;
+    for (int q = 0; q < QM; ++q) dinv[q] = (lane + WAVE * q < mu) ? 1.0 / ud[q] : 0.0;
     __threadfence_block();  // Ucol written by this wave becomes visible to all of its lanes
     // column-oriented back substitution: y_k = r_k / U_kk, then r_i -= U_ik y_k (i < k)
-    constexpr int BF = 4;  // columns of U in flight
-    double yv[QMAX], cbuf[BF][QMAX];
+    constexpr int BF = QM <= 4 ? 4 : 2;  // columns of U in flight
+    double yv[QM], cbuf[BF][QM];
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) yv[q] = 0.0;
+    for (int q = 0; q < QM; ++q) yv[q] = 0.0;
 #pragma unroll
     for (int f = 0; f < BF; ++f) {
         const int col = mu - 1 - f;
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
+        for (int q = 0; q < QM; ++q) {
             const int i = lane + WAVE * q;
             cbuf[f][q] = (col >= 0 && i < col) ? Ucol[(int64_t)col * m + i] : 0.0;
         }
@@ -424,23 +428,23 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
         const double yk = dist_get(rv, kk) * dist_get(dinv, kk);
         dist_set(yv, kk, yk);
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
+        for (int q = 0; q < QM; ++q) {
             const int i = lane + WAVE * q;
             if (i < kk) rv[q] = fma(-cbuf[0][q], yk, rv[q]);
         }
 #pragma unroll
         for (int f = 0; f + 1 < BF; ++f)
 #pragma unroll
-            for (int q = 0; q < QMAX; ++q) cbuf[f][q] = cbuf[f + 1][q];
+            for (int q = 0; q < QM; ++q) cbuf[f][q] = cbuf[f + 1][q];
         const int col = kk - BF;
 #pragma unroll
-        for (int q = 0; q < QMAX; ++q) {
+        for (int q = 0; q < QM; ++q) {
             const int i = lane + WAVE * q;
             cbuf[BF - 1][q] = (col >= 0 && i < col) ? Ucol[(int64_t)col * m + i] : 0.0;
         }
     }
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
+    for (int q = 0; q < QM; ++q) {
         const int jj = lane + WAVE * q;
         if (jj < mu) y[jj] = yv[q];
     }
@@ -451,6 +455,7 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
 // Node 0 (a = 0): log|det P[:mu]| and its sign (square case), the spectral scale
 // sigma = |det H_hat|^(1/mu) = exp((log|det K0[:mu]| - sum log|R_jj|)/mu), rcond of
 // R, the branch check for z^(-1/2), and -- for f = 1/z -- the solution itself.
+template <int QM>
 __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, const double* X, const DevCtrl* ctrl_c,
                                                                   DevCtrl* ctrl, const double* eta,
                                                                   const double* T1r, const double* K0r,
@@ -461,14 +466,14 @@ __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, 
     const int lane = threadIdx.x;
     // R diagonal statistics
     double lr = 0.0, rmin = 1e308, rmax = 0.0, rs = 1.0;
-    double dg[QMAX];
+    double dg[QM];
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
+    for (int q = 0; q < QM; ++q) {
         const int j = lane + 64 * q;
         dg[q] = (j < mu) ? X[j + (int64_t)s * j] : 1.0;
     }
 #pragma unroll
-    for (int q = 0; q < QMAX; ++q) {
+    for (int q = 0; q < QM; ++q) {
         if (lane + 64 * q < mu) {
             const double d = dg[q];
             lr += log(fabs(d));
@@ -487,9 +492,9 @@ __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, 
     const double rhs0 = beta * X[0];
     double ld = 0.0, sg = 1.0;
     if (is_ls) {
-        pencil_solve_wave<true, false>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, nullptr, nullptr);
+        pencil_solve_wave<true, false, QM>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, nullptr, nullptr);
     } else {
-        pencil_solve_wave<false, true>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, nullptr, &sg);
+        pencil_solve_wave<false, true, QM>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, nullptr, &sg);
         // log|det| = sum log|U_kk| (sg already holds the sign: row swaps and pivot signs)
         double lu = 0.0;
         for (int kk = lane; kk < mu; kk += 64) lu += log(fabs(Ubuf[(int64_t)kk * m + kk]));
@@ -518,6 +523,7 @@ __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, 
 // One launch evaluates every node of a group of consecutive orders (the nodes
 // are independent, Section 5.3); the reduction then applies the acceptance test
 // of Section 4.1 to the orders in sequence.
+template <int QM>
 __global__ __launch_bounds__(256) void quad_level_kernel(const DevCtrl* ctrl, QuadGroup grp, const double* T1r,
                                                          const double* K0r, double* Ubuf, double* Urhs,
                                                          double* nodebuf, int m, int is_ls, const double* X,
@@ -541,9 +547,9 @@ __global__ __launch_bounds__(256) void quad_level_kernel(const DevCtrl* ctrl, Qu
         const double w = (2.0 / l) / (1.0 + x);
         double* yi = nodebuf + (int64_t)i * m;
         if (is_ls)
-            pencil_solve_wave<true, false>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
+            pencil_solve_wave<true, false, QM>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
         else
-            pencil_solve_wave<false, false>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
+            pencil_solve_wave<false, false, QM>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
     }
 }
 
@@ -681,8 +687,10 @@ __global__ __launch_bounds__(256) void finish_coeffs_kernel(DevCtrl* ctrl, int m
     }
 }
 
-// x = U ys (N x mu times mu), rows parallel, coalesced over the basis columns.
-__global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict__ U, int64_t ldU, int64_t N, int m,
+// x = U ys (N x mu times mu), rows parallel, coalesced over the basis columns; the
+// basis is read in its storage type and accumulated in FP64.
+template <typename VT>
+__global__ __launch_bounds__(256) void assemble_kernel(const VT* __restrict__ U, int64_t ldU, int64_t N, int m,
                                                        const DevCtrl* ctrl, const double* __restrict__ ys,
                                                        double* __restrict__ x) {
     __shared__ double c[MMAX];
@@ -693,12 +701,12 @@ __global__ __launch_bounds__(256) void assemble_kernel(const double* __restrict_
         double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
         int j = 0;
         for (; j + 3 < mu; j += 4) {
-            a0 = fma(U[r + ldU * j], c[j], a0);
-            a1 = fma(U[r + ldU * (j + 1)], c[j + 1], a1);
-            a2 = fma(U[r + ldU * (j + 2)], c[j + 2], a2);
-            a3 = fma(U[r + ldU * (j + 3)], c[j + 3], a3);
+            a0 = fma(to_w<double>(U[r + ldU * j]), c[j], a0);
+            a1 = fma(to_w<double>(U[r + ldU * (j + 1)]), c[j + 1], a1);
+            a2 = fma(to_w<double>(U[r + ldU * (j + 2)]), c[j + 2], a2);
+            a3 = fma(to_w<double>(U[r + ldU * (j + 3)]), c[j + 3], a3);
         }
-        for (; j < mu; ++j) a0 = fma(U[r + ldU * j], c[j], a0);
+        for (; j < mu; ++j) a0 = fma(to_w<double>(U[r + ldU * j]), c[j], a0);
         x[r] = (a0 + a1) + (a2 + a3);
     }
 }
@@ -742,8 +750,12 @@ hipError_t launch_pencil_setup(const double* X, int s, int m, int k, const DevCt
 hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, const double* eta,
                                  const double* T1r, const double* K0r, double* Ubuf, double* Urhs, double* y0,
                                  int is_ls, int branch_check, hipStream_t st) {
-    hipLaunchKernelGGL(pencil_setup_scalars_kernel, dim3(1), dim3(64), 0, st, m, s, X, ctrl, ctrl, eta, T1r, K0r,
-                       Ubuf, Urhs, y0, is_ls, branch_check);
+    if (m <= 256)
+        hipLaunchKernelGGL(pencil_setup_scalars_kernel<4>, dim3(1), dim3(64), 0, st, m, s, X, ctrl, ctrl, eta, T1r,
+                           K0r, Ubuf, Urhs, y0, is_ls, branch_check);
+    else
+        hipLaunchKernelGGL(pencil_setup_scalars_kernel<8>, dim3(1), dim3(64), 0, st, m, s, X, ctrl, ctrl, eta, T1r,
+                           K0r, Ubuf, Urhs, y0, is_ls, branch_check);
     return hipGetLastError();
 }
 
@@ -752,8 +764,12 @@ hipError_t launch_quad_group(const DevCtrl* ctrl, const QuadGroup& g, const doub
                              const double* eta, hipStream_t st) {
     const int waves = g.total < NODE_SLOTS ? g.total : NODE_SLOTS;
     const int blocks = (waves + 3) / 4;
-    hipLaunchKernelGGL(quad_level_kernel, dim3(blocks), dim3(256), 0, st, ctrl, g, T1r, K0r, Ubuf, Urhs, nodebuf, m,
-                       is_ls, X, eta);
+    if (m <= 256)
+        hipLaunchKernelGGL(quad_level_kernel<4>, dim3(blocks), dim3(256), 0, st, ctrl, g, T1r, K0r, Ubuf, Urhs,
+                           nodebuf, m, is_ls, X, eta);
+    else
+        hipLaunchKernelGGL(quad_level_kernel<8>, dim3(blocks), dim3(256), 0, st, ctrl, g, T1r, K0r, Ubuf, Urhs,
+                           nodebuf, m, is_ls, X, eta);
     return hipGetLastError();
 }
 
@@ -781,11 +797,19 @@ hipError_t launch_finish_coeffs(DevCtrl* ctrl, int m, const double* y, const dou
     return hipGetLastError();
 }
 
-hipError_t launch_assemble(const double* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl, const double* ys,
-                           double* x, hipStream_t st) {
+hipError_t launch_assemble(const void* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl, const double* ys,
+                           double* x, int prec, hipStream_t st) {
     int64_t g = (N + 255) / 256;
-    hipLaunchKernelGGL(assemble_kernel, dim3((unsigned)(g < 8192 ? g : 8192)), dim3(256), 0, st, U, ldU, N, m, ctrl,
-                       ys, x);
+    const dim3 grid((unsigned)(g < 8192 ? g : 8192));
+    if (prec == 1)
+        hipLaunchKernelGGL(assemble_kernel<float>, grid, dim3(256), 0, st, static_cast<const float*>(U), ldU, N, m,
+                           ctrl, ys, x);
+    else if (prec == 2)
+        hipLaunchKernelGGL(assemble_kernel<bf16s>, grid, dim3(256), 0, st, static_cast<const bf16s*>(U), ldU, N, m,
+                           ctrl, ys, x);
+    else
+        hipLaunchKernelGGL(assemble_kernel<double>, grid, dim3(256), 0, st, static_cast<const double*>(U), ldU, N, m,
+                           ctrl, ys, x);
     return hipGetLastError();
 }
 

@@ -16,6 +16,7 @@ from . import _native as N
 
 FUNCS = {"invsqrt": N.SKFAB_F_INVSQRT, "exp": N.SKFAB_F_EXP, "inv": N.SKFAB_F_INV, "poly": N.SKFAB_F_POLY}
 METHODS = {"sfom": N.SKFAB_SFOM_CLOSED, "sfom_quad": N.SKFAB_SFOM_QUAD, "sgmres": N.SKFAB_SGMRES_QUAD}
+PRECS = {"fp64": N.SKFAB_PREC_FP64, "fp32": N.SKFAB_PREC_FP32, "bf16basis": N.SKFAB_PREC_FP32_BF16BASIS}
 
 
 class SkfabError(RuntimeError):
@@ -69,14 +70,14 @@ class CSR:
 
 
 def make_params(f="invsqrt", m=50, k=2, s=200, zeta=8, seed=0, method="sfom", fparam=0.0, poly=None,
-                l1=32, l2=45, lmax=1395, quad_tol=1e-13) -> N.skfab_params:
+                l1=32, l2=45, lmax=1395, quad_tol=1e-13, prec="fp64") -> N.skfab_params:
     p = N.skfab_params()
     p.f = FUNCS[f] if isinstance(f, str) else int(f)
     p.fparam = float(fparam)
     p.method = METHODS[method] if isinstance(method, str) else int(method)
     p.m, p.k, p.s, p.zeta, p.seed = int(m), int(k), int(s), int(zeta), int(seed)
     p.l1, p.l2, p.lmax, p.quad_tol = int(l1), int(l2), int(lmax), float(quad_tol)
-    p.prec = N.SKFAB_PREC_FP64
+    p.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
     if poly is not None:
         arr = (C.c_double * len(poly))(*[float(c) for c in poly])
         p.poly = C.cast(arr, C.POINTER(C.c_double))

@@ -61,7 +61,9 @@ def test_workspace_sizes_grow_with_problem():
     (dict(m=200, s=200), N.SKFAB_ERR_SHAPE),   # m < s violated
     (dict(k=0), N.SKFAB_ERR_SHAPE),
     (dict(k=9, m=50), N.SKFAB_ERR_SHAPE),      # k above the fused-kernel limit
-    (dict(m=300, s=600), N.SKFAB_ERR_SHAPE),   # m above the small-problem limit
+    (dict(m=600, s=1000), N.SKFAB_ERR_SHAPE),  # m above the small-problem limit
+    (dict(prec=1, k=8, m=50), N.SKFAB_ERR_ARG),  # reduced precision needs k <= 4
+    (dict(prec=3), N.SKFAB_ERR_ARG),
     (dict(s=2000), N.SKFAB_ERR_SHAPE),
     (dict(zeta=3), N.SKFAB_ERR_SHAPE),
     (dict(f=7), N.SKFAB_ERR_ARG),
