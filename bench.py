@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--workload", default="convdiff3d_n128_m200")
     ap.add_argument("--f", default="invsqrt", choices=["invsqrt", "inv"])
     ap.add_argument("--method", default="sfom", choices=["sfom", "sfom_quad", "sgmres"])
+    ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16basis"],
+                    help="storage/arithmetic of A, the basis and the SpMV (small problem and assembly stay FP64)")
     ap.add_argument("--no-parity", action="store_true", help="skip the full-size oracle comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=30)
@@ -69,11 +71,45 @@ def copy_calibration(gib: float):
                       "copy_gbs": round(16 * n / dt / 1e9, 1)}), flush=True)
 
 
-def step_kernel_bytes(N: int, nnz: int, k: int) -> int:
-    """Algorithmic HBM bytes of one fused Arnoldi step (FP64, int32 indices, implicit sketch):
-    A once (8 nnz values + 4 nnz columns + 4 (N+1) row pointers), the k window vectors and
-    A u_{j-1} read once (8 (k+1) N), u_j and A u_j written once (16 N)."""
-    return 12 * nnz + 4 * (N + 1) + 8 * (k + 1) * N + 16 * N
+# bytes per element of (A values, basis vectors u_j, products A u_j) per precision form
+PREC_BYTES = {"fp64": (8, 8, 8), "fp32": (4, 4, 4), "bf16basis": (4, 2, 4)}
+PREC_DTYPE = {"fp64": "f64", "fp32": "f32", "bf16basis": "bf16+f32"}
+
+
+def step_kernel_bytes(N: int, nnz: int, k: int, prec: str = "fp64") -> int:
+    """Algorithmic HBM bytes of one fused Arnoldi step (int32 indices, implicit sketch):
+    A once (nnz values + 4 nnz columns + 4 (N+1) row pointers), the k window vectors and
+    A u_{j-1} read once, u_j and A u_j written once.  FP64: 12 nnz + 4(N+1) + 8(k+1)N + 16N."""
+    ab, vb, wb = PREC_BYTES[prec]
+    return (ab + 4) * nnz + 4 * (N + 1) + (k * vb + wb) * N + (vb + wb) * N
+
+
+KERNEL_SOURCES = ("paper_2208_11447_amd/csrc/arnoldi.hip", "paper_2208_11447_amd/csrc/common.hpp",
+                  "paper_2208_11447_amd/csrc/device_state.hpp", "paper_2208_11447_amd/csrc/api.cpp")
+
+
+def recorded_traffic(workload: str, prec: str):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary of this workload (each counter scaled by its reading for a plain device copy of
+    known size), or None when there is no summary or the step kernel's sources (or its launch
+    code) have changed since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"arnoldi_step_{workload}_{prec}_hbm_counters.txt")
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    with open(path) as fh:
+        for line in fh:
+            if not line.startswith("#") and ":" in line:
+                key, val = line.split(":", 1)
+                fields[key.strip()] = val.strip()
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    if fields.get("source_sha256") != h.hexdigest():
+        return None
+    return int(fields["traffic_bytes_per_launch"])
 
 
 def cpu_baseline(cfg, arrays, b, sample_steps):
@@ -172,11 +208,11 @@ def main():
     bd = torch.as_tensor(b, device=dev)
     x = torch.empty_like(bd)
     p = sk.make_params(f=args.f, m=cfg["m"], k=cfg["k"], s=cfg["s"], zeta=cfg["zeta"], seed=cfg["sketch_seed"],
-                       method=args.method, quad_tol=1e-13)
+                       method=args.method, quad_tol=1e-13, prec=args.prec)
     ws = sk.alloc_workspace(sk.skfab_workspace_bytes(A, p), device=dev)
     ctx = sk.Context(0)
     print(f"# workload {args.workload}: N={N} nnz={nnz} m={cfg['m']} k={cfg['k']} s={cfg['s']} "
-          f"f={args.f} method={args.method}", file=sys.stderr, flush=True)
+          f"f={args.f} method={args.method} prec={args.prec}", file=sys.stderr, flush=True)
 
     info = sk.skfab_solve(ctx, A, bd, x, p, ws)
     if info.status != 0:
@@ -203,13 +239,13 @@ def main():
         ms_asm, n_asm = sk.skfab_timing_read(ctx, 1)
         sk.skfab_timing_enable(ctx, False)
         per_launch_s = ms_step / 1e3 / max(n_step, 1)
-        nbytes = step_kernel_bytes(N, nnz, cfg["k"])
+        nbytes = step_kernel_bytes(N, nnz, cfg["k"], args.prec)
         achieved = nbytes / per_launch_s / 1e9
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(args.workload, args.prec),
                 "kernel": "arnoldi_step_kernel", "bytes_per_launch": nbytes,
                 "mean_launch_us": round(per_launch_s * 1e6, 2), "launches": n_step,
-                "assembly_gbs": round((8 * N * cfg["m"] + 8 * N) / (ms_asm / 1e3 / max(n_asm, 1)) / 1e9, 1)
+                "assembly_gbs": round((PREC_BYTES[args.prec][1] * N * cfg["m"] + 8 * N) / (ms_asm / 1e3 / max(n_asm, 1)) / 1e9, 1)
                 if n_asm else None}
     x_host = x.cpu().numpy()
     print(f"# timed {args.steps} solves in {elapsed:.3f} s; m_used={info.m_used} l_used={info.l_used} "
@@ -220,7 +256,7 @@ def main():
     if not args.no_parity:
         t = time.perf_counter()
         err = oracle_parity(cfg, (rp, col, val), b, x_host, args.f, args.method)
-        parity = {"rel_err_vs_oracle": err, "tol": 1e-10, "oracle_seconds": round(time.perf_counter() - t, 1)}
+        parity = {"rel_err_vs_oracle": err, "tol": 1e-10 if args.prec == "fp64" else None, "oracle_seconds": round(time.perf_counter() - t, 1)}
         print(f"# parity vs oracle: {err:.3e}", file=sys.stderr, flush=True)
     cpu = None
     if not args.no_cpu_baseline:
@@ -240,11 +276,12 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": PREC_DTYPE[args.prec],
         "data": "synthetic",
-        "config": {"workload": f"{args.workload}_{args.f}_{args.method}", "grid": f"{cfg['n']}^{cfg['dim']}",
+        "config": {"workload": f"{args.workload}_{args.f}_{args.method}"
+                   + ("" if args.prec == "fp64" else f"_{args.prec}"), "grid": f"{cfg['n']}^{cfg['dim']}",
                    "N": N, "nnz": nnz, "m": cfg["m"], "k": cfg["k"], "s": cfg["s"], "zeta": cfg["zeta"],
-                   "f": args.f, "method": args.method, "parallelism": "single-gpu"},
+                   "f": args.f, "method": args.method, "prec": args.prec, "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
