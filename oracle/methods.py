@@ -125,17 +125,30 @@ def sfom_closed(arn: ArnoldiResult, f: str, fparam: float = 0.0, poly=None) -> S
                        info=dict(rcond_R=1.0 / np.linalg.cond(w.R)))
 
 
+# Rounding floor of the adaptive test (a reading, not in the paper): when the
+# requested tolerance lies below what the node solves can resolve, the relative
+# differences of consecutive orders stop falling at some small level; an order
+# whose difference is below QUAD_FLOOR and larger than half the previous
+# difference is then accepted instead of refining up to l_max.
+QUAD_FLOOR = 1e-10
+
+
 def _adaptive(eval_rule, tol: float, l1: int, l2: int, lmax: int):
-    """Adaptive order loop of Section 4.1 (relative test ||q1-q2|| <= tol ||q2||)."""
+    """Adaptive order loop of Section 4.1 (relative test ||q1-q2|| <= tol ||q2||),
+    with the rounding-floor acceptance described at QUAD_FLOOR."""
     q1 = eval_rule(l1)
     q2 = eval_rule(l2)
-    while np.linalg.norm(q1 - q2) > tol * np.linalg.norm(q2):
+    d_prev = np.inf
+    while True:
+        n2 = np.linalg.norm(q2)
+        d = np.linalg.norm(q1 - q2) / n2 if n2 > 0 else (0.0 if np.linalg.norm(q1) == 0 else np.inf)
+        if d <= tol or (d <= QUAD_FLOOR and d > 0.5 * d_prev):
+            return q2, l2
         nxt = quad.next_order(l2)
         if nxt > lmax:
             raise QuadratureError(f"no convergence up to l = {l2}")
-        q1, l1, l2 = q2, l2, nxt
+        q1, l1, l2, d_prev = q2, l2, nxt, d
         q2 = eval_rule(l2)
-    return q2, l2
 
 
 def sfom_quad(arn: ArnoldiResult, f: str = "invsqrt", tol: float = 1e-13,

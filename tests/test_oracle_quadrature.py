@@ -53,3 +53,48 @@ def test_rule_is_integral_of_measure():
     z = 2.7
     exact, _ = squad(lambda t: 1.0 / ((t + z) * np.sqrt(t) * np.pi), 0, np.inf, limit=200)
     assert abs(quad.scalar_invsqrt_rule(np.array([z]), 63)[0] - exact) < 1e-9
+
+
+def _rule_from_diffs(diffs):
+    """eval_rule whose consecutive results differ (relatively) by the given amounts,
+    indexed by the order sequence 32, 45, 63, ..."""
+    orders = [32]
+    while len(orders) < len(diffs) + 1:
+        orders.append(quad.next_order(orders[-1]))
+    vals = {orders[0]: np.array([1.0, 0.0])}
+    for l_prev, l, d in zip(orders, orders[1:], diffs):
+        vals[l] = vals[l_prev] + np.array([0.0, d])   # ||q_l - q_prev|| / ||q_l|| ~ d
+    return lambda l: vals[l], orders
+
+
+def test_adaptive_accepts_at_tolerance():
+    from oracle.methods import _adaptive
+    rule, orders = _rule_from_diffs([1e-2, 1e-5, 1e-9, 1e-14, 1e-15])
+    _, l = _adaptive(rule, 1e-13, 32, 45, 10_000)
+    assert l == orders[4]          # first difference below 1e-13
+
+
+def test_adaptive_accepts_at_rounding_floor():
+    """Differences stop falling at 3e-13 (above tol = 1e-13): the order where the
+    decrease stops (d > d_prev / 2, d <= 1e-10) is accepted."""
+    from oracle.methods import QUAD_FLOOR, _adaptive
+    rule, orders = _rule_from_diffs([1e-2, 1e-5, 1e-9, 4e-13, 3e-13, 5e-13, 2e-13])
+    _, l = _adaptive(rule, 1e-13, 32, 45, 10_000)
+    assert l == orders[5]
+    assert 3e-13 <= QUAD_FLOOR
+
+
+def test_adaptive_no_floor_acceptance_above_floor():
+    """A stagnation above the floor is a failure, not convergence."""
+    from oracle.methods import QuadratureError, _adaptive
+    rule, orders = _rule_from_diffs([1e-2, 1e-5, 1e-6, 1e-6, 1e-6, 1e-6])
+    with pytest.raises(QuadratureError):
+        _adaptive(rule, 1e-13, 32, 45, orders[-1])
+
+
+def test_adaptive_fast_decrease_is_not_stagnation():
+    """Below the floor but still falling faster than 2x per order: keep refining."""
+    from oracle.methods import _adaptive
+    rule, orders = _rule_from_diffs([1e-2, 1e-6, 1e-11, 1e-12, 9e-14])
+    _, l = _adaptive(rule, 1e-13, 32, 45, 10_000)
+    assert l == orders[5]
