@@ -40,7 +40,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="convdiff3d_n128_m200")
+    ap.add_argument("--workload", default="convdiff3d_n128_m200",
+                    help="a single-problem workload, or 'batch64x4' for the batched form (64 problems x 4 rhs)")
+    ap.add_argument("--nprob", type=int, default=64, help="problems of the batched workload")
+    ap.add_argument("--no-autotune", action="store_true", help="batched form: keep the default launch shape")
+    ap.add_argument("--tuning", default=None, metavar="BLOCK,SPW",
+                    help="batched form: fixed launch shape (threads per block, slices per wavefront)")
     ap.add_argument("--f", default="invsqrt", choices=["invsqrt", "inv"])
     ap.add_argument("--method", default="sfom", choices=["sfom", "sfom_quad", "sgmres"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16basis"],
@@ -181,6 +186,136 @@ def oracle_parity(cfg, arrays, b, x_gpu, f, method):
     return float(np.linalg.norm(x_gpu - xr) / np.linalg.norm(xr))
 
 
+def batch_step_bytes(Ns, nnzs, ms, R, k, prec):
+    """Algorithmic bytes of every step launch of a batched solve, summed: in step j
+    each problem with m_p >= j reads A once for its R right-hand sides (its blocks
+    share it through L2) and each pair moves its own vectors (as step_kernel_bytes)."""
+    ab, vb, wb = PREC_BYTES[prec]
+    total = 0
+    for N, nnz, m in zip(Ns, nnzs, ms):
+        a_bytes = (ab + 4) * nnz + 4 * (N + 1)
+        vec = (k * vb + wb) * N + (vb + wb) * N
+        total += m * (a_bytes + R * vec)   # steps j = 0 .. m-1 (the extension pass has no product)
+    return total
+
+
+def run_batched(args):
+    """The batched form: 64 2D convection-diffusion problems (grids 256^2..1024^2,
+    convection U[10, 200], m U{80..250}, s = 2m, k = 2), 4 right-hand sides each,
+    one skfab_solve_batched call per step of the benchmark."""
+    import numpy as np
+    import torch
+
+    from paper_2208_11447_amd import skfab as sk
+    from workloads import batched_problem_params, convdiff_csr
+
+    R = 4
+    params = batched_problem_params(args.nprob)
+    probs, hosts = [], []
+    t0 = time.perf_counter()
+    for i, q in enumerate(params):
+        rp, col, val = convdiff_csr(q["n"], 2, 1.0, q["c"])
+        N = rp.size - 1
+        B = np.random.default_rng(q["rhs_seedseq"]).standard_normal((R, N))
+        A = sk.CSR.from_numpy(rp, col, val)
+        Bt = torch.as_tensor(B, device="cuda")
+        probs.append(sk.BatchProblem(A, Bt, torch.empty_like(Bt), m=q["m"], s=q["s"], seed=q["sketch_seed"]))
+        hosts.append((rp, col, val, B))
+        if i % 16 == 15:
+            print(f"# generated {i + 1} problems ({time.perf_counter() - t0:.0f} s)", file=sys.stderr, flush=True)
+    Ns = [q.A.n for q in probs]
+    nnzs = [q.A.col.numel() for q in probs]
+    ms = [q.m for q in probs]
+    p = sk.make_params(f=args.f, k=2, zeta=8, method=args.method, quad_tol=1e-13, prec=args.prec)
+    nbytes = sk.skfab_batch_workspace_bytes(probs, p)
+    ws = sk.alloc_workspace(nbytes)
+    ctx = sk.Context(0)
+    print(f"# batch: {len(probs)} problems x {R} rhs, N {min(Ns)}..{max(Ns)} (sum {sum(Ns)}), m {min(ms)}..{max(ms)}, "
+          f"workspace {nbytes / 2**30:.1f} GiB, prec {args.prec}", file=sys.stderr, flush=True)
+    tuning = None
+    if args.tuning:
+        blk, spw = (int(v) for v in args.tuning.split(","))
+        sk.skfab_batch_set_tuning(ctx, blk, spw)
+        tuning = (blk, spw)
+    elif not args.no_autotune:
+        t = time.perf_counter()
+        tuning = sk.skfab_batch_autotune(ctx, probs, p, ws, steps=4)
+        print(f"# autotuned launch shape: block {tuning[0]}, {tuning[1]} slices per wavefront "
+              f"({time.perf_counter() - t:.1f} s)", file=sys.stderr, flush=True)
+    info = sk.skfab_solve_batched(ctx, probs, p, ws)
+    bad = [(i, r, info[i][r].status) for i in range(len(probs)) for r in range(R) if info[i][r].status != 0]
+    for _ in range(args.warmup):
+        sk.skfab_solve_batched(ctx, probs, p, ws, want_info=False)
+    torch.cuda.synchronize()
+    sk.skfab_timing_enable(ctx, True)
+    sk.skfab_timing_read(ctx, 0)
+    sk.skfab_timing_read(ctx, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        sk.skfab_solve_batched(ctx, probs, p, ws, want_info=False)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms_step, n_step = sk.skfab_timing_read(ctx, 0)
+    ms_asm, n_asm = sk.skfab_timing_read(ctx, 1)
+    sk.skfab_timing_enable(ctx, False)
+    step_bytes = batch_step_bytes(Ns, nnzs, ms, R, 2, args.prec) * args.steps
+    achieved = step_bytes / (ms_step / 1e3) / 1e9
+    asm_bytes = sum(R * (PREC_BYTES[args.prec][1] * N * m + 8 * N) for N, m in zip(Ns, ms)) * n_asm
+    print(f"# timed {args.steps} batches in {elapsed:.3f} s; {len(bad)} pairs with a nonzero status {bad[:4]}",
+          file=sys.stderr, flush=True)
+    # parity on a bounded sample: the two smallest problems, first right-hand side
+    parity = None
+    if not args.no_parity:
+        from oracle import arnoldi as oarn
+        from oracle import methods as ometh
+        from oracle import sketch as osk
+        import scipy.sparse as sp
+        errs = []
+        for i in np.argsort(Ns)[:2]:
+            rp, col, val, B = hosts[i]
+            N = rp.size - 1
+            A = sp.csr_matrix((val, col, rp), shape=(N, N))
+            S = osk.sparse_sign_matrix(N, probs[i].s, 8, probs[i].seed)
+            arn = oarn.truncated_arnoldi(A, B[0], probs[i].m, 2, S)
+            xr = ometh.sfom_closed(arn, args.f).x if args.method == "sfom" else ometh.sgmres(arn, args.f,
+                                                                                             tol=1e-13).x
+            xg = probs[i].X[0].cpu().numpy()
+            errs.append(float(np.linalg.norm(xg - xr) / np.linalg.norm(xr)))
+        parity = {"rel_err_vs_oracle_max": max(errs), "sample": "problems with the two smallest N, rhs 0",
+                  "tol": 1e-10 if args.prec == "fp64" else None}
+        print(f"# parity vs oracle (sample): {errs}", file=sys.stderr, flush=True)
+    solves = len(probs) * R
+    out = {
+        "metric": "f(A)b solves/s and SpMV+sketch HBM GB/s at rel. err 1e-8 vs FP64 oracle",
+        "value": round(solves * args.steps / elapsed, 3),
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": PREC_DTYPE[args.prec],
+        "data": "synthetic",
+        "config": {"workload": f"batch{len(probs)}x{R}_convdiff2d_{args.f}_{args.method}"
+                   + ("" if args.prec == "fp64" else f"_{args.prec}"),
+                   "problems": len(probs), "rhs_per_problem": R, "solves_per_step": solves,
+                   "N_range": [min(Ns), max(Ns)], "N_sum": sum(Ns), "m_range": [min(ms), max(ms)], "k": 2,
+                   "s": "2m", "zeta": 8, "prec": args.prec, "tuning": tuning, "parallelism": "single-gpu"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "arnoldi_step_batched_kernel", "bytes_per_batch": step_bytes // args.steps,
+                     "launches": n_step, "step_ms_per_batch": round(ms_step / args.steps, 3),
+                     "assembly_gbs": round(asm_bytes / (ms_asm / 1e3) / 1e9, 1) if n_asm else None},
+        "cpu_baseline": None,
+        "parity": parity,
+        "nonzero_status_pairs": len(bad),
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration > 0:
@@ -188,8 +323,7 @@ def main():
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path "
-              "(the sharded design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py runs on one GPU only: there is no multi-GPU path", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -198,6 +332,9 @@ def main():
     from paper_2208_11447_amd import skfab as sk
     from workloads import config, convdiff_csr, gaussian_rhs
 
+    if args.workload == "batch64x4":
+        run_batched(args)
+        return
     cfg = config(args.workload)
     rp, col, val = convdiff_csr(cfg["n"], cfg["dim"], cfg["diffusion"], cfg["convection"])
     N = rp.size - 1

@@ -232,6 +232,59 @@ skfab_status skfab_timing_enable(skfab_ctx *ctx, int32_t enable);
 skfab_status skfab_timing_read(skfab_ctx *ctx, int32_t kernel, double *total_ms,
                                int64_t *launches);
 
+/* ---------------------------------------------------------------- batches
+ * Many independent problems, each with several right-hand sides, solved together:
+ * one launch per Arnoldi step covers every (problem, right-hand side) pair whose
+ * Krylov dimension has not been reached (the method of Algorithm 1/2 applied to
+ * each pair independently; each pair has its own basis and sketches, and the
+ * right-hand sides of one problem share its sketch S and its copy of A). */
+typedef struct skfab_batch_problem {
+    skfab_csr A;            /* device CSR, FP64 values                               */
+    const double *B;        /* device, N x nrhs column-major (column r at B + r N)   */
+    double *X;              /* device, N x nrhs column-major: the results            */
+    int32_t m;              /* Krylov dimension of this problem, 1 <= m <= 512       */
+    int32_t s;              /* sketch size, m < s <= min(N, 1024)                    */
+    uint64_t seed;          /* seed of this problem's sketch S                       */
+} skfab_batch_problem;
+
+/* Launch shape of the batched step kernel: threads per block (256, 512, 1024) and
+ * the target number of 64-row SELL slices per wavefront (sets the blocks per
+ * (problem, right-hand side) pair, a multiple of 8 and at most 256). */
+typedef struct skfab_batch_tuning {
+    int32_t block;
+    int32_t slices_per_wave;
+} skfab_batch_tuning;
+
+/* Device workspace bytes of skfab_solve_batched / skfab_batch_autotune (host only;
+ * independent of the tuning).  p supplies f, method, k, zeta, prec and the
+ * quadrature parameters; p->m and p->s are ignored (per problem instead).
+ * Errors: SKFAB_ERR_ARG (nprob outside 1..4096, nrhs outside 1..4, f other than
+ * z^(-1/2) or 1/z, zeta != 8, k outside 1..4), SKFAB_ERR_SHAPE (a problem's sizes). */
+skfab_status skfab_batch_workspace_bytes(int32_t nprob, const skfab_batch_problem *probs,
+                                         int32_t nrhs, const skfab_params *p, size_t *bytes);
+
+/* X_p[:, r] <- approximation of f(A_p) B_p[:, r] for every problem p and column r
+ * (same method and parameters as skfab_solve).  ws: device workspace of at least
+ * skfab_batch_workspace_bytes, 256-byte aligned.  info: optional host array of
+ * nprob * nrhs entries (pair (p, r) at p * nrhs + r); if non-NULL the call
+ * synchronises.  The per-problem arrays in `probs` are read on the host during the
+ * call only.  Asynchronous otherwise, on the context's stream. */
+skfab_status skfab_solve_batched(skfab_ctx *ctx, int32_t nprob, const skfab_batch_problem *probs,
+                                 int32_t nrhs, const skfab_params *p, void *ws, size_t ws_bytes,
+                                 skfab_info *info);
+
+/* Set / read the context's launch shape for batched solves. */
+skfab_status skfab_batch_set_tuning(skfab_ctx *ctx, const skfab_batch_tuning *t);
+skfab_status skfab_batch_get_tuning(skfab_ctx *ctx, skfab_batch_tuning *t);
+
+/* Autotuner: times the batched step kernel on this batch for every candidate
+ * shape (block 256/512/1024 x 1/2/4/.../64 slices per wavefront) over `steps` Arnoldi
+ * steps (after an untimed first step), keeps the fastest in the context and
+ * returns it in *chosen (may be NULL).  Overwrites the workspace; synchronises. */
+skfab_status skfab_batch_autotune(skfab_ctx *ctx, int32_t nprob, const skfab_batch_problem *probs,
+                                  int32_t nrhs, const skfab_params *p, void *ws, size_t ws_bytes,
+                                  int32_t steps, skfab_batch_tuning *chosen);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,8 @@ EXPORTED = [
     "skfab_workspace_bytes", "skfab_solve", "skfab_arnoldi", "skfab_small_problem",
     "skfab_small_workspace_bytes", "skfab_sketch_pattern", "skfab_sketch_apply", "skfab_sketch_ws_bytes",
     "skfab_timing_enable", "skfab_timing_read",
+    "skfab_batch_workspace_bytes", "skfab_solve_batched", "skfab_batch_set_tuning", "skfab_batch_get_tuning",
+    "skfab_batch_autotune",
 ]
 
 
@@ -43,6 +45,15 @@ class skfab_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("m_used", C.c_int32), ("l_used", C.c_int32),
                 ("reserved", C.c_int32), ("eps_est", C.c_double), ("rcond_R", C.c_double),
                 ("sigma", C.c_double), ("beta", C.c_double), ("arnoldi_relres", C.c_double)]
+
+
+class skfab_batch_problem(C.Structure):
+    _fields_ = [("A", skfab_csr), ("B", C.c_void_p), ("X", C.c_void_p), ("m", C.c_int32), ("s", C.c_int32),
+                ("seed", C.c_uint64)]
+
+
+class skfab_batch_tuning(C.Structure):
+    _fields_ = [("block", C.c_int32), ("slices_per_wave", C.c_int32)]
 
 
 _lib = None
@@ -77,6 +88,15 @@ def lib():
         "skfab_sketch_ws_bytes": (C.c_size_t, [C.c_int64, C.c_int32]),
         "skfab_timing_enable": (C.c_int, [P, C.c_int32]),
         "skfab_timing_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+        "skfab_batch_workspace_bytes": (C.c_int, [C.c_int32, C.POINTER(skfab_batch_problem), C.c_int32,
+                                                  C.POINTER(skfab_params), C.POINTER(C.c_size_t)]),
+        "skfab_solve_batched": (C.c_int, [P, C.c_int32, C.POINTER(skfab_batch_problem), C.c_int32,
+                                          C.POINTER(skfab_params), P, C.c_size_t, C.POINTER(skfab_info)]),
+        "skfab_batch_set_tuning": (C.c_int, [P, C.POINTER(skfab_batch_tuning)]),
+        "skfab_batch_get_tuning": (C.c_int, [P, C.POINTER(skfab_batch_tuning)]),
+        "skfab_batch_autotune": (C.c_int, [P, C.c_int32, C.POINTER(skfab_batch_problem), C.c_int32,
+                                           C.POINTER(skfab_params), P, C.c_size_t, C.c_int32,
+                                           C.POINTER(skfab_batch_tuning)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

@@ -1,6 +1,7 @@
 // C ABI of libskfab: validation, workspace layout and the launch sequence.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -32,12 +33,15 @@ hipError_t launch_init_ctrl(DevCtrl* c, int m, hipStream_t st);
 hipError_t launch_qr(double* X, int s, int ncols_max, const DevCtrl* ctrl, double* Tws, hipStream_t st);
 hipError_t launch_pencil_setup(const double* X, int s, int m, int k, const DevCtrl* ctrl, const double* H,
                                double* K0r, double* T1r, hipStream_t st);
+hipError_t launch_hhat_rows(const DevCtrl* ctrl, int m, int s, const double* X, const double* T1r, const double* H,
+                            double* Hh, hipStream_t st);
+hipError_t launch_hhat_rows_batched(const SmallUnit* units, int nunits, int m, int s, hipStream_t st);
 hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, const double* eta,
-                                 const double* T1r, const double* K0r, double* Ubuf, double* Urhs, double* y0,
-                                 int is_ls, int branch_check, hipStream_t st);
+                                 const double* T1r, const double* K0r, const double* Hh, double* Ubuf, double* Urhs,
+                                 double* y0, int is_ls, int branch_check, hipStream_t st);
 hipError_t launch_quad_group(const DevCtrl* ctrl, const QuadGroup& g, const double* T1r, const double* K0r,
-                             double* Ubuf, double* Urhs, double* nodebuf, int m, int is_ls, const double* X,
-                             const double* eta, hipStream_t st);
+                             const double* Hh, double* Ubuf, double* Urhs, double* nodebuf, int m, int is_ls,
+                             const double* X, const double* eta, hipStream_t st);
 hipError_t launch_quad_reduce(DevCtrl* ctrl, const QuadGroup& g, const double* nodebuf, int m, double tol,
                               const double* T1r, double* qprev, double* y, hipStream_t st);
 hipError_t launch_quad_fail(DevCtrl* ctrl, hipStream_t st);
@@ -57,6 +61,25 @@ hipError_t launch_lu(DevCtrl* ctrl, int m, double* Q, int* piv, hipStream_t st);
 hipError_t launch_lu_solve_cols(const DevCtrl* ctrl, int m, const double* LU, const int* piv, double* P,
                                 hipStream_t st);
 hipError_t launch_first_column(const DevCtrl* ctrl, const double* X, const double* eta, double* y, hipStream_t st);
+hipError_t launch_arnoldi_step_batched(const BatchStepUnit* units, const int* base, int nact, int R, int j, int k,
+                                       int grid, int block, int smax, int prec, hipStream_t st);
+hipError_t launch_arnoldi_tail_batched(const BatchStepUnit* units, const SmallUnit* small, int nunits, int smax,
+                                       int mmax, hipStream_t st);
+hipError_t launch_arnoldi_check_batched(const SmallUnit* small, int nunits, int smax, int mmax, int k,
+                                        hipStream_t st);
+hipError_t launch_init_ctrl_batched(const SmallUnit* units, int nunits, hipStream_t st);
+hipError_t launch_qr_batched(const SmallUnit* units, int nunits, int s, int ncols_max, hipStream_t st);
+hipError_t launch_pencil_setup_batched(const SmallUnit* units, int nunits, int s, int m, int k, hipStream_t st);
+hipError_t launch_pencil_scalars_batched(const SmallUnit* units, int nunits, int m, int s, int is_ls, int branch_check,
+                                         hipStream_t st);
+hipError_t launch_quad_group_batched(const SmallUnit* units, int nunits, const QuadGroup& g, int m, int is_ls,
+                                     int slots, hipStream_t st);
+hipError_t launch_quad_reduce_batched(const SmallUnit* units, int nunits, const QuadGroup& g, int m, double tol,
+                                      hipStream_t st);
+hipError_t launch_quad_fail_batched(const SmallUnit* units, int nunits, hipStream_t st);
+hipError_t launch_finish_coeffs_batched(const SmallUnit* units, int nunits, int m, hipStream_t st);
+hipError_t launch_assemble_batched(const SmallUnit* units, int nunits, int64_t nmax, int m, int prec,
+                                   hipStream_t st);
 constexpr int QR_NB_HOST = 16;
 constexpr int NODE_SLOTS_HOST = 1024;
 }  // namespace skfab
@@ -72,6 +95,11 @@ struct skfab_ctx {
     size_t used[2] = {0, 0};
     double acc_ms[2] = {0.0, 0.0};
     int64_t count[2] = {0, 0};
+    // batched solves: launch shape of the step kernel, and the host copy of the
+    // unit descriptors (kept alive until the next batched call has synchronised)
+    int batch_block = 1024;
+    int batch_spw = 1;
+    std::vector<char> batch_host;
 };
 
 namespace {
@@ -161,7 +189,7 @@ Launch step_launch(int64_t N, int s) {
 }
 
 struct Layout {
-    size_t ctrl, eta, wnorm, H, gram, colnorm2, scal, U, W, skpart, SV, SAV, Tws, K0r, T1r, Ubuf, Urhs, nodebuf,
+    size_t ctrl, eta, wnorm, H, gram, colnorm2, scal, U, W, skpart, SV, SAV, Tws, K0r, T1r, Hh, Ubuf, Urhs, nodebuf,
         qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, chk, sl_len, sl_ptr, bsum, sl_col, sl_val, total;
     int64_t ldU;
     int64_t sell_capacity;
@@ -248,6 +276,7 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
     ly.Tws = take((size_t)QR_NB_HOST * QR_NB_HOST * d);
     ly.K0r = take((size_t)(m + 1) * m * d);
     ly.T1r = take((size_t)(m + 1) * m * d);
+    ly.Hh = take((size_t)m * m * d);
     ly.Ubuf = take((size_t)NODE_SLOTS_HOST * m * m * d);
     ly.Urhs = take((size_t)NODE_SLOTS_HOST * m * d);
     ly.nodebuf = take((size_t)ly.lnodes * m * d);
@@ -267,7 +296,7 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
 struct Ptrs {
     DevCtrl* ctrl;
     void *U, *W;
-    double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Ubuf, *Urhs,
+    double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Hh, *Ubuf, *Urhs,
         *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1, *chk;
     void* sl_val;
     int* piv;
@@ -282,7 +311,8 @@ Ptrs carve(void* ws, const Layout& ly) {
     auto D = [&](size_t o) { return reinterpret_cast<double*>(b + o); };
     p.eta = D(ly.eta); p.wnorm = D(ly.wnorm); p.H = D(ly.H); p.gram = D(ly.gram); p.colnorm2 = D(ly.colnorm2);
     p.scal = D(ly.scal); p.U = b + ly.U; p.W = b + ly.W; p.skpart = D(ly.skpart); p.SV = D(ly.SV); p.SAV = D(ly.SAV);
-    p.Tws = D(ly.Tws); p.K0r = D(ly.K0r); p.T1r = D(ly.T1r); p.Ubuf = D(ly.Ubuf); p.Urhs = D(ly.Urhs);
+    p.Tws = D(ly.Tws); p.K0r = D(ly.K0r); p.T1r = D(ly.T1r); p.Hh = D(ly.Hh); p.Ubuf = D(ly.Ubuf);
+    p.Urhs = D(ly.Urhs);
     p.nodebuf = D(ly.nodebuf); p.qprev = D(ly.qprev); p.qcur = D(ly.qcur); p.y = D(ly.y); p.ys = D(ly.ys);
     p.y0 = D(ly.y0); p.poly = D(ly.poly); p.expbuf = D(ly.expbuf); p.norm1 = D(ly.norm1);
     p.piv = reinterpret_cast<int*>(b + ly.piv);
@@ -367,6 +397,9 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
     a.SV = w.SV;
     a.SAV = w.SAV;
     a.ctrl = w.ctrl;
+    a.sctrl = w.ctrl;
+    a.ldS = s;
+    a.ldH = m + 1;
     a.eta = w.eta;
     a.wnorm = w.wnorm;
     a.H = w.H;
@@ -466,11 +499,15 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     HIP_TRY(launch_arnoldi_check(w.SV, w.SAV, w.H, s, m, p->k, w.ctrl, w.chk, st));
     HIP_TRY(launch_qr(w.SV, s, m + 1, w.ctrl, w.Tws, st));
     HIP_TRY(launch_pencil_setup(w.SV, s, m, p->k, w.ctrl, w.H, w.K0r, w.T1r, st));
+    HIP_TRY(launch_hhat_rows(w.ctrl, m, s, w.SV, w.T1r, w.H, w.Hh, st));
     const int branch = (p->f == SKFAB_F_INVSQRT && !ls) ? 1 : 0;
-    // square pencil at t = 0: sigma, rcond, branch check; for 1/z with sFOM also the solution
-    HIP_TRY(launch_pencil_scalars(m, s, w.SV, w.ctrl, w.eta, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.y0, 0, branch, st));
+    // square system at t = 0: sigma, rcond, branch check; for 1/z with sFOM also the solution
+    HIP_TRY(launch_pencil_scalars(m, s, w.SV, w.ctrl, w.eta, w.T1r, w.K0r, w.Hh, w.Ubuf, w.Urhs, w.y0, 0, branch,
+                                  st));
     if (p->f == SKFAB_F_INV) {
-        if (ls) HIP_TRY(launch_pencil_scalars(m, s, w.SV, w.ctrl, w.eta, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.y0, 1, 0, st));
+        if (ls)
+            HIP_TRY(launch_pencil_scalars(m, s, w.SV, w.ctrl, w.eta, w.T1r, w.K0r, w.Hh, w.Ubuf, w.Urhs, w.y0, 1, 0,
+                                          st));
         HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
         return SKFAB_OK;
     }
@@ -488,7 +525,8 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     }
     // z^(-1/2): adaptive Gauss-Chebyshev (Section 4.1 / 5.1), orders evaluated in groups
     for (const QuadGroup& g : quad_groups(l1, l2, lmax)) {
-        HIP_TRY(launch_quad_group(w.ctrl, g, w.T1r, w.K0r, w.Ubuf, w.Urhs, w.nodebuf, m, ls ? 1 : 0, w.SV, w.eta, st));
+        HIP_TRY(launch_quad_group(w.ctrl, g, w.T1r, w.K0r, w.Hh, w.Ubuf, w.Urhs, w.nodebuf, m, ls ? 1 : 0, w.SV,
+                                  w.eta, st));
         HIP_TRY(launch_quad_reduce(w.ctrl, g, w.nodebuf, m, tol, w.T1r, w.qprev, w.y0, st));
     }
     HIP_TRY(launch_quad_fail(w.ctrl, st));
@@ -716,6 +754,475 @@ skfab_status skfab_sketch_apply(skfab_ctx* ctx, int64_t n, int32_t s, int32_t ze
     if (!ws || ws_bytes < skfab_sketch_ws_bytes(n, s)) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     HIP_TRY(launch_sketch_apply(n, s, zeta, seed, v, Sv, static_cast<double*>(ws), ctx->stream));
+    return SKFAB_OK;
+}
+
+}  // extern "C"
+
+// ===================================================================== batch
+namespace {
+
+constexpr int BATCH_MAX_PROBLEMS = 4096;
+constexpr int BATCH_MAX_RHS = 4;
+constexpr int BATCH_GMAX = 256;     // step-kernel blocks per (problem, rhs) at most
+constexpr int BATCH_SLOTS = 128;    // quadrature scratch slots per unit
+
+struct BatchProbLayout {
+    int64_t N, nnz, ldU, nslices, capacity;
+    size_t sl_len, sl_ptr, bsum, sl_col, sl_val;
+};
+
+struct BatchUnitLayout {
+    size_t U, W, scal, skp, small, ubuf, nodebuf;
+};
+
+struct BatchLayout {
+    int nprob, R, nunits, mmax, smax, lnodes;
+    int64_t nmax;
+    std::vector<int> order;            // problems by decreasing m (stable)
+    std::vector<BatchProbLayout> prob; // indexed by original problem
+    std::vector<BatchUnitLayout> unit; // indexed by sorted position * R + r
+    size_t ctrl, steps, smalls, base;  // ctrl array, descriptor arrays, base[nprob+1]
+    size_t small_begin, small_end;     // contiguous per-unit small region (zero-filled per call)
+    size_t small_bytes;                // bytes of one unit's small block
+    // offsets inside one unit's small block
+    size_t o_eta, o_wnorm, o_H, o_gram, o_colnorm2, o_chk, o_SV, o_SAV, o_Tws, o_K0r, o_T1r, o_Hh, o_Urhs, o_qprev, o_y,
+        o_ys, o_y0;
+    size_t total;
+};
+
+skfab_status validate_batch(int32_t nprob, const skfab_batch_problem* probs, int32_t nrhs, const skfab_params* p,
+                            bool need_data) {
+    if (!probs || !p || nprob < 1 || nprob > BATCH_MAX_PROBLEMS) return SKFAB_ERR_ARG;
+    if (nrhs < 1 || nrhs > BATCH_MAX_RHS) return SKFAB_ERR_ARG;
+    if (p->f != SKFAB_F_INVSQRT && p->f != SKFAB_F_INV) return SKFAB_ERR_ARG;
+    if (p->method < 0 || p->method > 2) return SKFAB_ERR_ARG;
+    if (p->prec < SKFAB_PREC_FP64 || p->prec > SKFAB_PREC_FP32_BF16BASIS) return SKFAB_ERR_ARG;
+    if (p->zeta != 8 || p->k < 1 || p->k > 4) return SKFAB_ERR_ARG;
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    if (l1 < 1 || l2 <= l1 || lmax < l2) return SKFAB_ERR_ARG;
+    for (int i = 0; i < nprob; ++i) {
+        const skfab_batch_problem& q = probs[i];
+        if (need_data && (!q.A.rowptr || !q.A.col || !q.A.val || !q.B || !q.X)) return SKFAB_ERR_ARG;
+        if (q.A.val_type != SKFAB_VAL_F64) return SKFAB_ERR_ARG;
+        if (q.A.n <= 0 || q.A.nnz < 0 || q.A.nnz > INT32_MAX) return SKFAB_ERR_SHAPE;
+        if (q.m < 1 || q.m > MMAX) return SKFAB_ERR_SHAPE;
+        if (p->k > q.m) return SKFAB_ERR_SHAPE;
+        if (q.s <= q.m || q.s > SMAX || q.s > q.A.n) return SKFAB_ERR_SHAPE;
+    }
+    return SKFAB_OK;
+}
+
+BatchLayout make_batch_layout(int32_t nprob, const skfab_batch_problem* probs, int32_t R, const skfab_params* p) {
+    BatchLayout L;
+    L.nprob = nprob;
+    L.R = R;
+    L.nunits = nprob * R;
+    L.mmax = 0;
+    L.smax = 0;
+    L.nmax = 0;
+    for (int i = 0; i < nprob; ++i) {
+        L.mmax = probs[i].m > L.mmax ? probs[i].m : L.mmax;
+        L.smax = probs[i].s > L.smax ? probs[i].s : L.smax;
+        L.nmax = probs[i].A.n > L.nmax ? probs[i].A.n : L.nmax;
+    }
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    L.lnodes = max_level_nodes(l1, l2, lmax);
+    L.order.resize(nprob);
+    for (int i = 0; i < nprob; ++i) L.order[i] = i;
+    std::stable_sort(L.order.begin(), L.order.end(), [&](int a, int b) { return probs[a].m > probs[b].m; });
+    const size_t d = sizeof(double);
+    const int mmax = L.mmax, smax = L.smax;
+    // one unit's small block
+    size_t o = 0;
+    auto sub = [&](size_t bytes) { size_t r = o; o = align_up(o + bytes); return r; };
+    L.o_eta = sub((mmax + 2) * d);
+    L.o_wnorm = sub((mmax + 2) * d);
+    L.o_H = sub((size_t)(mmax + 1) * mmax * d);
+    L.o_gram = sub((size_t)(mmax + 1) * KMAX * d);
+    L.o_colnorm2 = sub((mmax + 1) * d);
+    L.o_chk = sub((size_t)2 * mmax * d);
+    L.o_SV = sub((size_t)smax * (mmax + 1) * d);
+    L.o_SAV = sub((size_t)smax * mmax * d);
+    L.o_Tws = sub((size_t)QR_NB_HOST * QR_NB_HOST * d);
+    L.o_K0r = sub((size_t)(mmax + 1) * mmax * d);
+    L.o_T1r = sub((size_t)(mmax + 1) * mmax * d);
+    L.o_Hh = sub((size_t)mmax * mmax * d);
+    L.o_Urhs = sub((size_t)BATCH_SLOTS * mmax * d);
+    L.o_qprev = sub(mmax * d);
+    L.o_y = sub(mmax * d);
+    L.o_ys = sub(mmax * d);
+    L.o_y0 = sub(mmax * d);
+    L.small_bytes = o;
+
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t r = off; off = align_up(off + bytes); return r; };
+    L.ctrl = take((size_t)L.nunits * sizeof(DevCtrl));
+    L.steps = take((size_t)L.nunits * sizeof(BatchStepUnit));
+    L.smalls = take((size_t)L.nunits * sizeof(SmallUnit));
+    L.base = take((size_t)(nprob + 1) * sizeof(int));
+    L.prob.resize(nprob);
+    for (int i = 0; i < nprob; ++i) {
+        BatchProbLayout& q = L.prob[i];
+        q.N = probs[i].A.n;
+        q.nnz = probs[i].A.nnz;
+        q.ldU = (q.N + 63) / 64 * 64;
+        q.nslices = (q.N + 63) / 64;
+        q.capacity = q.nnz + q.nnz / 4 + 64 * q.nslices;
+        q.sl_len = take((size_t)q.nslices * sizeof(int32_t));
+        q.sl_ptr = take((size_t)q.nslices * sizeof(int64_t));
+        q.bsum = take((size_t)sell_scan_blocks(q.nslices) * sizeof(int64_t));
+        q.sl_col = take((size_t)q.capacity * sizeof(int32_t));
+        q.sl_val = take((size_t)q.capacity * wbytes(p->prec));
+    }
+    L.unit.resize(L.nunits);
+    for (int qi = 0; qi < nprob; ++qi) {
+        const int pi = L.order[qi];
+        const BatchProbLayout& q = L.prob[pi];
+        for (int r = 0; r < R; ++r) {
+            BatchUnitLayout& u = L.unit[qi * R + r];
+            u.U = take((size_t)q.ldU * probs[pi].m * vbytes(p->prec));
+            u.W = take((size_t)2 * q.ldU * wbytes(p->prec));
+            u.scal = take((size_t)2 * NSC_MAX * BATCH_GMAX * d);
+            u.skp = take((size_t)2 * BATCH_GMAX * 2 * probs[pi].s * d);
+        }
+    }
+    L.small_begin = off;
+    for (int u = 0; u < L.nunits; ++u) L.unit[u].small = take(L.small_bytes);
+    L.small_end = off;
+    for (int u = 0; u < L.nunits; ++u) {
+        L.unit[u].ubuf = take((size_t)BATCH_SLOTS * mmax * mmax * d);
+        L.unit[u].nodebuf = take((size_t)L.lnodes * mmax * d);
+    }
+    L.total = off;
+    return L;
+}
+
+// Step-kernel blocks of a problem with `nslices` SELL slices: about `spw` slices per
+// wavefront, a multiple of 8 (whole XCD groups), at most BATCH_GMAX.
+int batch_blocks(int64_t nslices, int block, int spw) {
+    const int64_t per_block = (int64_t)(block / WAVE) * spw;
+    int64_t G = (nslices + per_block - 1) / per_block;
+    if (G > BATCH_GMAX) G = BATCH_GMAX;
+    G = (G + 7) / 8 * 8;
+    return (int)G;
+}
+
+struct BatchPlan {
+    std::vector<int> G;     // by sorted position
+    std::vector<int> base;  // [nprob + 1], sorted order
+};
+
+BatchPlan batch_plan(const BatchLayout& L, int block, int spw) {
+    BatchPlan P;
+    P.G.resize(L.nprob);
+    P.base.resize(L.nprob + 1);
+    P.base[0] = 0;
+    for (int qi = 0; qi < L.nprob; ++qi) {
+        P.G[qi] = batch_blocks(L.prob[L.order[qi]].nslices, block, spw);
+        P.base[qi + 1] = P.base[qi] + L.R * P.G[qi];
+    }
+    return P;
+}
+
+// Host images of the unit descriptors and the base table, for a launch plan.
+void batch_descriptors(const BatchLayout& L, const BatchPlan& P, const skfab_batch_problem* probs,
+                       const skfab_params* p, char* dev, std::vector<char>& host) {
+    host.assign(L.base + (size_t)(L.nprob + 1) * sizeof(int), 0);
+    BatchStepUnit* su = reinterpret_cast<BatchStepUnit*>(host.data() + L.steps);
+    SmallUnit* sm = reinterpret_cast<SmallUnit*>(host.data() + L.smalls);
+    int* base = reinterpret_cast<int*>(host.data() + L.base);
+    DevCtrl* ctrl = reinterpret_cast<DevCtrl*>(dev + L.ctrl);
+    for (int qi = 0; qi < L.nprob; ++qi) {
+        const int pi = L.order[qi];
+        const skfab_batch_problem& q = probs[pi];
+        const BatchProbLayout& ql = L.prob[pi];
+        for (int r = 0; r < L.R; ++r) {
+            const int u = qi * L.R + r;
+            const BatchUnitLayout& ul = L.unit[u];
+            char* sb = dev + ul.small;
+            StepArgs a;
+            std::memset(&a, 0, sizeof(a));
+            a.N = ql.N;
+            a.ldU = ql.ldU;
+            a.rowptr = q.A.rowptr;
+            a.col = q.A.col;
+            a.val = static_cast<const double*>(q.A.val);
+            a.sl_ptr = reinterpret_cast<const int64_t*>(dev + ql.sl_ptr);
+            a.sl_len = reinterpret_cast<const int32_t*>(dev + ql.sl_len);
+            a.sl_col = reinterpret_cast<const int32_t*>(dev + ql.sl_col);
+            a.sl_val = dev + ql.sl_val;
+            a.nslices = ql.nslices;
+            a.slices_per_chunk = (ql.nslices + P.G[qi] - 1) / P.G[qi];
+            a.rows_per_chunk = (ql.N + P.G[qi] - 1) / P.G[qi];
+            a.b = q.B + (int64_t)r * ql.N;
+            a.U = dev + ul.U;
+            a.SV = reinterpret_cast<double*>(sb + L.o_SV);
+            a.SAV = reinterpret_cast<double*>(sb + L.o_SAV);
+            a.ctrl = ctrl + u;
+            a.sctrl = ctrl + qi * L.R;  // the SELL copy is converted once per problem
+            a.eta = reinterpret_cast<double*>(sb + L.o_eta);
+            a.wnorm = reinterpret_cast<double*>(sb + L.o_wnorm);
+            a.H = reinterpret_cast<double*>(sb + L.o_H);
+            a.gram = reinterpret_cast<double*>(sb + L.o_gram);
+            a.ldS = L.smax;
+            a.ldH = L.mmax + 1;
+            a.seed = q.seed;
+            a.inv_sqrt_zeta = 1.0 / std::sqrt((double)p->zeta);
+            a.s = q.s;
+            a.k = p->k;
+            a.m = q.m;
+            a.G = P.G[qi];
+            BatchStepUnit& b = su[u];
+            b.a = a;
+            const size_t wb = (size_t)ql.ldU * wbytes(p->prec);
+            b.W[0] = dev + ul.W;
+            b.W[1] = dev + ul.W + wb;
+            b.scal[0] = reinterpret_cast<double*>(dev + ul.scal);
+            b.scal[1] = b.scal[0] + (size_t)NSC_MAX * BATCH_GMAX;
+            b.skp[0] = reinterpret_cast<double*>(dev + ul.skp);
+            b.skp[1] = b.skp[0] + (size_t)BATCH_GMAX * 2 * q.s;
+            SmallUnit& m = sm[u];
+            m.ctrl = ctrl + u;
+            m.SV = a.SV;
+            m.SAV = a.SAV;
+            m.H = a.H;
+            m.eta = a.eta;
+            m.colnorm2 = reinterpret_cast<double*>(sb + L.o_colnorm2);
+            m.chk = reinterpret_cast<double*>(sb + L.o_chk);
+            m.Tws = reinterpret_cast<double*>(sb + L.o_Tws);
+            m.K0r = reinterpret_cast<double*>(sb + L.o_K0r);
+            m.T1r = reinterpret_cast<double*>(sb + L.o_T1r);
+            m.Hh = reinterpret_cast<double*>(sb + L.o_Hh);
+            m.Ubuf = reinterpret_cast<double*>(dev + ul.ubuf);
+            m.Urhs = reinterpret_cast<double*>(sb + L.o_Urhs);
+            m.nodebuf = reinterpret_cast<double*>(dev + ul.nodebuf);
+            m.qprev = reinterpret_cast<double*>(sb + L.o_qprev);
+            m.y0 = reinterpret_cast<double*>(sb + L.o_y0);
+            m.ys = reinterpret_cast<double*>(sb + L.o_ys);
+            m.y = reinterpret_cast<double*>(sb + L.o_y);
+            m.U = a.U;
+            m.ldU = ql.ldU;
+            m.N = ql.N;
+            m.x = q.X + (int64_t)r * ql.N;
+            m.m = q.m;
+            m.pad = 0;
+        }
+    }
+    for (int qi = 0; qi <= L.nprob; ++qi) base[qi] = P.base[qi];
+}
+
+// Arnoldi part of a batch: control blocks, SELL copies, then one launch per step j
+// over every (problem, rhs) with m_p >= j (the last is the extension pass).
+skfab_status run_batch_arnoldi(skfab_ctx* ctx, const BatchLayout& L, const BatchPlan& P,
+                               const skfab_batch_problem* probs, const skfab_params* p, char* dev, int block,
+                               int jmax, hipStream_t st) {
+    const SmallUnit* sm = reinterpret_cast<const SmallUnit*>(dev + L.smalls);
+    const BatchStepUnit* su = reinterpret_cast<const BatchStepUnit*>(dev + L.steps);
+    const int* base = reinterpret_cast<const int*>(dev + L.base);
+    DevCtrl* ctrl = reinterpret_cast<DevCtrl*>(dev + L.ctrl);
+    HIP_TRY(launch_fill(reinterpret_cast<double*>(dev + L.small_begin),
+                        (int64_t)((L.small_end - L.small_begin) / sizeof(double)), 0.0, st));
+    HIP_TRY(launch_init_ctrl_batched(sm, L.nunits, st));
+    for (int qi = 0; qi < L.nprob; ++qi) {
+        const int pi = L.order[qi];
+        const BatchProbLayout& q = L.prob[pi];
+        HIP_TRY(launch_sell_convert(probs[pi].A.rowptr, probs[pi].A.col, static_cast<const double*>(probs[pi].A.val),
+                                    q.N, q.nslices, q.capacity, ctrl + qi * L.R,
+                                    reinterpret_cast<int32_t*>(dev + q.sl_len),
+                                    reinterpret_cast<int64_t*>(dev + q.sl_ptr),
+                                    reinterpret_cast<int64_t*>(dev + q.bsum),
+                                    reinterpret_cast<int32_t*>(dev + q.sl_col), dev + q.sl_val, p->prec, st));
+    }
+    int nact = L.nprob;
+    for (int j = 0; j <= jmax; ++j) {
+        while (nact > 0 && probs[L.order[nact - 1]].m < j) --nact;
+        if (nact == 0) break;
+        hipEvent_t stop;
+        HIP_TRY(timing_begin(ctx, 0, st, &stop));
+        HIP_TRY(launch_arnoldi_step_batched(su, base, nact, L.R, j, p->k, P.base[nact], block, L.smax, p->prec, st));
+        HIP_TRY(timing_end(stop, st));
+    }
+    return SKFAB_OK;
+}
+
+skfab_status run_batch_small(const BatchLayout& L, const skfab_params* p, char* dev, hipStream_t st) {
+    const SmallUnit* sm = reinterpret_cast<const SmallUnit*>(dev + L.smalls);
+    const BatchStepUnit* su = reinterpret_cast<const BatchStepUnit*>(dev + L.steps);
+    const int n = L.nunits, m = L.mmax, s = L.smax;
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    if (p->method == SKFAB_SFOM_CLOSED) tol = 1e-13;
+    const bool ls = p->method == SKFAB_SGMRES_QUAD;
+    HIP_TRY(launch_arnoldi_tail_batched(su, sm, n, s, m, st));
+    HIP_TRY(launch_arnoldi_check_batched(sm, n, s, m, p->k, st));
+    HIP_TRY(launch_qr_batched(sm, n, s, m + 1, st));
+    HIP_TRY(launch_pencil_setup_batched(sm, n, s, m, p->k, st));
+    HIP_TRY(launch_hhat_rows_batched(sm, n, m, s, st));
+    const int branch = (p->f == SKFAB_F_INVSQRT && !ls) ? 1 : 0;
+    HIP_TRY(launch_pencil_scalars_batched(sm, n, m, s, 0, branch, st));
+    if (p->f == SKFAB_F_INV) {
+        if (ls) HIP_TRY(launch_pencil_scalars_batched(sm, n, m, s, 1, 0, st));
+    } else {
+        for (const QuadGroup& g : quad_groups(l1, l2, lmax)) {
+            HIP_TRY(launch_quad_group_batched(sm, n, g, m, ls ? 1 : 0, BATCH_SLOTS, st));
+            HIP_TRY(launch_quad_reduce_batched(sm, n, g, m, tol, st));
+        }
+        HIP_TRY(launch_quad_fail_batched(sm, n, st));
+    }
+    HIP_TRY(launch_finish_coeffs_batched(sm, n, m, st));
+    return SKFAB_OK;
+}
+
+skfab_status batch_prepare(skfab_ctx* ctx, int32_t nprob, const skfab_batch_problem* probs, int32_t nrhs,
+                           const skfab_params* p, void* ws, size_t ws_bytes, BatchLayout* L) {
+    if (!ctx) return SKFAB_ERR_ARG;
+    skfab_status v = validate_batch(nprob, probs, nrhs, p, true);
+    if (v != SKFAB_OK) return v;
+    *L = make_batch_layout(nprob, probs, nrhs, p);
+    if (!ws || ws_bytes < L->total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    // the previous call's descriptor upload may still read the host copy
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+    return SKFAB_OK;
+}
+
+skfab_status batch_upload(skfab_ctx* ctx, const BatchLayout& L, const BatchPlan& P, const skfab_batch_problem* probs,
+                          const skfab_params* p, char* dev) {
+    batch_descriptors(L, P, probs, p, dev, ctx->batch_host);
+    HIP_TRY(hipMemcpyAsync(dev + L.steps, ctx->batch_host.data() + L.steps, ctx->batch_host.size() - L.steps,
+                           hipMemcpyHostToDevice, ctx->stream));
+    return SKFAB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+skfab_status skfab_batch_workspace_bytes(int32_t nprob, const skfab_batch_problem* probs, int32_t nrhs,
+                                         const skfab_params* p, size_t* bytes) {
+    if (!bytes) return SKFAB_ERR_ARG;
+    skfab_status v = validate_batch(nprob, probs, nrhs, p, false);
+    if (v != SKFAB_OK) return v;
+    *bytes = make_batch_layout(nprob, probs, nrhs, p).total;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_batch_set_tuning(skfab_ctx* ctx, const skfab_batch_tuning* t) {
+    if (!ctx || !t) return SKFAB_ERR_ARG;
+    if (t->block != 256 && t->block != 512 && t->block != 1024) return SKFAB_ERR_ARG;
+    if (t->slices_per_wave < 1 || t->slices_per_wave > 64) return SKFAB_ERR_ARG;
+    ctx->batch_block = t->block;
+    ctx->batch_spw = t->slices_per_wave;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_batch_get_tuning(skfab_ctx* ctx, skfab_batch_tuning* t) {
+    if (!ctx || !t) return SKFAB_ERR_ARG;
+    t->block = ctx->batch_block;
+    t->slices_per_wave = ctx->batch_spw;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_solve_batched(skfab_ctx* ctx, int32_t nprob, const skfab_batch_problem* probs, int32_t nrhs,
+                                 const skfab_params* p, void* ws, size_t ws_bytes, skfab_info* info) {
+    BatchLayout L;
+    skfab_status r = batch_prepare(ctx, nprob, probs, nrhs, p, ws, ws_bytes, &L);
+    if (r != SKFAB_OK) return r;
+    char* dev = static_cast<char*>(ws);
+    hipStream_t st = ctx->stream;
+    const BatchPlan P = batch_plan(L, ctx->batch_block, ctx->batch_spw);
+    r = batch_upload(ctx, L, P, probs, p, dev);
+    if (r != SKFAB_OK) return r;
+    r = run_batch_arnoldi(ctx, L, P, probs, p, dev, ctx->batch_block, L.mmax, st);
+    if (r != SKFAB_OK) return r;
+    r = run_batch_small(L, p, dev, st);
+    if (r != SKFAB_OK) return r;
+    const SmallUnit* sm = reinterpret_cast<const SmallUnit*>(dev + L.smalls);
+    hipEvent_t stop;
+    HIP_TRY(timing_begin(ctx, 1, st, &stop));
+    HIP_TRY(launch_assemble_batched(sm, L.nunits, L.nmax, L.mmax, p->prec, st));
+    HIP_TRY(timing_end(stop, st));
+    if (!info) return SKFAB_OK;
+    std::vector<DevCtrl> c(L.nunits);
+    HIP_TRY(hipMemcpyAsync(c.data(), dev + L.ctrl, sizeof(DevCtrl) * L.nunits, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int qi = 0; qi < L.nprob; ++qi) {
+        const int pi = L.order[qi];
+        for (int rr = 0; rr < L.R; ++rr) {
+            const DevCtrl& cc = c[qi * L.R + rr];
+            skfab_info& o = info[pi * L.R + rr];
+            o.status = cc.status;
+            o.m_used = cc.m_used;
+            o.l_used = cc.l_used;
+            o.reserved = 0;
+            o.eps_est = cc.eps_est;
+            o.rcond_R = cc.rcond;
+            o.sigma = cc.sigma;
+            o.beta = cc.beta;
+            o.arnoldi_relres = cc.relres;
+        }
+    }
+    return SKFAB_OK;
+}
+
+skfab_status skfab_batch_autotune(skfab_ctx* ctx, int32_t nprob, const skfab_batch_problem* probs, int32_t nrhs,
+                                  const skfab_params* p, void* ws, size_t ws_bytes, int32_t steps,
+                                  skfab_batch_tuning* chosen) {
+    BatchLayout L;
+    skfab_status r = batch_prepare(ctx, nprob, probs, nrhs, p, ws, ws_bytes, &L);
+    if (r != SKFAB_OK) return r;
+    if (steps < 1) steps = 4;
+    char* dev = static_cast<char*>(ws);
+    hipStream_t st = ctx->stream;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    const int blocks[3] = {256, 512, 1024};
+    const int spws[7] = {1, 2, 4, 8, 16, 32, 64};
+    float best = 1e30f;
+    int bb = ctx->batch_block, bs = ctx->batch_spw;
+    const bool timing = ctx->timing;
+    ctx->timing = false;
+    for (int bi = 0; bi < 3 && r == SKFAB_OK; ++bi) {
+        for (int si = 0; si < 7 && r == SKFAB_OK; ++si) {
+            const BatchPlan P = batch_plan(L, blocks[bi], spws[si]);
+            // the step launches of a candidate time j = 1 .. steps (j = 0 has no
+            // previous step to reduce and is run untimed first)
+            if (hipStreamSynchronize(st) != hipSuccess) { r = SKFAB_ERR_HIP; break; }
+            r = batch_upload(ctx, L, P, probs, p, dev);
+            if (r != SKFAB_OK) break;
+            r = run_batch_arnoldi(ctx, L, P, probs, p, dev, blocks[bi], 0, st);
+            if (r != SKFAB_OK) break;
+            if (hipEventRecord(e0, st) != hipSuccess) { r = SKFAB_ERR_HIP; break; }
+            const BatchStepUnit* su = reinterpret_cast<const BatchStepUnit*>(dev + L.steps);
+            const int* base = reinterpret_cast<const int*>(dev + L.base);
+            int nact = L.nprob;
+            for (int j = 1; j <= steps; ++j) {
+                while (nact > 0 && probs[L.order[nact - 1]].m < j) --nact;
+                if (nact == 0) break;
+                if (launch_arnoldi_step_batched(su, base, nact, L.R, j, p->k, P.base[nact], blocks[bi], L.smax,
+                                                p->prec, st) != hipSuccess) { r = SKFAB_ERR_HIP; break; }
+            }
+            if (r != SKFAB_OK) break;
+            float ms = 0.f;
+            if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { r = SKFAB_ERR_HIP; break; }
+            if (ms < best) { best = ms; bb = blocks[bi]; bs = spws[si]; }
+        }
+    }
+    ctx->timing = timing;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (r != SKFAB_OK) return r;
+    ctx->batch_block = bb;
+    ctx->batch_spw = bs;
+    if (chosen) { chosen->block = bb; chosen->slices_per_wave = bs; }
     return SKFAB_OK;
 }
 

@@ -40,8 +40,8 @@ namespace skfab {
 // entries of v_p and the coefficients of u_{p+1}.  Runs on one thread.
 // Returns false on breakdown (m_used set to p, or 0 for b = 0).
 template <int KW>
-__device__ bool step_coefficients(const double* red, int p, int k, int m, bool writer,
-                                  const StepArgs& a, double* coef) {
+__device__ bool step_coefficients(const double* red, int p, int k, bool writer, const StepArgs& a,
+                                  double* coef) {
     const double uu = red[0], uw = red[1], ww = red[2];
     const double eta_p = sqrt(uu);
     bool ok;
@@ -55,7 +55,7 @@ __device__ bool step_coefficients(const double* red, int p, int k, int m, bool w
         if (writer) {
             a.ctrl->m_used = p;
             a.ctrl->stop = 1;
-            if (p >= 1) a.H[p + (int64_t)(m + 1) * (p - 1)] = eta_p;
+            if (p >= 1) a.H[p + a.ldH * (p - 1)] = eta_p;
         }
         return false;
     }
@@ -101,7 +101,7 @@ __device__ bool step_coefficients(const double* red, int p, int k, int m, bool w
     if (writer) {
         a.eta[p] = eta_p;
         a.wnorm[p] = wn;
-        const int64_t ldh = m + 1;
+        const int64_t ldh = a.ldH;
         for (int o = 0; o < nwp; ++o) a.H[(p - o) + ldh * p] = h[o];
         if (p >= 1) a.H[p + ldh * (p - 1)] = eta_p;
         for (int o = 1; o < nwp; ++o) a.gram[(int64_t)p * KMAX + (o - 1)] = gp[o];
@@ -114,8 +114,8 @@ __device__ bool step_coefficients(const double* red, int p, int k, int m, bool w
 // it has wavefronts.  Bin i < s goes to SV[:, p] (scale_v), bin s + i to SAV[:, p]
 // (scale_av, skipped when write_av is false).
 template <int BLOCK>
-__device__ void reduce_prev_sketch_tail(const double* skp, int G, int s, int p, int c0, int c1, double scale_v,
-                                        double scale_av, bool write_av, double* SV, double* SAV) {
+__device__ void reduce_prev_sketch_tail(const double* skp, int G, int s, int64_t ldS, int p, int c0, int c1,
+                                        double scale_v, double scale_av, bool write_av, double* SV, double* SAV) {
     const int lane = threadIdx.x & (WAVE - 1), wid = threadIdx.x / WAVE;
     constexpr int NW = BLOCK / WAVE;
     for (int bin = c0 + wid; bin < c1; bin += NW) {
@@ -125,8 +125,8 @@ __device__ void reduce_prev_sketch_tail(const double* skp, int G, int s, int p, 
         for (int g = lane; g < G; g += WAVE) t += src[g];
         t = wave_sum(t);
         if (lane == 0) {
-            if (bin < s) SV[(int64_t)p * s + bin] = t * scale_v;
-            else SAV[(int64_t)p * s + (bin - s)] = t * scale_av;
+            if (bin < s) SV[(int64_t)p * ldS + bin] = t * scale_v;
+            else SAV[(int64_t)p * ldS + (bin - s)] = t * scale_av;
         }
     }
 }
@@ -140,8 +140,11 @@ template <int KW> struct SellBatch { static constexpr int value = KW <= 2 ? 8 : 
 // rounded value is what enters the product with A, the sketch and the dots (so
 // the stored basis, its sketch and its image under A stay consistent).  Dot
 // products and sketch bins accumulate in FP64.
+//
+// The body serves both the single-problem kernel and the batched one: `bid` is
+// the block's index among the G blocks of its (problem, right-hand side) pair.
 template <int KW, int ZETA, int BLOCK, typename P>
-__global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
+__device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     using VT = typename P::V;
     using WT = typename P::W;
     using AT = typename P::A;
@@ -153,6 +156,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
 
     // a breakdown detected by an earlier step ends the recurrence (the step that
     // detects it still runs its prologue to write the extension column)
+    const int sell_flag = a.sctrl->sell_ok;  // issued with the control-block loads
     if (a.ctrl->stop && a.ctrl->m_used < a.j - 1) return;
     constexpr int NSC = 2 * KW + 1;
     constexpr int NW = BLOCK / WAVE;
@@ -173,8 +177,8 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
         }
         (void)PER;
         const int nb = 2 * s;
-        const int b0 = (int)(((int64_t)blockIdx.x * nb) / gridDim.x);
-        const int b1 = (int)(((int64_t)(blockIdx.x + 1) * nb) / gridDim.x);
+        const int b0 = (int)(((int64_t)bid * nb) / G);
+        const int b1 = (int)(((int64_t)(bid + 1) * nb) / G);
         // sketch partial sums of this block's bins (one wavefront per bin)
         double skv = 0.0;
         int mybin = -1;
@@ -190,19 +194,19 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
         // every thread's scalar partials reduced in a fixed tree through the (not yet
         // used) sketch-bin region of LDS
         block_reduce_multi<NSC, BLOCK>(sv, bins, red);
-        if (tid == 0) s_ok = step_coefficients<KW>(red, j - 1, k, a.m, blockIdx.x == 0, a, coef) ? 1 : 0;
+        if (tid == 0) s_ok = step_coefficients<KW>(red, j - 1, k, bid == 0, a, coef) ? 1 : 0;
         skv = wave_sum(skv);
         __syncthreads();
         // S v_{j-1}, S A v_{j-1}; after a breakdown, S u_{j-1} unnormalised (extension column)
         const double eta_p = coef[KMAX + 1];
         const bool ok = s_ok != 0;
         if (mybin >= 0 && lane == 0) {
-            if (mybin < s) a.SV[(int64_t)(j - 1) * s + mybin] = skv * (ok ? a.inv_sqrt_zeta / eta_p : a.inv_sqrt_zeta);
-            else if (ok) a.SAV[(int64_t)(j - 1) * s + (mybin - s)] = skv * (a.inv_sqrt_zeta / eta_p);
+            if (mybin < s) a.SV[(int64_t)(j - 1) * a.ldS + mybin] = skv * (ok ? a.inv_sqrt_zeta / eta_p : a.inv_sqrt_zeta);
+            else if (ok) a.SAV[(int64_t)(j - 1) * a.ldS + (mybin - s)] = skv * (a.inv_sqrt_zeta / eta_p);
         }
         // bins beyond one per wave (only when 2s > 16 G): fall back to the generic loop
         if (b1 - b0 > NW)
-            reduce_prev_sketch_tail<BLOCK>(a.skp_prev, G, s, j - 1, b0 + NW, b1,
+            reduce_prev_sketch_tail<BLOCK>(a.skp_prev, G, s, a.ldS, j - 1, b0 + NW, b1,
                                            ok ? a.inv_sqrt_zeta / eta_p : a.inv_sqrt_zeta,
                                            a.inv_sqrt_zeta / eta_p, ok, a.SV, a.SAV);
         if (!ok) return;
@@ -241,8 +245,8 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
 #pragma unroll
     for (int o = 0; o < KW; ++o) { acc_lw[o] = 0.0; acc_ul[o] = 0.0; }
 
-    const int chunk = xcd_chunk(blockIdx.x, G);
-    const bool sell = a.ctrl->sell_ok != 0;
+    const int chunk = xcd_chunk(bid, G);
+    const bool sell = sell_flag != 0;
     // rows of this block: SELL slices [sl0, sl1) or CSR rows [r_begin, r_end)
     int64_t it0, it1, step;
     if (sell) {
@@ -359,14 +363,61 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
     for (int o = 0; o < KW - 1; ++o) { vals[3 + o] = acc_lw[o]; vals[3 + (KW - 1) + o] = acc_ul[o]; }
     __syncthreads();
     block_reduce_multi<NSC, BLOCK>(vals, bins, red);
-    if (tid < NSC) a.scal_cur[(int64_t)tid * G + blockIdx.x] = red[tid];
+    if (tid < NSC) a.scal_cur[(int64_t)tid * G + bid] = red[tid];
+}
+
+template <int KW, int ZETA, int BLOCK, typename P>
+__global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
+    step_body<KW, ZETA, BLOCK, P>(a, blockIdx.x);
+}
+
+// Unit (problem, right-hand side) of a block of the batched step launch.
+// Problems are ordered by decreasing m and problem q owns the blocks
+// [base[q], base[q+1]); within it block g' serves right-hand side (g' / 8) % R
+// and local block 8 (g' / 8R) + g' % 8, so the R blocks that read the same rows
+// of A are dispatched one after another onto the same XCD (A read once from HBM,
+// shared through L2) and the local index keeps the XCD-contiguous chunk mapping.
+struct BatchLookup {
+    int unit;
+    int bid;
+};
+
+__device__ __forceinline__ BatchLookup batch_lookup(const int* __restrict__ base, int nact, int R, int g) {
+    int lo = 0, hi = nact;  // base[lo] <= g < base[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= g) lo = mid; else hi = mid;
+    }
+    const int gp = g - base[lo];
+    BatchLookup r;
+    r.unit = lo * R + (gp >> 3) % R;
+    r.bid = (gp / (8 * R)) * 8 + (gp & 7);
+    return r;
+}
+
+template <int KW, int ZETA, int BLOCK, typename P>
+__global__ __launch_bounds__(BLOCK) void arnoldi_step_batched_kernel(const BatchStepUnit* __restrict__ units,
+                                                                     const int* __restrict__ base, int nact, int R,
+                                                                     int j) {
+    const BatchLookup lk = batch_lookup(base, nact, R, blockIdx.x);
+    const BatchStepUnit& u = units[lk.unit];
+    StepArgs a = u.a;
+    a.j = j;
+    a.extend = (j == a.m) ? 1 : 0;
+    a.Wcur = u.W[j & 1];
+    a.Wprev = u.W[(j + 1) & 1];
+    a.scal_prev = u.scal[(j + 1) & 1];
+    a.scal_cur = u.scal[j & 1];
+    a.skp_prev = u.skp[(j + 1) & 1];
+    a.skp_cur = u.skp[j & 1];
+    step_body<KW, ZETA, BLOCK, P>(a, lk.bid);
 }
 
 // After the extension step m: S u_m (unnormalised) into SV[:, m_used], eta_m and
 // h_{m+1,m} (unless the recurrence broke down earlier, in which case the step
 // that detected it already wrote the extension column), then ||S v_j||^2 for the
 // epsilon monitor.  One wavefront per sketch bin in the first ceil(s/4) blocks.
-__global__ __launch_bounds__(256) void arnoldi_tail_kernel(StepArgs a) {
+__device__ __forceinline__ void tail_body(const StepArgs& a) {
     const int m = a.m, s = a.s, G = a.G;
     const int lane = threadIdx.x & 63;
     const int bin = blockIdx.x * 4 + (threadIdx.x >> 6);
@@ -377,7 +428,7 @@ __global__ __launch_bounds__(256) void arnoldi_tail_kernel(StepArgs a) {
         v = wave_sum_fast(v);
         if (lane == 0) {
             a.eta[m] = sqrt(v);
-            a.H[m + (int64_t)(m + 1) * (m - 1)] = sqrt(v);
+            a.H[m + a.ldH * (m - 1)] = sqrt(v);
         }
     }
     if (bin < s) {
@@ -387,13 +438,24 @@ __global__ __launch_bounds__(256) void arnoldi_tail_kernel(StepArgs a) {
         for (; g + 64 < G; g += 128) { t0 += src[g]; t1 += src[g + 64]; }
         if (g < G) t0 += src[g];
         const double t = wave_sum_fast(t0 + t1);
-        if (lane == 0) a.SV[(int64_t)m * s + bin] = t * a.inv_sqrt_zeta;
+        if (lane == 0) a.SV[(int64_t)m * a.ldS + bin] = t * a.inv_sqrt_zeta;
     }
 }
 
+__global__ __launch_bounds__(256) void arnoldi_tail_kernel(StepArgs a) { tail_body(a); }
+
+// Batched tail: blockIdx.y = unit, arguments of its last (extension) step.
+__global__ __launch_bounds__(256) void arnoldi_tail_batched_kernel(const BatchStepUnit* __restrict__ units) {
+    const BatchStepUnit& u = units[blockIdx.y];
+    StepArgs a = u.a;
+    a.scal_prev = u.scal[a.m & 1];
+    a.skp_prev = u.skp[a.m & 1];
+    tail_body(a);
+}
+
 // ||S v_j||^2 for the epsilon monitor, one wavefront per column.
-__global__ __launch_bounds__(256) void colnorm_kernel(const double* SV, int s, int m, const DevCtrl* ctrl,
-                                                      double* colnorm2) {
+__device__ __forceinline__ void colnorm_body(const double* SV, int s, int m, const DevCtrl* ctrl,
+                                             double* colnorm2) {
     const int lane = threadIdx.x & 63;
     const int jj = blockIdx.x * 4 + (threadIdx.x >> 6);
     if (jj >= m) return;
@@ -408,12 +470,22 @@ __global__ __launch_bounds__(256) void colnorm_kernel(const double* SV, int s, i
     if (lane == 0) colnorm2[jj] = (jj < mu) ? t : 1.0;
 }
 
+__global__ __launch_bounds__(256) void colnorm_kernel(const double* SV, int s, int m, const DevCtrl* ctrl,
+                                                      double* colnorm2) {
+    colnorm_body(SV, s, m, ctrl, colnorm2);
+}
+
+__global__ __launch_bounds__(256) void colnorm_batched_kernel(const SmallUnit* __restrict__ units, int s, int m) {
+    const SmallUnit& u = units[blockIdx.y];
+    colnorm_body(u.SV, s, m, u.ctrl, u.colnorm2);
+}
+
 // relres = ||SAV - [SV, S u] Hbar1||_F / ||SAV||_F over the first m_used columns,
 // Hbar1 = [H; e_mu^T] (Arnoldi relation in the sketched space).  One block per
 // column, partial sums in part[2 m]; the last block to finish would need an
 // atomic, so the final sum is taken by the small-problem kernels instead.
-__global__ __launch_bounds__(256) void arnoldi_check_kernel(const double* SV, const double* SAV, const double* H,
-                                                           int s, int m, int k, const DevCtrl* ctrl, double* part) {
+__device__ __forceinline__ void check_body(const double* SV, const double* SAV, const double* H, int s, int m,
+                                           int k, const DevCtrl* ctrl, double* part) {
     __shared__ double scratch[4];
     const int mu = ctrl->m_used;
     const int jj = blockIdx.x;
@@ -435,13 +507,33 @@ __global__ __launch_bounds__(256) void arnoldi_check_kernel(const double* SV, co
     if (threadIdx.x == 0) { part[jj] = num; part[m + jj] = den; }
 }
 
-__global__ __launch_bounds__(256) void arnoldi_check_finish_kernel(const double* part, int m, DevCtrl* ctrl) {
+__global__ __launch_bounds__(256) void arnoldi_check_kernel(const double* SV, const double* SAV, const double* H,
+                                                           int s, int m, int k, const DevCtrl* ctrl, double* part) {
+    check_body(SV, SAV, H, s, m, k, ctrl, part);
+}
+
+__global__ __launch_bounds__(256) void arnoldi_check_batched_kernel(const SmallUnit* __restrict__ units, int s, int m,
+                                                                   int k) {
+    const SmallUnit& u = units[blockIdx.y];
+    check_body(u.SV, u.SAV, u.H, s, m, k, u.ctrl, u.chk);
+}
+
+__device__ __forceinline__ void check_finish_body(const double* part, int m, DevCtrl* ctrl) {
     __shared__ double scratch[4];
     double num = 0.0, den = 0.0;
     for (int i = threadIdx.x; i < m; i += 256) { num += part[i]; den += part[m + i]; }
     num = block_sum(num, scratch);
     den = block_sum(den, scratch);
     if (threadIdx.x == 0) ctrl->relres = (den > 0.0) ? sqrt(num / den) : 0.0;
+}
+
+__global__ __launch_bounds__(256) void arnoldi_check_finish_kernel(const double* part, int m, DevCtrl* ctrl) {
+    check_finish_body(part, m, ctrl);
+}
+
+__global__ __launch_bounds__(256) void arnoldi_check_finish_batched_kernel(const SmallUnit* __restrict__ units, int m) {
+    const SmallUnit& u = units[blockIdx.y];
+    check_finish_body(u.chk, m, u.ctrl);
 }
 
 // V[:, j] = U[:, j] / eta_j (zero beyond m_used); test hook only.
@@ -665,6 +757,64 @@ hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const 
     else
         hipLaunchKernelGGL(sell_fill_kernel<float>, dim3(g), dim3(256), 0, st, rowptr, col, val, N, nslices, ctrl,
                            sl_ptr, sl_len, sl_col, static_cast<float*>(sl_val));
+    return hipGetLastError();
+}
+
+
+// ------------------------------------------------------- batched launchers
+template <int KW, int ZETA, typename P>
+static hipError_t launch_step_batched_t(const BatchStepUnit* units, const int* base, int nact, int R, int j,
+                                        int grid, int block, int smax, hipStream_t st) {
+    const size_t bins = (size_t)(block / WAVE) * 2 * smax;
+    const size_t red = (size_t)(2 * KW + 1) * (block + 72);
+    const size_t lds = (bins > red ? bins : red) * sizeof(double);
+    if (block == 1024)
+        hipLaunchKernelGGL((arnoldi_step_batched_kernel<KW, ZETA, 1024, P>), dim3(grid), dim3(1024), lds, st, units,
+                           base, nact, R, j);
+    else if (block == 512)
+        hipLaunchKernelGGL((arnoldi_step_batched_kernel<KW, ZETA, 512, P>), dim3(grid), dim3(512), lds, st, units,
+                           base, nact, R, j);
+    else
+        hipLaunchKernelGGL((arnoldi_step_batched_kernel<KW, ZETA, 256, P>), dim3(grid), dim3(256), lds, st, units,
+                           base, nact, R, j);
+    return hipGetLastError();
+}
+
+template <typename P>
+static hipError_t launch_step_batched_p(const BatchStepUnit* units, const int* base, int nact, int R, int j, int k,
+                                        int grid, int block, int smax, hipStream_t st) {
+    switch (k) {
+        case 1: return launch_step_batched_t<1, 8, P>(units, base, nact, R, j, grid, block, smax, st);
+        case 2: return launch_step_batched_t<2, 8, P>(units, base, nact, R, j, grid, block, smax, st);
+        case 3: return launch_step_batched_t<3, 8, P>(units, base, nact, R, j, grid, block, smax, st);
+        default: return launch_step_batched_t<4, 8, P>(units, base, nact, R, j, grid, block, smax, st);
+    }
+}
+
+// Batched step launch (sketch density 8, k <= 4): `grid` blocks, the first nact
+// problems (by decreasing m) active.
+hipError_t launch_arnoldi_step_batched(const BatchStepUnit* units, const int* base, int nact, int R, int j, int k,
+                                       int grid, int block, int smax, int prec, hipStream_t st) {
+    if (prec == 1) return launch_step_batched_p<PrecF32>(units, base, nact, R, j, k, grid, block, smax, st);
+    if (prec == 2) return launch_step_batched_p<PrecBF16>(units, base, nact, R, j, k, grid, block, smax, st);
+    return launch_step_batched_p<PrecF64>(units, base, nact, R, j, k, grid, block, smax, st);
+}
+
+hipError_t launch_arnoldi_tail_batched(const BatchStepUnit* units, const SmallUnit* small, int nunits, int smax,
+                                       int mmax, hipStream_t st) {
+    hipLaunchKernelGGL(arnoldi_tail_batched_kernel, dim3((smax + 3) / 4, nunits), dim3(256), 0, st, units);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(colnorm_batched_kernel, dim3((mmax + 3) / 4, nunits), dim3(256), 0, st, small, smax, mmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_arnoldi_check_batched(const SmallUnit* small, int nunits, int smax, int mmax, int k,
+                                        hipStream_t st) {
+    hipLaunchKernelGGL(arnoldi_check_batched_kernel, dim3(mmax, nunits), dim3(256), 0, st, small, smax, mmax, k);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(arnoldi_check_finish_batched_kernel, dim3(1, nunits), dim3(256), 0, st, small, mmax);
     return hipGetLastError();
 }
 

@@ -21,7 +21,8 @@ struct DevCtrl {
     double rcond;       // min |R_jj| / max |R_jj|
     double logdet;      // log |det H_hat|
     double relres;      // ||S A V - [S V, S u_{m+1}] Hbar||_F / ||S A V||_F (Arnoldi relation check)
-    double pad2[2];
+    double qdiff_prev;  // relative difference of the last two quadrature orders tested
+    double pad2;
     int64_t sell_total; // entries of the SELL-64 copy of A (padded)
     int32_t sell_ok;    // 1: the SELL-64 copy fits the workspace and is used
     int32_t pad3;
@@ -58,10 +59,34 @@ struct StepArgs {
     double* wnorm;  // [m]   ||A v_j||
     double* H;      // [(m+1) x m] truncated MGS coefficients
     double* gram;   // [m][KMAX] <v_j, v_{j-1-q}>
+    const DevCtrl* sctrl;  // control block of the SELL-64 conversion of A (sell_ok)
+    int64_t ldS;      // leading dimension of SV, SAV (>= s; rows s.. stay zero)
+    int64_t ldH;      // leading dimension of H (>= m + 1)
     uint64_t seed;
     double inv_sqrt_zeta;
     int32_t s, k, j, m, G;
     int32_t extend;   // 1: form u_m and its sketch only (no product with A)
+};
+
+// One (problem, right-hand side) pair of a batched solve: the step arguments
+// that do not depend on j, and the double-buffered arrays selected by j's parity.
+struct BatchStepUnit {
+    StepArgs a;
+    void* W[2];
+    double* scal[2];
+    double* skp[2];
+};
+
+// Per-unit pointers of the batched small problem and assembly.  Every unit's
+// small arrays use the batch's common leading dimensions (m_max, s_max); the
+// unit's own Krylov dimension is its control block's m_used.
+struct SmallUnit {
+    DevCtrl* ctrl;
+    double *SV, *SAV, *H, *eta, *colnorm2, *chk, *Tws, *K0r, *T1r, *Hh, *Ubuf, *Urhs, *nodebuf, *qprev, *y0, *ys, *y;
+    const void* U;
+    int64_t ldU, N;
+    double* x;
+    int32_t m, pad;
 };
 
 // A group of consecutive quadrature orders evaluated by one launch.

@@ -9,14 +9,19 @@
 //     P(t) = t R_e[:, :m] + K0,     K0 = R_e Hbar,
 //
 // and with Q_e^T S b = beta R_e[0,0] e_1:
-//   * sketched Galerkin condition (eq. ym_hat):  P(t)[:m, :] y(t) = beta R_00 e_1
+//   * sketched Galerkin condition (eq. ym_hat):  P(t)[:m, :] y(t) = beta R_00 e_1,
+//     i.e. R (t I + H_hat) y(t) = beta R_00 e_1 with H_hat = H_m + (R^-1 R_e[:m, m]) e_m^T,
+//     solved as (t I + H_hat) y(t) = beta e_1 (no factor R: its condition number
+//     would otherwise multiply the rounding error of every node solve)
 //   * sketched GMRES (eq. sgmres integrand):       y(t) = argmin || beta R_00 e_1 - P(t) y ||
 // The approximants are V_m int y(t) dmu(t) (sFOM, sGMRES).  For z^(-1/2) the
 // integral is the Gauss-Chebyshev rule after t = (1-x)/(1+x) (Section 5.1) with the
 // spectral scaling t -> sigma t, sigma = |det H_hat|^(1/m) (geometric mean of the
 // eigenvalue moduli of the projected matrix), and the adaptive order update
-// l <- floor(sqrt(2) l) of Section 4.1.  Every node is an O(m^2) Hessenberg solve
-// (partial pivoting) or Givens least-squares solve, one wavefront per node.
+// l <- floor(sqrt(2) l) of Section 4.1 (accepting an order at the rounding floor
+// QUAD_FLOOR when the requested tolerance is out of reach).  Every node is an
+// O(m^2) Hessenberg solve (partial pivoting) or Givens least-squares solve, one
+// wavefront per node.
 #include "common.hpp"
 #include "device_state.hpp"
 
@@ -24,6 +29,10 @@ namespace skfab {
 
 constexpr int QR_NB = 16;        // Householder panel width
 constexpr int NODE_SLOTS = 1024;  // concurrent quadrature nodes (scratch slots)
+// Rounding floor of the adaptive quadrature test: an order whose relative difference
+// to the previous one is below this and no longer decreasing is accepted even when
+// the requested tolerance lies below what the node solves can resolve.
+constexpr double QUAD_FLOOR = 1e-10;
 
 // ------------------------------------------------------------ utilities
 __global__ void fill_kernel(double* p, int64_t n, double v) {
@@ -31,11 +40,21 @@ __global__ void fill_kernel(double* p, int64_t n, double v) {
         p[i] = v;
 }
 
-__global__ void init_ctrl_kernel(DevCtrl* c, int m) {
+__device__ __forceinline__ void init_ctrl_body(DevCtrl* c, int m) {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
         c->m_used = m; c->stop = 0; c->status = 0; c->l_used = 0; c->converged = 0; c->l_prev = 0;
         c->beta = 0.0; c->sigma = 1.0; c->eps_est = 0.0; c->rcond = 0.0; c->logdet = 0.0;
+        c->qdiff_prev = INFINITY;
     }
+}
+
+__global__ void init_ctrl_kernel(DevCtrl* c, int m) { init_ctrl_body(c, m); }
+
+// Batched forms below take blockIdx.y as the unit index and read the unit's
+// pointers from a SmallUnit array; blockIdx.x keeps its single-problem meaning.
+__global__ void init_ctrl_batched_kernel(const SmallUnit* __restrict__ units) {
+    const SmallUnit& u = units[blockIdx.y];
+    init_ctrl_body(u.ctrl, u.m);
 }
 
 // ------------------------------------------------------- Householder QR
@@ -46,8 +65,7 @@ __global__ void init_ctrl_kernel(DevCtrl* c, int m) {
 // reduction of the squared norm and the dot products with the later columns.
 constexpr int QR_NT = 256;
 
-__global__ __launch_bounds__(QR_NT) void qr_panel_kernel(double* X, int s, int c0, const DevCtrl* ctrl,
-                                                          double* Tws) {
+__device__ __forceinline__ void qr_panel_body(double* X, int s, int c0, const DevCtrl* ctrl, double* Tws) {
     extern __shared__ double P[];  // [QR_NB][nrows]
     __shared__ double red[2][QR_NT / WAVE][QR_NB + 1];
     __shared__ double tau[QR_NB];
@@ -170,9 +188,18 @@ __global__ __launch_bounds__(QR_NT) void qr_panel_kernel(double* X, int s, int c
         for (int r = tid; r < nrows; r += QR_NT) X[(int64_t)(c0 + r) + (int64_t)s * (c0 + cc)] = P[cc * nrows + r];
 }
 
+__global__ __launch_bounds__(QR_NT) void qr_panel_kernel(double* X, int s, int c0, const DevCtrl* ctrl,
+                                                          double* Tws) {
+    qr_panel_body(X, s, c0, ctrl, Tws);
+}
+
+__global__ __launch_bounds__(QR_NT) void qr_panel_batched_kernel(const SmallUnit* __restrict__ units, int s, int c0) {
+    const SmallUnit& u = units[blockIdx.y];
+    qr_panel_body(u.SV, s, c0, u.ctrl, u.Tws);
+}
+
 // Trailing update C <- (I - Y T Y^T)^T C for columns c0+nb .. ncols-1, one block per column.
-__global__ __launch_bounds__(256) void qr_update_kernel(double* X, int s, int c0, const DevCtrl* ctrl,
-                                                        const double* Tws) {
+__device__ __forceinline__ void qr_update_body(double* X, int s, int c0, const DevCtrl* ctrl, const double* Tws) {
     __shared__ double red[4][QR_NB];
     __shared__ double W[QR_NB], Z[QR_NB];
     const int ncols = ctrl->m_used + 1;
@@ -228,11 +255,21 @@ __global__ __launch_bounds__(256) void qr_update_kernel(double* X, int s, int c0
     }
 }
 
+__global__ __launch_bounds__(256) void qr_update_kernel(double* X, int s, int c0, const DevCtrl* ctrl,
+                                                        const double* Tws) {
+    qr_update_body(X, s, c0, ctrl, Tws);
+}
+
+__global__ __launch_bounds__(256) void qr_update_batched_kernel(const SmallUnit* __restrict__ units, int s, int c0) {
+    const SmallUnit& u = units[blockIdx.y];
+    qr_update_body(u.SV, s, c0, u.ctrl, u.Tws);
+}
+
 // --------------------------------------------------------- pencil setup
 // K0 = R_e Hbar ((mu+1) x mu, row-major, ld = m), T1 = R_e[:, :mu] (row-major),
 // where Hbar = [H(:mu, :mu); e_mu^T] and H is banded (k+1 diagonals).
-__global__ void pencil_setup_kernel(const double* X, int s, int m, int k, const DevCtrl* ctrl, const double* H,
-                                    double* K0r, double* T1r) {
+__device__ __forceinline__ void pencil_setup_body(const double* X, int s, int m, int k, const DevCtrl* ctrl,
+                                                  const double* H, double* K0r, double* T1r) {
     const int mu = ctrl->m_used;
     const int64_t ldh = m + 1;
     for (int idx = blockIdx.x * blockDim.x + threadIdx.x; idx < (mu + 1) * mu; idx += gridDim.x * blockDim.x) {
@@ -250,18 +287,23 @@ __global__ void pencil_setup_kernel(const double* X, int s, int m, int k, const 
     }
 }
 
+__global__ void pencil_setup_kernel(const double* X, int s, int m, int k, const DevCtrl* ctrl, const double* H,
+                                    double* K0r, double* T1r) {
+    pencil_setup_body(X, s, m, k, ctrl, H, K0r, T1r);
+}
+
+__global__ void pencil_setup_batched_kernel(const SmallUnit* __restrict__ units, int s, int m, int k) {
+    const SmallUnit& u = units[blockIdx.y];
+    pencil_setup_body(u.SV, s, m, k, u.ctrl, u.H, u.K0r, u.T1r);
+}
+
 // ------------------------------------------------ one-wave pencil solves
-// Solves with P(a) = a T1 + K0 (upper Hessenberg), right-hand side rhs0 e_1.
-//   LS = false: square system P[:mu] y = rhs0 e_1 (Gaussian elimination with
-//               partial pivoting between the two candidate rows of each column)
-//   LS = true:  least squares min || rhs0 e_1 - P y || over the (mu+1) x mu pencil
-//               (Givens rotations)
-// The triangular factor is written row-major into Ubuf (mu x mu, ld = m) and read
-// back by the back substitution.  One wavefront; columns j = lane + 64 q.
-// Returns log|det| and the sign of det(P[:mu]) for the square case in *logdet / *sgn.
+// Helpers of the one-wavefront Hessenberg solves below (vectors distributed as
+// index lane + 64 q over the lanes of the wavefront).
 
 // raw entries of row kk of T1 and K0, columns >= c0 (zero elsewhere); combined into
-// P(a) = a T1 + K0 only when the row is used, so the loads stay in flight
+// P(a) = a T1 + K0 only when the row is used, so the loads stay in flight.
+// T1r == nullptr stands for T1 = I (the square systems a I + H_hat).
 template <int QM>
 struct PRow {
     double t[QM], k[QM];
@@ -271,14 +313,24 @@ template <int QM>
 __device__ __forceinline__ void load_pencil_row(PRow<QM>& row, int kk, int c0, int mu, int m,
                                                 const double* __restrict__ T1r, const double* __restrict__ K0r) {
     const int lane = threadIdx.x & 63;
-    const double* t1 = T1r + (int64_t)kk * m;
     const double* k0 = K0r + (int64_t)kk * m;
+    if (T1r) {
+        const double* t1 = T1r + (int64_t)kk * m;
 #pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        const int jj = lane + WAVE * q;
-        const bool in = jj >= c0 && jj < mu;
-        row.t[q] = in ? t1[jj] : 0.0;
-        row.k[q] = in ? k0[jj] : 0.0;
+        for (int q = 0; q < QM; ++q) {
+            const int jj = lane + WAVE * q;
+            const bool in = jj >= c0 && jj < mu;
+            row.t[q] = in ? t1[jj] : 0.0;
+            row.k[q] = in ? k0[jj] : 0.0;
+        }
+    } else {  // T1 = I
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int jj = lane + WAVE * q;
+            const bool in = jj >= c0 && jj < mu;
+            row.t[q] = (in && jj == kk) ? 1.0 : 0.0;
+            row.k[q] = in ? k0[jj] : 0.0;
+        }
     }
 }
 
@@ -305,6 +357,83 @@ __device__ __forceinline__ void dist_set(double (&v)[QM], int i, double x) {
 #pragma unroll
     for (int q = 0; q < QM; ++q)
         if (q == i / WAVE && lane == i % WAVE) v[q] = x;
+}
+
+// ------------------------------------------------------------- H_hat rows
+// H_hat = H_mu + x e_mu^T with x = R^-1 r, r = R_e[:mu, mu] (the extension column
+// of the QR'd sketch): the projected matrix of the sketched FOM in the basis V_m
+// (remark of Section 2.2).  Written row-major into Hh (ld m) for the square node
+// systems (t I + H_hat) y = beta e_1.  256 threads.  x by blocked back
+// substitution: for each 64-column block from the right, its diagonal block is
+// staged in LDS and solved by wavefront 0 (one lane per row), then all threads
+// update the rows above with the block's columns.
+constexpr int HH_NT = 256;
+constexpr int HH_B = 64;
+
+template <int QM>
+__device__ __forceinline__ void hhat_rows_body(const DevCtrl* ctrl, int m, int s, const double* X,
+                                              const double* T1r, const double* H, double* Hh) {
+    __shared__ double xs[MMAX];
+    __shared__ double D[HH_B][HH_B + 1];
+    __shared__ double dinv[HH_B];
+    (void)QM;
+    const int mu = ctrl->m_used;
+    if (mu == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    const int64_t ldh = m + 1;
+    for (int i = tid; i < mu; i += HH_NT) xs[i] = X[i + (int64_t)s * mu];
+    // H's first mu - 1 columns (independent of x)
+    const int n = mu * (mu - 1);
+    for (int idx = tid; idx < n; idx += HH_NT) {
+        const int i = idx / (mu - 1), j = idx - i * (mu - 1);
+        Hh[(int64_t)i * m + j] = H[i + ldh * j];
+    }
+    for (int kb = ((mu - 1) / HH_B) * HH_B; kb >= 0; kb -= HH_B) {
+        const int nb = min(HH_B, mu - kb);
+        __syncthreads();  // xs of the previous update / initial load complete
+        for (int idx = tid; idx < nb * nb; idx += HH_NT) {
+            const int a = idx / nb, b = idx - a * nb;
+            D[a][b] = (b >= a) ? T1r[(int64_t)(kb + a) * m + (kb + b)] : 0.0;
+        }
+        if (tid < nb) dinv[tid] = 1.0 / T1r[(int64_t)(kb + tid) * m + (kb + tid)];
+        __syncthreads();
+        if (wid == 0) {
+            double r = (lane < nb) ? xs[kb + lane] : 0.0;
+            for (int a = nb - 1; a >= 0; --a) {
+                const double xa = bcast_lane(r, a) * dinv[a];
+                if (lane < a) r = fma(-D[lane][a], xa, r);
+                else if (lane == a) r = xa;
+            }
+            if (lane < nb) xs[kb + lane] = r;
+        }
+        __syncthreads();
+        // rows above the block: xs[i] -= R[i, kb:kb+nb] x[kb:kb+nb]
+        for (int i = tid; i < kb; i += HH_NT) {
+            const double* row = T1r + (int64_t)i * m + kb;
+            double a0 = 0.0, a1 = 0.0;
+            int b = 0;
+            for (; b + 1 < nb; b += 2) {
+                a0 = fma(row[b], xs[kb + b], a0);
+                a1 = fma(row[b + 1], xs[kb + b + 1], a1);
+            }
+            if (b < nb) a0 = fma(row[b], xs[kb + b], a0);
+            xs[i] -= a0 + a1;
+        }
+    }
+    __syncthreads();
+    for (int i = tid; i < mu; i += HH_NT) Hh[(int64_t)i * m + (mu - 1)] = H[i + ldh * (mu - 1)] + xs[i];
+}
+
+template <int QM>
+__global__ __launch_bounds__(HH_NT) void hhat_rows_kernel(const DevCtrl* ctrl, int m, int s, const double* X,
+                                                         const double* T1r, const double* H, double* Hh) {
+    hhat_rows_body<QM>(ctrl, m, s, X, T1r, H, Hh);
+}
+
+template <int QM>
+__global__ __launch_bounds__(HH_NT) void hhat_rows_batched_kernel(const SmallUnit* __restrict__ units, int m, int s) {
+    const SmallUnit& u = units[blockIdx.y];
+    hhat_rows_body<QM>(u.ctrl, m, s, u.SV, u.T1r, u.H, u.Hh);
 }
 
 // Solves with P(a) = a T1 + K0 (upper Hessenberg), right-hand side rhs0 e_1.
@@ -452,20 +581,21 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
     if (sgn) *sgn = sg;
 }
 
-// Node 0 (a = 0): log|det P[:mu]| and its sign (square case), the spectral scale
-// sigma = |det H_hat|^(1/mu) = exp((log|det K0[:mu]| - sum log|R_jj|)/mu), rcond of
-// R, the branch check for z^(-1/2), and -- for f = 1/z -- the solution itself.
+// Node 0 (a = 0): log|det H_hat| and its sign (square case), the spectral scale
+// sigma = |det H_hat|^(1/mu) (geometric mean of the moduli of the sketched Ritz
+// values), rcond of R, the branch check for z^(-1/2) (a negative determinant means
+// an odd number of negative real eigenvalues), and -- for f = 1/z -- the solution
+// itself (H_hat y = beta e_1, or the least-squares pencil problem for sGMRES).
 template <int QM>
-__global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, const double* X, const DevCtrl* ctrl_c,
-                                                                  DevCtrl* ctrl, const double* eta,
-                                                                  const double* T1r, const double* K0r,
-                                                                  double* Ubuf, double* Urhs, double* y0,
-                                                                  int is_ls, int branch_check) {
+__device__ __forceinline__ void pencil_scalars_body(int m, int s, const double* X, const DevCtrl* ctrl_c,
+                                                   DevCtrl* ctrl, const double* eta, const double* T1r,
+                                                   const double* K0r, const double* Hh, double* Ubuf, double* Urhs,
+                                                   double* y0, int is_ls, int branch_check) {
     const int mu = ctrl_c->m_used;
     if (mu == 0) return;
     const int lane = threadIdx.x;
-    // R diagonal statistics
-    double lr = 0.0, rmin = 1e308, rmax = 0.0, rs = 1.0;
+    // R diagonal statistics (rank test)
+    double rmin = 1e308, rmax = 0.0;
     double dg[QM];
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
@@ -475,26 +605,19 @@ __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, 
 #pragma unroll
     for (int q = 0; q < QM; ++q) {
         if (lane + 64 * q < mu) {
-            const double d = dg[q];
-            lr += log(fabs(d));
-            rmin = fmin(rmin, fabs(d));
-            rmax = fmax(rmax, fabs(d));
-            if (d < 0.0) rs = -rs;
+            rmin = fmin(rmin, fabs(dg[q]));
+            rmax = fmax(rmax, fabs(dg[q]));
         }
     }
-    lr = wave_sum(lr);
     rmax = wave_max(rmax);
     rmin = -wave_max(-rmin);
-    // product of signs: count negatives
-    double neg = (rs < 0.0) ? 1.0 : 0.0;
-    neg = wave_sum(neg);
     const double beta = eta[0];
-    const double rhs0 = beta * X[0];
     double ld = 0.0, sg = 1.0;
     if (is_ls) {
-        pencil_solve_wave<true, false, QM>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, nullptr, nullptr);
+        pencil_solve_wave<true, false, QM>(mu, m, 0.0, T1r, K0r, beta * X[0], Ubuf, Urhs, y0, nullptr, nullptr);
     } else {
-        pencil_solve_wave<false, true, QM>(mu, m, 0.0, T1r, K0r, rhs0, Ubuf, Urhs, y0, nullptr, &sg);
+        // H_hat y = beta e_1: the a = 0 system of the square case, and det H_hat
+        pencil_solve_wave<false, true, QM>(mu, m, 0.0, nullptr, Hh, beta, Ubuf, Urhs, y0, nullptr, &sg);
         // log|det| = sum log|U_kk| (sg already holds the sign: row swaps and pivot signs)
         double lu = 0.0;
         for (int kk = lane; kk < mu; kk += 64) lu += log(fabs(Ubuf[(int64_t)kk * m + kk]));
@@ -505,15 +628,31 @@ __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, 
         ctrl->rcond = (rmax > 0.0) ? rmin / rmax : 0.0;
         if (!(rmin > 2.220446049250313e-16 * rmax)) ctrl->status = 3;  // SKFAB_ERR_RANK
         if (!is_ls) {
-            const double lg = (ld - lr) / mu;
-            ctrl->logdet = ld - lr;
+            const double lg = ld / mu;
+            ctrl->logdet = ld;
             ctrl->sigma = exp(lg);
-            const int negs = (int)neg;
-            const double sdet = sg * ((negs & 1) ? -1.0 : 1.0);  // sign of det H_hat
+            const double sdet = sg;  // sign of det H_hat
             if (branch_check && sdet < 0.0 && ctrl->status == 0) ctrl->status = 4;  // SKFAB_ERR_BRANCH
             if (!isfinite(lg) && ctrl->status == 0) ctrl->status = 3;
         }
     }
+}
+
+template <int QM>
+__global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, const double* X, const DevCtrl* ctrl_c,
+                                                                  DevCtrl* ctrl, const double* eta,
+                                                                  const double* T1r, const double* K0r,
+                                                                  const double* Hh, double* Ubuf, double* Urhs,
+                                                                  double* y0, int is_ls, int branch_check) {
+    pencil_scalars_body<QM>(m, s, X, ctrl_c, ctrl, eta, T1r, K0r, Hh, Ubuf, Urhs, y0, is_ls, branch_check);
+}
+
+template <int QM>
+__global__ __launch_bounds__(64) void pencil_scalars_batched_kernel(const SmallUnit* __restrict__ units, int m, int s,
+                                                                    int is_ls, int branch_check) {
+    const SmallUnit& u = units[blockIdx.y];
+    pencil_scalars_body<QM>(m, s, u.SV, u.ctrl, u.ctrl, u.eta, u.T1r, u.K0r, u.Hh, u.Ubuf, u.Urhs, u.y0, is_ls,
+                            branch_check);
 }
 
 // sigma for the least-squares case: use the square pencil's scale as well.
@@ -524,15 +663,17 @@ __global__ __launch_bounds__(64) void pencil_setup_scalars_kernel(int m, int s, 
 // are independent, Section 5.3); the reduction then applies the acceptance test
 // of Section 4.1 to the orders in sequence.
 template <int QM>
-__global__ __launch_bounds__(256) void quad_level_kernel(const DevCtrl* ctrl, QuadGroup grp, const double* T1r,
-                                                         const double* K0r, double* Ubuf, double* Urhs,
-                                                         double* nodebuf, int m, int is_ls, const double* X,
-                                                         const double* eta) {
+__device__ __forceinline__ void quad_level_body(const DevCtrl* ctrl, const QuadGroup& grp, const double* T1r,
+                                               const double* K0r, const double* Hh, double* Ubuf, double* Urhs,
+                                               double* nodebuf, int m, int is_ls, const double* X,
+                                               const double* eta) {
     if (ctrl->converged || ctrl->status != 0) return;
     const int mu = ctrl->m_used;
     if (mu == 0) return;
     const double sigma = ctrl->sigma;
-    const double rhs0 = eta[0] * X[0];
+    // least squares: the pencil t R + R_e Hbar with rhs beta R_00 e_1; square:
+    // t I + H_hat with rhs beta e_1 (the same solution, without the factor R)
+    const double rhs0 = is_ls ? eta[0] * X[0] : eta[0];
     const int wave = blockIdx.x * (blockDim.x / WAVE) + (threadIdx.x / WAVE);
     const int nwaves_total = gridDim.x * (blockDim.x / WAVE);
     double* U = Ubuf + (int64_t)wave * m * m;   // slot = global wave index < NODE_SLOTS
@@ -549,8 +690,23 @@ __global__ __launch_bounds__(256) void quad_level_kernel(const DevCtrl* ctrl, Qu
         if (is_ls)
             pencil_solve_wave<true, false, QM>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
         else
-            pencil_solve_wave<false, false, QM>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
+            pencil_solve_wave<false, false, QM>(mu, m, t * sigma, nullptr, Hh, rhs0 * w, U, Ur, yi, nullptr, nullptr);
     }
+}
+
+template <int QM>
+__global__ __launch_bounds__(256) void quad_level_kernel(const DevCtrl* ctrl, QuadGroup grp, const double* T1r,
+                                                         const double* K0r, const double* Hh, double* Ubuf,
+                                                         double* Urhs, double* nodebuf, int m, int is_ls,
+                                                         const double* X, const double* eta) {
+    quad_level_body<QM>(ctrl, grp, T1r, K0r, Hh, Ubuf, Urhs, nodebuf, m, is_ls, X, eta);
+}
+
+template <int QM>
+__global__ __launch_bounds__(256) void quad_level_batched_kernel(const SmallUnit* __restrict__ units, QuadGroup grp,
+                                                                 int m, int is_ls) {
+    const SmallUnit& u = units[blockIdx.y];
+    quad_level_body<QM>(u.ctrl, grp, u.T1r, u.K0r, u.Hh, u.Ubuf, u.Urhs, u.nodebuf, m, is_ls, u.SV, u.eta);
 }
 
 // For each level of the group: q_l = sqrt(sigma) sum_i nodebuf[i] (fixed order), and
@@ -558,9 +714,9 @@ __global__ __launch_bounds__(256) void quad_level_kernel(const DevCtrl* ctrl, Qu
 // summed in parallel (one wavefront each), then the acceptance test of Section 4.1
 // is applied in sequence: the sequence's first level only seeds qprev; accept q_l
 // when ||R (q_l - q_prev)|| <= tol ||R q_l||.
-__global__ __launch_bounds__(1024) void quad_reduce_kernel(DevCtrl* ctrl, QuadGroup grp, const double* nodebuf, int m,
-                                                           double tol, const double* T1r, double* qprev, double* y,
-                                                           double* qlev) {
+__device__ __forceinline__ void quad_reduce_body(DevCtrl* ctrl, const QuadGroup& grp, const double* nodebuf, int m,
+                                                double tol, const double* T1r, double* qprev, double* y,
+                                                double* qlev) {
     __shared__ double nd[MAX_GROUP_LEVELS], nc[MAX_GROUP_LEVELS];
     __shared__ double qs[MAX_GROUP_LEVELS + 1][MMAX];
     if (ctrl->converged || ctrl->status != 0) return;
@@ -615,10 +771,15 @@ __global__ __launch_bounds__(1024) void quad_reduce_kernel(DevCtrl* ctrl, QuadGr
     int acc_lev = -1;
     int last = grp.nlev - 1;
     bool bad = false;
+    double dprev = ctrl->qdiff_prev;
     for (int lev = 0; lev < grp.nlev; ++lev) {
         if (grp.first && lev == 0) continue;
         if (!isfinite(nd[lev]) || !isfinite(nc[lev])) { bad = true; last = lev; break; }
-        if (sqrt(nd[lev]) <= tol * sqrt(nc[lev])) { acc_lev = lev; break; }
+        // relative difference of consecutive orders; accepted below tol, or at the
+        // rounding floor: below QUAD_FLOOR and no longer falling (d > d_prev / 2)
+        const double d = (nc[lev] > 0.0) ? sqrt(nd[lev] / nc[lev]) : (nd[lev] > 0.0 ? INFINITY : 0.0);
+        if (d <= tol || (d <= QUAD_FLOOR && d > 0.5 * dprev)) { acc_lev = lev; break; }
+        dprev = d;
     }
     if (acc_lev >= 0) {
         for (int jj = threadIdx.x; jj < mu; jj += 1024) y[jj] = qs[acc_lev + 1][jj];
@@ -627,12 +788,29 @@ __global__ __launch_bounds__(1024) void quad_reduce_kernel(DevCtrl* ctrl, QuadGr
     }
     if (threadIdx.x == 0) {
         if (acc_lev >= 0) { ctrl->converged = 1; ctrl->l_used = grp.lev_l[acc_lev]; }
-        else ctrl->l_prev = grp.lev_l[last];
+        else { ctrl->l_prev = grp.lev_l[last]; ctrl->qdiff_prev = dprev; }
         if (bad) ctrl->status = 5;
     }
 }
 
+__global__ __launch_bounds__(1024) void quad_reduce_kernel(DevCtrl* ctrl, QuadGroup grp, const double* nodebuf, int m,
+                                                           double tol, const double* T1r, double* qprev, double* y,
+                                                           double* qlev) {
+    quad_reduce_body(ctrl, grp, nodebuf, m, tol, T1r, qprev, y, qlev);
+}
+
+__global__ __launch_bounds__(1024) void quad_reduce_batched_kernel(const SmallUnit* __restrict__ units, QuadGroup grp,
+                                                                   int m, double tol) {
+    const SmallUnit& u = units[blockIdx.y];
+    quad_reduce_body(u.ctrl, grp, u.nodebuf, m, tol, u.T1r, u.qprev, u.y0, nullptr);
+}
+
 __global__ void quad_fail_kernel(DevCtrl* ctrl) {
+    if (threadIdx.x == 0 && ctrl->status == 0 && !ctrl->converged && ctrl->m_used > 0) ctrl->status = 5;
+}
+
+__global__ void quad_fail_batched_kernel(const SmallUnit* __restrict__ units) {
+    DevCtrl* ctrl = units[blockIdx.y].ctrl;
     if (threadIdx.x == 0 && ctrl->status == 0 && !ctrl->converged && ctrl->m_used > 0) ctrl->status = 5;
 }
 
@@ -669,8 +847,8 @@ __global__ __launch_bounds__(64) void poly_kernel(const DevCtrl* ctrl, int m, co
 }
 
 // ys[j] = y[j] / eta_j (basis stored unnormalised), zero beyond m_used; eps monitor.
-__global__ __launch_bounds__(256) void finish_coeffs_kernel(DevCtrl* ctrl, int m, const double* y, const double* eta,
-                                                            const double* colnorm2, double* ys, double* yout) {
+__device__ __forceinline__ void finish_coeffs_body(DevCtrl* ctrl, int m, const double* y, const double* eta,
+                                                  const double* colnorm2, double* ys, double* yout) {
     __shared__ double scratch[4];
     const int mu = ctrl->m_used;
     double e = 0.0;
@@ -687,12 +865,22 @@ __global__ __launch_bounds__(256) void finish_coeffs_kernel(DevCtrl* ctrl, int m
     }
 }
 
+__global__ __launch_bounds__(256) void finish_coeffs_kernel(DevCtrl* ctrl, int m, const double* y, const double* eta,
+                                                            const double* colnorm2, double* ys, double* yout) {
+    finish_coeffs_body(ctrl, m, y, eta, colnorm2, ys, yout);
+}
+
+__global__ __launch_bounds__(256) void finish_coeffs_batched_kernel(const SmallUnit* __restrict__ units, int m) {
+    const SmallUnit& u = units[blockIdx.y];
+    finish_coeffs_body(u.ctrl, m, u.y0, u.eta, u.colnorm2, u.ys, u.y);
+}
+
 // x = U ys (N x mu times mu), rows parallel, coalesced over the basis columns; the
 // basis is read in its storage type and accumulated in FP64.
 template <typename VT>
-__global__ __launch_bounds__(256) void assemble_kernel(const VT* __restrict__ U, int64_t ldU, int64_t N, int m,
-                                                       const DevCtrl* ctrl, const double* __restrict__ ys,
-                                                       double* __restrict__ x) {
+__device__ __forceinline__ void assemble_body(const VT* __restrict__ U, int64_t ldU, int64_t N, int m,
+                                             const DevCtrl* ctrl, const double* __restrict__ ys,
+                                             double* __restrict__ x) {
     __shared__ double c[MMAX];
     const int mu = ctrl->m_used;
     for (int j = threadIdx.x; j < m; j += blockDim.x) c[j] = (j < mu) ? ys[j] : 0.0;
@@ -709,6 +897,19 @@ __global__ __launch_bounds__(256) void assemble_kernel(const VT* __restrict__ U,
         for (; j < mu; ++j) a0 = fma(to_w<double>(U[r + ldU * j]), c[j], a0);
         x[r] = (a0 + a1) + (a2 + a3);
     }
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void assemble_kernel(const VT* __restrict__ U, int64_t ldU, int64_t N, int m,
+                                                       const DevCtrl* ctrl, const double* __restrict__ ys,
+                                                       double* __restrict__ x) {
+    assemble_body<VT>(U, ldU, N, m, ctrl, ys, x);
+}
+
+template <typename VT>
+__global__ __launch_bounds__(256) void assemble_batched_kernel(const SmallUnit* __restrict__ units, int m) {
+    const SmallUnit& u = units[blockIdx.y];
+    assemble_body<VT>(static_cast<const VT*>(u.U), u.ldU, u.N, m, u.ctrl, u.ys, u.x);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -747,28 +948,37 @@ hipError_t launch_pencil_setup(const double* X, int s, int m, int k, const DevCt
     return hipGetLastError();
 }
 
+hipError_t launch_hhat_rows(const DevCtrl* ctrl, int m, int s, const double* X, const double* T1r, const double* H,
+                            double* Hh, hipStream_t st) {
+    if (m <= 256)
+        hipLaunchKernelGGL(hhat_rows_kernel<4>, dim3(1), dim3(HH_NT), 0, st, ctrl, m, s, X, T1r, H, Hh);
+    else
+        hipLaunchKernelGGL(hhat_rows_kernel<8>, dim3(1), dim3(HH_NT), 0, st, ctrl, m, s, X, T1r, H, Hh);
+    return hipGetLastError();
+}
+
 hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, const double* eta,
-                                 const double* T1r, const double* K0r, double* Ubuf, double* Urhs, double* y0,
-                                 int is_ls, int branch_check, hipStream_t st) {
+                                 const double* T1r, const double* K0r, const double* Hh, double* Ubuf, double* Urhs,
+                                 double* y0, int is_ls, int branch_check, hipStream_t st) {
     if (m <= 256)
         hipLaunchKernelGGL(pencil_setup_scalars_kernel<4>, dim3(1), dim3(64), 0, st, m, s, X, ctrl, ctrl, eta, T1r,
-                           K0r, Ubuf, Urhs, y0, is_ls, branch_check);
+                           K0r, Hh, Ubuf, Urhs, y0, is_ls, branch_check);
     else
         hipLaunchKernelGGL(pencil_setup_scalars_kernel<8>, dim3(1), dim3(64), 0, st, m, s, X, ctrl, ctrl, eta, T1r,
-                           K0r, Ubuf, Urhs, y0, is_ls, branch_check);
+                           K0r, Hh, Ubuf, Urhs, y0, is_ls, branch_check);
     return hipGetLastError();
 }
 
 hipError_t launch_quad_group(const DevCtrl* ctrl, const QuadGroup& g, const double* T1r, const double* K0r,
-                             double* Ubuf, double* Urhs, double* nodebuf, int m, int is_ls, const double* X,
-                             const double* eta, hipStream_t st) {
+                             const double* Hh, double* Ubuf, double* Urhs, double* nodebuf, int m, int is_ls,
+                             const double* X, const double* eta, hipStream_t st) {
     const int waves = g.total < NODE_SLOTS ? g.total : NODE_SLOTS;
     const int blocks = (waves + 3) / 4;
     if (m <= 256)
-        hipLaunchKernelGGL(quad_level_kernel<4>, dim3(blocks), dim3(256), 0, st, ctrl, g, T1r, K0r, Ubuf, Urhs,
+        hipLaunchKernelGGL(quad_level_kernel<4>, dim3(blocks), dim3(256), 0, st, ctrl, g, T1r, K0r, Hh, Ubuf, Urhs,
                            nodebuf, m, is_ls, X, eta);
     else
-        hipLaunchKernelGGL(quad_level_kernel<8>, dim3(blocks), dim3(256), 0, st, ctrl, g, T1r, K0r, Ubuf, Urhs,
+        hipLaunchKernelGGL(quad_level_kernel<8>, dim3(blocks), dim3(256), 0, st, ctrl, g, T1r, K0r, Hh, Ubuf, Urhs,
                            nodebuf, m, is_ls, X, eta);
     return hipGetLastError();
 }
@@ -810,6 +1020,97 @@ hipError_t launch_assemble(const void* U, int64_t ldU, int64_t N, int m, const D
     else
         hipLaunchKernelGGL(assemble_kernel<double>, grid, dim3(256), 0, st, static_cast<const double*>(U), ldU, N, m,
                            ctrl, ys, x);
+    return hipGetLastError();
+}
+
+
+// ------------------------------------------------------- batched launchers
+// Every unit uses the common leading dimensions m (= m_max) and s (= s_max).
+hipError_t launch_init_ctrl_batched(const SmallUnit* units, int nunits, hipStream_t st) {
+    hipLaunchKernelGGL(init_ctrl_batched_kernel, dim3(1, nunits), dim3(64), 0, st, units);
+    return hipGetLastError();
+}
+
+hipError_t launch_qr_batched(const SmallUnit* units, int nunits, int s, int ncols_max, hipStream_t st) {
+    for (int c0 = 0; c0 < ncols_max; c0 += QR_NB) {
+        const int nrows = s - c0;
+        const size_t lds = (size_t)QR_NB * nrows * sizeof(double);
+        hipLaunchKernelGGL(qr_panel_batched_kernel, dim3(1, nunits), dim3(QR_NT), lds, st, units, s, c0);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        const int rest = ncols_max - c0 - QR_NB;
+        if (rest > 0) {
+            hipLaunchKernelGGL(qr_update_batched_kernel, dim3(rest, nunits), dim3(256), 0, st, units, s, c0);
+            e = hipGetLastError();
+            if (e != hipSuccess) return e;
+        }
+    }
+    return hipSuccess;
+}
+
+hipError_t launch_pencil_setup_batched(const SmallUnit* units, int nunits, int s, int m, int k, hipStream_t st) {
+    const int n = (m + 1) * m;
+    hipLaunchKernelGGL(pencil_setup_batched_kernel, dim3((n + 255) / 256, nunits), dim3(256), 0, st, units, s, m, k);
+    return hipGetLastError();
+}
+
+hipError_t launch_hhat_rows_batched(const SmallUnit* units, int nunits, int m, int s, hipStream_t st) {
+    if (m <= 256)
+        hipLaunchKernelGGL(hhat_rows_batched_kernel<4>, dim3(1, nunits), dim3(HH_NT), 0, st, units, m, s);
+    else
+        hipLaunchKernelGGL(hhat_rows_batched_kernel<8>, dim3(1, nunits), dim3(HH_NT), 0, st, units, m, s);
+    return hipGetLastError();
+}
+
+hipError_t launch_pencil_scalars_batched(const SmallUnit* units, int nunits, int m, int s, int is_ls, int branch_check,
+                                         hipStream_t st) {
+    if (m <= 256)
+        hipLaunchKernelGGL(pencil_scalars_batched_kernel<4>, dim3(1, nunits), dim3(64), 0, st, units, m, s, is_ls,
+                           branch_check);
+    else
+        hipLaunchKernelGGL(pencil_scalars_batched_kernel<8>, dim3(1, nunits), dim3(64), 0, st, units, m, s, is_ls,
+                           branch_check);
+    return hipGetLastError();
+}
+
+// slots: quadrature scratch slots (wavefronts) per unit; Ubuf holds slots x m x m per unit
+hipError_t launch_quad_group_batched(const SmallUnit* units, int nunits, const QuadGroup& g, int m, int is_ls,
+                                     int slots, hipStream_t st) {
+    const int waves = g.total < slots ? g.total : slots;
+    const int blocks = (waves + 3) / 4;
+    if (m <= 256)
+        hipLaunchKernelGGL(quad_level_batched_kernel<4>, dim3(blocks, nunits), dim3(256), 0, st, units, g, m, is_ls);
+    else
+        hipLaunchKernelGGL(quad_level_batched_kernel<8>, dim3(blocks, nunits), dim3(256), 0, st, units, g, m, is_ls);
+    return hipGetLastError();
+}
+
+hipError_t launch_quad_reduce_batched(const SmallUnit* units, int nunits, const QuadGroup& g, int m, double tol,
+                                      hipStream_t st) {
+    hipLaunchKernelGGL(quad_reduce_batched_kernel, dim3(1, nunits), dim3(1024), 0, st, units, g, m, tol);
+    return hipGetLastError();
+}
+
+hipError_t launch_quad_fail_batched(const SmallUnit* units, int nunits, hipStream_t st) {
+    hipLaunchKernelGGL(quad_fail_batched_kernel, dim3(1, nunits), dim3(64), 0, st, units);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish_coeffs_batched(const SmallUnit* units, int nunits, int m, hipStream_t st) {
+    hipLaunchKernelGGL(finish_coeffs_batched_kernel, dim3(1, nunits), dim3(256), 0, st, units, m);
+    return hipGetLastError();
+}
+
+hipError_t launch_assemble_batched(const SmallUnit* units, int nunits, int64_t nmax, int m, int prec,
+                                   hipStream_t st) {
+    int64_t g = (nmax + 255) / 256;
+    const dim3 grid((unsigned)(g < 1024 ? g : 1024), nunits);
+    if (prec == 1)
+        hipLaunchKernelGGL(assemble_batched_kernel<float>, grid, dim3(256), 0, st, units, m);
+    else if (prec == 2)
+        hipLaunchKernelGGL(assemble_batched_kernel<bf16s>, grid, dim3(256), 0, st, units, m);
+    else
+        hipLaunchKernelGGL(assemble_batched_kernel<double>, grid, dim3(256), 0, st, units, m);
     return hipGetLastError();
 }
 

@@ -201,3 +201,83 @@ def skfab_timing_read(ctx: Context, kernel: int = 0):
     n = C.c_int64()
     _check(N.lib().skfab_timing_read(ctx.handle, kernel, C.byref(ms), C.byref(n)), "skfab_timing_read")
     return ms.value, n.value
+
+
+# ----------------------------------------------------------------- batches
+@dataclass
+class BatchProblem:
+    """One problem of a batch: device CSR, right-hand sides B and results X as
+    (nrhs, N) contiguous float64 tensors (row r = column r of the C ABI's
+    column-major N x nrhs), Krylov dimension m, sketch size s and sketch seed."""
+    A: CSR
+    B: torch.Tensor
+    X: torch.Tensor
+    m: int
+    s: int
+    seed: int = 0
+
+
+def _batch_array(probs, need_data: bool = True):
+    arr = (N.skfab_batch_problem * len(probs))()
+    for i, q in enumerate(probs):
+        if need_data:
+            _require_device(q.B, torch.float64, "B")
+            _require_device(q.X, torch.float64, "X")
+            if q.B.shape != q.X.shape or q.B.dim() != 2 or q.B.shape[1] != q.A.n:
+                raise ValueError("B and X must be (nrhs, N) tensors of the problem's size")
+            arr[i].A = q.A.c_struct()
+            arr[i].B = q.B.data_ptr()
+            arr[i].X = q.X.data_ptr()
+        else:
+            arr[i].A = N.skfab_csr(q.A.n, q.A.col.numel(), None, None, None, N.SKFAB_VAL_F64)
+        arr[i].m, arr[i].s, arr[i].seed = int(q.m), int(q.s), int(q.seed)
+    return arr
+
+
+def _nrhs(probs) -> int:
+    r = {int(q.B.shape[0]) for q in probs}
+    if len(r) != 1:
+        raise ValueError("every problem of a batch needs the same number of right-hand sides")
+    return r.pop()
+
+
+def skfab_batch_workspace_bytes(probs, p: N.skfab_params, nrhs: int | None = None) -> int:
+    nr = _nrhs(probs) if nrhs is None else int(nrhs)
+    out = C.c_size_t()
+    _check(N.lib().skfab_batch_workspace_bytes(len(probs), _batch_array(probs, False), nr, C.byref(p),
+                                               C.byref(out)), "skfab_batch_workspace_bytes")
+    return out.value
+
+
+def skfab_solve_batched(ctx: Context, probs, p: N.skfab_params, ws: torch.Tensor, want_info: bool = True):
+    """X_p[r] <- f(A_p) B_p[r] for every problem p and right-hand side r; returns a
+    list (per problem) of lists (per right-hand side) of skfab_info, or None."""
+    nr = _nrhs(probs)
+    arr = _batch_array(probs)
+    info = (N.skfab_info * (len(probs) * nr))() if want_info else None
+    st = N.lib().skfab_solve_batched(ctx.handle, len(probs), arr, nr, C.byref(p), _ptr(ws), ws.numel(), info)
+    _check(st, "skfab_solve_batched")
+    if info is None:
+        return None
+    return [[info[i * nr + r] for r in range(nr)] for i in range(len(probs))]
+
+
+def skfab_batch_set_tuning(ctx: Context, block: int, slices_per_wave: int):
+    t = N.skfab_batch_tuning(int(block), int(slices_per_wave))
+    _check(N.lib().skfab_batch_set_tuning(ctx.handle, C.byref(t)), "skfab_batch_set_tuning")
+
+
+def skfab_batch_get_tuning(ctx: Context):
+    t = N.skfab_batch_tuning()
+    _check(N.lib().skfab_batch_get_tuning(ctx.handle, C.byref(t)), "skfab_batch_get_tuning")
+    return t.block, t.slices_per_wave
+
+
+def skfab_batch_autotune(ctx: Context, probs, p: N.skfab_params, ws: torch.Tensor, steps: int = 4):
+    """Time every launch shape of the batched step kernel on this batch; keeps and
+    returns the fastest (block, slices_per_wave)."""
+    nr = _nrhs(probs)
+    t = N.skfab_batch_tuning()
+    _check(N.lib().skfab_batch_autotune(ctx.handle, len(probs), _batch_array(probs), nr, C.byref(p), _ptr(ws),
+                                        ws.numel(), int(steps), C.byref(t)), "skfab_batch_autotune")
+    return t.block, t.slices_per_wave

@@ -1,0 +1,144 @@
+"""Batched form through the C ABI: several 2D convection-diffusion problems of
+uneven size, Krylov dimension and convection, each with several right-hand
+sides, in one skfab_solve_batched call; every (problem, right-hand side) pair is
+checked against the FP64 oracle run on that pair alone (same sketch, m, k), and
+against the single-problem GPU path.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+import torch
+
+from gpu_common import ctx, gpu_solve, log, oracle_run, rel
+from oracle import methods as ometh
+from paper_2208_11447_amd import skfab as sk
+from workloads import convdiff_csr, gaussian_rhs
+
+pytestmark = pytest.mark.gpu
+
+# (grid n, convection, m) per problem: N from 1600 to 4096, m from 18 to 44
+SPECS = [(40, 10.0, 30), (64, 150.0, 44), (48, 80.0, 18), (56, 40.0, 36)]
+NRHS = 3
+
+
+def build_batch(specs=SPECS, nrhs=NRHS, seed0=100):
+    hosts, probs = [], []
+    for i, (n, c, m) in enumerate(specs):
+        rp, col, val = convdiff_csr(n, 2, 1.0, c)
+        N_ = rp.size - 1
+        B = gaussian_rhs(N_, seed0 + i, nrhs)  # N x nrhs
+        if nrhs == 1:
+            B = B[:, None]
+        A = sk.CSR.from_numpy(rp, col, val)
+        Bt = torch.as_tensor(np.ascontiguousarray(B.T), device="cuda")
+        Xt = torch.full_like(Bt, np.nan)
+        probs.append(sk.BatchProblem(A, Bt, Xt, m=m, s=2 * m, seed=i))
+        hosts.append((sp.csr_matrix((val, col, rp), shape=(N_, N_)), np.asarray(B), (rp, col, val)))
+    return hosts, probs
+
+
+def run_batch(probs, **pkw):
+    p = sk.make_params(**pkw)
+    ws = sk.alloc_workspace(sk.skfab_batch_workspace_bytes(probs, p))
+    info = sk.skfab_solve_batched(ctx(), probs, p, ws)
+    torch.cuda.synchronize()
+    return [q.X.cpu().numpy() for q in probs], info
+
+
+@pytest.fixture(scope="module")
+def batch():
+    return build_batch()
+
+
+@pytest.mark.parametrize("method", ["sfom", "sgmres"])
+def test_batched_matches_oracle(batch, method):
+    hosts, probs = batch
+    X, info = run_batch(probs, f="invsqrt", k=2, method=method)
+    worst = 0.0
+    for i, ((A, B, _), q) in enumerate(zip(hosts, probs)):
+        for r in range(NRHS):
+            assert info[i][r].status == 0, (i, r, info[i][r].status)
+            assert info[i][r].m_used == q.m
+            arn, _ = oracle_run(A, B[:, r], q.m, 2, q.s, seed=q.seed)
+            xr = ometh.sfom_closed(arn, "invsqrt").x if method == "sfom" else ometh.sgmres(arn, "invsqrt",
+                                                                                           tol=1e-13).x
+            e = rel(X[i][r], xr)
+            worst = max(worst, e)
+            assert e < 1e-10, (i, r, e)
+    log(f"batched {method}: {len(probs)} problems x {NRHS} rhs, worst rel. err vs oracle {worst:.2e}")
+
+
+def test_batched_equals_single_problem_path(batch):
+    hosts, probs = batch
+    X, _ = run_batch(probs, f="invsqrt", k=2)
+    worst = 0.0
+    for i, ((A, B, arrs), q) in enumerate(zip(hosts, probs)):
+        for r in range(NRHS):
+            xs, inf = gpu_solve(arrs, B[:, r], f="invsqrt", m=q.m, k=2, s=q.s, seed=q.seed)
+            assert inf.status == 0
+            worst = max(worst, rel(X[i][r], xs))
+    log(f"batched vs single-problem GPU path: worst rel. diff {worst:.2e}")
+    assert worst < 1e-12
+
+
+def test_batched_inverse_and_determinism(batch):
+    hosts, probs = batch
+    X1, info = run_batch(probs, f="inv", k=2)
+    X2, _ = run_batch(probs, f="inv", k=2)
+    for i, ((A, B, _), q) in enumerate(zip(hosts, probs)):
+        assert np.array_equal(X1[i], X2[i]), "batched solve is not bitwise reproducible"
+        for r in range(NRHS):
+            assert info[i][r].status == 0
+            arn, _ = oracle_run(A, B[:, r], q.m, 2, q.s, seed=q.seed)
+            assert rel(X1[i][r], ometh.sfom_closed(arn, "inv").x) < 1e-10
+
+
+def test_batched_breakdown_and_single_rhs():
+    """A problem whose right-hand side lies in a 3-dimensional invariant subspace
+    (lucky breakdown at m_used = 3) batched with a regular one, one rhs each."""
+    hosts, probs = build_batch(specs=[(48, 40.0, 30)], nrhs=1)
+    Nb = 1500
+    rng = np.random.default_rng(7)
+    blk = np.diag(rng.uniform(2.0, 5.0, 3)) + np.triu(rng.uniform(-0.3, 0.3, (3, 3)), 1)
+    diag = rng.uniform(1.0, 9.0, Nb)
+    A = sp.lil_matrix((Nb, Nb))
+    A.setdiag(diag)
+    A[:3, :3] = blk
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    b = np.zeros(Nb)
+    b[:3] = rng.standard_normal(3)
+    Ad = sk.CSR.from_numpy(A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data)
+    Bt = torch.as_tensor(b[None, :].copy(), device="cuda")
+    probs.append(sk.BatchProblem(Ad, Bt, torch.zeros_like(Bt), m=12, s=40, seed=9))
+    X, info = run_batch(probs, f="invsqrt", k=3)
+    assert info[1][0].status == 0 and info[1][0].m_used == 3
+    import scipy.linalg as sla
+    truth = np.zeros(Nb)
+    truth[:3] = np.linalg.solve(sla.sqrtm(blk).real, b[:3])
+    assert rel(X[1][0], truth) < 1e-10
+    assert info[0][0].status == 0 and info[0][0].m_used == 30
+    arn, _ = oracle_run(hosts[0][0], hosts[0][1][:, 0], 30, 3, 60, seed=0)
+    assert rel(X[0][0], ometh.sfom_closed(arn, "invsqrt").x) < 1e-10
+
+
+def test_batched_autotune_keeps_results(batch):
+    hosts, probs = batch
+    p = sk.make_params(f="invsqrt", k=2)
+    ws = sk.alloc_workspace(sk.skfab_batch_workspace_bytes(probs, p))
+    c = ctx()
+    saved = sk.skfab_batch_get_tuning(c)
+    try:
+        X0, _ = run_batch(probs, f="invsqrt", k=2)
+        block, spw = sk.skfab_batch_autotune(c, probs, p, ws, steps=3)
+        assert block in (256, 512, 1024) and spw in (1, 2, 4, 8, 16, 32, 64)
+        assert sk.skfab_batch_get_tuning(c) == (block, spw)
+        log(f"autotuned launch shape on the test batch: block {block}, {spw} slices per wavefront")
+        for blk, s in ((256, 2), (512, 8), (block, spw)):
+            sk.skfab_batch_set_tuning(c, blk, s)
+            X1, info = run_batch(probs, f="invsqrt", k=2)
+            for i in range(len(probs)):
+                assert all(info[i][r].status == 0 for r in range(NRHS))
+                assert rel(X1[i], X0[i]) < 1e-12
+    finally:
+        sk.skfab_batch_set_tuning(c, *saved)

@@ -80,3 +80,52 @@ def test_status_strings():
     for s in range(8):
         assert lib.skfab_status_string(s)
     assert lib.skfab_status_string(99) == b"unknown status"
+
+
+def _batch(sizes, ms, ss=None):
+    arr = (N.skfab_batch_problem * len(sizes))()
+    for i, (n, m) in enumerate(zip(sizes, ms)):
+        arr[i].A = N.skfab_csr(n, 5 * n, None, None, None, 0)
+        arr[i].m = m
+        arr[i].s = 2 * m if ss is None else ss[i]
+        arr[i].seed = i
+    return arr
+
+
+def _batch_ws(sizes, ms, nrhs=4, ss=None, **kw):
+    out = C.c_size_t()
+    st = N.lib().skfab_batch_workspace_bytes(len(sizes), _batch(sizes, ms, ss), nrhs, C.byref(_params(**kw)),
+                                             C.byref(out))
+    return st, out.value
+
+
+def test_batch_workspace_holds_every_basis():
+    sizes, ms = [65_536, 262_144, 1_048_576], [80, 250, 160]
+    st, nbytes = _batch_ws(sizes, ms)
+    assert st == N.SKFAB_OK
+    # four right-hand sides per problem, each with its own N x m basis
+    assert nbytes >= sum(4 * 8 * n * m for n, m in zip(sizes, ms))
+    st1, one = _batch_ws(sizes, ms, nrhs=1)
+    assert st1 == N.SKFAB_OK and one < nbytes
+
+
+@pytest.mark.parametrize("kw,nrhs,status", [
+    (dict(), 5, N.SKFAB_ERR_ARG),            # at most 4 right-hand sides
+    (dict(), 0, N.SKFAB_ERR_ARG),
+    (dict(f=1), 4, N.SKFAB_ERR_ARG),         # exp is not offered batched
+    (dict(zeta=4), 4, N.SKFAB_ERR_ARG),      # batched kernels: 8 nonzeros per column
+    (dict(k=5), 4, N.SKFAB_ERR_ARG),
+    (dict(prec=3), 4, N.SKFAB_ERR_ARG),
+])
+def test_batch_host_validation(kw, nrhs, status):
+    st, _ = _batch_ws([10_000, 20_000], [50, 60], nrhs=nrhs, **kw)
+    assert st == status
+
+
+def test_batch_shape_validation():
+    assert _batch_ws([10_000], [50], ss=[50])[0] == N.SKFAB_ERR_SHAPE       # s > m
+    assert _batch_ws([100], [50], ss=[200])[0] == N.SKFAB_ERR_SHAPE        # s <= N
+    assert _batch_ws([10_000], [600], ss=[1000])[0] == N.SKFAB_ERR_SHAPE   # m <= 512
+    out = C.c_size_t()
+    assert N.lib().skfab_batch_workspace_bytes(0, _batch([10], [2]), 1, C.byref(_params()),
+                                               C.byref(out)) == N.SKFAB_ERR_ARG
