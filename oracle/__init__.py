@@ -18,10 +18,13 @@ step, in NumPy/SciPy double precision:
                    the adaptive order sequence (Section 4.1, Section 5.1),
 * ``methods``    - whitening QR, the closed form (sFOM'''), the integral forms
                    (sFOM) and (sGMRES), the equivalent forms used as pins, and
-                   the sketched stopping estimate (Section 4.3).
+                   the sketched stopping estimate and the adaptive-m loop
+                   (Section 4.3),
+* ``features``   - Gershgorin bounds (controller features),
+* ``mlp``        - the controller network, its loss gradient and Adam step.
 
 Parity status: every function here is pinned by a CPU test against values the
 paper prints or against mathematics it fixes (closed forms, invariants,
 special cases); see tests/test_oracle_*.py.
 """
-from . import sketch, arnoldi, quadrature, methods  # noqa: F401
+from . import sketch, arnoldi, quadrature, methods, features, mlp  # noqa: F401

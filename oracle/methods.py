@@ -290,3 +290,52 @@ def solve(A, b, f: str, m: int, k: int, S, method: str = "sfom", fparam: float =
     else:
         raise ValueError(method)
     return res, arn
+
+
+# ------------------------------------------------ adaptive m (Section 4.3) ---
+def _prefix(arn: ArnoldiResult, m: int) -> ArnoldiResult:
+    """The data of the first m steps of a longer run: the truncated recurrence is
+    sequential, so these are exactly the arrays an m-step run produces."""
+    return ArnoldiResult(arn.V[:, :m].copy(), arn.SV[:, :m].copy(), arn.SAV[:, :m].copy(),
+                         arn.H[:m + 1, :m].copy(), arn.beta, m)
+
+
+def relative_stopping_estimate(arn_m: ArnoldiResult, y_m: np.ndarray, y_prev: np.ndarray) -> float:
+    """Relative form of the Section 4.3 estimate used by the adaptive loop:
+    || S V_m (y_m - [y_prev; 0]) || / || S V_m y_m || * sqrt((1 + eps) / (1 - eps)),
+    i.e. the upper estimate of ||f_m - f_prev|| over the lower estimate of ||f_m||
+    (eps from the Section 4.3 monitor)."""
+    eps = embedding_eps_estimate(arn_m)
+    num = sketched_difference(arn_m.SV, y_m, y_prev)
+    den = float(np.linalg.norm(arn_m.SV @ y_m))
+    if den == 0.0:
+        return 0.0 if num == 0.0 else np.inf
+    return num / den * np.sqrt((1.0 + eps) / (1.0 - eps))
+
+
+def adaptive_m(A, b, f: str, k: int, S, m0: int, d: int, m_max: int, tol: float,
+               fparam: float = 0.0):
+    """Plain adaptive-m sketched FOM: evaluate the closed form at m0, m0 + d, ...
+    (<= m_max) on the nested truncated basis and stop at the first m whose
+    relative stopping estimate against the previous checkpoint is <= tol.
+    Returns (SolveResult, m_stop, estimate); the estimate is inf when no
+    checkpoint pair passed (the result is then the one at the last checkpoint).
+    A breakdown before a checkpoint ends the loop with the exact result."""
+    from .arnoldi import truncated_arnoldi
+    arn = truncated_arnoldi(A, b, m_max, k, S)
+    prev = None
+    est = np.inf
+    res = None
+    m = m0
+    while m <= m_max:
+        if arn.m_used < m:
+            return sfom_closed(arn, f, fparam), arn.m_used, 0.0
+        am = _prefix(arn, m)
+        res = sfom_closed(am, f, fparam)
+        if prev is not None:
+            est = relative_stopping_estimate(am, res.y, prev.y)
+            if est <= tol:
+                return res, m, est
+        prev = res
+        m += d
+    return res, m - d, est
