@@ -285,6 +285,52 @@ skfab_status skfab_batch_autotune(skfab_ctx *ctx, int32_t nprob, const skfab_bat
                                   int32_t nrhs, const skfab_params *p, void *ws, size_t ws_bytes,
                                   int32_t steps, skfab_batch_tuning *chosen);
 
+/* ------------------------------------------------------------ adaptive m
+ * Sketched FOM with the Krylov dimension chosen on the fly (Section 4.3): the
+ * recurrence runs up to p->m steps; at the checkpoints m0, m0 + d, ... (< p->m)
+ * the approximant of the first m' steps is formed from the nested basis, and the
+ * run stops at the first checkpoint whose relative stopping estimate against the
+ * previous checkpoint,
+ *     || S V_m' (y_m' - [y_prev; 0]) || / || S V_m' y_m' || * sqrt((1+eps)/(1-eps)),
+ * eps = max_j | ||S v_j||^2 - 1 |  (the Section 4.3 monitor), is <= tol.  Without
+ * such a checkpoint the result is the full p->m solve (its estimate against the
+ * last checkpoint is returned).  Every checkpoint synchronises the stream once.
+ *   p->method must be SKFAB_SFOM_CLOSED; k <= m0 <= p->m, d >= 1, tol > 0.
+ *   m_stop, estimate: optional host outputs; info as for skfab_solve.
+ *   ws: at least skfab_adaptive_workspace_bytes, 256-byte aligned. */
+skfab_status skfab_adaptive_workspace_bytes(const skfab_csr *A, const skfab_params *p, size_t *bytes);
+skfab_status skfab_solve_adaptive(skfab_ctx *ctx, const skfab_csr *A, const double *b, double *x,
+                                  const skfab_params *p, int32_t m0, int32_t d, double tol,
+                                  void *ws, size_t ws_bytes, skfab_info *info, int32_t *m_stop,
+                                  double *estimate);
+
+/* ----------------------------------------------------- learned controller
+ * Features and the network of the controller that predicts (m, k, s) for a
+ * requested tolerance (the plain adaptive-m solve above is its fallback).
+ *
+ * bounds[0] = min_i (a_ii - sum_{j != i} |a_ij|), bounds[1] = max_i (a_ii + sum |a_ij|)
+ * (Gershgorin discs), device double[2]; ws of skfab_gershgorin_ws_bytes(n) bytes. */
+size_t skfab_gershgorin_ws_bytes(int64_t n);
+skfab_status skfab_gershgorin(skfab_ctx *ctx, const skfab_csr *A, double *bounds, void *ws,
+                              size_t ws_bytes);
+
+/* Network 16 -> 64 -> 64 -> 3, ReLU hidden layers, linear output, FP32.
+ * params: device float[skfab_mlp_param_count()] laid out row-major as
+ * W1[64][16], b1[64], W2[64][64], b2[64], W3[3][64], b3[3].
+ * X: device float[B][16]; Y, T: device float[B][3]; ws: skfab_mlp_ws_bytes(B).
+ * loss_grad: grad (device, param_count) of L = (1/(3B)) sum (y - t)^2, and L in
+ * *loss (device float, may be NULL).  adam: one Adam step (Kingma & Ba 2015) with
+ * step number t >= 1 on params with moment buffers m1, m2 (device, param_count). */
+int32_t skfab_mlp_param_count(void);
+size_t skfab_mlp_ws_bytes(int32_t batch);
+skfab_status skfab_mlp_forward(skfab_ctx *ctx, const float *X, int32_t B, const float *params,
+                               float *Y, void *ws, size_t ws_bytes);
+skfab_status skfab_mlp_loss_grad(skfab_ctx *ctx, const float *X, const float *T, int32_t B,
+                                 const float *params, float *grad, float *loss, void *ws,
+                                 size_t ws_bytes);
+skfab_status skfab_mlp_adam(skfab_ctx *ctx, float *params, const float *grad, float *m1, float *m2,
+                            int32_t t, float lr, float beta1, float beta2, float eps);
+
 #ifdef __cplusplus
 }
 #endif

@@ -26,6 +26,8 @@ EXPORTED = [
     "skfab_timing_enable", "skfab_timing_read",
     "skfab_batch_workspace_bytes", "skfab_solve_batched", "skfab_batch_set_tuning", "skfab_batch_get_tuning",
     "skfab_batch_autotune",
+    "skfab_adaptive_workspace_bytes", "skfab_solve_adaptive", "skfab_gershgorin_ws_bytes", "skfab_gershgorin",
+    "skfab_mlp_param_count", "skfab_mlp_ws_bytes", "skfab_mlp_forward", "skfab_mlp_loss_grad", "skfab_mlp_adam",
 ]
 
 
@@ -97,6 +99,18 @@ def lib():
         "skfab_batch_autotune": (C.c_int, [P, C.c_int32, C.POINTER(skfab_batch_problem), C.c_int32,
                                            C.POINTER(skfab_params), P, C.c_size_t, C.c_int32,
                                            C.POINTER(skfab_batch_tuning)]),
+        "skfab_adaptive_workspace_bytes": (C.c_int, [C.POINTER(skfab_csr), C.POINTER(skfab_params),
+                                                     C.POINTER(C.c_size_t)]),
+        "skfab_solve_adaptive": (C.c_int, [P, C.POINTER(skfab_csr), P, P, C.POINTER(skfab_params), C.c_int32,
+                                           C.c_int32, C.c_double, P, C.c_size_t, C.POINTER(skfab_info),
+                                           C.POINTER(C.c_int32), C.POINTER(C.c_double)]),
+        "skfab_gershgorin_ws_bytes": (C.c_size_t, [C.c_int64]),
+        "skfab_gershgorin": (C.c_int, [P, C.POINTER(skfab_csr), P, P, C.c_size_t]),
+        "skfab_mlp_param_count": (C.c_int32, []),
+        "skfab_mlp_ws_bytes": (C.c_size_t, [C.c_int32]),
+        "skfab_mlp_forward": (C.c_int, [P, P, C.c_int32, P, P, P, C.c_size_t]),
+        "skfab_mlp_loss_grad": (C.c_int, [P, P, P, C.c_int32, P, P, P, P, C.c_size_t]),
+        "skfab_mlp_adam": (C.c_int, [P, P, P, P, P, C.c_int32, C.c_float, C.c_float, C.c_float, C.c_float]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(L, name)

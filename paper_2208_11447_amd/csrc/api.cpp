@@ -80,6 +80,21 @@ hipError_t launch_quad_fail_batched(const SmallUnit* units, int nunits, hipStrea
 hipError_t launch_finish_coeffs_batched(const SmallUnit* units, int nunits, int m, hipStream_t st);
 hipError_t launch_assemble_batched(const SmallUnit* units, int nunits, int64_t nmax, int m, int prec,
                                    hipStream_t st);
+hipError_t launch_snapshot(const double* SV, int s, const double* H, int64_t ldh, const double* eta, int mp,
+                           double* SVs, double* Hs, double* etas, double* cn2, double* SAVs, hipStream_t st);
+hipError_t launch_adaptive_est(const double* SV, int s, int mp, const double* y, const double* yp, int mprev,
+                               const DevCtrl* sctrl, double* out, double* ysave, hipStream_t st);
+hipError_t launch_rescale_coeffs(const double* y, const double* eta, int mp, double* ys, hipStream_t st);
+int gershgorin_blocks(int64_t N);
+hipError_t launch_gershgorin(const int32_t* rowptr, const int32_t* col, const double* val, int64_t N, double* part,
+                             double* out, hipStream_t st);
+int mlp_param_count();
+size_t mlp_ws_floats(int B);
+hipError_t launch_mlp_forward(const float* X, int B, const float* p, float* Y, float* ws, hipStream_t st);
+hipError_t launch_mlp_loss_grad(const float* X, const float* T, int B, const float* p, float* g, float* loss,
+                                float* ws, hipStream_t st);
+hipError_t launch_mlp_adam(float* p, const float* g, float* m1, float* m2, int n, float lr, float b1, float b2,
+                           float eps, float c1, float c2, hipStream_t st);
 constexpr int QR_NB_HOST = 16;
 constexpr int NODE_SLOTS_HOST = 1024;
 }  // namespace skfab
@@ -371,14 +386,16 @@ skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matri
         if (_e != hipSuccess) return SKFAB_ERR_HIP;     \
     } while (0)
 
-// k-truncated Arnoldi with sketches, plus the extension vector u_m (Algorithm 2, basis part).
-skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, const skfab_params* p,
-                         const Layout& ly, const Ptrs& w, hipStream_t st) {
+// k-truncated Arnoldi with sketches, plus the extension vector u_m (Algorithm 2, basis part):
+// arnoldi_setup (control block, SELL copy of A, step arguments), one arnoldi_step per
+// j = 0..m (j = m forms the extension only), arnoldi_tail (its sketch and eta_m).
+skfab_status arnoldi_setup(const skfab_csr* A, const double* b, const skfab_params* p, const Layout& ly,
+                           const Ptrs& w, hipStream_t st, StepArgs* out) {
     const int m = p->m, s = p->s;
     HIP_TRY(launch_init_ctrl(w.ctrl, m, st));
     HIP_TRY(launch_sell_convert(A->rowptr, A->col, static_cast<const double*>(A->val), A->n, ly.L.nslices,
                                 ly.sell_capacity, w.ctrl, w.sl_len, w.sl_ptr, w.bsum, w.sl_col, w.sl_val, p->prec, st));
-    StepArgs a;
+    StepArgs& a = *out;
     std::memset(&a, 0, sizeof(a));
     a.N = A->n;
     a.ldU = ly.ldU;
@@ -411,28 +428,47 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
     a.m = m;
     a.G = ly.L.G;
     HIP_TRY(launch_fill(w.H, (int64_t)(m + 1) * m, 0.0, st));
+    return SKFAB_OK;
+}
+
+skfab_status arnoldi_step(skfab_ctx* ctx, StepArgs& a, const skfab_params* p, const Layout& ly, const Ptrs& w,
+                          int j, hipStream_t st) {
     const int64_t nsc = (int64_t)NSC_MAX * ly.L.G;
-    const int64_t nsk = (int64_t)2 * s * ly.L.G;
-    for (int j = 0; j <= m; ++j) {
-        a.j = j;
-        a.extend = (j == m) ? 1 : 0;
-        a.Wcur = static_cast<char*>(w.W) + (int64_t)(j & 1) * ly.ldU * wbytes(p->prec);
-        a.Wprev = static_cast<char*>(w.W) + (int64_t)((j + 1) & 1) * ly.ldU * wbytes(p->prec);
-        a.scal_prev = w.scal + ((j + 1) & 1) * nsc;
-        a.scal_cur = w.scal + (j & 1) * nsc;
-        a.skp_prev = w.skpart + ((j + 1) & 1) * nsk;
-        a.skp_cur = w.skpart + (j & 1) * nsk;
-        hipEvent_t stop;
-        const bool timed = j < m;  // the extension pass has no product with A
-        if (timed) HIP_TRY(timing_begin(ctx, 0, st, &stop));
-        HIP_TRY(launch_arnoldi_step(a, p->zeta, ly.L.block, p->prec, st));
-        if (timed) HIP_TRY(timing_end(stop, st));
-    }
-    // tail: the extension step's partials
-    a.scal_prev = w.scal + (m & 1) * nsc;
-    a.skp_prev = w.skpart + (m & 1) * nsk;
+    const int64_t nsk = (int64_t)2 * p->s * ly.L.G;
+    a.j = j;
+    a.extend = (j == p->m) ? 1 : 0;
+    a.Wcur = static_cast<char*>(w.W) + (int64_t)(j & 1) * ly.ldU * wbytes(p->prec);
+    a.Wprev = static_cast<char*>(w.W) + (int64_t)((j + 1) & 1) * ly.ldU * wbytes(p->prec);
+    a.scal_prev = w.scal + ((j + 1) & 1) * nsc;
+    a.scal_cur = w.scal + (j & 1) * nsc;
+    a.skp_prev = w.skpart + ((j + 1) & 1) * nsk;
+    a.skp_cur = w.skpart + (j & 1) * nsk;
+    hipEvent_t stop;
+    const bool timed = j < p->m;  // the extension pass has no product with A
+    if (timed) HIP_TRY(timing_begin(ctx, 0, st, &stop));
+    HIP_TRY(launch_arnoldi_step(a, p->zeta, ly.L.block, p->prec, st));
+    if (timed) HIP_TRY(timing_end(stop, st));
+    return SKFAB_OK;
+}
+
+skfab_status arnoldi_tail(StepArgs& a, const skfab_params* p, const Layout& ly, const Ptrs& w, hipStream_t st) {
+    const int m = p->m;
+    a.scal_prev = w.scal + (m & 1) * (int64_t)NSC_MAX * ly.L.G;
+    a.skp_prev = w.skpart + (m & 1) * (int64_t)2 * p->s * ly.L.G;
     HIP_TRY(launch_arnoldi_tail(a, w.colnorm2, st));
     return SKFAB_OK;
+}
+
+skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, const skfab_params* p,
+                         const Layout& ly, const Ptrs& w, hipStream_t st) {
+    StepArgs a;
+    skfab_status r = arnoldi_setup(A, b, p, ly, w, st, &a);
+    if (r != SKFAB_OK) return r;
+    for (int j = 0; j <= p->m; ++j) {
+        r = arnoldi_step(ctx, a, p, ly, w, j, st);
+        if (r != SKFAB_OK) return r;
+    }
+    return arnoldi_tail(a, p, ly, w, st);
 }
 
 // y0 = exp(-tau H_hat) beta e_1 by [13/13] Pade scaling and squaring.  Reads ||A||_1
@@ -1223,6 +1259,192 @@ skfab_status skfab_batch_autotune(skfab_ctx* ctx, int32_t nprob, const skfab_bat
     ctx->batch_block = bb;
     ctx->batch_spw = bs;
     if (chosen) { chosen->block = bb; chosen->slices_per_wave = bs; }
+    return SKFAB_OK;
+}
+
+}  // extern "C"
+
+// ============================================================ adaptive m
+namespace {
+
+struct AdaptiveLayout {
+    Layout main, snap;
+    size_t snap_off, ysave_off, out_off, total;
+};
+
+AdaptiveLayout make_adaptive_layout(const skfab_csr* A, const skfab_params* p) {
+    int l1, l2, lmax;
+    double tol;
+    defaults(p, &l1, &l2, &lmax, &tol);
+    AdaptiveLayout L;
+    L.main = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec);
+    L.snap = make_layout(0, 0, p->m, p->s, l1, l2, lmax, p->npoly, false, 0);
+    L.snap_off = align_up(L.main.total);
+    L.ysave_off = align_up(L.snap_off + L.snap.total);
+    L.out_off = align_up(L.ysave_off + (size_t)2 * p->m * sizeof(double));
+    L.total = align_up(L.out_off + 2 * sizeof(double));
+    return L;
+}
+
+void fill_info(const DevCtrl& c, skfab_info* info) {
+    info->status = c.status;
+    info->m_used = c.m_used;
+    info->l_used = c.l_used;
+    info->reserved = 0;
+    info->eps_est = c.eps_est;
+    info->rcond_R = c.rcond;
+    info->sigma = c.sigma;
+    info->beta = c.beta;
+    info->arnoldi_relres = c.relres;
+}
+
+}  // namespace
+
+extern "C" {
+
+skfab_status skfab_adaptive_workspace_bytes(const skfab_csr* A, const skfab_params* p, size_t* bytes) {
+    if (!bytes || !A || !p) return SKFAB_ERR_ARG;
+    skfab_status v = validate(A, p, false);
+    if (v != SKFAB_OK) return v;
+    if (A->n <= 0) return SKFAB_ERR_SHAPE;
+    *bytes = make_adaptive_layout(A, p).total;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_solve_adaptive(skfab_ctx* ctx, const skfab_csr* A, const double* b, double* x,
+                                  const skfab_params* p, int32_t m0, int32_t d, double tol, void* ws,
+                                  size_t ws_bytes, skfab_info* info, int32_t* m_stop, double* estimate) {
+    if (!ctx || !b || !x) return SKFAB_ERR_ARG;
+    skfab_status v = validate(A, p, true);
+    if (v != SKFAB_OK) return v;
+    if (p->method != SKFAB_SFOM_CLOSED) return SKFAB_ERR_ARG;
+    if (d < 1 || m0 < p->k || m0 > p->m || !(tol > 0.0)) return SKFAB_ERR_ARG;
+    const AdaptiveLayout L = make_adaptive_layout(A, p);
+    if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    char* base = static_cast<char*>(ws);
+    const Ptrs w = carve(ws, L.main);
+    double* ysave[2] = {reinterpret_cast<double*>(base + L.ysave_off),
+                        reinterpret_cast<double*>(base + L.ysave_off) + p->m};
+    double* dout = reinterpret_cast<double*>(base + L.out_off);
+    hipStream_t st = ctx->stream;
+    const int m = p->m, s = p->s;
+    int l1, l2, lmax;
+    double qtol;
+    defaults(p, &l1, &l2, &lmax, &qtol);
+    StepArgs a;
+    skfab_status r = arnoldi_setup(A, b, p, L.main, w, st, &a);
+    if (r != SKFAB_OK) return r;
+    int mprev = 0, cur = 0;
+    bool broke = false;
+    double est = INFINITY;
+    for (int j = 0; j <= m; ++j) {
+        r = arnoldi_step(ctx, a, p, L.main, w, j, st);
+        if (r != SKFAB_OK) return r;
+        const int mp = j - 1;
+        if (broke || j < 1 || mp < m0 || (mp - m0) % d != 0 || mp >= m) continue;
+        // checkpoint mp: the first mp steps as a small problem of their own
+        const Layout sl = make_layout(0, 0, mp, s, l1, l2, lmax, p->npoly, false, 0);
+        const Ptrs sw = carve(base + L.snap_off, sl);
+        HIP_TRY(launch_init_ctrl(sw.ctrl, mp, st));
+        HIP_TRY(launch_snapshot(w.SV, s, w.H, m + 1, w.eta, mp, sw.SV, sw.H, sw.eta, sw.colnorm2, sw.SAV, st));
+        skfab_params q = *p;
+        q.m = mp;
+        r = run_small(&q, sl, sw, st);
+        if (r != SKFAB_OK) return r;
+        HIP_TRY(launch_adaptive_est(w.SV, s, mp, sw.y, ysave[1 - cur], mprev, sw.ctrl, dout, ysave[cur], st));
+        double hout[2];
+        DevCtrl mc;
+        HIP_TRY(hipMemcpyAsync(hout, dout, sizeof(hout), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipMemcpyAsync(&mc, w.ctrl, sizeof(DevCtrl), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        if (mc.stop && mc.m_used <= mp) { broke = true; continue; }  // the final solve is exact
+        est = hout[0];
+        if (est <= tol) {
+            HIP_TRY(launch_rescale_coeffs(sw.y, w.eta, mp, sw.ys, st));
+            HIP_TRY(launch_assemble(w.U, L.main.ldU, A->n, mp, sw.ctrl, sw.ys, x, p->prec, st));
+            if (m_stop) *m_stop = mp;
+            if (estimate) *estimate = est;
+            if (info) {
+                DevCtrl c;
+                HIP_TRY(hipMemcpyAsync(&c, sw.ctrl, sizeof(DevCtrl), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                fill_info(c, info);
+            }
+            return SKFAB_OK;
+        }
+        mprev = mp;
+        cur = 1 - cur;
+    }
+    // no checkpoint passed (or a breakdown): the full solve at m, judged against the last checkpoint
+    r = arnoldi_tail(a, p, L.main, w, st);
+    if (r != SKFAB_OK) return r;
+    r = run_small(p, L.main, w, st);
+    if (r != SKFAB_OK) return r;
+    HIP_TRY(launch_adaptive_est(w.SV, s, m, w.y, ysave[1 - cur], broke ? 0 : mprev, w.ctrl, dout, ysave[cur], st));
+    HIP_TRY(launch_assemble(w.U, L.main.ldU, A->n, m, w.ctrl, w.ys, x, p->prec, st));
+    double hout[2];
+    DevCtrl c;
+    HIP_TRY(hipMemcpyAsync(hout, dout, sizeof(hout), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(&c, w.ctrl, sizeof(DevCtrl), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (m_stop) *m_stop = c.m_used;
+    if (estimate) *estimate = broke ? 0.0 : hout[0];
+    if (info) fill_info(c, info);
+    return SKFAB_OK;
+}
+
+// ------------------------------------------------------- controller support
+size_t skfab_gershgorin_ws_bytes(int64_t n) {
+    if (n <= 0) return 0;
+    return (size_t)2 * gershgorin_blocks(n) * sizeof(double);
+}
+
+skfab_status skfab_gershgorin(skfab_ctx* ctx, const skfab_csr* A, double* bounds, void* ws, size_t ws_bytes) {
+    if (!ctx || !A || !bounds || !A->rowptr || !A->col || !A->val) return SKFAB_ERR_ARG;
+    if (A->val_type != SKFAB_VAL_F64) return SKFAB_ERR_ARG;
+    if (A->n <= 0) return SKFAB_ERR_SHAPE;
+    if (!ws || ws_bytes < skfab_gershgorin_ws_bytes(A->n)) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    HIP_TRY(launch_gershgorin(A->rowptr, A->col, static_cast<const double*>(A->val), A->n,
+                              static_cast<double*>(ws), bounds, ctx->stream));
+    return SKFAB_OK;
+}
+
+int32_t skfab_mlp_param_count(void) { return mlp_param_count(); }
+
+size_t skfab_mlp_ws_bytes(int32_t batch) {
+    if (batch <= 0) return 0;
+    return mlp_ws_floats(batch) * sizeof(float);
+}
+
+skfab_status skfab_mlp_forward(skfab_ctx* ctx, const float* X, int32_t B, const float* params, float* Y, void* ws,
+                               size_t ws_bytes) {
+    if (!ctx || !X || !params || !Y || B <= 0) return SKFAB_ERR_ARG;
+    if (!ws || ws_bytes < skfab_mlp_ws_bytes(B)) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    HIP_TRY(launch_mlp_forward(X, B, params, Y, static_cast<float*>(ws), ctx->stream));
+    return SKFAB_OK;
+}
+
+skfab_status skfab_mlp_loss_grad(skfab_ctx* ctx, const float* X, const float* T, int32_t B, const float* params,
+                                 float* grad, float* loss, void* ws, size_t ws_bytes) {
+    if (!ctx || !X || !T || !params || !grad || B <= 0) return SKFAB_ERR_ARG;
+    if (!ws || ws_bytes < skfab_mlp_ws_bytes(B)) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    HIP_TRY(launch_mlp_loss_grad(X, T, B, params, grad, loss, static_cast<float*>(ws), ctx->stream));
+    return SKFAB_OK;
+}
+
+skfab_status skfab_mlp_adam(skfab_ctx* ctx, float* params, const float* grad, float* m1, float* m2, int32_t t,
+                            float lr, float beta1, float beta2, float eps) {
+    if (!ctx || !params || !grad || !m1 || !m2 || t < 1) return SKFAB_ERR_ARG;
+    if (!(lr > 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return SKFAB_ERR_ARG;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    const float c1 = (float)(1.0 / (1.0 - std::pow((double)beta1, t)));
+    const float c2 = (float)(1.0 / (1.0 - std::pow((double)beta2, t)));
+    HIP_TRY(launch_mlp_adam(params, grad, m1, m2, mlp_param_count(), lr, beta1, beta2, eps, c1, c2, ctx->stream));
     return SKFAB_OK;
 }
 

@@ -281,3 +281,70 @@ def skfab_batch_autotune(ctx: Context, probs, p: N.skfab_params, ws: torch.Tenso
     _check(N.lib().skfab_batch_autotune(ctx.handle, len(probs), _batch_array(probs), nr, C.byref(p), _ptr(ws),
                                         ws.numel(), int(steps), C.byref(t)), "skfab_batch_autotune")
     return t.block, t.slices_per_wave
+
+
+# -------------------------------------------------------------- adaptive m
+def skfab_adaptive_workspace_bytes(A: CSR | int, p: N.skfab_params) -> int:
+    n = A.n if isinstance(A, CSR) else int(A)
+    nnz = A.col.numel() if isinstance(A, CSR) else 0
+    csr = N.skfab_csr(n, nnz, None, None, None, N.SKFAB_VAL_F64)
+    out = C.c_size_t()
+    _check(N.lib().skfab_adaptive_workspace_bytes(C.byref(csr), C.byref(p), C.byref(out)),
+           "skfab_adaptive_workspace_bytes")
+    return out.value
+
+
+def skfab_solve_adaptive(ctx: Context, A: CSR, b: torch.Tensor, x: torch.Tensor, p: N.skfab_params, m0: int,
+                         d: int, tol: float, ws: torch.Tensor):
+    """Returns (info, m_stop, estimate)."""
+    _require_device(b, torch.float64, "b")
+    _require_device(x, torch.float64, "x")
+    csr = A.c_struct()
+    info = N.skfab_info()
+    ms = C.c_int32()
+    est = C.c_double()
+    _check(N.lib().skfab_solve_adaptive(ctx.handle, C.byref(csr), _ptr(b), _ptr(x), C.byref(p), int(m0), int(d),
+                                        float(tol), _ptr(ws), ws.numel(), C.byref(info), C.byref(ms),
+                                        C.byref(est)), "skfab_solve_adaptive")
+    return info, ms.value, est.value
+
+
+# ------------------------------------------------------ controller kernels
+def skfab_gershgorin(ctx: Context, A: CSR, bounds: torch.Tensor, ws: torch.Tensor):
+    _require_device(bounds, torch.float64, "bounds")
+    csr = A.c_struct()
+    _check(N.lib().skfab_gershgorin(ctx.handle, C.byref(csr), _ptr(bounds), _ptr(ws), ws.numel()),
+           "skfab_gershgorin")
+
+
+def skfab_gershgorin_ws_bytes(n: int) -> int:
+    return N.lib().skfab_gershgorin_ws_bytes(int(n))
+
+
+def skfab_mlp_param_count() -> int:
+    return N.lib().skfab_mlp_param_count()
+
+
+def skfab_mlp_ws_bytes(batch: int) -> int:
+    return N.lib().skfab_mlp_ws_bytes(int(batch))
+
+
+def skfab_mlp_forward(ctx: Context, X: torch.Tensor, params: torch.Tensor, Y: torch.Tensor, ws: torch.Tensor):
+    for t, nm in ((X, "X"), (params, "params"), (Y, "Y")):
+        _require_device(t, torch.float32, nm)
+    _check(N.lib().skfab_mlp_forward(ctx.handle, _ptr(X), X.shape[0], _ptr(params), _ptr(Y), _ptr(ws),
+                                     ws.numel()), "skfab_mlp_forward")
+
+
+def skfab_mlp_loss_grad(ctx: Context, X: torch.Tensor, T: torch.Tensor, params: torch.Tensor, grad: torch.Tensor,
+                        loss: torch.Tensor | None, ws: torch.Tensor):
+    for t, nm in ((X, "X"), (T, "T"), (params, "params"), (grad, "grad")):
+        _require_device(t, torch.float32, nm)
+    _check(N.lib().skfab_mlp_loss_grad(ctx.handle, _ptr(X), _ptr(T), X.shape[0], _ptr(params), _ptr(grad),
+                                       _ptr(loss), _ptr(ws), ws.numel()), "skfab_mlp_loss_grad")
+
+
+def skfab_mlp_adam(ctx: Context, params: torch.Tensor, grad: torch.Tensor, m1: torch.Tensor, m2: torch.Tensor,
+                   t: int, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    _check(N.lib().skfab_mlp_adam(ctx.handle, _ptr(params), _ptr(grad), _ptr(m1), _ptr(m2), int(t), float(lr),
+                                  float(beta1), float(beta2), float(eps)), "skfab_mlp_adam")
