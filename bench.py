@@ -41,7 +41,11 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="convdiff3d_n128_m200",
-                    help="a single-problem workload, or 'batch64x4' for the batched form (64 problems x 4 rhs)")
+                    help="a single-problem workload, 'batch64x4' for the batched form (64 problems x 4 rhs), "
+                         "or 'controller' for the learned controller against plain adaptive-m")
+    ap.add_argument("--train-problems", type=int, default=2500,
+                    help="controller: training problems (4 method runs each)")
+    ap.add_argument("--test-problems", type=int, default=256, help="controller: held-out problems")
     ap.add_argument("--nprob", type=int, default=64, help="problems of the batched workload")
     ap.add_argument("--no-autotune", action="store_true", help="batched form: keep the default launch shape")
     ap.add_argument("--tuning", default=None, metavar="BLOCK,SPW",
@@ -316,6 +320,75 @@ def run_batched(args):
     print(json.dumps(out), flush=True)
 
 
+def run_controller(args):
+    """The learned controller: labels from 4 adaptive-m runs per training problem
+    ((k, s/m) in {2, 4} x {2, 4}, tol 1e-8), full-batch training on the device
+    kernels, then held-out problems solved by plain adaptive-m (k = 2, s = 2 m_cap,
+    checks every 10 steps from m = 10) and by the controlled solve (features, network,
+    checks from the predicted m, adaptive fallback)."""
+    import numpy as np
+    import torch
+
+    from paper_2208_11447_amd import controller as ctl
+
+    tol = 1e-8
+    runner = ctl.Runner(0)
+    t0 = time.perf_counter()
+    X, Y, runs = [], [], 0
+    specs = ctl.random_specs(args.train_problems, seed=11)
+    for i, spec in enumerate(specs):
+        f, lab, r = ctl.label_problem(runner, spec, tol)
+        runs += r
+        if lab is not None:
+            X.append(f)
+            Y.append(lab)
+        if (i + 1) % 100 == 0:
+            print(f"# labelled {i + 1} problems, {runs} runs ({time.perf_counter() - t0:.0f} s)", file=sys.stderr,
+                  flush=True)
+    t_label = time.perf_counter() - t0
+    X, Y = np.asarray(X), np.asarray(Y)
+    t0 = time.perf_counter()
+    model = ctl.train(runner, X, Y, steps=3000, lr=2e-3, log_every=1000)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"# trained on {len(X)} labelled problems in {t_train:.1f} s, loss {model.history}", file=sys.stderr,
+          flush=True)
+    rows = []
+    for i, spec in enumerate(ctl.random_specs(args.test_problems, seed=12)):
+        A, b = spec.build()
+        _, ip, mp, ep, sp_ = runner.adaptive(A, b, 2, 2, 10, ctl.M_CAP, tol)
+        _, ic, mc, ec, sc, fb = ctl.controlled_solve(runner, model, spec, A, b, tol)
+        rows.append((ip.status == 0 and ep <= tol, ic.status == 0 and ec <= tol, sp_, sc, mp, mc, fb))
+        if (i + 1) % 64 == 0:
+            print(f"# evaluated {i + 1} held-out problems", file=sys.stderr, flush=True)
+    ok_p = [r for r in rows if r[0]]
+    t_p = sum(r[2] for r in ok_p)
+    t_c = sum(r[3] for r in ok_p)
+    out = {
+        "metric": "f(A)b solves/s at rel. err 1e-8 (stopping estimate), learned controller vs plain adaptive-m",
+        "value": round(len(ok_p) / t_c, 2) if t_c > 0 else None,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "higher_is_better": True,
+        "data": "synthetic",
+        "config": {"workload": "controller_convdiff2d3d", "train_problems": args.train_problems,
+                   "method_runs": runs, "labelled": int(len(X)), "test_problems": args.test_problems,
+                   "tol": tol, "network": "16-64-64-3 relu fp32", "train_steps": 3000},
+        "plain_adaptive_solves_per_s": round(len(ok_p) / t_p, 2) if t_p > 0 else None,
+        "speedup": round(t_p / t_c, 3) if t_c > 0 else None,
+        "held_out_met_by_plain": len(ok_p),
+        "held_out_met_by_controller": sum(1 for r in rows if r[1]),
+        "controller_meets_tol_where_plain_does": sum(1 for r in ok_p if r[1]),
+        "krylov_steps_plain": int(sum(r[4] for r in ok_p)),
+        "krylov_steps_controller": int(sum(r[5] for r in ok_p)),
+        "fallbacks": int(sum(r[6] for r in ok_p)),
+        "label_seconds": round(t_label, 1),
+        "train_seconds": round(t_train, 2),
+        "train_loss": model.history,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.copy_calibration > 0:
@@ -334,6 +407,9 @@ def main():
 
     if args.workload == "batch64x4":
         run_batched(args)
+        return
+    if args.workload == "controller":
+        run_controller(args)
         return
     cfg = config(args.workload)
     rp, col, val = convdiff_csr(cfg["n"], cfg["dim"], cfg["diffusion"], cfg["convection"])
