@@ -163,6 +163,21 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     const int j = a.j, k = a.k, s = a.s, G = a.G;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
 
+    // SELL path: every slice's entry count and offset are read once, lane i holding
+    // those of the wave's i-th slice (a window of 64 slices), so a slice's index and
+    // value loads do not wait on a metadata load.  The first window is requested
+    // before the prologue so that its latency overlaps the reductions.
+    const int chunk = xcd_chunk(bid, G);
+    const int64_t sl0 = (int64_t)chunk * a.slices_per_chunk + wid;
+    const int64_t sl1 = min(a.nslices, (int64_t)(chunk + 1) * a.slices_per_chunk);
+    int wlen = 0;
+    int64_t wptr = 0;
+    if (!a.extend) {
+        const int64_t itl = sl0 + (int64_t)lane * NW;
+        wlen = (itl < sl1) ? a.sl_len[itl] : 0;
+        wptr = (itl < sl1) ? a.sl_ptr[itl] : 0;
+    }
+
     if (j > 0) {
         // issue every load of the prologue before any reduction: the partial scalars
         // of step j-1 (G per scalar), this block's share of its sketch partials, and
@@ -196,6 +211,9 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         block_reduce_multi<NSC, BLOCK>(sv, bins, red);
         if (tid == 0) s_ok = step_coefficients<KW>(red, j - 1, k, bid == 0, a, coef) ? 1 : 0;
         skv = wave_sum(skv);
+        // the bin region is free again: the other wavefronts clear it meanwhile
+        if (wid > 0)
+            for (int i = tid - WAVE; i < NW * 2 * s; i += BLOCK - WAVE) bins[i] = 0.0;
         __syncthreads();
         // S v_{j-1}, S A v_{j-1}; after a breakdown, S u_{j-1} unnormalised (extension column)
         const double eta_p = coef[KMAX + 1];
@@ -210,12 +228,14 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                                            ok ? a.inv_sqrt_zeta / eta_p : a.inv_sqrt_zeta,
                                            a.inv_sqrt_zeta / eta_p, ok, a.SV, a.SAV);
         if (!ok) return;
-    } else if (tid == 0) {
-        coef[0] = 1.0;
-        for (int o = 0; o < KW; ++o) coef[1 + o] = 0.0;
+    } else {
+        if (tid == 0) {
+            coef[0] = 1.0;
+            for (int o = 0; o < KW; ++o) coef[1 + o] = 0.0;
+        }
+        for (int i = tid; i < NW * 2 * s; i += BLOCK) bins[i] = 0.0;
+        __syncthreads();
     }
-    for (int i = tid; i < NW * 2 * s; i += BLOCK) bins[i] = 0.0;
-    __syncthreads();
 
     const int nwin = (j == 0) ? 0 : min(k, j);   // vectors j-1 .. j-nwin form u_j
     const int ndot = min(k - 1, j);              // vectors j-1 .. j-ndot enter the dots
@@ -245,13 +265,12 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
 #pragma unroll
     for (int o = 0; o < KW; ++o) { acc_lw[o] = 0.0; acc_ul[o] = 0.0; }
 
-    const int chunk = xcd_chunk(bid, G);
     const bool sell = sell_flag != 0;
     // rows of this block: SELL slices [sl0, sl1) or CSR rows [r_begin, r_end)
     int64_t it0, it1, step;
     if (sell) {
-        it0 = (int64_t)chunk * a.slices_per_chunk + wid;
-        it1 = min(a.nslices, (int64_t)(chunk + 1) * a.slices_per_chunk);
+        it0 = sl0;
+        it1 = sl1;
         step = NW;
     } else {
         const int64_t r_begin = (int64_t)chunk * a.rows_per_chunk;
@@ -259,9 +278,25 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         it1 = min(a.N, r_begin + a.rows_per_chunk);
         step = BLOCK;
     }
-    for (int64_t it = it0; it < it1; it += step) {
+    constexpr int SB = SellBatch<KW>::value;
+    const bool pre = sell && !a.extend;
+    int wbase = 0;
+    int iter = 0;
+    for (int64_t it = it0; it < it1; it += step, ++iter) {
         const int64_t r = sell ? it * WAVE + lane : it;
         const bool valid = r < a.N;
+        int len = 0;
+        int64_t e0 = 0;
+        if (pre) {
+            if (iter - wbase == WAVE) {  // next window of 64 slices
+                wbase += WAVE;
+                const int64_t itl = it + (int64_t)lane * step;
+                wlen = (itl < it1) ? a.sl_len[itl] : 0;
+                wptr = (itl < it1) ? a.sl_ptr[itl] : 0;
+            }
+            len = readlane_i32(wlen, iter - wbase);
+            e0 = readlane_i64(wptr, iter - wbase) + lane;
+        }
         WT uo[KW];
         WT u = (WT)0;
         if (valid) {
@@ -283,9 +318,6 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             if (sell) {
                 // entries in batches of SB: all index and value loads of a batch, then all
                 // gathers, then the products -- one memory round trip per batch
-                const int len = a.sl_len[it];
-                const int64_t e0 = a.sl_ptr[it] + lane;
-                constexpr int SB = SellBatch<KW>::value;
                 for (int q0 = 0; q0 < len; q0 += SB) {
                     int cc[SB];
                     WT vv[SB], xb[SB], xu[SB][KW];

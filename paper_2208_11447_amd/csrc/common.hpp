@@ -91,6 +91,16 @@ __device__ __forceinline__ double wave_sum(double v) {
 
 // Broadcast of a double from a wave-uniform lane through two scalar reads
 // (no LDS crossbar round trip).
+__device__ __forceinline__ int readlane_i32(int v, int src_lane) {
+    return __builtin_amdgcn_readlane(v, src_lane);
+}
+
+__device__ __forceinline__ int64_t readlane_i64(int64_t v, int src_lane) {
+    const int lo = __builtin_amdgcn_readlane((int)(v & 0xffffffffll), src_lane);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src_lane);
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
 __device__ __forceinline__ double bcast_lane(double v, int src_lane) {
     const long long b = __double_as_longlong(v);
     const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), src_lane);
