@@ -58,6 +58,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-steps", type=int, default=30)
     ap.add_argument("--no-timing-events", action="store_true")
+    ap.add_argument("--timing-stride", type=int, default=8,
+                    help="single-problem workloads: HIP events bracket every n-th step-kernel (and assembly) launch "
+                         "of the timed region; "
+                         "the events cost a few microseconds of queue time each, so timing every launch "
+                         "would lower the solves/s figure they are quoted with")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB (5 times) and report its GB/s; "
                          "used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
@@ -251,6 +256,7 @@ def run_batched(args):
     for _ in range(args.warmup):
         sk.skfab_solve_batched(ctx, probs, p, ws, want_info=False)
     torch.cuda.synchronize()
+    # every launch timed: the launches differ in size (units drop out as their m is reached)
     sk.skfab_timing_enable(ctx, True)
     sk.skfab_timing_read(ctx, 0)
     sk.skfab_timing_read(ctx, 1)
@@ -436,7 +442,7 @@ def main():
 
     timing = not args.no_timing_events
     if timing:
-        sk.skfab_timing_enable(ctx, True)
+        sk.skfab_timing_enable(ctx, True, stride=args.timing_stride)
         sk.skfab_timing_read(ctx, 0)
         sk.skfab_timing_read(ctx, 1)
     torch.cuda.synchronize()
@@ -458,6 +464,7 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(args.workload, args.prec),
                 "kernel": "arnoldi_step_kernel", "bytes_per_launch": nbytes,
                 "mean_launch_us": round(per_launch_s * 1e6, 2), "launches": n_step,
+                "timed_every": args.timing_stride,
                 "assembly_gbs": round((PREC_BYTES[args.prec][1] * N * cfg["m"] + 8 * N) / (ms_asm / 1e3 / max(n_asm, 1)) / 1e9, 1)
                 if n_asm else None}
     x_host = x.cpu().numpy()

@@ -221,9 +221,11 @@ skfab_status skfab_sketch_apply(skfab_ctx *ctx, int64_t n, int32_t s, int32_t ze
 size_t skfab_sketch_ws_bytes(int64_t n, int32_t s);
 
 /* Kernel timing with HIP events on the context's stream (benchmark support).
- * While enabled, every launch of the timed kernel classes is bracketed by a pair
- * of events; skfab_timing_read synchronises the stream and returns the summed
- * event durations and the launch count since the last read (then resets).
+ * enable = 0 turns timing off; enable = n >= 1 brackets every n-th launch of each
+ * timed kernel class with a pair of events (n = 1: every launch; a larger n keeps
+ * the events' own cost out of most launches); negative values are rejected with
+ * SKFAB_ERR_ARG.  skfab_timing_read synchronises the stream and returns the summed
+ * event durations and the count of timed launches since the last read (then resets).
  *   kernel 0: the fused Arnoldi step kernel (SpMV + orthogonalisation dots +
  *             sparse-sign sketches), kernel 1: the assembly x = V_m y.
  * Events are host runtime objects created by skfab_timing_enable; no device

@@ -106,6 +106,8 @@ struct skfab_ctx {
     hipStream_t stream;
     // optional per-launch timing of kernel classes (0: Arnoldi step, 1: assembly)
     bool timing = false;
+    int32_t stride = 1;             // every stride-th launch of a class is timed
+    int64_t tick[2] = {0, 0};       // launches of each class seen while enabled
     std::vector<hipEvent_t> ev[2];  // start/stop pairs, flattened
     size_t used[2] = {0, 0};
     double acc_ms[2] = {0.0, 0.0};
@@ -140,6 +142,7 @@ hipError_t timing_flush(skfab_ctx* ctx, int c) {
 hipError_t timing_begin(skfab_ctx* ctx, int c, hipStream_t st, hipEvent_t* stop) {
     *stop = nullptr;
     if (!ctx || !ctx->timing) return hipSuccess;
+    if (ctx->tick[c]++ % ctx->stride != 0) return hipSuccess;
     if (ctx->used[c] == TIMING_PAIRS) {
         hipError_t e = timing_flush(ctx, c);
         if (e != hipSuccess) return e;
@@ -637,7 +640,7 @@ skfab_status skfab_destroy(skfab_ctx* ctx) {
 }
 
 skfab_status skfab_timing_enable(skfab_ctx* ctx, int32_t enable) {
-    if (!ctx) return SKFAB_ERR_ARG;
+    if (!ctx || enable < 0) return SKFAB_ERR_ARG;
     if (enable && ctx->ev[0].empty()) {
         if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
         for (int c = 0; c < 2; ++c) {
@@ -649,6 +652,8 @@ skfab_status skfab_timing_enable(skfab_ctx* ctx, int32_t enable) {
         for (int c = 0; c < 2; ++c) HIP_TRY(timing_flush(ctx, c));
     }
     ctx->timing = enable != 0;
+    ctx->stride = enable > 0 ? enable : 1;
+    ctx->tick[0] = ctx->tick[1] = 0;
     return SKFAB_OK;
 }
 

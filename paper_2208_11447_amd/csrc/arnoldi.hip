@@ -36,19 +36,31 @@
 namespace skfab {
 
 // ----------------------------------------------------------- coefficients
+// Window values read by the coefficients of step p, fetched by thread t < KW^2 at
+// the start of the next launch so that their latency overlaps the reductions:
+// win[0] = ||A v_{p-1}||, win[o] = eta_{p-o} (1 <= o < KW), and
+// win[KW + (o-1) KW + o2] = <v_{p-o}, v_{p-o2}> (1 <= o < o2 < KW); 0 where absent.
+template <int KW>
+__device__ __forceinline__ double window_value(const StepArgs& a, int p, int t) {
+    if (t == 0) return (p >= 1) ? a.wnorm[p - 1] : 0.0;
+    if (t < KW) return (p - t >= 0) ? a.eta[p - t] : 0.0;
+    const int q = t - KW, o = 1 + q / KW, o2 = q % KW;
+    return (o2 > o && p - o2 >= 0) ? a.gram[(int64_t)(p - o) * KMAX + (o2 - o - 1)] : 0.0;
+}
+
 // Turns the reduced dot products of step p into eta_p, h_{.,p}, the Gram
 // entries of v_p and the coefficients of u_{p+1}.  Runs on one thread.
 // Returns false on breakdown (m_used set to p, or 0 for b = 0).
 template <int KW>
-__device__ bool step_coefficients(const double* red, int p, int k, bool writer, const StepArgs& a,
-                                  double* coef) {
+__device__ bool step_coefficients(const double* red, const double* win, int p, int k, bool writer,
+                                  const StepArgs& a, double* coef) {
     const double uu = red[0], uw = red[1], ww = red[2];
     const double eta_p = sqrt(uu);
     bool ok;
     if (p == 0) {
         ok = eta_p > 0.0;
     } else {
-        ok = eta_p > BREAKDOWN_TOL * a.wnorm[p - 1];
+        ok = eta_p > BREAKDOWN_TOL * win[0];
     }
     if (coef) coef[KMAX + 1] = eta_p;
     if (!ok) {
@@ -68,7 +80,7 @@ __device__ bool step_coefficients(const double* red, int p, int k, bool writer, 
 #pragma unroll
     for (int o = 1; o < KW; ++o) {
         if (o < nwp) {
-            const double eo = a.eta[p - o];
+            const double eo = win[o];
             d[o] = red[3 + (o - 1)] / (eo * eta_p);
             gp[o] = red[3 + (KW - 1) + (o - 1)] / (eta_p * eo);
         }
@@ -77,13 +89,11 @@ __device__ bool step_coefficients(const double* red, int p, int k, bool writer, 
 #pragma unroll
     for (int o = KW - 1; o >= 0; --o) {
         if (o < nwp) {
-            const int i = p - o;
             double hi = d[o];
 #pragma unroll
             for (int o2 = KW - 1; o2 > o; --o2) {
                 if (o2 < nwp) {
-                    const int l = p - o2;
-                    const double gil = (o == 0) ? gp[o2] : a.gram[(int64_t)i * KMAX + (i - l - 1)];
+                    const double gil = (o == 0) ? gp[o2] : win[KW + (o - 1) * KW + o2];
                     hi -= h[o2] * gil;
                 }
             }
@@ -94,7 +104,7 @@ __device__ bool step_coefficients(const double* red, int p, int k, bool writer, 
         coef[0] = 1.0 / eta_p;
 #pragma unroll
         for (int o = 0; o < KW; ++o) {
-            const double eo = (o == 0) ? eta_p : ((o < nwp) ? a.eta[p - o] : 1.0);
+            const double eo = (o == 0) ? eta_p : ((o < nwp) ? win[o] : 1.0);
             coef[1 + o] = (o < nwp) ? -h[o] / eo : 0.0;
         }
     }
@@ -151,6 +161,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     extern __shared__ double bins[];  // [BLOCK/64][2s]
     __shared__ double red[NSC_MAX];
     __shared__ double coef[KMAX + 2];
+    __shared__ double win[KW * KW];
     __shared__ double scratch[BLOCK / WAVE];
     __shared__ int s_ok;
 
@@ -191,6 +202,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             sv[sc] = t;
         }
         (void)PER;
+        const double wv = (tid < KW * KW) ? window_value<KW>(a, j - 1, tid) : 0.0;
         const int nb = 2 * s;
         const int b0 = (int)(((int64_t)bid * nb) / G);
         const int b1 = (int)(((int64_t)(bid + 1) * nb) / G);
@@ -206,10 +218,11 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             if (g < G) t0 += src[g];
             skv = t0 + t1;
         }
+        if (tid < KW * KW) win[tid] = wv;
         // every thread's scalar partials reduced in a fixed tree through the (not yet
-        // used) sketch-bin region of LDS
+        // used) sketch-bin region of LDS (its first barrier also publishes win)
         block_reduce_multi<NSC, BLOCK>(sv, bins, red);
-        if (tid == 0) s_ok = step_coefficients<KW>(red, j - 1, k, bid == 0, a, coef) ? 1 : 0;
+        if (tid == 0) s_ok = step_coefficients<KW>(red, win, j - 1, k, bid == 0, a, coef) ? 1 : 0;
         skv = wave_sum(skv);
         // the bin region is free again: the other wavefronts clear it meanwhile
         if (wid > 0)
@@ -314,7 +327,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         u = to_w<WT>(us);  // the stored value is the one used everywhere
         WT w = (WT)0;
         if (!a.extend) {
-            if (valid) Uj[r] = us;
+            if (valid) store_nt(us, &Uj[r]);
             if (sell) {
                 // entries in batches of SB: all index and value loads of a batch, then all
                 // gathers, then the products -- one memory round trip per batch
@@ -355,7 +368,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                     w = fma((WT)a.val[e], x, w);
                 }
             }
-            if (valid) Wc[r] = w;
+            if (valid) store_nt(w, &Wc[r]);
         }
         if (valid) {
             const double ud = (double)u, wd = (double)w;

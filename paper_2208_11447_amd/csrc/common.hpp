@@ -32,6 +32,13 @@ template <typename W> __device__ __forceinline__ W to_w(double x) { return (W)x;
 template <typename W> __device__ __forceinline__ W to_w(float x) { return (W)x; }
 template <typename W> __device__ __forceinline__ W to_w(bf16s x) { return (W)bf16_to_f32(x); }
 
+// Stores of the basis and of A u_j with the non-temporal hint: every vector is
+// read again only in later launches, after the whole matrix has streamed past;
+// the hint keeps it from displacing the matrix in the caches (measured: 2 % per
+// step on the 3D 128^3 workload; non-temporal loads were slower).
+template <typename T> __device__ __forceinline__ void store_nt(T v, T* p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_nt(bf16s v, bf16s* p) { __builtin_nontemporal_store(v.bits, &p->bits); }
+
 template <typename V> struct Store;
 template <> struct Store<double> {
     __device__ static double put(double x) { return x; }

@@ -58,119 +58,102 @@ __global__ void init_ctrl_batched_kernel(const SmallUnit* __restrict__ units) {
 }
 
 // ------------------------------------------------------- Householder QR
-// Panel factorisation of columns [c0, c0+nb) of X (s x ncols, ld s), rows c0..s-1,
-// in LDS.  Householder vectors are stored below the diagonal (unit diagonal
-// implied), R on and above it; T (nb x nb, upper) is the compact-WY factor.
-// Rows are owned by threads (r = tid + 256 i), so each column costs one block
-// reduction of the squared norm and the dot products with the later columns.
+// Panel factorisation of columns [c0, c0+nb) of X (s x ncols, ld s), rows c0..s-1.
+// Wave w holds panel columns CPW w .. CPW w + CPW - 1 in registers, lane l the rows
+// l + 64 i (i < RPW).  Column cc's reflector is formed by the wave that holds it and
+// published through LDS (two buffers, one barrier per column); every wave then
+// applies it to its later columns and takes the Gram entries <v_l, v_cc> of its
+// earlier ones (for T), each with one wave reduction.  Householder vectors are
+// stored below the diagonal (unit diagonal implied), R on and above it; T (nb x nb,
+// upper) is the compact-WY factor.
 constexpr int QR_NT = 256;
+constexpr int QR_CPW = QR_NB / (QR_NT / WAVE);  // panel columns per wavefront
 
+template <int RPW>
 __device__ __forceinline__ void qr_panel_body(double* X, int s, int c0, const DevCtrl* ctrl, double* Tws) {
-    extern __shared__ double P[];  // [QR_NB][nrows]
-    __shared__ double red[2][QR_NT / WAVE][QR_NB + 1];
+    __shared__ double vbuf[2][WAVE * RPW];
     __shared__ double tau[QR_NB];
     __shared__ double G[QR_NB][QR_NB];
     __shared__ double Ts[QR_NB][QR_NB];
     const int ncols = ctrl->m_used + 1;
     if (ctrl->m_used == 0 || c0 >= ncols) return;
     const int pc = min(QR_NB, ncols - c0);
-    const int nrows = s - c0;
+    const int nrows = s - c0;  // <= WAVE * RPW (launcher)
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-    constexpr int NW = QR_NT / WAVE;
-    {
-        // every load of the panel issued before the first use (s <= SMAX rows)
-        constexpr int RPT = SMAX / QR_NT;
-        double ld[QR_NB][RPT];
+    double a[QR_CPW][RPW];
 #pragma unroll
-        for (int cc = 0; cc < QR_NB; ++cc)
+    for (int q = 0; q < QR_CPW; ++q)
 #pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const int r = tid + QR_NT * i;
-                ld[cc][i] = (cc < pc && r < nrows) ? X[(int64_t)(c0 + r) + (int64_t)s * (c0 + cc)] : 0.0;
-            }
-#pragma unroll
-        for (int cc = 0; cc < QR_NB; ++cc)
-#pragma unroll
-            for (int i = 0; i < RPT; ++i) {
-                const int r = tid + QR_NT * i;
-                if (cc < pc && r < nrows) P[cc * nrows + r] = ld[cc][i];
-            }
-    }
-    __syncthreads();
-    for (int cc = 0; cc < pc; ++cc) {
-        const int buf = cc & 1;
-        double* xc = P + cc * nrows;
-        // partial sums over own rows below the diagonal: index 0 = sigma^2, 1 + c2 = x^T P[:, c2]
-        double acc[QR_NB + 1];
-#pragma unroll
-        for (int i = 0; i <= QR_NB; ++i) acc[i] = 0.0;
-        for (int r = cc + 1 + tid; r < nrows; r += QR_NT) {
-            const double x = xc[r];
-            acc[0] = fma(x, x, acc[0]);
-#pragma unroll
-            for (int c2 = 0; c2 < QR_NB; ++c2)
-                if (c2 > cc && c2 < pc) acc[1 + c2] = fma(x, P[c2 * nrows + r], acc[1 + c2]);
+        for (int i = 0; i < RPW; ++i) {
+            const int c = wid * QR_CPW + q, r = lane + WAVE * i;
+            a[q][i] = (c < pc && r < nrows) ? X[(int64_t)(c0 + r) + (int64_t)s * (c0 + c)] : 0.0;
         }
-        // all sums unconditionally: the independent DPP chains interleave
+    if (tid < QR_NB * QR_NB) {
+        G[tid / QR_NB][tid % QR_NB] = 0.0;
+        Ts[tid / QR_NB][tid % QR_NB] = 0.0;
+    }
+    for (int cc = 0; cc < pc; ++cc) {
+        double* vb = vbuf[cc & 1];
+        // the wave holding column cc (all earlier reflectors applied) forms v_cc
 #pragma unroll
-        for (int i = 0; i <= QR_NB; ++i) acc[i] = wave_sum_fast(acc[i]);
-        if (lane == 0) {
+        for (int q = 0; q < QR_CPW; ++q) {
+            if (wid * QR_CPW + q != cc) continue;
+            double t = 0.0;
 #pragma unroll
-            for (int i = 0; i <= QR_NB; ++i) red[buf][wid][i] = acc[i];
+            for (int i = 0; i < RPW; ++i)
+                if (lane + WAVE * i > cc) t = fma(a[q][i], a[q][i], t);
+            const double sig2 = wave_sum_fast(t);
+            const double alpha = bcast_lane(a[q][0], cc);  // row cc < QR_NB: lane cc of i = 0
+            double beta, tc, scale;
+            if (sig2 == 0.0) {
+                beta = alpha; tc = 0.0; scale = 0.0;
+            } else {
+                const double nrm = sqrt(alpha * alpha + sig2);
+                beta = (alpha >= 0.0) ? -nrm : nrm;
+                tc = (beta - alpha) / beta;
+                scale = 1.0 / (alpha - beta);
+            }
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) {
+                const int r = lane + WAVE * i;
+                double v = 0.0;
+                if (r > cc) { v = scale * a[q][i]; a[q][i] = v; }
+                else if (r == cc) { v = 1.0; a[q][i] = beta; }
+                if (r < nrows) vb[r] = v;
+            }
+            if (lane == 0) tau[cc] = tc;
         }
         __syncthreads();
-        double sig2 = 0.0;
-        for (int w = 0; w < NW; ++w) sig2 += red[buf][w][0];
-        const double alpha = xc[cc];
-        double beta, tc, scale;
-        if (sig2 == 0.0) {
-            beta = alpha; tc = 0.0; scale = 0.0;
-        } else {
-            const double nrm = sqrt(alpha * alpha + sig2);
-            beta = (alpha >= 0.0) ? -nrm : nrm;
-            tc = (beta - alpha) / beta;
-            scale = 1.0 / (alpha - beta);
-        }
-        double wv[QR_NB];
+        double v[RPW];
 #pragma unroll
-        for (int c2 = 0; c2 < QR_NB; ++c2) {
-            wv[c2] = 0.0;
-            if (c2 > cc && c2 < pc) {
-                double d = 0.0;
-                for (int w = 0; w < NW; ++w) d += red[buf][w][1 + c2];
-                wv[c2] = tc * (P[c2 * nrows + cc] + scale * d);   // tau * v^T P[:, c2]
+        for (int i = 0; i < RPW; ++i) {
+            const int r = lane + WAVE * i;
+            v[i] = (r < nrows) ? vb[r] : 0.0;
+        }
+        const double tc = tau[cc];
+        double part[QR_CPW];
+#pragma unroll
+        for (int q = 0; q < QR_CPW; ++q) {
+            part[q] = 0.0;
+#pragma unroll
+            for (int i = 0; i < RPW; ++i) part[q] = fma(v[i], a[q][i], part[q]);
+        }
+        // v_cc vanishes above row cc: for a later column this is v^T x, for an
+        // earlier column l it meets only v_l's rows below its diagonal (= <v_l, v_cc>)
+#pragma unroll
+        for (int q = 0; q < QR_CPW; ++q) part[q] = wave_sum_fast(part[q]);
+#pragma unroll
+        for (int q = 0; q < QR_CPW; ++q) {
+            const int c = wid * QR_CPW + q;
+            if (c > cc && c < pc) {
+                const double w = tc * part[q];
+#pragma unroll
+                for (int i = 0; i < RPW; ++i) a[q][i] = fma(-w, v[i], a[q][i]);
+            } else if (c < cc && lane == 0) {
+                G[c][cc] = part[q];
             }
         }
-        __syncthreads();  // every thread has read row cc before its owner updates it
-        for (int r = cc + tid; r < nrows; r += QR_NT) {
-            const double v = (r == cc) ? 1.0 : scale * xc[r];
-            if (r == cc) xc[r] = beta;
-            else xc[r] = v;
-#pragma unroll
-            for (int c2 = 0; c2 < QR_NB; ++c2)
-                if (c2 > cc && c2 < pc) P[c2 * nrows + r] = fma(-wv[c2], v, P[c2 * nrows + r]);
-        }
-        if (tid == 0) tau[cc] = tc;
     }
-    __syncthreads();
-    // Gram of the Householder vectors (unit diagonal, zero above) for T: one
-    // thread per pair (l < i), four partial sums over the rows
-    if (tid < QR_NB * QR_NB) {
-        const int i = tid / QR_NB, l = tid % QR_NB;
-        if (l < i && i < pc) {
-            double t0 = P[l * nrows + i], t1 = 0.0, t2 = 0.0, t3 = 0.0;  // row i: y_i = 1
-            int r = i + 1;
-            for (; r + 3 < nrows; r += 4) {
-                t0 = fma(P[i * nrows + r], P[l * nrows + r], t0);
-                t1 = fma(P[i * nrows + r + 1], P[l * nrows + r + 1], t1);
-                t2 = fma(P[i * nrows + r + 2], P[l * nrows + r + 2], t2);
-                t3 = fma(P[i * nrows + r + 3], P[l * nrows + r + 3], t3);
-            }
-            for (; r < nrows; ++r) t0 = fma(P[i * nrows + r], P[l * nrows + r], t0);
-            G[l][i] = (t0 + t1) + (t2 + t3);
-        }
-    }
-    if (tid < QR_NB * QR_NB) Ts[tid / QR_NB][tid % QR_NB] = 0.0;
     __syncthreads();
     // compact-WY factor, column by column: T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
     for (int i = 0; i < pc; ++i) {
@@ -184,18 +167,25 @@ __device__ __forceinline__ void qr_panel_body(double* X, int s, int c0, const De
         __syncthreads();
     }
     if (tid < QR_NB * QR_NB) Tws[tid] = Ts[tid / QR_NB][tid % QR_NB];
-    for (int cc = 0; cc < pc; ++cc)
-        for (int r = tid; r < nrows; r += QR_NT) X[(int64_t)(c0 + r) + (int64_t)s * (c0 + cc)] = P[cc * nrows + r];
+#pragma unroll
+    for (int q = 0; q < QR_CPW; ++q)
+#pragma unroll
+        for (int i = 0; i < RPW; ++i) {
+            const int c = wid * QR_CPW + q, r = lane + WAVE * i;
+            if (c < pc && r < nrows) X[(int64_t)(c0 + r) + (int64_t)s * (c0 + c)] = a[q][i];
+        }
 }
 
+template <int RPW>
 __global__ __launch_bounds__(QR_NT) void qr_panel_kernel(double* X, int s, int c0, const DevCtrl* ctrl,
                                                           double* Tws) {
-    qr_panel_body(X, s, c0, ctrl, Tws);
+    qr_panel_body<RPW>(X, s, c0, ctrl, Tws);
 }
 
+template <int RPW>
 __global__ __launch_bounds__(QR_NT) void qr_panel_batched_kernel(const SmallUnit* __restrict__ units, int s, int c0) {
     const SmallUnit& u = units[blockIdx.y];
-    qr_panel_body(u.SV, s, c0, u.ctrl, u.Tws);
+    qr_panel_body<RPW>(u.SV, s, c0, u.ctrl, u.Tws);
 }
 
 // Trailing update C <- (I - Y T Y^T)^T C for columns c0+nb .. ncols-1, one block per column.
@@ -925,10 +915,17 @@ hipError_t launch_init_ctrl(DevCtrl* c, int m, hipStream_t st) {
     return hipGetLastError();
 }
 
+// Rows per lane of a panel with nrows rows (nrows <= SMAX = 64 * 16).
+static int qr_rpw(int nrows) { return nrows <= 128 ? 2 : (nrows <= 256 ? 4 : (nrows <= 512 ? 8 : 16)); }
+
 hipError_t launch_qr(double* X, int s, int ncols_max, const DevCtrl* ctrl, double* Tws, hipStream_t st) {
     for (int c0 = 0; c0 < ncols_max; c0 += QR_NB) {
-        const size_t lds = (size_t)QR_NB * (s - c0) * sizeof(double);
-        hipLaunchKernelGGL(qr_panel_kernel, dim3(1), dim3(QR_NT), lds, st, X, s, c0, ctrl, Tws);
+        switch (qr_rpw(s - c0)) {
+            case 2: hipLaunchKernelGGL(qr_panel_kernel<2>, dim3(1), dim3(QR_NT), 0, st, X, s, c0, ctrl, Tws); break;
+            case 4: hipLaunchKernelGGL(qr_panel_kernel<4>, dim3(1), dim3(QR_NT), 0, st, X, s, c0, ctrl, Tws); break;
+            case 8: hipLaunchKernelGGL(qr_panel_kernel<8>, dim3(1), dim3(QR_NT), 0, st, X, s, c0, ctrl, Tws); break;
+            default: hipLaunchKernelGGL(qr_panel_kernel<16>, dim3(1), dim3(QR_NT), 0, st, X, s, c0, ctrl, Tws); break;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const int rest = ncols_max - c0 - QR_NB;
@@ -1033,9 +1030,13 @@ hipError_t launch_init_ctrl_batched(const SmallUnit* units, int nunits, hipStrea
 
 hipError_t launch_qr_batched(const SmallUnit* units, int nunits, int s, int ncols_max, hipStream_t st) {
     for (int c0 = 0; c0 < ncols_max; c0 += QR_NB) {
-        const int nrows = s - c0;
-        const size_t lds = (size_t)QR_NB * nrows * sizeof(double);
-        hipLaunchKernelGGL(qr_panel_batched_kernel, dim3(1, nunits), dim3(QR_NT), lds, st, units, s, c0);
+        const dim3 g(1, nunits);
+        switch (qr_rpw(s - c0)) {
+            case 2: hipLaunchKernelGGL(qr_panel_batched_kernel<2>, g, dim3(QR_NT), 0, st, units, s, c0); break;
+            case 4: hipLaunchKernelGGL(qr_panel_batched_kernel<4>, g, dim3(QR_NT), 0, st, units, s, c0); break;
+            case 8: hipLaunchKernelGGL(qr_panel_batched_kernel<8>, g, dim3(QR_NT), 0, st, units, s, c0); break;
+            default: hipLaunchKernelGGL(qr_panel_batched_kernel<16>, g, dim3(QR_NT), 0, st, units, s, c0); break;
+        }
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
         const int rest = ncols_max - c0 - QR_NB;

@@ -191,8 +191,9 @@ def skfab_sketch_apply(ctx: Context, n: int, s: int, zeta: int, seed: int, v: to
            "skfab_sketch_apply")
 
 
-def skfab_timing_enable(ctx: Context, enable: bool = True):
-    _check(N.lib().skfab_timing_enable(ctx.handle, 1 if enable else 0), "skfab_timing_enable")
+def skfab_timing_enable(ctx: Context, enable: bool = True, stride: int = 1):
+    """Event timing of every stride-th launch of each timed kernel class (off: enable=False)."""
+    _check(N.lib().skfab_timing_enable(ctx.handle, int(stride) if enable else 0), "skfab_timing_enable")
 
 
 def skfab_timing_read(ctx: Context, kernel: int = 0):
