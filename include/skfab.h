@@ -125,7 +125,10 @@ typedef struct skfab_info {
     int32_t status;         /* device-detected numerical status (skfab_status)       */
     int32_t m_used;         /* Krylov dimension actually used (< m after breakdown)  */
     int32_t l_used;         /* quadrature order accepted (0 if none)                 */
-    int32_t reserved;
+    int32_t a_format;       /* storage of A in the Arnoldi steps: 0 CSR (or no product with A),
+                               1 SELL-64 with int32 columns, 2 SELL-64 with int16 offsets
+                               col - row (chosen when every col - row of A lies in
+                               [-32768, 32767])                                      */
     double eps_est;         /* max_j | ||S v_j||^2 - 1 |  (Section 4.3 monitor)        */
     double rcond_R;         /* min|R_jj| / max|R_jj| of the whitening factor         */
     double sigma;           /* spectral scale used by the quadrature                 */

@@ -45,7 +45,7 @@ class skfab_params(C.Structure):
 
 class skfab_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("m_used", C.c_int32), ("l_used", C.c_int32),
-                ("reserved", C.c_int32), ("eps_est", C.c_double), ("rcond_R", C.c_double),
+                ("a_format", C.c_int32), ("eps_est", C.c_double), ("rcond_R", C.c_double),
                 ("sigma", C.c_double), ("beta", C.c_double), ("arnoldi_relres", C.c_double)]
 
 

@@ -573,6 +573,9 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     return SKFAB_OK;
 }
 
+// Storage form of A used by the step kernel (skfab_info.a_format).
+int32_t a_format(const DevCtrl& c) { return c.sell_ok ? (c.col16 ? 2 : 1) : 0; }
+
 skfab_status read_info(const Ptrs& w, hipStream_t st, skfab_info* info) {
     if (!info) return SKFAB_OK;
     DevCtrl c;
@@ -581,7 +584,7 @@ skfab_status read_info(const Ptrs& w, hipStream_t st, skfab_info* info) {
     info->status = c.status;
     info->m_used = c.m_used;
     info->l_used = c.l_used;
-    info->reserved = 0;
+    info->a_format = a_format(c);
     info->eps_est = c.eps_est;
     info->rcond_R = c.rcond;
     info->sigma = c.sigma;
@@ -1201,7 +1204,7 @@ skfab_status skfab_solve_batched(skfab_ctx* ctx, int32_t nprob, const skfab_batc
             o.status = cc.status;
             o.m_used = cc.m_used;
             o.l_used = cc.l_used;
-            o.reserved = 0;
+            o.a_format = a_format(c[qi * L.R]);  // the problem's SELL flags sit in its first unit
             o.eps_est = cc.eps_est;
             o.rcond_R = cc.rcond;
             o.sigma = cc.sigma;
@@ -1295,7 +1298,7 @@ void fill_info(const DevCtrl& c, skfab_info* info) {
     info->status = c.status;
     info->m_used = c.m_used;
     info->l_used = c.l_used;
-    info->reserved = 0;
+    info->a_format = a_format(c);
     info->eps_est = c.eps_est;
     info->rcond_R = c.rcond;
     info->sigma = c.sigma;

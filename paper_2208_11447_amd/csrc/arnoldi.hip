@@ -168,6 +168,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     // a breakdown detected by an earlier step ends the recurrence (the step that
     // detects it still runs its prologue to write the extension column)
     const int sell_flag = a.sctrl->sell_ok;  // issued with the control-block loads
+    const int col16 = a.sctrl->col16;
     if (a.ctrl->stop && a.ctrl->m_used < a.j - 1) return;
     constexpr int NSC = 2 * KW + 1;
     constexpr int NW = BLOCK / WAVE;
@@ -331,14 +332,25 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             if (sell) {
                 // entries in batches of SB: all index and value loads of a batch, then all
                 // gathers, then the products -- one memory round trip per batch
+                const int32_t rr = valid ? (int32_t)r : 0;  // offsets of rows beyond N are 0
+                const int16_t* __restrict__ slo = reinterpret_cast<const int16_t*>(a.sl_col);
                 for (int q0 = 0; q0 < len; q0 += SB) {
                     int cc[SB];
                     WT vv[SB], xb[SB], xu[SB][KW];
+                    if (col16) {
 #pragma unroll
-                    for (int q = 0; q < SB; ++q) {
-                        const bool in = q0 + q < len;
-                        cc[q] = in ? a.sl_col[e0 + (int64_t)(q0 + q) * WAVE] : 0;
-                        vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
+                        for (int q = 0; q < SB; ++q) {
+                            const bool in = q0 + q < len;
+                            cc[q] = in ? rr + (int32_t)slo[e0 + (int64_t)(q0 + q) * WAVE] : 0;
+                            vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
+                        }
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) {
+                            const bool in = q0 + q < len;
+                            cc[q] = in ? a.sl_col[e0 + (int64_t)(q0 + q) * WAVE] : 0;
+                            vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
+                        }
                     }
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
@@ -593,15 +605,29 @@ __global__ void normalize_basis_kernel(const VT* U, int64_t ldU, int64_t N, int 
 }
 
 // ------------------------------------------------------ SELL-64 conversion
-// sl_len[sl] = max row length in slice sl (one wavefront per slice).
-__global__ __launch_bounds__(256) void sell_len_kernel(const int32_t* rowptr, int64_t N, int64_t nslices,
-                                                       int32_t* sl_len) {
+// sl_len[sl] = max row length in slice sl (one wavefront per slice); ctrl->col_wide
+// is raised when a column lies outside [row - 32768, row + 32767], i.e. when the
+// 16-bit offset form of the column indices cannot be used.
+__global__ __launch_bounds__(256) void sell_len_kernel(const int32_t* rowptr, const int32_t* col, int64_t N,
+                                                       int64_t nslices, int32_t* sl_len, DevCtrl* ctrl) {
     const int lane = threadIdx.x & 63;
     for (int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sl < nslices; sl += (int64_t)gridDim.x * 4) {
         const int64_t r = sl * 64 + lane;
-        int len = (r < N) ? rowptr[r + 1] - rowptr[r] : 0;
-        for (int off = 32; off > 0; off >>= 1) len = max(len, __shfl_xor(len, off, 64));
-        if (lane == 0) sl_len[sl] = len;
+        const int e0 = (r < N) ? rowptr[r] : 0, e1 = (r < N) ? rowptr[r + 1] : 0;
+        int len = e1 - e0;
+        int wide = 0;
+        for (int e = e0; e < e1; ++e) {
+            const int64_t d = (int64_t)col[e] - r;
+            wide |= (d < -32768 || d > 32767) ? 1 : 0;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            len = max(len, __shfl_xor(len, off, 64));
+            wide |= __shfl_xor(wide, off, 64);
+        }
+        if (lane == 0) {
+            sl_len[sl] = len;
+            if (wide) atomicOr(&ctrl->col_wide, 1);
+        }
     }
 }
 
@@ -633,6 +659,7 @@ __global__ __launch_bounds__(1024) void sell_scan_top_kernel(int64_t* bsum, int6
         for (int i = 0; i < 1024; ++i) { const int64_t v = part[i]; part[i] = run; run += v; }
         ctrl->sell_total = run;
         ctrl->sell_ok = (run <= capacity) ? 1 : 0;
+        ctrl->col16 = ctrl->col_wide ? 0 : 1;
     }
     __syncthreads();
     int64_t run = part[threadIdx.x];
@@ -666,12 +693,15 @@ __global__ __launch_bounds__(1024) void sell_scan_apply_kernel(const int32_t* sl
 }
 
 // interleaved copy; padding entries have value 0 and their own row as column
+// (offset 0 in the int16 form, also for the rows beyond N of the last slice)
 template <typename AT>
 __global__ __launch_bounds__(256) void sell_fill_kernel(const int32_t* rowptr, const int32_t* col, const double* val,
                                                         int64_t N, int64_t nslices, const DevCtrl* ctrl,
                                                         const int64_t* sl_ptr, const int32_t* sl_len,
                                                         int32_t* sl_col, AT* sl_val) {
     if (!ctrl->sell_ok) return;
+    const bool c16 = ctrl->col16 != 0;
+    int16_t* sl_off = reinterpret_cast<int16_t*>(sl_col);
     const int lane = threadIdx.x & 63;
     for (int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sl < nslices; sl += (int64_t)gridDim.x * 4) {
         const int64_t r = sl * 64 + lane;
@@ -692,7 +722,8 @@ __global__ __launch_bounds__(256) void sell_fill_kernel(const int32_t* rowptr, c
 #pragma unroll
             for (int q = 0; q < 8; ++q) {
                 if (q0 + q < len) {
-                    sl_col[o + (int64_t)(q0 + q) * 64] = cb[q];
+                    if (c16) sl_off[o + (int64_t)(q0 + q) * 64] = (int16_t)((r < N) ? cb[q] - r : 0);
+                    else sl_col[o + (int64_t)(q0 + q) * 64] = cb[q];
                     sl_val[o + (int64_t)(q0 + q) * 64] = (AT)vb[q];
                 }
             }
@@ -791,7 +822,7 @@ hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const 
                                int64_t* bsum, int32_t* sl_col, void* sl_val, int prec, hipStream_t st) {
     const int64_t g64 = (nslices + 3) / 4;
     const unsigned g = (unsigned)(g64 < 65536 ? g64 : 65536);
-    hipLaunchKernelGGL(sell_len_kernel, dim3(g), dim3(256), 0, st, rowptr, N, nslices, sl_len);
+    hipLaunchKernelGGL(sell_len_kernel, dim3(g), dim3(256), 0, st, rowptr, col, N, nslices, sl_len, ctrl);
     const int64_t nb = sell_scan_blocks(nslices);
     hipLaunchKernelGGL(sell_scan_sums_kernel, dim3((unsigned)nb), dim3(1024), 0, st, sl_len, nslices, bsum);
     hipLaunchKernelGGL(sell_scan_top_kernel, dim3(1), dim3(1024), 0, st, bsum, nb, capacity, ctrl);

@@ -14,7 +14,8 @@ struct DevCtrl {
     int32_t l_used;     // accepted quadrature order
     int32_t converged;  // quadrature convergence flag
     int32_t l_prev;     // order of the rule held in qprev
-    int32_t pad[2];
+    int32_t col_wide;   // set by the SELL conversion when some |col - row| exceeds the int16 range
+    int32_t pad;
     double beta;        // ||b||
     double sigma;       // spectral scale of the quadrature
     double eps_est;     // max_j | ||S v_j||^2 - 1 |
@@ -25,7 +26,7 @@ struct DevCtrl {
     double pad2;
     int64_t sell_total; // entries of the SELL-64 copy of A (padded)
     int32_t sell_ok;    // 1: the SELL-64 copy fits the workspace and is used
-    int32_t pad3;
+    int32_t col16;      // 1: the SELL-64 copy stores column offsets col - row as int16
 };
 
 // Arguments of the fused Arnoldi step kernel.
@@ -33,7 +34,8 @@ struct StepArgs {
     int64_t N;
     int64_t ldU;
     // CSR (fallback) and its SELL-64 copy: slice sl holds rows 64 sl .. 64 sl + 63,
-    // entry q of row 64 sl + l at sl_ptr[sl] + 64 q + l, sl_len[sl] entries per row.
+    // entry q of row 64 sl + l at sl_ptr[sl] + 64 q + l, sl_len[sl] entries per row;
+    // sl_col holds int32 columns, or int16 offsets col - row when ctrl->col16 is set.
     const int32_t* rowptr;
     const int32_t* col;
     const double* val;

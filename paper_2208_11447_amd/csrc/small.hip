@@ -45,6 +45,7 @@ __device__ __forceinline__ void init_ctrl_body(DevCtrl* c, int m) {
         c->m_used = m; c->stop = 0; c->status = 0; c->l_used = 0; c->converged = 0; c->l_prev = 0;
         c->beta = 0.0; c->sigma = 1.0; c->eps_est = 0.0; c->rcond = 0.0; c->logdet = 0.0;
         c->qdiff_prev = INFINITY;
+        c->col_wide = 0;
     }
 }
 
