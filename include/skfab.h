@@ -254,7 +254,10 @@ typedef struct skfab_batch_problem {
 
 /* Launch shape of the batched step kernel: threads per block (256, 512, 1024) and
  * the target number of 64-row SELL slices per wavefront (sets the blocks per
- * (problem, right-hand side) pair, a multiple of 8 and at most 256). */
+ * (problem, right-hand side) pair, a multiple of 8 and at most 256).  A block size
+ * whose per-wave sketch bins (2 s_max doubles each) would not fit the CU's LDS is
+ * lowered by halving for the call (the stored tuning is kept); the autotuner skips
+ * such sizes. */
 typedef struct skfab_batch_tuning {
     int32_t block;
     int32_t slices_per_wave;

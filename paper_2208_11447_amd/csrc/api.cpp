@@ -182,15 +182,21 @@ struct Launch {
     int64_t rows_per_chunk;
 };
 
-Launch step_launch(int64_t N, int s) {
-    // largest block whose per-wave sketch bins fit in LDS (160 KiB, keep 4 KiB spare)
+// Largest step-kernel block (from `block` down to 256) whose LDS fits the CU's
+// 160 KiB with 4 KiB spare: per-wave sketch bins (2s doubles, shared with the
+// reduction scratch) and the per-wave slice-metadata ring (64 x 8 bytes).
+int step_block_fit(int block, int s) {
     const size_t lds_budget = 156 * 1024;
-    int block = 1024;
     auto lds_of = [&](int bl) {
         const size_t bins = (size_t)(bl / 64) * 2 * s, red = (size_t)(2 * KMAX + 1) * (bl + 72);
-        return (bins > red ? bins : red) * sizeof(double);
+        return (bins > red ? bins : red) * sizeof(double) + (size_t)(bl / 64) * 64 * 8;
     };
     while (block > 256 && lds_of(block) > lds_budget) block /= 2;
+    return block;
+}
+
+Launch step_launch(int64_t N, int s) {
+    int block = step_block_fit(1024, s);
     if (N < (int64_t)block * 256) block = 256;  // small problems: more, smaller blocks
     Launch L;
     L.block = block;
@@ -1180,10 +1186,11 @@ skfab_status skfab_solve_batched(skfab_ctx* ctx, int32_t nprob, const skfab_batc
     if (r != SKFAB_OK) return r;
     char* dev = static_cast<char*>(ws);
     hipStream_t st = ctx->stream;
-    const BatchPlan P = batch_plan(L, ctx->batch_block, ctx->batch_spw);
+    const int block = step_block_fit(ctx->batch_block, L.smax);
+    const BatchPlan P = batch_plan(L, block, ctx->batch_spw);
     r = batch_upload(ctx, L, P, probs, p, dev);
     if (r != SKFAB_OK) return r;
-    r = run_batch_arnoldi(ctx, L, P, probs, p, dev, ctx->batch_block, L.mmax, st);
+    r = run_batch_arnoldi(ctx, L, P, probs, p, dev, block, L.mmax, st);
     if (r != SKFAB_OK) return r;
     r = run_batch_small(L, p, dev, st);
     if (r != SKFAB_OK) return r;
@@ -1234,6 +1241,7 @@ skfab_status skfab_batch_autotune(skfab_ctx* ctx, int32_t nprob, const skfab_bat
     const bool timing = ctx->timing;
     ctx->timing = false;
     for (int bi = 0; bi < 3 && r == SKFAB_OK; ++bi) {
+        if (step_block_fit(blocks[bi], L.smax) != blocks[bi]) continue;  // bins do not fit LDS
         for (int si = 0; si < 7 && r == SKFAB_OK; ++si) {
             const BatchPlan P = batch_plan(L, blocks[bi], spws[si]);
             // the step launches of a candidate time j = 1 .. steps (j = 0 has no

@@ -142,6 +142,7 @@ __device__ void reduce_prev_sketch_tail(const double* skp, int G, int s, int64_t
 }
 
 // ------------------------------------------------------------- step kernel
+#define NW_OF(BLOCK) ((BLOCK) / 64)
 // SELL entries per load batch (fewer for wide windows to bound register use)
 template <int KW> struct SellBatch { static constexpr int value = KW <= 2 ? 8 : (KW <= 4 ? 4 : 1); };
 
@@ -162,6 +163,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     __shared__ double red[NSC_MAX];
     __shared__ double coef[KMAX + 2];
     __shared__ double win[KW * KW];
+    __shared__ int2 meta[NW_OF(BLOCK)][WAVE];  // per-wave ring: (entries, offset / 64) of 64 slices
     __shared__ double scratch[BLOCK / WAVE];
     __shared__ int s_ok;
 
@@ -175,10 +177,11 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     const int j = a.j, k = a.k, s = a.s, G = a.G;
     const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
 
-    // SELL path: every slice's entry count and offset are read once, lane i holding
-    // those of the wave's i-th slice (a window of 64 slices), so a slice's index and
-    // value loads do not wait on a metadata load.  The first window is requested
-    // before the prologue so that its latency overlaps the reductions.
+    // SELL path: every slice's entry count and offset are read once per window of 64
+    // slices (lane i fetching the wave's i-th slice) into a per-wave LDS ring, so a
+    // slice's loads wait neither on a metadata load from memory nor on the stores of
+    // the previous slice.  The first window is requested before the prologue so that
+    // its latency overlaps the reductions.
     const int chunk = xcd_chunk(bid, G);
     const int64_t sl0 = (int64_t)chunk * a.slices_per_chunk + wid;
     const int64_t sl1 = min(a.nslices, (int64_t)(chunk + 1) * a.slices_per_chunk);
@@ -251,6 +254,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         __syncthreads();
     }
 
+    meta[wid][lane] = make_int2(wlen, (int)(wptr >> 6));
     const int nwin = (j == 0) ? 0 : min(k, j);   // vectors j-1 .. j-nwin form u_j
     const int ndot = min(k - 1, j);              // vectors j-1 .. j-ndot enter the dots
     const double alpha = coef[0];
@@ -305,30 +309,26 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             if (iter - wbase == WAVE) {  // next window of 64 slices
                 wbase += WAVE;
                 const int64_t itl = it + (int64_t)lane * step;
-                wlen = (itl < it1) ? a.sl_len[itl] : 0;
-                wptr = (itl < it1) ? a.sl_ptr[itl] : 0;
+                const int nl = (itl < it1) ? a.sl_len[itl] : 0;
+                const int np = (itl < it1) ? (int)(a.sl_ptr[itl] >> 6) : 0;
+                meta[wid][lane] = make_int2(nl, np);
             }
-            len = readlane_i32(wlen, iter - wbase);
-            e0 = readlane_i64(wptr, iter - wbase) + lane;
+            const int2 md = meta[wid][iter - wbase];
+            len = md.x;
+            e0 = ((int64_t)md.y << 6) + lane;
         }
-        WT uo[KW];
-        WT u = (WT)0;
+        // the row's own inputs of u_j: requested before the matrix entries and used
+        // only after the product, which needs u_j at the neighbours, not at the row
+        WT wrow = (WT)0;
+        VT urow[KW];
         if (valid) {
-            u = alpha_w * (first ? (WT)b0p[r] : Wp[r]);
+            wrow = first ? (WT)b0p[r] : Wp[r];
 #pragma unroll
-            for (int o = 0; o < KW; ++o) {
-                uo[o] = (o < nwin) ? to_w<WT>(Uo[o][r]) : (WT)0;
-                if (o < nwin) u = fma(cf_w[o], uo[o], u);
-            }
-        } else {
-#pragma unroll
-            for (int o = 0; o < KW; ++o) uo[o] = (WT)0;
+            for (int o = 0; o < KW; ++o)
+                if (o < nwin) urow[o] = Uo[o][r];
         }
-        const VT us = Store<VT>::put(u);
-        u = to_w<WT>(us);  // the stored value is the one used everywhere
         WT w = (WT)0;
         if (!a.extend) {
-            if (valid) store_nt(us, &Uj[r]);
             if (sell) {
                 // entries in batches of SB: all index and value loads of a batch, then all
                 // gathers, then the products -- one memory round trip per batch
@@ -338,12 +338,16 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                     int cc[SB];
                     WT vv[SB], xb[SB], xu[SB][KW];
                     if (col16) {
+                        // every offset and value load issued before the first offset is
+                        // used (converting each offset as it arrives would serialise them)
 #pragma unroll
                         for (int q = 0; q < SB; ++q) {
                             const bool in = q0 + q < len;
-                            cc[q] = in ? rr + (int32_t)slo[e0 + (int64_t)(q0 + q) * WAVE] : 0;
+                            cc[q] = in ? (int32_t)slo[e0 + (int64_t)(q0 + q) * WAVE] : 0;
                             vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
                         }
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) cc[q] = (q0 + q < len) ? rr + cc[q] : 0;
                     } else {
 #pragma unroll
                         for (int q = 0; q < SB; ++q) {
@@ -380,7 +384,26 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                     w = fma((WT)a.val[e], x, w);
                 }
             }
-            if (valid) store_nt(w, &Wc[r]);
+        }
+        // u_j at the row, with the same operations as at the gathered columns
+        WT uo[KW];
+        WT u = (WT)0;
+        if (valid) {
+            u = alpha_w * wrow;
+#pragma unroll
+            for (int o = 0; o < KW; ++o) {
+                uo[o] = (o < nwin) ? to_w<WT>(urow[o]) : (WT)0;
+                if (o < nwin) u = fma(cf_w[o], uo[o], u);
+            }
+        } else {
+#pragma unroll
+            for (int o = 0; o < KW; ++o) uo[o] = (WT)0;
+        }
+        const VT us = Store<VT>::put(u);
+        u = to_w<WT>(us);  // the stored value is the one used everywhere
+        if (!a.extend && valid) {
+            store_nt(us, &Uj[r]);
+            store_nt(w, &Wc[r]);
         }
         if (valid) {
             const double ud = (double)u, wd = (double)w;
