@@ -195,8 +195,10 @@ int step_block_fit(int block, int s) {
     return block;
 }
 
-Launch step_launch(int64_t N, int s) {
-    int block = step_block_fit(1024, s);
+Launch step_launch(int64_t N, int s, int k) {
+    // windows wider than 4 (k > 4) need more than the 128 registers per thread that
+    // a 1024-thread block leaves; 512-thread blocks allow 256
+    int block = step_block_fit(k > 4 ? 512 : 1024, s);
     if (N < (int64_t)block * 256) block = 256;  // small problems: more, smaller blocks
     Launch L;
     L.block = block;
@@ -264,9 +266,9 @@ size_t vbytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 size_t wbytes(int prec) { return prec == 0 ? 8 : 4; }
 
 Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lmax, int npoly, bool with_basis,
-                   int prec) {
+                   int prec, int k = 1) {
     Layout ly;
-    ly.L = step_launch(N > 0 ? N : 1, s);
+    ly.L = step_launch(N > 0 ? N : 1, s, k);
     ly.ldU = (N + 63) / 64 * 64;
     ly.lnodes = max_level_nodes(l1, l2, lmax);
     size_t off = 0;
@@ -684,7 +686,7 @@ skfab_status skfab_workspace_bytes(const skfab_csr* A, const skfab_params* p, si
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    *bytes = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec).total;
+    *bytes = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k).total;
     return SKFAB_OK;
 }
 
@@ -696,7 +698,7 @@ skfab_status skfab_solve(skfab_ctx* ctx, const skfab_csr* A, const double* b, do
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec);
+    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k);
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);
@@ -721,7 +723,7 @@ skfab_status skfab_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, 
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec);
+    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k);
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);
@@ -1293,7 +1295,7 @@ AdaptiveLayout make_adaptive_layout(const skfab_csr* A, const skfab_params* p) {
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
     AdaptiveLayout L;
-    L.main = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec);
+    L.main = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k);
     L.snap = make_layout(0, 0, p->m, p->s, l1, l2, lmax, p->npoly, false, 0);
     L.snap_off = align_up(L.main.total);
     L.ysave_off = align_up(L.snap_off + L.snap.total);

@@ -30,6 +30,8 @@
 // [2s][G] partial array; the next step's blocks reduce it in slot order and
 // write S v_j and S A v_j (scaled by 1/eta_j) into SV, SAV.  Every sum has a
 // fixed order: results are bitwise reproducible run to run.
+#include <type_traits>
+
 #include "common.hpp"
 #include "device_state.hpp"
 
@@ -143,8 +145,10 @@ __device__ void reduce_prev_sketch_tail(const double* skp, int G, int s, int64_t
 
 // ------------------------------------------------------------- step kernel
 #define NW_OF(BLOCK) ((BLOCK) / 64)
-// SELL entries per load batch (fewer for wide windows to bound register use)
-template <int KW> struct SellBatch { static constexpr int value = KW <= 2 ? 8 : (KW <= 4 ? 4 : 1); };
+// SELL entries per load batch (fewer for wide windows to bound register use).  Seven
+// covers a 7-point stencil row in one batch: an eighth slot would cost a guarded
+// load and three gathers per row for nothing (measured 2.3 us per step, 3D 128^3).
+template <int KW> struct SellBatch { static constexpr int value = KW <= 2 ? 7 : (KW <= 4 ? 4 : 1); };
 
 // P: storage/arithmetic policy (PrecF64, PrecF32, PrecBF16).  The basis u_j is
 // formed in the SpMV type W, rounded to the basis type V for storage, and the
@@ -166,6 +170,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     __shared__ int2 meta[NW_OF(BLOCK)][WAVE];  // per-wave ring: (entries, offset / 64) of 64 slices
     __shared__ double scratch[BLOCK / WAVE];
     __shared__ int s_ok;
+    __shared__ int s_prog;  // slices finished by the block's wavefronts (main loop)
 
     // a breakdown detected by an earlier step ends the recurrence (the step that
     // detects it still runs its prologue to write the extension column)
@@ -231,6 +236,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         // the bin region is free again: the other wavefronts clear it meanwhile
         if (wid > 0)
             for (int i = tid - WAVE; i < NW * 2 * s; i += BLOCK - WAVE) bins[i] = 0.0;
+        if (tid == WAVE) s_prog = 0;
         __syncthreads();
         // S v_{j-1}, S A v_{j-1}; after a breakdown, S u_{j-1} unnormalised (extension column)
         const double eta_p = coef[KMAX + 1];
@@ -251,11 +257,12 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             for (int o = 0; o < KW; ++o) coef[1 + o] = 0.0;
         }
         for (int i = tid; i < NW * 2 * s; i += BLOCK) bins[i] = 0.0;
+        if (tid == 0) s_prog = 0;
         __syncthreads();
     }
 
     meta[wid][lane] = make_int2(wlen, (int)(wptr >> 6));
-    const int nwin = (j == 0) ? 0 : min(k, j);   // vectors j-1 .. j-nwin form u_j
+    const int nwin_all = (j == 0) ? 0 : min(k, j);   // vectors j-1 .. j-nwin form u_j
     const int ndot = min(k - 1, j);              // vectors j-1 .. j-ndot enter the dots
     const double alpha = coef[0];
     double cf[KW];
@@ -264,10 +271,10 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
 
     const WT* __restrict__ Wp = static_cast<const WT*>(a.Wprev);
     const double* __restrict__ b0p = a.b;
-    const bool first = (j == 0);
+    const bool first_all = (j == 0);
     const VT* Uo[KW];
 #pragma unroll
-    for (int o = 0; o < KW; ++o) Uo[o] = static_cast<const VT*>(a.U) + (int64_t)((o < nwin) ? (j - 1 - o) : 0) * a.ldU;
+    for (int o = 0; o < KW; ++o) Uo[o] = static_cast<const VT*>(a.U) + (int64_t)((o < nwin_all) ? (j - 1 - o) : 0) * a.ldU;
     VT* __restrict__ Uj = static_cast<VT*>(a.U) + (int64_t)(a.extend ? 0 : j) * a.ldU;
     WT* __restrict__ Wc = static_cast<WT*>(a.Wcur);
     const AT* __restrict__ slv = static_cast<const AT*>(a.sl_val);
@@ -298,6 +305,12 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     }
     constexpr int SB = SellBatch<KW>::value;
     const bool pre = sell && !a.extend;
+    // the loop twice: once for the steps whose window is full (j >= k, every test of
+    // the window length folded away), once for the first k steps
+    auto main_loop = [&](auto full_tag) {
+    constexpr bool FULL = decltype(full_tag)::value;
+    const bool first = FULL ? false : first_all;
+    const int nwin = FULL ? KW : nwin_all;
     int wbase = 0;
     int iter = 0;
     for (int64_t it = it0; it < it1; it += step, ++iter) {
@@ -306,6 +319,13 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         int len = 0;
         int64_t e0 = 0;
         if (pre) {
+            // the four wavefronts of a SIMD share its issue slots, which go to the oldest
+            // first: with equal static shares the youngest would finish last.  A
+            // wavefront behind the block's average takes the higher priority instead
+            // (timing only: the slices each wavefront owns do not change).
+            const int done = __hip_atomic_load(&s_prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if (done > iter * NW) __builtin_amdgcn_s_setprio(3);
+            else __builtin_amdgcn_s_setprio(0);
             if (iter - wbase == WAVE) {  // next window of 64 slices
                 wbase += WAVE;
                 const int64_t itl = it + (int64_t)lane * step;
@@ -319,13 +339,17 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         }
         // the row's own inputs of u_j: requested before the matrix entries and used
         // only after the product, which needs u_j at the neighbours, not at the row
+        // (for the widest windows only W: holding all k values through the product
+        // would spill registers)
         WT wrow = (WT)0;
         VT urow[KW];
         if (valid) {
             wrow = first ? (WT)b0p[r] : Wp[r];
+            if constexpr (KW <= 4) {
 #pragma unroll
-            for (int o = 0; o < KW; ++o)
-                if (o < nwin) urow[o] = Uo[o][r];
+                for (int o = 0; o < KW; ++o)
+                    if (o < nwin) urow[o] = Uo[o][r];
+            }
         }
         WT w = (WT)0;
         if (!a.extend) {
@@ -386,6 +410,13 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             }
         }
         // u_j at the row, with the same operations as at the gathered columns
+        if constexpr (KW > 4) {
+            if (valid) {
+#pragma unroll
+                for (int o = 0; o < KW; ++o)
+                    if (o < nwin) urow[o] = Uo[o][r];
+            }
+        }
         WT uo[KW];
         WT u = (WT)0;
         if (valid) {
@@ -427,7 +458,16 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                 for (int q = 0; q < ZETA; ++q) lds_add(binAV + rows[q], sg[q] * wd);
             }
         }
+        if (pre && lane == 0) __hip_atomic_fetch_add(&s_prog, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
+    };
+    if constexpr (KW <= 4) {  // (for the widest window the second copy would spill registers)
+        if (nwin_all == KW && !first_all) main_loop(std::integral_constant<bool, true>());
+        else main_loop(std::integral_constant<bool, false>());
+    } else {
+        main_loop(std::integral_constant<bool, false>());
+    }
+    __builtin_amdgcn_s_setprio(0);
 
     // partial sketches, bin-major; slot = chunk keeps one XCD's slots contiguous
     __syncthreads();

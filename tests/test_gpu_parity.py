@@ -45,7 +45,8 @@ def test_sketch_apply(N, s):
     assert rel(out.cpu().numpy(), S @ v) < 1e-14
 
 
-@pytest.mark.parametrize("n,m,k,s", [(30, 20, 2, 80), (37, 25, 3, 100), (40, 16, 1, 64), (33, 12, 4, 60)])
+@pytest.mark.parametrize("n,m,k,s", [(30, 20, 2, 80), (37, 25, 3, 100), (40, 16, 1, 64), (33, 12, 4, 60),
+                                     (31, 20, 6, 80), (29, 18, 8, 72)])
 def test_arnoldi_state_parity(n, m, k, s):
     """V, SV, S A V and the truncated Hessenberg entries against the oracle; ragged N."""
     log(f"arnoldi parity n={n} m={m} k={k} s={s}")
