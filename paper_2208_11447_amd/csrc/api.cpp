@@ -161,7 +161,7 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int EXP_BUFS = 10;  // dense m x m work matrices of the exponential
-constexpr int GMAX_BLOCKS = 256;  // step-kernel blocks for large N (one per CU)
+constexpr int GMAX_BLOCKS = STEP_GMAX_1024;  // step-kernel blocks for large N (one per CU at 1024 threads)
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -817,6 +817,7 @@ namespace {
 constexpr int BATCH_MAX_PROBLEMS = 4096;
 constexpr int BATCH_MAX_RHS = 4;
 constexpr int BATCH_GMAX = 256;     // step-kernel blocks per (problem, rhs) at most
+static_assert(BATCH_GMAX <= STEP_GMAX_1024, "the step kernel reduces at most STEP_GMAX_1024 * 1024 / block partials");
 constexpr int BATCH_SLOTS = 128;    // quadrature scratch slots per unit
 
 struct BatchProbLayout {

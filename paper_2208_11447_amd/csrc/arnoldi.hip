@@ -42,12 +42,19 @@ namespace skfab {
 // the start of the next launch so that their latency overlaps the reductions:
 // win[0] = ||A v_{p-1}||, win[o] = eta_{p-o} (1 <= o < KW), and
 // win[KW + (o-1) KW + o2] = <v_{p-o}, v_{p-o2}> (1 <= o < o2 < KW); 0 where absent.
+// (unconditional loads from clamped addresses, then a select: a load inside a
+// branch, or from a selected pointer, would be waited for before the loads that
+// follow it are issued)
 template <int KW>
 __device__ __forceinline__ double window_value(const StepArgs& a, int p, int t) {
-    if (t == 0) return (p >= 1) ? a.wnorm[p - 1] : 0.0;
-    if (t < KW) return (p - t >= 0) ? a.eta[p - t] : 0.0;
     const int q = t - KW, o = 1 + q / KW, o2 = q % KW;
-    return (o2 > o && p - o2 >= 0) ? a.gram[(int64_t)(p - o) * KMAX + (o2 - o - 1)] : 0.0;
+    const bool okw = t == 0 && p >= 1;
+    const bool oke = t > 0 && t < KW && p - t >= 0;
+    const bool okg = t >= KW && t < KW * KW && o2 > o && p - o2 >= 0;
+    const double vw = a.wnorm[okw ? p - 1 : 0];
+    const double ve = a.eta[oke ? p - t : 0];
+    const double vg = a.gram[okg ? (int64_t)(p - o) * KMAX + (o2 - o - 1) : 0];
+    return okw ? vw : (oke ? ve : (okg ? vg : 0.0));
 }
 
 // Turns the reduced dot products of step p into eta_p, h_{.,p}, the Gram
@@ -172,11 +179,14 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     __shared__ int s_ok;
     __shared__ int s_prog;  // slices finished by the block's wavefronts (main loop)
 
-    // a breakdown detected by an earlier step ends the recurrence (the step that
-    // detects it still runs its prologue to write the extension column)
     const int sell_flag = a.sctrl->sell_ok;  // issued with the control-block loads
     const int col16 = a.sctrl->col16;
-    if (a.ctrl->stop && a.ctrl->m_used < a.j - 1) return;
+    // A breakdown detected by an earlier step ends the recurrence (the step that
+    // detects it still runs its prologue to write the extension column).  The test
+    // is made only after every load of the prologue has been issued, so that the
+    // control block's latency overlaps theirs.
+    const int stop_flag = a.ctrl->stop, stop_m = a.ctrl->m_used;
+    const bool stopped = stop_flag && stop_m < a.j - 1;
     constexpr int NSC = 2 * KW + 1;
     constexpr int NW = BLOCK / WAVE;
     const int j = a.j, k = a.k, s = a.s, G = a.G;
@@ -190,43 +200,67 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     const int chunk = xcd_chunk(bid, G);
     const int64_t sl0 = (int64_t)chunk * a.slices_per_chunk + wid;
     const int64_t sl1 = min(a.nslices, (int64_t)(chunk + 1) * a.slices_per_chunk);
-    int wlen = 0;
-    int64_t wptr = 0;
-    if (!a.extend) {
-        const int64_t itl = sl0 + (int64_t)lane * NW;
-        wlen = (itl < sl1) ? a.sl_len[itl] : 0;
-        wptr = (itl < sl1) ? a.sl_ptr[itl] : 0;
-    }
+    // (loaded from a clamped, always valid index and masked only when written to
+    // LDS after the prologue: a guarded load would be waited for on the spot)
+    const int64_t itl0 = sl0 + (int64_t)lane * NW;
+    const bool win_in = !a.extend && itl0 < sl1;
+    const int64_t itl0c = win_in ? itl0 : 0;
+    const int wlen = a.sl_len[itl0c];
+    const int64_t wptr = a.sl_ptr[itl0c];
 
     if (j > 0) {
         // issue every load of the prologue before any reduction: the partial scalars
         // of step j-1 (G per scalar), this block's share of its sketch partials, and
         // the window's eta / Gram entries used by the coefficients
-        constexpr int PER = (NSC * 256 + BLOCK - 1) / BLOCK;  // G <= 256 * (1024 / BLOCK)
+        // (fixed trip counts and clamped indices: every load is issued before the first
+        // is used; the host never launches more than STEP_GMAX_1024 * 1024 / BLOCK blocks)
+        constexpr int GM = STEP_GMAX_1024 * (1024 / BLOCK);
+        constexpr int GPT = (GM + BLOCK - 1) / BLOCK;  // partial slots per thread
+        constexpr int GPL = (GM + WAVE - 1) / WAVE;    // slots per lane of one sketch bin
         double sv[NSC];
+        {
+            double ld[NSC][GPT];
 #pragma unroll
-        for (int sc = 0; sc < NSC; ++sc) {
-            double t = 0.0;
-            for (int g = tid; g < G; g += BLOCK) t += a.scal_prev[(int64_t)sc * G + g];
-            sv[sc] = t;
+            for (int q = 0; q < GPT; ++q) {
+                const int g = tid + q * BLOCK, gc = (g < G) ? g : 0;
+#pragma unroll
+                for (int sc = 0; sc < NSC; ++sc) ld[sc][q] = a.scal_prev[(int64_t)sc * G + gc];
+            }
+#pragma unroll
+            for (int sc = 0; sc < NSC; ++sc) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < GPT; ++q)  // mask by a factor 0 / 1: exact, and no branch
+                    t = fma((tid + q * BLOCK < G) ? 1.0 : 0.0, ld[sc][q], t);
+                sv[sc] = t;
+            }
         }
-        (void)PER;
-        const double wv = (tid < KW * KW) ? window_value<KW>(a, j - 1, tid) : 0.0;
+        const double wv = window_value<KW>(a, j - 1, tid);  // nonzero for tid < KW^2 only
         const int nb = 2 * s;
-        const int b0 = (int)(((int64_t)bid * nb) / G);
-        const int b1 = (int)(((int64_t)(bid + 1) * nb) / G);
+        const int b0 = (bid * nb) / G;        // bid nb <= 1024 * 2048: 32-bit arithmetic
+        const int b1 = ((bid + 1) * nb) / G;
         // sketch partial sums of this block's bins (one wavefront per bin)
         double skv = 0.0;
         int mybin = -1;
         if (b0 + wid < b1) {
             mybin = b0 + wid;
             const double* src = a.skp_prev + (int64_t)mybin * G;
-            double t0 = 0.0, t1 = 0.0;
-            int g = lane;
-            for (; g + WAVE < G; g += 2 * WAVE) { t0 += src[g]; t1 += src[g + WAVE]; }
-            if (g < G) t0 += src[g];
+            double ld[GPL];
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                const int g = lane + q * WAVE;
+                ld[q] = src[(g < G) ? g : 0];
+            }
+            double t0 = 0.0, t1 = 0.0;  // even slots of 64 into t0, odd into t1
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                const double mk = (lane + q * WAVE < G) ? 1.0 : 0.0;
+                if (q & 1) t1 = fma(mk, ld[q], t1);
+                else t0 = fma(mk, ld[q], t0);
+            }
             skv = t0 + t1;
         }
+        if (stopped) return;
         if (tid < KW * KW) win[tid] = wv;
         // every thread's scalar partials reduced in a fixed tree through the (not yet
         // used) sketch-bin region of LDS (its first barrier also publishes win)
@@ -252,6 +286,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                                            a.inv_sqrt_zeta / eta_p, ok, a.SV, a.SAV);
         if (!ok) return;
     } else {
+        if (stopped) return;
         if (tid == 0) {
             coef[0] = 1.0;
             for (int o = 0; o < KW; ++o) coef[1 + o] = 0.0;
@@ -261,7 +296,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         __syncthreads();
     }
 
-    meta[wid][lane] = make_int2(wlen, (int)(wptr >> 6));
+    meta[wid][lane] = win_in ? make_int2(wlen, (int)(wptr >> 6)) : make_int2(0, 0);
     const int nwin_all = (j == 0) ? 0 : min(k, j);   // vectors j-1 .. j-nwin form u_j
     const int ndot = min(k - 1, j);              // vectors j-1 .. j-ndot enter the dots
     const double alpha = coef[0];

@@ -10,6 +10,7 @@ constexpr int KMAX = 8;                 // largest truncation length of the fuse
 constexpr int NSC_MAX = 2 * KMAX + 1;   // partial scalars per Arnoldi step
 constexpr int MMAX = 512;               // largest Krylov dimension
 constexpr int SMAX = 1024;              // largest sketch size
+constexpr int STEP_GMAX_1024 = 256;     // step-kernel blocks at most, per 1024 threads of block size
 constexpr double BREAKDOWN_TOL = 1e-14; // lucky-breakdown threshold on h_{j+1,j} / ||A v_j||
 
 // ------------------------------------------------------------ precisions
