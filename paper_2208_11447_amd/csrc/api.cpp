@@ -31,6 +31,9 @@ int sketch_apply_blocks(int64_t n);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_init_ctrl(DevCtrl* c, int m, hipStream_t st);
 hipError_t launch_qr(double* X, int s, int ncols_max, const DevCtrl* ctrl, double* Tws, hipStream_t st);
+// launch rule of the step kernel (arnoldi.hip)
+int step_block_fit(int block, int s);
+Launch step_launch(int64_t N, int s, int k);
 hipError_t launch_pencil_setup(const double* X, int s, int m, int k, const DevCtrl* ctrl, const double* H,
                                double* K0r, double* T1r, hipStream_t st);
 hipError_t launch_hhat_rows(const DevCtrl* ctrl, int m, int s, const double* X, const double* T1r, const double* H,
@@ -161,7 +164,6 @@ namespace {
 
 constexpr size_t ALIGN = 256;
 constexpr int EXP_BUFS = 10;  // dense m x m work matrices of the exponential
-constexpr int GMAX_BLOCKS = STEP_GMAX_1024;  // step-kernel blocks for large N (one per CU at 1024 threads)
 
 size_t align_up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
@@ -172,46 +174,6 @@ int next_order(int l) {
     while (q * q > t) --q;
     while ((q + 1) * (q + 1) <= t) ++q;
     return (int)q;
-}
-
-struct Launch {
-    int block;
-    int G;
-    int64_t nslices;
-    int64_t slices_per_chunk;
-    int64_t rows_per_chunk;
-};
-
-// Largest step-kernel block (from `block` down to 256) whose LDS fits the CU's
-// 160 KiB with 4 KiB spare: per-wave sketch bins (2s doubles, shared with the
-// reduction scratch) and the per-wave slice-metadata ring (64 x 8 bytes).
-int step_block_fit(int block, int s) {
-    const size_t lds_budget = 156 * 1024;
-    auto lds_of = [&](int bl) {
-        const size_t bins = (size_t)(bl / 64) * 2 * s, red = (size_t)(2 * KMAX + 1) * (bl + 72);
-        return (bins > red ? bins : red) * sizeof(double) + (size_t)(bl / 64) * 64 * 8;
-    };
-    while (block > 256 && lds_of(block) > lds_budget) block /= 2;
-    return block;
-}
-
-Launch step_launch(int64_t N, int s, int k) {
-    // windows wider than 4 (k > 4) need more than the 128 registers per thread that
-    // a 1024-thread block leaves; 512-thread blocks allow 256
-    int block = step_block_fit(k > 4 ? 512 : 1024, s);
-    if (N < (int64_t)block * 256) block = 256;  // small problems: more, smaller blocks
-    Launch L;
-    L.block = block;
-    L.nslices = (N + 63) / 64;
-    const int waves = block / 64;
-    int64_t G = (L.nslices + waves - 1) / waves;
-    const int64_t gmax = (int64_t)GMAX_BLOCKS * (1024 / block);
-    if (G > gmax) G = gmax;
-    G = (G + 7) / 8 * 8;
-    L.G = (int)G;
-    L.slices_per_chunk = (L.nslices + G - 1) / G;
-    L.rows_per_chunk = (N + G - 1) / G;
-    return L;
 }
 
 struct Layout {

@@ -869,6 +869,39 @@ static hipError_t launch_step_p(const StepArgs& a, int block, hipStream_t st) {
     }
 }
 
+// ----------------------------------------------------------- launch rule
+// Largest step-kernel block (from `block` down to 256) whose LDS fits the CU's
+// 160 KiB with 4 KiB spare: per-wave sketch bins (2s doubles, shared with the
+// reduction scratch) and the per-wave slice-metadata ring (64 x 8 bytes).
+int step_block_fit(int block, int s) {
+    const size_t lds_budget = 156 * 1024;
+    auto lds_of = [&](int bl) {
+        const size_t bins = (size_t)(bl / 64) * 2 * s, red = (size_t)(2 * KMAX + 1) * (bl + 72);
+        return (bins > red ? bins : red) * sizeof(double) + (size_t)(bl / 64) * 64 * 8;
+    };
+    while (block > 256 && lds_of(block) > lds_budget) block /= 2;
+    return block;
+}
+
+Launch step_launch(int64_t N, int s, int k) {
+    // windows wider than 4 (k > 4) need more than the 128 registers per thread that
+    // a 1024-thread block leaves; 512-thread blocks allow 256
+    int block = step_block_fit(k > 4 ? 512 : 1024, s);
+    if (N < (int64_t)block * 256) block = 256;  // small problems: more, smaller blocks
+    Launch L;
+    L.block = block;
+    L.nslices = (N + 63) / 64;
+    const int waves = block / 64;
+    int64_t G = (L.nslices + waves - 1) / waves;
+    const int64_t gmax = (int64_t)STEP_GMAX_1024 * (1024 / block);
+    if (G > gmax) G = gmax;
+    G = (G + 7) / 8 * 8;
+    L.G = (int)G;
+    L.slices_per_chunk = (L.nslices + G - 1) / G;
+    L.rows_per_chunk = (N + G - 1) / G;
+    return L;
+}
+
 hipError_t launch_arnoldi_step(const StepArgs& a, int zeta, int block, int prec, hipStream_t st) {
     if (prec == 1) return launch_step_p<PrecF32>(a, block, st);
     if (prec == 2) return launch_step_p<PrecBF16>(a, block, st);

@@ -29,6 +29,17 @@ struct DevCtrl {
     int32_t col16;      // 1: the SELL-64 copy stores column offsets col - row as int16
 };
 
+// Launch shape of the step kernel for one problem (host side): block size, grid
+// G (a multiple of 8, at most STEP_GMAX_1024 * 1024 / block) and the contiguous
+// slice / row chunks of the G blocks.
+struct Launch {
+    int block;
+    int G;
+    int64_t nslices;
+    int64_t slices_per_chunk;
+    int64_t rows_per_chunk;
+};
+
 // Arguments of the fused Arnoldi step kernel.
 struct StepArgs {
     int64_t N;
