@@ -129,7 +129,10 @@ def sfom_closed(arn: ArnoldiResult, f: str, fparam: float = 0.0, poly=None) -> S
 # requested tolerance lies below what the node solves can resolve, the relative
 # differences of consecutive orders stop falling at some small level; an order
 # whose difference is below QUAD_FLOOR and larger than half the previous
-# difference is then accepted instead of refining up to l_max.
+# difference is then accepted instead of refining up to l_max.  At the last
+# order the sequence allows (the next one would exceed l_max), a difference below
+# QUAD_FLOOR is accepted even while it is still falling: no further order exists
+# to show the floor, and the difference already bounds the change at that level.
 QUAD_FLOOR = 1e-10
 
 
@@ -146,6 +149,8 @@ def _adaptive(eval_rule, tol: float, l1: int, l2: int, lmax: int):
             return q2, l2
         nxt = quad.next_order(l2)
         if nxt > lmax:
+            if d <= QUAD_FLOOR:
+                return q2, l2
             raise QuadratureError(f"no convergence up to l = {l2}")
         q1, l1, l2, d_prev = q2, l2, nxt, d
         q2 = eval_rule(l2)

@@ -92,6 +92,18 @@ def test_adaptive_no_floor_acceptance_above_floor():
         _adaptive(rule, 1e-13, 32, 45, orders[-1])
 
 
+def test_adaptive_final_order_below_floor_is_accepted():
+    """Still falling fast, but the sequence ends (l_max): below the floor is accepted
+    at the last order, above it is a failure."""
+    from oracle.methods import QUAD_FLOOR, QuadratureError, _adaptive
+    rule, orders = _rule_from_diffs([1e-2, 1e-6, 1e-9, 4e-11])
+    _, l = _adaptive(rule, 1e-13, 32, 45, orders[4])
+    assert l == orders[4] and 4e-11 <= QUAD_FLOOR
+    rule, orders = _rule_from_diffs([1e-2, 1e-6, 1e-9, 4e-10])
+    with pytest.raises(QuadratureError):
+        _adaptive(rule, 1e-13, 32, 45, orders[4])
+
+
 def test_adaptive_fast_decrease_is_not_stagnation():
     """Below the floor but still falling faster than 2x per order: keep refining."""
     from oracle.methods import _adaptive
