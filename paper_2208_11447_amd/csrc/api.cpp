@@ -41,10 +41,10 @@ hipError_t launch_hhat_rows(const DevCtrl* ctrl, int m, int s, const double* X, 
 hipError_t launch_hhat_rows_batched(const SmallUnit* units, int nunits, int m, int s, hipStream_t st);
 hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, const double* eta,
                                  const double* T1r, const double* K0r, const double* Hh, double* Ubuf, double* Urhs,
-                                 double* y0, int is_ls, int branch_check, hipStream_t st);
+                                 double* y0, int is_ls, int branch_check, int k, hipStream_t st);
 hipError_t launch_quad_group(const DevCtrl* ctrl, const QuadGroup& g, const double* T1r, const double* K0r,
                              const double* Hh, double* Ubuf, double* Urhs, double* nodebuf, int m, int is_ls,
-                             const double* X, const double* eta, hipStream_t st);
+                             const double* X, const double* eta, int k, hipStream_t st);
 hipError_t launch_quad_reduce(DevCtrl* ctrl, const QuadGroup& g, const double* nodebuf, int m, double tol,
                               const double* T1r, double* qprev, double* y, hipStream_t st);
 hipError_t launch_quad_fail(DevCtrl* ctrl, hipStream_t st);
@@ -74,9 +74,9 @@ hipError_t launch_init_ctrl_batched(const SmallUnit* units, int nunits, hipStrea
 hipError_t launch_qr_batched(const SmallUnit* units, int nunits, int s, int ncols_max, hipStream_t st);
 hipError_t launch_pencil_setup_batched(const SmallUnit* units, int nunits, int s, int m, int k, hipStream_t st);
 hipError_t launch_pencil_scalars_batched(const SmallUnit* units, int nunits, int m, int s, int is_ls, int branch_check,
-                                         hipStream_t st);
+                                         int k, hipStream_t st);
 hipError_t launch_quad_group_batched(const SmallUnit* units, int nunits, const QuadGroup& g, int m, int is_ls,
-                                     int slots, hipStream_t st);
+                                     int slots, int k, hipStream_t st);
 hipError_t launch_quad_reduce_batched(const SmallUnit* units, int nunits, const QuadGroup& g, int m, double tol,
                                       hipStream_t st);
 hipError_t launch_quad_fail_batched(const SmallUnit* units, int nunits, hipStream_t st);
@@ -214,6 +214,7 @@ std::vector<QuadGroup> quad_groups(int l1, int l2, int lmax) {
         g.nlev += 1;
     }
     if (g.nlev > 0) out.push_back(g);
+    if (!out.empty()) out.back().last = 1;
     return out;
 }
 
@@ -512,11 +513,11 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     const int branch = (p->f == SKFAB_F_INVSQRT && !ls) ? 1 : 0;
     // square system at t = 0: sigma, rcond, branch check; for 1/z with sFOM also the solution
     HIP_TRY(launch_pencil_scalars(m, s, w.SV, w.ctrl, w.eta, w.T1r, w.K0r, w.Hh, w.Ubuf, w.Urhs, w.y0, 0, branch,
-                                  st));
+                                  p->k, st));
     if (p->f == SKFAB_F_INV) {
         if (ls)
             HIP_TRY(launch_pencil_scalars(m, s, w.SV, w.ctrl, w.eta, w.T1r, w.K0r, w.Hh, w.Ubuf, w.Urhs, w.y0, 1, 0,
-                                          st));
+                                          p->k, st));
         HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
         return SKFAB_OK;
     }
@@ -535,7 +536,7 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     // z^(-1/2): adaptive Gauss-Chebyshev (Section 4.1 / 5.1), orders evaluated in groups
     for (const QuadGroup& g : quad_groups(l1, l2, lmax)) {
         HIP_TRY(launch_quad_group(w.ctrl, g, w.T1r, w.K0r, w.Hh, w.Ubuf, w.Urhs, w.nodebuf, m, ls ? 1 : 0, w.SV,
-                                  w.eta, st));
+                                  w.eta, p->k, st));
         HIP_TRY(launch_quad_reduce(w.ctrl, g, w.nodebuf, m, tol, w.T1r, w.qprev, w.y0, st));
     }
     HIP_TRY(launch_quad_fail(w.ctrl, st));
@@ -1080,12 +1081,12 @@ skfab_status run_batch_small(const BatchLayout& L, const skfab_params* p, char* 
     HIP_TRY(launch_pencil_setup_batched(sm, n, s, m, p->k, st));
     HIP_TRY(launch_hhat_rows_batched(sm, n, m, s, st));
     const int branch = (p->f == SKFAB_F_INVSQRT && !ls) ? 1 : 0;
-    HIP_TRY(launch_pencil_scalars_batched(sm, n, m, s, 0, branch, st));
+    HIP_TRY(launch_pencil_scalars_batched(sm, n, m, s, 0, branch, p->k, st));
     if (p->f == SKFAB_F_INV) {
-        if (ls) HIP_TRY(launch_pencil_scalars_batched(sm, n, m, s, 1, 0, st));
+        if (ls) HIP_TRY(launch_pencil_scalars_batched(sm, n, m, s, 1, 0, p->k, st));
     } else {
         for (const QuadGroup& g : quad_groups(l1, l2, lmax)) {
-            HIP_TRY(launch_quad_group_batched(sm, n, g, m, ls ? 1 : 0, BATCH_SLOTS, st));
+            HIP_TRY(launch_quad_group_batched(sm, n, g, m, ls ? 1 : 0, BATCH_SLOTS, p->k, st));
             HIP_TRY(launch_quad_reduce_batched(sm, n, g, m, tol, st));
         }
         HIP_TRY(launch_quad_fail_batched(sm, n, st));

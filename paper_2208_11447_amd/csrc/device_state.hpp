@@ -110,6 +110,7 @@ struct QuadGroup {
     int32_t lev_l[MAX_GROUP_LEVELS];     // order of each level
     int32_t lev_off[MAX_GROUP_LEVELS];   // first node of each level
     int32_t first;                       // 1: the group starts the sequence (its first level seeds qprev)
+    int32_t last;                        // 1: the group ends the sequence (its last level is the final order)
 };
 
 }  // namespace skfab

@@ -685,6 +685,192 @@ __device__ __forceinline__ void quad_level_body(const DevCtrl* ctrl, const QuadG
     }
 }
 
+// ------------------------------------------------ banded square node solves
+// In the square case the node systems are (a I + H_hat) y = rhs0 e_1 with
+// H_hat = H_m + r e_m^T: H_m from the k-truncated recurrence is zero outside
+// i-1 <= c <= i+k-1, so a row of H_hat holds at most k+1 band entries plus its
+// last-column entry.  Gaussian elimination with partial pivoting keeps that shape
+// (two candidate rows per column), so one lane solves one node in O(m k).  The
+// operations on the band entries are those of the dense Hessenberg elimination.
+constexpr int BAND_NT = 256;
+
+// Band rows of H_hat (row-major, ld m) into LDS: Bs[i KB + d] = H_hat[i][i-1+d] for
+// 0 <= i-1+d < mu-1 (KB = k+1), Ls[i] = H_hat[i][mu-1]; whole block.
+template <int KB>
+__device__ __forceinline__ void load_band(const double* __restrict__ Hh, int m, int mu, double* Bs, double* Ls) {
+    for (int idx = threadIdx.x; idx < mu * KB; idx += blockDim.x) {
+        const int i = idx / KB, d = idx - i * KB, c = i - 1 + d;
+        Bs[idx] = (c >= 0 && c < mu - 1) ? Hh[(int64_t)i * m + c] : 0.0;
+    }
+    for (int i = threadIdx.x; i < mu; i += blockDim.x) Ls[i] = Hh[(int64_t)i * m + (mu - 1)];
+}
+
+// One node on the calling lane: y (stride 1) <- (a I + H_hat)^-1 rhs0 e_1.  Row kk
+// of U goes to Us[(kk (KB+2) + f) fstride], f = 0: pivot, 1..KB-1: entries right of
+// it, KB: last column, KB+1: transformed right-hand side.  *lad = sum log|pivot|,
+// *neg = parity of row swaps plus negative pivots (sign of the determinant).
+template <int KB>
+__device__ void band_node_solve(int mu, double a, double rhs0, const double* Bs, const double* Ls,
+                                double* __restrict__ Us, int64_t fstride, double* __restrict__ y, double* lad,
+                                int* neg) {
+    constexpr int F = KB + 2;
+    double c[KB];  // carry row: columns kk .. kk+KB-1 (the last slot is zero on entry)
+#pragma unroll
+    for (int d = 0; d + 1 < KB; ++d) c[d] = Bs[d + 1];
+    c[KB - 1] = 0.0;
+    double cL = Ls[0], cR = rhs0;
+    if (mu > 1) c[0] += a;
+    else cL += a;
+    int ng = 0;
+    double ld = 0.0;
+    for (int kk = 0; kk + 1 < mu; ++kk) {
+        double n[KB];
+#pragma unroll
+        for (int d = 0; d < KB; ++d) n[d] = Bs[(kk + 1) * KB + d];
+        double nL = Ls[kk + 1], nR = 0.0;
+        if (kk + 2 < mu) n[1] += a;  // the diagonal of row kk+1 (in the last column for the last row)
+        else nL += a;
+        if (fabs(n[0]) > fabs(c[0])) {
+#pragma unroll
+            for (int d = 0; d < KB; ++d) { const double t = c[d]; c[d] = n[d]; n[d] = t; }
+            double t = cL; cL = nL; nL = t;
+            t = cR; cR = nR; nR = t;
+            ng ^= 1;
+        }
+        const double p = c[0];
+        const double l = (p != 0.0) ? n[0] / p : 0.0;
+        double* u = Us + (int64_t)kk * F * fstride;
+#pragma unroll
+        for (int d = 0; d < KB; ++d) u[d * fstride] = c[d];
+        u[KB * fstride] = cL;
+        u[(KB + 1) * fstride] = cR;
+        ld += log(fabs(p));
+        if (p < 0.0) ng ^= 1;
+#pragma unroll
+        for (int d = 0; d + 1 < KB; ++d) c[d] = fma(-l, c[d + 1], n[d + 1]);
+        c[KB - 1] = 0.0;
+        cL = fma(-l, cL, nL);
+        cR = fma(-l, cR, nR);
+    }
+    // last pivot: column mu-1 lives in the last-column slot
+    const double pl = cL;
+    ld += log(fabs(pl));
+    if (pl < 0.0) ng ^= 1;
+    const double ylast = cR * (1.0 / pl);
+    y[mu - 1] = ylast;
+    // back substitution, columns in descending order as in the dense elimination;
+    // yw[d] = y[kk+1+d] (zero beyond column mu-2: those band slots hold zeros)
+    double yw[KB];
+#pragma unroll
+    for (int d = 0; d < KB; ++d) yw[d] = 0.0;
+    for (int kk = mu - 2; kk >= 0; --kk) {
+        const double* u = Us + (int64_t)kk * F * fstride;
+        double sres = fma(-u[KB * fstride], ylast, u[(KB + 1) * fstride]);
+#pragma unroll
+        for (int d = KB - 1; d >= 1; --d) sres = fma(-u[d * fstride], yw[d - 1], sres);
+        const double yk = sres * (1.0 / u[0]);
+        y[kk] = yk;
+#pragma unroll
+        for (int d = KB - 1; d >= 1; --d) yw[d] = yw[d - 1];
+        yw[0] = yk;
+    }
+    if (lad) *lad = ld;
+    if (neg) *neg = ng;
+}
+
+// Nodes of a quadrature group, square case, one lane per node.  Ubuf holds the
+// U rows of the group's nodes, field-major (node index fastest, stride grp.total:
+// a group of one high order can hold more than NODE_SLOTS nodes).
+template <int KB>
+__device__ __forceinline__ void quad_level_band_body(const DevCtrl* ctrl, const QuadGroup& grp,
+                                                     const double* __restrict__ Hh, double* Ubuf,
+                                                     double* nodebuf, int m, const double* eta) {
+    __shared__ double Bs[MMAX * KB];
+    __shared__ double Ls[MMAX];
+    if (ctrl->converged || ctrl->status != 0) return;
+    const int mu = ctrl->m_used;
+    if (mu == 0) return;
+    load_band<KB>(Hh, m, mu, Bs, Ls);
+    __syncthreads();
+    const int i = blockIdx.x * BAND_NT + threadIdx.x;
+    if (i >= grp.total) return;
+    int lev = 0;
+    while (lev + 1 < grp.nlev && i >= grp.lev_off[lev + 1]) ++lev;
+    const int l = grp.lev_l[lev];
+    const int ii = i - grp.lev_off[lev];
+    const double x = cos((2.0 * ii + 1.0) * M_PI / (2.0 * l));
+    const double t = (1.0 - x) / (1.0 + x);
+    const double w = (2.0 / l) / (1.0 + x);
+    band_node_solve<KB>(mu, t * ctrl->sigma, eta[0] * w, Bs, Ls, Ubuf + i, grp.total, nodebuf + (int64_t)i * m,
+                        nullptr, nullptr);
+}
+
+template <int KB>
+__global__ __launch_bounds__(BAND_NT) void quad_level_band_kernel(const DevCtrl* ctrl, QuadGroup grp,
+                                                                  const double* Hh, double* Ubuf, double* nodebuf,
+                                                                  int m, const double* eta) {
+    quad_level_band_body<KB>(ctrl, grp, Hh, Ubuf, nodebuf, m, eta);
+}
+
+template <int KB>
+__global__ __launch_bounds__(BAND_NT) void quad_level_band_batched_kernel(const SmallUnit* __restrict__ units,
+                                                                          QuadGroup grp, int m) {
+    const SmallUnit& u = units[blockIdx.y];
+    quad_level_band_body<KB>(u.ctrl, grp, u.Hh, u.Ubuf, u.nodebuf, m, u.eta);
+}
+
+// Square case of the pencil scalars with the band elimination: beta, the rank
+// test on diag(R), H_hat y0 = beta e_1 (lane 0), log|det H_hat|, sigma and the
+// sign of det H_hat for the branch test.  One wavefront.
+template <int KB>
+__device__ __forceinline__ void pencil_scalars_band_body(int m, int s, const double* X, DevCtrl* ctrl,
+                                                         const double* eta, const double* Hh, double* Ubuf,
+                                                         double* y0, int branch_check) {
+    __shared__ double Bs[MMAX * KB];
+    __shared__ double Ls[MMAX];
+    const int mu = ctrl->m_used;
+    if (mu == 0) return;
+    const int lane = threadIdx.x;
+    double rmin = 1e308, rmax = 0.0;
+    for (int j = lane; j < mu; j += WAVE) {
+        const double dg = fabs(X[j + (int64_t)s * j]);
+        rmin = fmin(rmin, dg);
+        rmax = fmax(rmax, dg);
+    }
+    rmax = wave_max(rmax);
+    rmin = -wave_max(-rmin);
+    load_band<KB>(Hh, m, mu, Bs, Ls);
+    __syncthreads();
+    if (lane == 0) {
+        const double beta = eta[0];
+        double ld = 0.0;
+        int ng = 0;
+        band_node_solve<KB>(mu, 0.0, beta, Bs, Ls, Ubuf, 1, y0, &ld, &ng);
+        ctrl->beta = beta;
+        ctrl->rcond = (rmax > 0.0) ? rmin / rmax : 0.0;
+        if (!(rmin > 2.220446049250313e-16 * rmax)) ctrl->status = 3;  // SKFAB_ERR_RANK
+        const double lg = ld / mu;
+        ctrl->logdet = ld;
+        ctrl->sigma = exp(lg);
+        if (branch_check && ng && ctrl->status == 0) ctrl->status = 4;  // SKFAB_ERR_BRANCH: det H_hat < 0
+        if (!isfinite(lg) && ctrl->status == 0) ctrl->status = 3;
+    }
+}
+
+template <int KB>
+__global__ __launch_bounds__(64) void pencil_scalars_band_kernel(int m, int s, const double* X, DevCtrl* ctrl,
+                                                                 const double* eta, const double* Hh, double* Ubuf,
+                                                                 double* y0, int branch_check) {
+    pencil_scalars_band_body<KB>(m, s, X, ctrl, eta, Hh, Ubuf, y0, branch_check);
+}
+
+template <int KB>
+__global__ __launch_bounds__(64) void pencil_scalars_band_batched_kernel(const SmallUnit* __restrict__ units, int m,
+                                                                         int s, int branch_check) {
+    const SmallUnit& u = units[blockIdx.y];
+    pencil_scalars_band_body<KB>(m, s, u.SV, u.ctrl, u.eta, u.Hh, u.Ubuf, u.y0, branch_check);
+}
+
 template <int QM>
 __global__ __launch_bounds__(256) void quad_level_kernel(const DevCtrl* ctrl, QuadGroup grp, const double* T1r,
                                                          const double* K0r, const double* Hh, double* Ubuf,
@@ -767,9 +953,11 @@ __device__ __forceinline__ void quad_reduce_body(DevCtrl* ctrl, const QuadGroup&
         if (grp.first && lev == 0) continue;
         if (!isfinite(nd[lev]) || !isfinite(nc[lev])) { bad = true; last = lev; break; }
         // relative difference of consecutive orders; accepted below tol, or at the
-        // rounding floor: below QUAD_FLOOR and no longer falling (d > d_prev / 2)
+        // rounding floor: below QUAD_FLOOR and no longer falling (d > d_prev / 2), or
+        // below QUAD_FLOOR at the final order of the sequence
         const double d = (nc[lev] > 0.0) ? sqrt(nd[lev] / nc[lev]) : (nd[lev] > 0.0 ? INFINITY : 0.0);
-        if (d <= tol || (d <= QUAD_FLOOR && d > 0.5 * dprev)) { acc_lev = lev; break; }
+        const bool final_order = grp.last && lev == grp.nlev - 1;
+        if (d <= tol || (d <= QUAD_FLOOR && (d > 0.5 * dprev || final_order))) { acc_lev = lev; break; }
         dprev = d;
     }
     if (acc_lev >= 0) {
@@ -955,9 +1143,26 @@ hipError_t launch_hhat_rows(const DevCtrl* ctrl, int m, int s, const double* X, 
     return hipGetLastError();
 }
 
+// Square case with the band elimination: window k <= 4 and U rows that fit the
+// node scratch (m >= k + 3); otherwise the dense one-wave elimination.
+static bool band_ok(int k, int m) { return k >= 1 && k <= 4 && m >= k + 3; }
+
+#define BAND_DISPATCH(KB_RT, LAUNCH)          \
+    switch (KB_RT) {                          \
+        case 2: { constexpr int KB = 2; LAUNCH; break; } \
+        case 3: { constexpr int KB = 3; LAUNCH; break; } \
+        case 4: { constexpr int KB = 4; LAUNCH; break; } \
+        default: { constexpr int KB = 5; LAUNCH; break; } \
+    }
+
 hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, const double* eta,
                                  const double* T1r, const double* K0r, const double* Hh, double* Ubuf, double* Urhs,
-                                 double* y0, int is_ls, int branch_check, hipStream_t st) {
+                                 double* y0, int is_ls, int branch_check, int k, hipStream_t st) {
+    if (!is_ls && band_ok(k, m)) {
+        BAND_DISPATCH(k + 1, hipLaunchKernelGGL(pencil_scalars_band_kernel<KB>, dim3(1), dim3(64), 0, st, m, s, X,
+                                                ctrl, eta, Hh, Ubuf, y0, branch_check));
+        return hipGetLastError();
+    }
     if (m <= 256)
         hipLaunchKernelGGL(pencil_setup_scalars_kernel<4>, dim3(1), dim3(64), 0, st, m, s, X, ctrl, ctrl, eta, T1r,
                            K0r, Hh, Ubuf, Urhs, y0, is_ls, branch_check);
@@ -969,7 +1174,15 @@ hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, c
 
 hipError_t launch_quad_group(const DevCtrl* ctrl, const QuadGroup& g, const double* T1r, const double* K0r,
                              const double* Hh, double* Ubuf, double* Urhs, double* nodebuf, int m, int is_ls,
-                             const double* X, const double* eta, hipStream_t st) {
+                             const double* X, const double* eta, int k, hipStream_t st) {
+    // one lane per node; the U rows of all g.total nodes, (k + 3) m doubles each, fit the
+    // NODE_SLOTS x m x m node scratch when g.total (k + 3) <= NODE_SLOTS m
+    if (!is_ls && band_ok(k, m) && (int64_t)g.total * (k + 3) <= (int64_t)NODE_SLOTS * m) {
+        const int blocks = (g.total + BAND_NT - 1) / BAND_NT;
+        BAND_DISPATCH(k + 1, hipLaunchKernelGGL(quad_level_band_kernel<KB>, dim3(blocks), dim3(BAND_NT), 0, st, ctrl,
+                                                g, Hh, Ubuf, nodebuf, m, eta));
+        return hipGetLastError();
+    }
     const int waves = g.total < NODE_SLOTS ? g.total : NODE_SLOTS;
     const int blocks = (waves + 3) / 4;
     if (m <= 256)
@@ -1065,7 +1278,13 @@ hipError_t launch_hhat_rows_batched(const SmallUnit* units, int nunits, int m, i
 }
 
 hipError_t launch_pencil_scalars_batched(const SmallUnit* units, int nunits, int m, int s, int is_ls, int branch_check,
-                                         hipStream_t st) {
+                                         int k, hipStream_t st) {
+    // the band U rows of the one node: (k + 3) m doubles of the unit's node scratch
+    if (!is_ls && band_ok(k, m)) {
+        BAND_DISPATCH(k + 1, hipLaunchKernelGGL(pencil_scalars_band_batched_kernel<KB>, dim3(1, nunits), dim3(64), 0,
+                                                st, units, m, s, branch_check));
+        return hipGetLastError();
+    }
     if (m <= 256)
         hipLaunchKernelGGL(pencil_scalars_batched_kernel<4>, dim3(1, nunits), dim3(64), 0, st, units, m, s, is_ls,
                            branch_check);
@@ -1077,7 +1296,15 @@ hipError_t launch_pencil_scalars_batched(const SmallUnit* units, int nunits, int
 
 // slots: quadrature scratch slots (wavefronts) per unit; Ubuf holds slots x m x m per unit
 hipError_t launch_quad_group_batched(const SmallUnit* units, int nunits, const QuadGroup& g, int m, int is_ls,
-                                     int slots, hipStream_t st) {
+                                     int slots, int k, hipStream_t st) {
+    // one lane per node; U rows of the group's nodes: g.total (k + 3) m doubles of the
+    // unit's slots x m x m scratch
+    if (!is_ls && band_ok(k, m) && (int64_t)g.total * (k + 3) <= (int64_t)slots * m) {
+        const int blocks = (g.total + BAND_NT - 1) / BAND_NT;
+        BAND_DISPATCH(k + 1, hipLaunchKernelGGL(quad_level_band_batched_kernel<KB>, dim3(blocks, nunits),
+                                                dim3(BAND_NT), 0, st, units, g, m));
+        return hipGetLastError();
+    }
     const int waves = g.total < slots ? g.total : slots;
     const int blocks = (waves + 3) / 4;
     if (m <= 256)

@@ -74,6 +74,34 @@ CASES_C1 = [
 ]
 
 
+@pytest.mark.parametrize("k", [1, 3, 4, 6])
+def test_solve_parity_window_lengths(k):
+    """Square-case node solves: the band elimination (k <= 4) and the dense one
+    (beyond), each against the oracle on a 2D problem, m = 30."""
+    A, b, arrs = problem(40, c=60.0, seed=k)
+    m, s = 30, 120
+    x, info = gpu_solve(arrs, b, f="invsqrt", m=m, k=k, s=s, method="sfom", quad_tol=1e-13)
+    assert info.status == 0 and info.m_used == m
+    arn, _ = oracle_run(A, b, m, k, s)
+    e = rel(x, ometh.sfom_closed(arn, "invsqrt").x)
+    log(f"window k={k}: rel. err vs oracle {e:.2e}")
+    assert e < 1e-10
+
+
+def test_high_quadrature_orders_match():
+    """Orders 987 and 1395 from the start: groups of more than 1024 nodes (one lane per
+    node in the band elimination, each node's U rows in its own slots)."""
+    A, b, arrs = problem(40, c=60.0, seed=11)
+    m, k, s = 30, 2, 120
+    x_hi, info = gpu_solve(arrs, b, f="invsqrt", m=m, k=k, s=s, method="sfom", l1=987, l2=1395, lmax=1395)
+    assert info.status == 0 and info.l_used in (1395,)
+    x_lo, _ = gpu_solve(arrs, b, f="invsqrt", m=m, k=k, s=s, method="sfom")
+    arn, _ = oracle_run(A, b, m, k, s)
+    xr = ometh.sfom_closed(arn, "invsqrt").x
+    log(f"orders 987/1395: rel. err vs oracle {rel(x_hi, xr):.2e}, vs default orders {rel(x_hi, x_lo):.2e}")
+    assert rel(x_hi, xr) < 1e-10 and rel(x_hi, x_lo) < 1e-10
+
+
 @pytest.mark.parametrize("method,f", CASES_C1)
 def test_solve_parity_convdiff2d_n100(method, f):
     """2D convection-diffusion, 100x100 grid, m=50, k=2, s=200, zeta=8."""
