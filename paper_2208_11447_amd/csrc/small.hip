@@ -707,12 +707,13 @@ __device__ __forceinline__ void load_band(const double* __restrict__ Hh, int m, 
 
 // One node on the calling lane: y (stride 1) <- (a I + H_hat)^-1 rhs0 e_1.  Row kk
 // of U goes to Us[(kk (KB+2) + f) fstride], f = 0: pivot, 1..KB-1: entries right of
-// it, KB: last column, KB+1: transformed right-hand side.  *lad = sum log|pivot|,
-// *neg = parity of row swaps plus negative pivots (sign of the determinant).
-template <int KB>
-__device__ void band_node_solve(int mu, double a, double rhs0, const double* Bs, const double* Ls,
-                                double* __restrict__ Us, int64_t fstride, double* __restrict__ y, double* lad,
-                                int* neg) {
+// it, KB: last column, KB+1: transformed right-hand side.  With DET, *lad = sum
+// log|pivot| and *neg = parity of row swaps plus negative pivots (sign of the
+// determinant).
+template <int KB, bool DET>
+__device__ __forceinline__ void band_node_solve(int mu, double a, double rhs0, const double* Bs, const double* Ls,
+                                                double* __restrict__ Us, int64_t fstride, double* __restrict__ y,
+                                                double* lad, int* neg) {
     constexpr int F = KB + 2;
     double c[KB];  // carry row: columns kk .. kk+KB-1 (the last slot is zero on entry)
 #pragma unroll
@@ -744,8 +745,10 @@ __device__ void band_node_solve(int mu, double a, double rhs0, const double* Bs,
         for (int d = 0; d < KB; ++d) u[d * fstride] = c[d];
         u[KB * fstride] = cL;
         u[(KB + 1) * fstride] = cR;
-        ld += log(fabs(p));
-        if (p < 0.0) ng ^= 1;
+        if (DET) {
+            ld += log(fabs(p));
+            if (p < 0.0) ng ^= 1;
+        }
 #pragma unroll
         for (int d = 0; d + 1 < KB; ++d) c[d] = fma(-l, c[d + 1], n[d + 1]);
         c[KB - 1] = 0.0;
@@ -754,28 +757,46 @@ __device__ void band_node_solve(int mu, double a, double rhs0, const double* Bs,
     }
     // last pivot: column mu-1 lives in the last-column slot
     const double pl = cL;
-    ld += log(fabs(pl));
-    if (pl < 0.0) ng ^= 1;
+    if (DET) {
+        ld += log(fabs(pl));
+        if (pl < 0.0) ng ^= 1;
+    }
     const double ylast = cR * (1.0 / pl);
     y[mu - 1] = ylast;
     // back substitution, columns in descending order as in the dense elimination;
-    // yw[d] = y[kk+1+d] (zero beyond column mu-2: those band slots hold zeros)
+    // yw[d] = y[kk+1+d] (zero beyond column mu-2: those band slots hold zeros).  The
+    // next row's fields are requested before the current row is used.
     double yw[KB];
 #pragma unroll
     for (int d = 0; d < KB; ++d) yw[d] = 0.0;
-    for (int kk = mu - 2; kk >= 0; --kk) {
-        const double* u = Us + (int64_t)kk * F * fstride;
-        double sres = fma(-u[KB * fstride], ylast, u[(KB + 1) * fstride]);
+    double nu[F];
+    if (mu >= 2) {
+        const double* u = Us + (int64_t)(mu - 2) * F * fstride;
 #pragma unroll
-        for (int d = KB - 1; d >= 1; --d) sres = fma(-u[d * fstride], yw[d - 1], sres);
-        const double yk = sres * (1.0 / u[0]);
+        for (int f = 0; f < F; ++f) nu[f] = u[f * fstride];
+    }
+    for (int kk = mu - 2; kk >= 0; --kk) {
+        double cu[F];
+#pragma unroll
+        for (int f = 0; f < F; ++f) cu[f] = nu[f];
+        if (kk > 0) {
+            const double* u = Us + (int64_t)(kk - 1) * F * fstride;
+#pragma unroll
+            for (int f = 0; f < F; ++f) nu[f] = u[f * fstride];
+        }
+        double sres = fma(-cu[KB], ylast, cu[KB + 1]);
+#pragma unroll
+        for (int d = KB - 1; d >= 1; --d) sres = fma(-cu[d], yw[d - 1], sres);
+        const double yk = sres * (1.0 / cu[0]);
         y[kk] = yk;
 #pragma unroll
         for (int d = KB - 1; d >= 1; --d) yw[d] = yw[d - 1];
         yw[0] = yk;
     }
-    if (lad) *lad = ld;
-    if (neg) *neg = ng;
+    if (DET) {
+        *lad = ld;
+        *neg = ng;
+    }
 }
 
 // Nodes of a quadrature group, square case, one lane per node.  Ubuf holds the
@@ -801,8 +822,8 @@ __device__ __forceinline__ void quad_level_band_body(const DevCtrl* ctrl, const 
     const double x = cos((2.0 * ii + 1.0) * M_PI / (2.0 * l));
     const double t = (1.0 - x) / (1.0 + x);
     const double w = (2.0 / l) / (1.0 + x);
-    band_node_solve<KB>(mu, t * ctrl->sigma, eta[0] * w, Bs, Ls, Ubuf + i, grp.total, nodebuf + (int64_t)i * m,
-                        nullptr, nullptr);
+    band_node_solve<KB, false>(mu, t * ctrl->sigma, eta[0] * w, Bs, Ls, Ubuf + i, grp.total,
+                               nodebuf + (int64_t)i * m, nullptr, nullptr);
 }
 
 template <int KB>
@@ -828,9 +849,11 @@ __device__ __forceinline__ void pencil_scalars_band_body(int m, int s, const dou
                                                          double* y0, int branch_check) {
     __shared__ double Bs[MMAX * KB];
     __shared__ double Ls[MMAX];
+    __shared__ double Us[MMAX * (KB + 2)];  // U rows of the one node (fstride 1)
     const int mu = ctrl->m_used;
     if (mu == 0) return;
     const int lane = threadIdx.x;
+    (void)Ubuf;
     double rmin = 1e308, rmax = 0.0;
     for (int j = lane; j < mu; j += WAVE) {
         const double dg = fabs(X[j + (int64_t)s * j]);
@@ -845,7 +868,7 @@ __device__ __forceinline__ void pencil_scalars_band_body(int m, int s, const dou
         const double beta = eta[0];
         double ld = 0.0;
         int ng = 0;
-        band_node_solve<KB>(mu, 0.0, beta, Bs, Ls, Ubuf, 1, y0, &ld, &ng);
+        band_node_solve<KB, true>(mu, 0.0, beta, Bs, Ls, Us, 1, y0, &ld, &ng);
         ctrl->beta = beta;
         ctrl->rcond = (rmax > 0.0) ? rmin / rmax : 0.0;
         if (!(rmin > 2.220446049250313e-16 * rmax)) ctrl->status = 3;  // SKFAB_ERR_RANK
