@@ -192,7 +192,10 @@ skfab_status skfab_arnoldi(skfab_ctx *ctx, const skfab_csr *A, const double *b,
  *   SVext  device, s x (m+1) (ld = s): columns 0..m-1 are S v_1..S v_m (unit basis
  *          vectors), column m is S u_{m+1} = h_{m+1,m} S v_{m+1} (unnormalised)
  *   Hbar   device, (m+1) x m (ld = m+1): the Arnoldi coefficients h_ij of
- *          A v_j = sum_i h_ij v_i + u_{j+1}; row m is ignored (taken as e_m^T)
+ *          A v_j = sum_i h_ij v_i + u_{j+1}; row m is ignored (taken as e_m^T).
+ *          Its band must match p->k (h_ij = 0 unless j-k+1 <= i <= j+1), as the
+ *          k-truncated recurrence produces it: the pencil and, for k <= 4, the
+ *          square-case node solves (band elimination) use only those entries.
  *   beta   ||b|| (host)
  *   y      device, m: coefficients of the approximant V_m y (Sections 2.1, 3, 4.1)
  * Uses the same device algorithm as skfab_solve after the basis is built. */

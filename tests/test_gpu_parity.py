@@ -206,3 +206,32 @@ def test_seed_matters_and_zeta():
         x, info = gpu_solve(arrs, b, m=20, k=2, s=80, zeta=zeta, seed=seed)
         arn, _ = oracle_run(A, b, 20, 2, 80, zeta=zeta, seed=seed)
         assert rel(x, ometh.sfom_closed(arn, "invsqrt").x) < FP64_TOL
+
+
+def test_timing_stride_counts_launches():
+    """skfab_timing_enable(n): every n-th step launch is timed (counts add up over
+    solves), n = 1 times them all, a negative n is refused; timing leaves x unchanged."""
+    A, b, arrs = problem(30)
+    m = 20
+    Ad = device_csr(arrs)
+    p = sk.make_params(m=m, k=2, s=80)
+    ws = sk.alloc_workspace(sk.skfab_workspace_bytes(Ad, p))
+    bd = dev(b)
+    x0 = torch.empty_like(bd)
+    x1 = torch.empty_like(bd)
+    c = ctx()
+    sk.skfab_solve(c, Ad, bd, x0, p, ws, want_info=False)
+    for stride, solves in ((1, 2), (3, 3)):
+        sk.skfab_timing_enable(c, True, stride=stride)
+        sk.skfab_timing_read(c, 0)
+        for _ in range(solves):
+            sk.skfab_solve(c, Ad, bd, x1, p, ws, want_info=False)
+        ms, n = sk.skfab_timing_read(c, 0)
+        sk.skfab_timing_enable(c, False)
+        launches = solves * m  # step launches j = 0 .. m-1 are timed (the extension pass is not)
+        assert n == (launches + stride - 1) // stride, (stride, n)
+        assert ms > 0.0
+    torch.cuda.synchronize()
+    assert torch.equal(x0, x1)
+    with pytest.raises(RuntimeError):
+        sk.skfab_timing_enable(c, True, stride=-2)
