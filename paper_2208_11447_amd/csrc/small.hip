@@ -75,7 +75,6 @@ __device__ __forceinline__ void qr_panel_body(double* X, int s, int c0, const De
     __shared__ double vbuf[2][WAVE * RPW];
     __shared__ double tau[QR_NB];
     __shared__ double G[QR_NB][QR_NB];
-    __shared__ double Ts[QR_NB][QR_NB];
     const int ncols = ctrl->m_used + 1;
     if (ctrl->m_used == 0 || c0 >= ncols) return;
     const int pc = min(QR_NB, ncols - c0);
@@ -89,10 +88,7 @@ __device__ __forceinline__ void qr_panel_body(double* X, int s, int c0, const De
             const int c = wid * QR_CPW + q, r = lane + WAVE * i;
             a[q][i] = (c < pc && r < nrows) ? X[(int64_t)(c0 + r) + (int64_t)s * (c0 + c)] : 0.0;
         }
-    if (tid < QR_NB * QR_NB) {
-        G[tid / QR_NB][tid % QR_NB] = 0.0;
-        Ts[tid / QR_NB][tid % QR_NB] = 0.0;
-    }
+    if (tid < QR_NB * QR_NB) G[tid / QR_NB][tid % QR_NB] = 0.0;
     for (int cc = 0; cc < pc; ++cc) {
         double* vb = vbuf[cc & 1];
         // the wave holding column cc (all earlier reflectors applied) forms v_cc
@@ -156,18 +152,28 @@ __device__ __forceinline__ void qr_panel_body(double* X, int s, int c0, const De
         }
     }
     __syncthreads();
-    // compact-WY factor, column by column: T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]
-    for (int i = 0; i < pc; ++i) {
-        if (tid < i) {
-            double t = 0.0;
-            for (int q = tid; q < i; ++q) t += Ts[tid][q] * G[q][i];
-            Ts[tid][i] = -tau[i] * t;
-        } else if (tid == i) {
-            Ts[i][i] = tau[i];
+    // compact-WY factor T[0:i, i] = -tau_i T[0:i, 0:i] G[0:i, i]: row l of T needs only
+    // its own earlier entries, so lane l builds row l alone (no barrier)
+    if (tid < QR_NB) {
+        const int l = tid;
+        double trow[QR_NB];
+#pragma unroll
+        for (int i = 0; i < QR_NB; ++i) {
+            double v = 0.0;
+            if (i < pc && i == l) {
+                v = tau[i];
+            } else if (i < pc && i > l) {
+                double t = 0.0;
+#pragma unroll
+                for (int q = 0; q < QR_NB; ++q)
+                    if (q >= l && q < i) t += trow[q] * G[q][i];
+                v = -tau[i] * t;
+            }
+            trow[i] = v;
         }
-        __syncthreads();
+#pragma unroll
+        for (int i = 0; i < QR_NB; ++i) Tws[l * QR_NB + i] = trow[i];
     }
-    if (tid < QR_NB * QR_NB) Tws[tid] = Ts[tid / QR_NB][tid % QR_NB];
 #pragma unroll
     for (int q = 0; q < QR_CPW; ++q)
 #pragma unroll
