@@ -51,9 +51,9 @@ __device__ __forceinline__ double window_value(const StepArgs& a, int p, int t) 
     const bool okw = t == 0 && p >= 1;
     const bool oke = t > 0 && t < KW && p - t >= 0;
     const bool okg = t >= KW && t < KW * KW && o2 > o && p - o2 >= 0;
-    const double vw = a.wnorm[okw ? p - 1 : 0];
-    const double ve = a.eta[oke ? p - t : 0];
-    const double vg = a.gram[okg ? (int64_t)(p - o) * KMAX + (o2 - o - 1) : 0];
+    const double vw = gptr(a.wnorm)[okw ? p - 1 : 0];
+    const double ve = gptr(a.eta)[oke ? p - t : 0];
+    const double vg = gptr(a.gram)[okg ? (int64_t)(p - o) * KMAX + (o2 - o - 1) : 0];
     return okw ? vw : (oke ? ve : (okg ? vg : 0.0));
 }
 
@@ -179,13 +179,13 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     __shared__ int s_ok;
     __shared__ int s_prog;  // slices finished by the block's wavefronts (main loop)
 
-    const int sell_flag = a.sctrl->sell_ok;  // issued with the control-block loads
-    const int col16 = a.sctrl->col16;
+    const int sell_flag = gptr(a.sctrl)->sell_ok;  // issued with the control-block loads
+    const int col16 = gptr(a.sctrl)->col16;
     // A breakdown detected by an earlier step ends the recurrence (the step that
     // detects it still runs its prologue to write the extension column).  The test
     // is made only after every load of the prologue has been issued, so that the
     // control block's latency overlaps theirs.
-    const int stop_flag = a.ctrl->stop, stop_m = a.ctrl->m_used;
+    const int stop_flag = gptr(a.ctrl)->stop, stop_m = gptr(a.ctrl)->m_used;
     const bool stopped = stop_flag && stop_m < a.j - 1;
     constexpr int NSC = 2 * KW + 1;
     constexpr int NW = BLOCK / WAVE;
@@ -205,8 +205,10 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     const int64_t itl0 = sl0 + (int64_t)lane * NW;
     const bool win_in = !a.extend && itl0 < sl1;
     const int64_t itl0c = win_in ? itl0 : 0;
-    const int wlen = a.sl_len[itl0c];
-    const int64_t wptr = a.sl_ptr[itl0c];
+    const GAS int32_t* __restrict__ sl_len = gptr(a.sl_len);
+    const GAS int64_t* __restrict__ sl_ptr = gptr(a.sl_ptr);
+    const int wlen = sl_len[itl0c];
+    const int64_t wptr = sl_ptr[itl0c];
 
     if (j > 0) {
         // issue every load of the prologue before any reduction: the partial scalars
@@ -224,7 +226,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             for (int q = 0; q < GPT; ++q) {
                 const int g = tid + q * BLOCK, gc = (g < G) ? g : 0;
 #pragma unroll
-                for (int sc = 0; sc < NSC; ++sc) ld[sc][q] = a.scal_prev[(int64_t)sc * G + gc];
+                for (int sc = 0; sc < NSC; ++sc) ld[sc][q] = gptr(a.scal_prev)[(int64_t)sc * G + gc];
             }
 #pragma unroll
             for (int sc = 0; sc < NSC; ++sc) {
@@ -244,7 +246,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         int mybin = -1;
         if (b0 + wid < b1) {
             mybin = b0 + wid;
-            const double* src = a.skp_prev + (int64_t)mybin * G;
+            const GAS double* src = gptr(a.skp_prev) + (int64_t)mybin * G;
             double ld[GPL];
 #pragma unroll
             for (int q = 0; q < GPL; ++q) {
@@ -276,8 +278,8 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         const double eta_p = coef[KMAX + 1];
         const bool ok = s_ok != 0;
         if (mybin >= 0 && lane == 0) {
-            if (mybin < s) a.SV[(int64_t)(j - 1) * a.ldS + mybin] = skv * (ok ? a.inv_sqrt_zeta / eta_p : a.inv_sqrt_zeta);
-            else if (ok) a.SAV[(int64_t)(j - 1) * a.ldS + (mybin - s)] = skv * (a.inv_sqrt_zeta / eta_p);
+            if (mybin < s) gptr(a.SV)[(int64_t)(j - 1) * a.ldS + mybin] = skv * (ok ? a.inv_sqrt_zeta / eta_p : a.inv_sqrt_zeta);
+            else if (ok) gptr(a.SAV)[(int64_t)(j - 1) * a.ldS + (mybin - s)] = skv * (a.inv_sqrt_zeta / eta_p);
         }
         // bins beyond one per wave (only when 2s > 16 G): fall back to the generic loop
         if (b1 - b0 > NW)
@@ -304,15 +306,20 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
 #pragma unroll
     for (int o = 0; o < KW; ++o) cf[o] = coef[1 + o];
 
-    const WT* __restrict__ Wp = static_cast<const WT*>(a.Wprev);
-    const double* __restrict__ b0p = a.b;
+    const GAS WT* __restrict__ Wp = gptr(static_cast<const WT*>(a.Wprev));
+    const GAS double* __restrict__ b0p = gptr(a.b);
     const bool first_all = (j == 0);
-    const VT* Uo[KW];
+    const GAS VT* Uo[KW];
 #pragma unroll
-    for (int o = 0; o < KW; ++o) Uo[o] = static_cast<const VT*>(a.U) + (int64_t)((o < nwin_all) ? (j - 1 - o) : 0) * a.ldU;
-    VT* __restrict__ Uj = static_cast<VT*>(a.U) + (int64_t)(a.extend ? 0 : j) * a.ldU;
-    WT* __restrict__ Wc = static_cast<WT*>(a.Wcur);
-    const AT* __restrict__ slv = static_cast<const AT*>(a.sl_val);
+    for (int o = 0; o < KW; ++o) Uo[o] = gptr(static_cast<const VT*>(a.U)) + (int64_t)((o < nwin_all) ? (j - 1 - o) : 0) * a.ldU;
+    GAS VT* __restrict__ Uj = gptr(static_cast<VT*>(a.U)) + (int64_t)(a.extend ? 0 : j) * a.ldU;
+    GAS WT* __restrict__ Wc = gptr(static_cast<WT*>(a.Wcur));
+    const GAS AT* __restrict__ slv = gptr(static_cast<const AT*>(a.sl_val));
+    const GAS int32_t* __restrict__ sl_col = gptr(a.sl_col);
+    const GAS int16_t* __restrict__ slo = gptr(reinterpret_cast<const int16_t*>(a.sl_col));
+    const GAS int32_t* __restrict__ rowptr = gptr(a.rowptr);
+    const GAS int32_t* __restrict__ colp = gptr(a.col);
+    const GAS double* __restrict__ valp = gptr(a.val);
     const WT alpha_w = (WT)alpha;
     WT cf_w[KW];
 #pragma unroll
@@ -364,8 +371,8 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             if (iter - wbase == WAVE) {  // next window of 64 slices
                 wbase += WAVE;
                 const int64_t itl = it + (int64_t)lane * step;
-                const int nl = (itl < it1) ? a.sl_len[itl] : 0;
-                const int np = (itl < it1) ? (int)(a.sl_ptr[itl] >> 6) : 0;
+                const int nl = (itl < it1) ? sl_len[itl] : 0;
+                const int np = (itl < it1) ? (int)(sl_ptr[itl] >> 6) : 0;
                 meta[wid][lane] = make_int2(nl, np);
             }
             const int2 md = meta[wid][iter - wbase];
@@ -383,7 +390,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             if constexpr (KW <= 4) {
 #pragma unroll
                 for (int o = 0; o < KW; ++o)
-                    if (o < nwin) urow[o] = Uo[o][r];
+                    if (o < nwin) urow[o] = gload(Uo[o] + r);
             }
         }
         WT w = (WT)0;
@@ -392,7 +399,6 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                 // entries in batches of SB: all index and value loads of a batch, then all
                 // gathers, then the products -- one memory round trip per batch
                 const int32_t rr = valid ? (int32_t)r : 0;  // offsets of rows beyond N are 0
-                const int16_t* __restrict__ slo = reinterpret_cast<const int16_t*>(a.sl_col);
                 for (int q0 = 0; q0 < len; q0 += SB) {
                     int cc[SB];
                     WT vv[SB], xb[SB], xu[SB][KW];
@@ -411,7 +417,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
 #pragma unroll
                         for (int q = 0; q < SB; ++q) {
                             const bool in = q0 + q < len;
-                            cc[q] = in ? a.sl_col[e0 + (int64_t)(q0 + q) * WAVE] : 0;
+                            cc[q] = in ? sl_col[e0 + (int64_t)(q0 + q) * WAVE] : 0;
                             vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
                         }
                     }
@@ -419,7 +425,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                     for (int q = 0; q < SB; ++q) {
                         xb[q] = first ? (WT)b0p[cc[q]] : Wp[cc[q]];
 #pragma unroll
-                        for (int o = 0; o < KW; ++o) xu[q][o] = (o < nwin) ? to_w<WT>(Uo[o][cc[q]]) : (WT)0;
+                        for (int o = 0; o < KW; ++o) xu[q][o] = (o < nwin) ? to_w<WT>(gload(Uo[o] + cc[q])) : (WT)0;
                     }
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
@@ -432,15 +438,15 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                     }
                 }
             } else if (valid) {
-                const int e0 = a.rowptr[r], e1 = a.rowptr[r + 1];
+                const int e0 = rowptr[r], e1 = rowptr[r + 1];
                 for (int e = e0; e < e1; ++e) {
-                    const int c = a.col[e];
+                    const int c = colp[e];
                     WT x = alpha_w * (first ? (WT)b0p[c] : Wp[c]);
 #pragma unroll
                     for (int o = 0; o < KW; ++o)
-                        if (o < nwin) x = fma(cf_w[o], to_w<WT>(Uo[o][c]), x);
+                        if (o < nwin) x = fma(cf_w[o], to_w<WT>(gload(Uo[o] + c)), x);
                     x = to_w<WT>(Store<VT>::put(x));
-                    w = fma((WT)a.val[e], x, w);
+                    w = fma((WT)valp[e], x, w);
                 }
             }
         }
@@ -449,7 +455,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             if (valid) {
 #pragma unroll
                 for (int o = 0; o < KW; ++o)
-                    if (o < nwin) urow[o] = Uo[o][r];
+                    if (o < nwin) urow[o] = gload(Uo[o] + r);
             }
         }
         WT uo[KW];
@@ -509,7 +515,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     for (int i = tid; i < 2 * s; i += BLOCK) {
         double t = 0.0;
         for (int wv = 0; wv < NW; ++wv) t += bins[wv * 2 * s + i];
-        a.skp_cur[(int64_t)i * G + chunk] = t;
+        gptr(a.skp_cur)[(int64_t)i * G + chunk] = t;
     }
     // partial scalars of this block, reduced through the (now free) bin region
     double vals[NSC];
@@ -518,7 +524,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     for (int o = 0; o < KW - 1; ++o) { vals[3 + o] = acc_lw[o]; vals[3 + (KW - 1) + o] = acc_ul[o]; }
     __syncthreads();
     block_reduce_multi<NSC, BLOCK>(vals, bins, red);
-    if (tid < NSC) a.scal_cur[(int64_t)tid * G + bid] = red[tid];
+    if (tid < NSC) gptr(a.scal_cur)[(int64_t)tid * G + bid] = red[tid];
 }
 
 template <int KW, int ZETA, int BLOCK, typename P>

@@ -40,6 +40,18 @@ template <typename W> __device__ __forceinline__ W to_w(bf16s x) { return (W)bf1
 template <typename T> __device__ __forceinline__ void store_nt(T v, T* p) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void store_nt(bf16s v, bf16s* p) { __builtin_nontemporal_store(v.bits, &p->bits); }
 
+// Device memory seen through the global address space.  A pointer read from memory
+// (rather than passed as a kernel argument) is generic to the compiler, which then
+// reaches it with flat instructions; these also count against the LDS wait counter,
+// so that every LDS access waits for all loads in flight.  Typed this way, the
+// accesses compile to global instructions.
+#define GAS __attribute__((address_space(1)))
+template <typename T> __device__ __forceinline__ GAS T* gptr(T* p) { return (GAS T*)p; }
+template <typename T> __device__ __forceinline__ T gload(const GAS T* p) { return *p; }
+__device__ __forceinline__ bf16s gload(const GAS bf16s* p) { return bf16s{p->bits}; }
+template <typename T> __device__ __forceinline__ void store_nt(T v, GAS T* p) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void store_nt(bf16s v, GAS bf16s* p) { __builtin_nontemporal_store(v.bits, &p->bits); }
+
 template <typename V> struct Store;
 template <> struct Store<double> {
     __device__ static double put(double x) { return x; }
