@@ -360,61 +360,102 @@ __device__ __forceinline__ void dist_set(double (&v)[QM], int i, double x) {
 // H_hat = H_mu + x e_mu^T with x = R^-1 r, r = R_e[:mu, mu] (the extension column
 // of the QR'd sketch): the projected matrix of the sketched FOM in the basis V_m
 // (remark of Section 2.2).  Written row-major into Hh (ld m) for the square node
-// systems (t I + H_hat) y = beta e_1.  256 threads.  x by blocked back
-// substitution: for each 64-column block from the right, its diagonal block is
-// staged in LDS and solved by wavefront 0 (one lane per row), then all threads
-// update the rows above with the block's columns.
-constexpr int HH_NT = 256;
+// systems (t I + H_hat) y = beta e_1.  Block 0 (1024 threads) computes x by
+// blocked back substitution: for each 64-column block from the right, its
+// diagonal block is solved from LDS by wavefront 0 (one lane per row) while the
+// other wavefronts already hold the block's columns of the rows above (one
+// wavefront per row: a coalesced read and a wavefront sum) and the next diagonal
+// block; every read of T1 is thus in flight during a solve.  Blocks 1..HH_CB copy
+// H's first mu - 1 columns into Hh meanwhile (one column per wavefront).
+constexpr int HH_NT = 1024;
 constexpr int HH_B = 64;
+constexpr int HH_CB = 15;
 
 template <int QM>
-__device__ __forceinline__ void hhat_rows_body(const DevCtrl* ctrl, int m, int s, const double* X,
-                                              const double* T1r, const double* H, double* Hh) {
+__device__ __forceinline__ void hhat_rows_body(int blk, const DevCtrl* ctrl, int m, int s,
+                                              const double* __restrict__ X, const double* __restrict__ T1r,
+                                              const double* __restrict__ H, double* __restrict__ Hh) {
     __shared__ double xs[MMAX];
     __shared__ double D[HH_B][HH_B + 1];
-    __shared__ double dinv[HH_B];
-    (void)QM;
     const int mu = ctrl->m_used;
     if (mu == 0) return;
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+    constexpr int NWV = HH_NT / WAVE;
     const int64_t ldh = m + 1;
-    for (int i = tid; i < mu; i += HH_NT) xs[i] = X[i + (int64_t)s * mu];
-    // H's first mu - 1 columns (independent of x)
-    const int n = mu * (mu - 1);
-    for (int idx = tid; idx < n; idx += HH_NT) {
-        const int i = idx / (mu - 1), j = idx - i * (mu - 1);
-        Hh[(int64_t)i * m + j] = H[i + ldh * j];
+    if (blk > 0) {
+        // column j of H into column j of the row-major Hh (QM * 64 >= m rows: every
+        // read is issued before the first store)
+        for (int j = (blk - 1) * NWV + wid; j < mu - 1; j += HH_CB * NWV) {
+            double v[QM];
+#pragma unroll
+            for (int q = 0; q < QM; ++q) v[q] = H[min(lane + WAVE * q, mu - 1) + ldh * j];
+#pragma unroll
+            for (int q = 0; q < QM; ++q) {
+                const int i = lane + WAVE * q;
+                if (i < mu) Hh[(int64_t)i * m + j] = v[q];
+            }
+        }
+        return;
     }
-    for (int kb = ((mu - 1) / HH_B) * HH_B; kb >= 0; kb -= HH_B) {
+    // rows above a diagonal block held by one wavefront: w, w + NWV, ... (< QM * 64 - 64)
+    constexpr int UR = (QM * WAVE - HH_B) / NWV;
+    constexpr int DPT = HH_B * HH_B / HH_NT;  // entries of a diagonal block per thread
+    for (int i = tid; i < mu; i += HH_NT) xs[i] = X[i + (int64_t)s * mu];
+    int kb = ((mu - 1) / HH_B) * HH_B;
+    {
+        const int nb = mu - kb;
+#pragma unroll
+        for (int u = 0; u < DPT; ++u) {
+            const int idx = tid + HH_NT * u, a = idx / HH_B, b = idx % HH_B;
+            if (a < nb && b < nb) D[a][b] = (b >= a) ? T1r[(int64_t)(kb + a) * m + (kb + b)] : 0.0;
+        }
+    }
+    for (; kb >= 0; kb -= HH_B) {
         const int nb = min(HH_B, mu - kb);
-        __syncthreads();  // xs of the previous update / initial load complete
-        for (int idx = tid; idx < nb * nb; idx += HH_NT) {
-            const int a = idx / nb, b = idx - a * nb;
-            D[a][b] = (b >= a) ? T1r[(int64_t)(kb + a) * m + (kb + b)] : 0.0;
+        const int rlast = max(kb - 1, 0);
+        double pr[UR];
+#pragma unroll
+        for (int t = 0; t < UR; ++t)
+            pr[t] = T1r[(int64_t)min(wid + NWV * t, rlast) * m + kb + min(lane, nb - 1)];
+        const int kn = kb - HH_B;  // next block (full width)
+        double dn[DPT];
+#pragma unroll
+        for (int u = 0; u < DPT; ++u) {
+            const int idx = tid + HH_NT * u, a = idx / HH_B, b = idx % HH_B;
+            const int rn = min(max(kn, 0) + a, mu - 1), cn = min(max(kn, 0) + b, mu - 1);
+            dn[u] = (kn >= 0 && b >= a) ? T1r[(int64_t)rn * m + cn] : 0.0;
         }
-        if (tid < nb) dinv[tid] = 1.0 / T1r[(int64_t)(kb + tid) * m + (kb + tid)];
-        __syncthreads();
+        __syncthreads();  // D and the previous update of xs complete
         if (wid == 0) {
-            double r = (lane < nb) ? xs[kb + lane] : 0.0;
+            const bool in = lane < nb;
+            double r = in ? xs[kb + lane] : 0.0;
+            const double di = in ? 1.0 / D[lane][lane] : 0.0;
+            double dc = D[lane][nb - 1];
             for (int a = nb - 1; a >= 0; --a) {
-                const double xa = bcast_lane(r, a) * dinv[a];
-                if (lane < a) r = fma(-D[lane][a], xa, r);
-                else if (lane == a) r = xa;
+                const double dnx = D[lane][a > 0 ? a - 1 : 0];  // next column, read off the chain
+                const double xa = bcast_lane(r * di, a);
+                r = (lane < a) ? fma(-dc, xa, r) : ((lane == a) ? xa : r);
+                dc = dnx;
             }
-            if (lane < nb) xs[kb + lane] = r;
+            if (in) xs[kb + lane] = r;
         }
-        __syncthreads();
-        // rows above the block: xs[i] -= R[i, kb:kb+nb] x[kb:kb+nb]
-        for (int i = tid; i < kb; i += HH_NT) {
-            const double* row = T1r + (int64_t)i * m + kb;
-            double a0 = 0.0, a1 = 0.0;
-            int b = 0;
-            for (; b + 1 < nb; b += 2) {
-                a0 = fma(row[b], xs[kb + b], a0);
-                a1 = fma(row[b + 1], xs[kb + b + 1], a1);
+        __syncthreads();  // x of the block complete; D free
+        if (kn >= 0) {
+#pragma unroll
+            for (int u = 0; u < DPT; ++u) {
+                const int idx = tid + HH_NT * u;
+                D[idx / HH_B][idx % HH_B] = dn[u];
             }
-            if (b < nb) a0 = fma(row[b], xs[kb + b], a0);
-            xs[i] -= a0 + a1;
+        }
+        // rows above the block: xs[i] -= R[i, kb:kb+nb] x[kb:kb+nb]
+        const double xb = (lane < nb) ? xs[kb + lane] : 0.0;
+#pragma unroll
+        for (int t = 0; t < UR; ++t) {
+            const int i = wid + NWV * t;
+            if (i < kb) {
+                const double v = wave_sum((lane < nb) ? pr[t] * xb : 0.0);
+                if (lane == 0) xs[i] -= v;
+            }
         }
     }
     __syncthreads();
@@ -424,13 +465,13 @@ __device__ __forceinline__ void hhat_rows_body(const DevCtrl* ctrl, int m, int s
 template <int QM>
 __global__ __launch_bounds__(HH_NT) void hhat_rows_kernel(const DevCtrl* ctrl, int m, int s, const double* X,
                                                          const double* T1r, const double* H, double* Hh) {
-    hhat_rows_body<QM>(ctrl, m, s, X, T1r, H, Hh);
+    hhat_rows_body<QM>(blockIdx.x, ctrl, m, s, X, T1r, H, Hh);
 }
 
 template <int QM>
 __global__ __launch_bounds__(HH_NT) void hhat_rows_batched_kernel(const SmallUnit* __restrict__ units, int m, int s) {
     const SmallUnit& u = units[blockIdx.y];
-    hhat_rows_body<QM>(u.ctrl, m, s, u.SV, u.T1r, u.H, u.Hh);
+    hhat_rows_body<QM>(blockIdx.x, u.ctrl, m, s, u.SV, u.T1r, u.H, u.Hh);
 }
 
 // Solves with P(a) = a T1 + K0 (upper Hessenberg), right-hand side rhs0 e_1.
@@ -1166,9 +1207,9 @@ hipError_t launch_pencil_setup(const double* X, int s, int m, int k, const DevCt
 hipError_t launch_hhat_rows(const DevCtrl* ctrl, int m, int s, const double* X, const double* T1r, const double* H,
                             double* Hh, hipStream_t st) {
     if (m <= 256)
-        hipLaunchKernelGGL(hhat_rows_kernel<4>, dim3(1), dim3(HH_NT), 0, st, ctrl, m, s, X, T1r, H, Hh);
+        hipLaunchKernelGGL(hhat_rows_kernel<4>, dim3(1 + HH_CB), dim3(HH_NT), 0, st, ctrl, m, s, X, T1r, H, Hh);
     else
-        hipLaunchKernelGGL(hhat_rows_kernel<8>, dim3(1), dim3(HH_NT), 0, st, ctrl, m, s, X, T1r, H, Hh);
+        hipLaunchKernelGGL(hhat_rows_kernel<8>, dim3(1 + HH_CB), dim3(HH_NT), 0, st, ctrl, m, s, X, T1r, H, Hh);
     return hipGetLastError();
 }
 
@@ -1300,9 +1341,9 @@ hipError_t launch_pencil_setup_batched(const SmallUnit* units, int nunits, int s
 
 hipError_t launch_hhat_rows_batched(const SmallUnit* units, int nunits, int m, int s, hipStream_t st) {
     if (m <= 256)
-        hipLaunchKernelGGL(hhat_rows_batched_kernel<4>, dim3(1, nunits), dim3(HH_NT), 0, st, units, m, s);
+        hipLaunchKernelGGL(hhat_rows_batched_kernel<4>, dim3(1 + HH_CB, nunits), dim3(HH_NT), 0, st, units, m, s);
     else
-        hipLaunchKernelGGL(hhat_rows_batched_kernel<8>, dim3(1, nunits), dim3(HH_NT), 0, st, units, m, s);
+        hipLaunchKernelGGL(hhat_rows_batched_kernel<8>, dim3(1 + HH_CB, nunits), dim3(HH_NT), 0, st, units, m, s);
     return hipGetLastError();
 }
 

@@ -102,6 +102,27 @@ def test_high_quadrature_orders_match():
     assert rel(x_hi, xr) < 1e-10 and rel(x_hi, x_lo) < 1e-10
 
 
+@pytest.mark.parametrize("method", ["sfom", "sfom_quad", "sgmres"])
+def test_solve_parity_m300(method):
+    """Krylov dimension above 256: the small-problem kernels in their wider
+    register form (up to 512 rows: QR panels, H_hat rows, node solves, pencil),
+    2D 200x200 grid, convection 200, m=300, k=2, s=600, f = z^(-1/2).  (The
+    sketched basis stays well conditioned here, cond(R) ~ 10; on a 100x100 grid
+    with convection 60 the truncated basis is numerically dependent at m=300,
+    cond(R) ~ 1e16, and H_hat built from R then has a real eigenvalue on the
+    negative axis: the branch status is the right answer there.)"""
+    A, b, arrs = problem(200, c=200.0, seed=7)
+    m, k, s = 300, 2, 600
+    x, info = gpu_solve(arrs, b, f="invsqrt", m=m, k=k, s=s, method=method, quad_tol=1e-13)
+    assert info.status == 0 and info.m_used == m
+    arn, _ = oracle_run(A, b, m, k, s)
+    ref = {"sfom": ometh.sfom_closed, "sgmres": ometh.sgmres, "sfom_quad": ometh.sfom_quad}[method]
+    xr = (ref(arn, "invsqrt") if method == "sfom" else ref(arn, "invsqrt", tol=1e-13)).x
+    err = rel(x, xr)
+    log(f"m=300 {method}: rel err vs oracle {err:.3e}  l_used={info.l_used} rcond={info.rcond_R:.3e}")
+    assert err < FP64_TOL
+
+
 @pytest.mark.parametrize("method,f", CASES_C1)
 def test_solve_parity_convdiff2d_n100(method, f):
     """2D convection-diffusion, 100x100 grid, m=50, k=2, s=200, zeta=8."""
