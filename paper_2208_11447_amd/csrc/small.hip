@@ -753,14 +753,16 @@ __device__ __forceinline__ void load_band(const double* __restrict__ Hh, int m, 
 }
 
 // One node on the calling lane: y (stride 1) <- (a I + H_hat)^-1 rhs0 e_1.  Row kk
-// of U goes to Us[(kk (KB+2) + f) fstride], f = 0: pivot, 1..KB-1: entries right of
-// it, KB: last column, KB+1: transformed right-hand side.  With DET, *lad = sum
-// log|pivot| and *neg = parity of row swaps plus negative pivots (sign of the
-// determinant).
+// of U goes to Us[(kk (KB+2) + f) fstride], f = 0: reciprocal of the pivot (one
+// division per row: the multiplier and the back substitution both use it),
+// 1..KB-1: entries right of the pivot, KB: last column, KB+1: transformed
+// right-hand side.  With DET, the last pivot's reciprocal goes to field 0 of row
+// mu-1 (so that field 0 of row kk holds 1 / pivot_kk for every kk < mu) and *neg =
+// parity of row swaps plus negative pivots (sign of the determinant).
 template <int KB, bool DET>
 __device__ __forceinline__ void band_node_solve(int mu, double a, double rhs0, const double* Bs, const double* Ls,
                                                 double* __restrict__ Us, int64_t fstride, double* __restrict__ y,
-                                                double* lad, int* neg) {
+                                                int* neg) {
     constexpr int F = KB + 2;
     double c[KB];  // carry row: columns kk .. kk+KB-1 (the last slot is zero on entry)
 #pragma unroll
@@ -770,7 +772,6 @@ __device__ __forceinline__ void band_node_solve(int mu, double a, double rhs0, c
     if (mu > 1) c[0] += a;
     else cL += a;
     int ng = 0;
-    double ld = 0.0;
     for (int kk = 0; kk + 1 < mu; ++kk) {
         double n[KB];
 #pragma unroll
@@ -786,16 +787,15 @@ __device__ __forceinline__ void band_node_solve(int mu, double a, double rhs0, c
             ng ^= 1;
         }
         const double p = c[0];
-        const double l = (p != 0.0) ? n[0] / p : 0.0;
+        const double rp = 1.0 / p;
+        const double l = (p != 0.0) ? n[0] * rp : 0.0;
         double* u = Us + (int64_t)kk * F * fstride;
+        u[0] = rp;
 #pragma unroll
-        for (int d = 0; d < KB; ++d) u[d * fstride] = c[d];
+        for (int d = 1; d < KB; ++d) u[d * fstride] = c[d];
         u[KB * fstride] = cL;
         u[(KB + 1) * fstride] = cR;
-        if (DET) {
-            ld += log(fabs(p));
-            if (p < 0.0) ng ^= 1;
-        }
+        if (DET && p < 0.0) ng ^= 1;
 #pragma unroll
         for (int d = 0; d + 1 < KB; ++d) c[d] = fma(-l, c[d + 1], n[d + 1]);
         c[KB - 1] = 0.0;
@@ -804,46 +804,51 @@ __device__ __forceinline__ void band_node_solve(int mu, double a, double rhs0, c
     }
     // last pivot: column mu-1 lives in the last-column slot
     const double pl = cL;
+    const double rpl = 1.0 / pl;
     if (DET) {
-        ld += log(fabs(pl));
         if (pl < 0.0) ng ^= 1;
+        Us[(int64_t)(mu - 1) * F * fstride] = rpl;
     }
-    const double ylast = cR * (1.0 / pl);
+    const double ylast = cR * rpl;
     y[mu - 1] = ylast;
     // back substitution, columns in descending order as in the dense elimination;
     // yw[d] = y[kk+1+d] (zero beyond column mu-2: those band slots hold zeros).  The
-    // next row's fields are requested before the current row is used.
+    // fields of the next BPD rows are in flight while a row is used (clamped row
+    // indices: unconditional loads, re-reading row 0 at the end).
+    constexpr int BPD = 4;
     double yw[KB];
 #pragma unroll
     for (int d = 0; d < KB; ++d) yw[d] = 0.0;
-    double nu[F];
-    if (mu >= 2) {
-        const double* u = Us + (int64_t)(mu - 2) * F * fstride;
+    double nu[BPD][F];
 #pragma unroll
-        for (int f = 0; f < F; ++f) nu[f] = u[f * fstride];
+    for (int q = 0; q < BPD; ++q) {
+        const double* u = Us + (int64_t)max(mu - 2 - q, 0) * F * fstride;
+#pragma unroll
+        for (int f = 0; f < F; ++f) nu[q][f] = u[f * fstride];
     }
     for (int kk = mu - 2; kk >= 0; --kk) {
         double cu[F];
 #pragma unroll
-        for (int f = 0; f < F; ++f) cu[f] = nu[f];
-        if (kk > 0) {
-            const double* u = Us + (int64_t)(kk - 1) * F * fstride;
+        for (int f = 0; f < F; ++f) cu[f] = nu[0][f];
 #pragma unroll
-            for (int f = 0; f < F; ++f) nu[f] = u[f * fstride];
+        for (int q = 0; q + 1 < BPD; ++q)
+#pragma unroll
+            for (int f = 0; f < F; ++f) nu[q][f] = nu[q + 1][f];
+        {
+            const double* u = Us + (int64_t)max(kk - BPD, 0) * F * fstride;
+#pragma unroll
+            for (int f = 0; f < F; ++f) nu[BPD - 1][f] = u[f * fstride];
         }
         double sres = fma(-cu[KB], ylast, cu[KB + 1]);
 #pragma unroll
         for (int d = KB - 1; d >= 1; --d) sres = fma(-cu[d], yw[d - 1], sres);
-        const double yk = sres * (1.0 / cu[0]);
+        const double yk = sres * cu[0];
         y[kk] = yk;
 #pragma unroll
         for (int d = KB - 1; d >= 1; --d) yw[d] = yw[d - 1];
         yw[0] = yk;
     }
-    if (DET) {
-        *lad = ld;
-        *neg = ng;
-    }
+    if (DET) *neg = ng;
 }
 
 // Nodes of a quadrature group, square case, one lane per node.  Ubuf holds the
@@ -870,7 +875,7 @@ __device__ __forceinline__ void quad_level_band_body(const DevCtrl* ctrl, const 
     const double t = (1.0 - x) / (1.0 + x);
     const double w = (2.0 / l) / (1.0 + x);
     band_node_solve<KB, false>(mu, t * ctrl->sigma, eta[0] * w, Bs, Ls, Ubuf + i, grp.total,
-                               nodebuf + (int64_t)i * m, nullptr, nullptr);
+                               nodebuf + (int64_t)i * m, nullptr);
 }
 
 template <int KB>
@@ -911,11 +916,16 @@ __device__ __forceinline__ void pencil_scalars_band_body(int m, int s, const dou
     rmin = -wave_max(-rmin);
     load_band<KB>(Hh, m, mu, Bs, Ls);
     __syncthreads();
+    const double beta = eta[0];
+    int ng = 0;
+    if (lane == 0) band_node_solve<KB, true>(mu, 0.0, beta, Bs, Ls, Us, 1, y0, &ng);
+    __syncthreads();
+    // log|det H_hat| = sum log|pivot| = -sum log|1 / pivot| over the U rows, all
+    // lanes (a log per pivot on the solving lane would lengthen its serial chain)
+    double lu = 0.0;
+    for (int kk = lane; kk < mu; kk += WAVE) lu += log(fabs(Us[kk * (KB + 2)]));
+    const double ld = -wave_sum_fast(lu);
     if (lane == 0) {
-        const double beta = eta[0];
-        double ld = 0.0;
-        int ng = 0;
-        band_node_solve<KB, true>(mu, 0.0, beta, Bs, Ls, Us, 1, y0, &ld, &ng);
         ctrl->beta = beta;
         ctrl->rcond = (rmax > 0.0) ? rmin / rmax : 0.0;
         if (!(rmin > 2.220446049250313e-16 * rmax)) ctrl->status = 3;  // SKFAB_ERR_RANK
@@ -961,6 +971,7 @@ __global__ __launch_bounds__(256) void quad_level_batched_kernel(const SmallUnit
 // summed in parallel (one wavefront each), then the acceptance test of Section 4.1
 // is applied in sequence: the sequence's first level only seeds qprev; accept q_l
 // when ||R (q_l - q_prev)|| <= tol ||R q_l||.
+
 __device__ __forceinline__ void quad_reduce_body(DevCtrl* ctrl, const QuadGroup& grp, const double* nodebuf, int m,
                                                 double tol, const double* T1r, double* qprev, double* y,
                                                 double* qlev) {
