@@ -104,11 +104,12 @@ KERNEL_SOURCES = ("paper_2208_11447_amd/csrc/arnoldi.hip", "paper_2208_11447_amd
                   "paper_2208_11447_amd/csrc/device_state.hpp")
 
 
-def recorded_traffic(workload: str, prec: str):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
-    summary of this workload (each counter scaled by its reading for a plain device copy of
-    known size), or None when there is no summary or the step kernel's sources (or its launch
-    code) have changed since the counters were taken."""
+def recorded_traffic(workload: str, prec: str, field: str = "traffic_bytes_per_launch"):
+    """HBM bytes per step-kernel launch (per batch for the batched workload: field
+    traffic_bytes_per_batch) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of
+    this workload (each counter scaled by its reading for a plain device copy of known size),
+    or None when there is no summary or the step kernel's sources (or its launch code) have
+    changed since the counters were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", f"arnoldi_step_{workload}_{prec}_hbm_counters.txt")
     if not os.path.exists(path):
@@ -125,7 +126,7 @@ def recorded_traffic(workload: str, prec: str):
             h.update(fh.read())
     if fields.get("source_sha256") != h.hexdigest():
         return None
-    return int(fields["traffic_bytes_per_launch"])
+    return int(fields[field])
 
 
 def cpu_baseline(cfg, arrays, b, sample_steps):
@@ -317,7 +318,10 @@ def run_batched(args):
                    "N_range": [min(Ns), max(Ns)], "N_sum": sum(Ns), "m_range": [min(ms), max(ms)], "k": 2,
                    "s": "2m", "zeta": 8, "prec": args.prec, "tuning": tuning, "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     # counters recorded at the autotuner's shape (1024 threads, 64 slices per wavefront)
+                     "traffic": recorded_traffic(args.workload, args.prec, "traffic_bytes_per_batch")
+                     if list(tuning) == [1024, 64] else None,
                      "kernel": "arnoldi_step_batched_kernel", "bytes_per_batch": step_bytes // args.steps,
                      "launches": n_step, "step_ms_per_batch": round(ms_step / args.steps, 3),
                      "assembly_gbs": round(asm_bytes / (ms_asm / 1e3) / 1e9, 1) if n_asm else None},

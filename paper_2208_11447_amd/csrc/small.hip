@@ -365,14 +365,16 @@ __device__ __forceinline__ void dist_set(double (&v)[QM], int i, double x) {
 // diagonal block is solved from LDS by wavefront 0 (one lane per row) while the
 // other wavefronts already hold the block's columns of the rows above (one
 // wavefront per row: a coalesced read and a wavefront sum) and the next diagonal
-// block; every read of T1 is thus in flight during a solve.  Blocks 1..HH_CB copy
-// H's first mu - 1 columns into Hh meanwhile (one column per wavefront).
+// block; every read of T1 is thus in flight during a solve.  Blocks 1..ncb copy
+// H's first mu - 1 columns into Hh meanwhile (one column per wavefront); with ncb
+// = 0 (the batched form, where the units already fill the device) block 0 copies
+// them itself first.
 constexpr int HH_NT = 1024;
 constexpr int HH_B = 64;
 constexpr int HH_CB = 15;
 
 template <int QM>
-__device__ __forceinline__ void hhat_rows_body(int blk, const DevCtrl* ctrl, int m, int s,
+__device__ __forceinline__ void hhat_rows_body(int blk, int ncb, const DevCtrl* ctrl, int m, int s,
                                               const double* __restrict__ X, const double* __restrict__ T1r,
                                               const double* __restrict__ H, double* __restrict__ Hh) {
     __shared__ double xs[MMAX];
@@ -382,10 +384,11 @@ __device__ __forceinline__ void hhat_rows_body(int blk, const DevCtrl* ctrl, int
     const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
     constexpr int NWV = HH_NT / WAVE;
     const int64_t ldh = m + 1;
-    if (blk > 0) {
+    if (blk > 0 || ncb == 0) {
         // column j of H into column j of the row-major Hh (QM * 64 >= m rows: every
         // read is issued before the first store)
-        for (int j = (blk - 1) * NWV + wid; j < mu - 1; j += HH_CB * NWV) {
+        const int nbk = (ncb > 0) ? ncb : 1, bk = (ncb > 0) ? blk - 1 : 0;
+        for (int j = bk * NWV + wid; j < mu - 1; j += nbk * NWV) {
             double v[QM];
 #pragma unroll
             for (int q = 0; q < QM; ++q) v[q] = H[min(lane + WAVE * q, mu - 1) + ldh * j];
@@ -395,7 +398,7 @@ __device__ __forceinline__ void hhat_rows_body(int blk, const DevCtrl* ctrl, int
                 if (i < mu) Hh[(int64_t)i * m + j] = v[q];
             }
         }
-        return;
+        if (blk > 0) return;
     }
     // rows above a diagonal block held by one wavefront: w, w + NWV, ... (< QM * 64 - 64)
     constexpr int UR = (QM * WAVE - HH_B) / NWV;
@@ -465,13 +468,13 @@ __device__ __forceinline__ void hhat_rows_body(int blk, const DevCtrl* ctrl, int
 template <int QM>
 __global__ __launch_bounds__(HH_NT) void hhat_rows_kernel(const DevCtrl* ctrl, int m, int s, const double* X,
                                                          const double* T1r, const double* H, double* Hh) {
-    hhat_rows_body<QM>(blockIdx.x, ctrl, m, s, X, T1r, H, Hh);
+    hhat_rows_body<QM>(blockIdx.x, HH_CB, ctrl, m, s, X, T1r, H, Hh);
 }
 
 template <int QM>
 __global__ __launch_bounds__(HH_NT) void hhat_rows_batched_kernel(const SmallUnit* __restrict__ units, int m, int s) {
     const SmallUnit& u = units[blockIdx.y];
-    hhat_rows_body<QM>(blockIdx.x, u.ctrl, m, s, u.SV, u.T1r, u.H, u.Hh);
+    hhat_rows_body<QM>(0, 0, u.ctrl, m, s, u.SV, u.T1r, u.H, u.Hh);
 }
 
 // Solves with P(a) = a T1 + K0 (upper Hessenberg), right-hand side rhs0 e_1.
@@ -1352,9 +1355,9 @@ hipError_t launch_pencil_setup_batched(const SmallUnit* units, int nunits, int s
 
 hipError_t launch_hhat_rows_batched(const SmallUnit* units, int nunits, int m, int s, hipStream_t st) {
     if (m <= 256)
-        hipLaunchKernelGGL(hhat_rows_batched_kernel<4>, dim3(1 + HH_CB, nunits), dim3(HH_NT), 0, st, units, m, s);
+        hipLaunchKernelGGL(hhat_rows_batched_kernel<4>, dim3(1, nunits), dim3(HH_NT), 0, st, units, m, s);
     else
-        hipLaunchKernelGGL(hhat_rows_batched_kernel<8>, dim3(1 + HH_CB, nunits), dim3(HH_NT), 0, st, units, m, s);
+        hipLaunchKernelGGL(hhat_rows_batched_kernel<8>, dim3(1, nunits), dim3(HH_NT), 0, st, units, m, s);
     return hipGetLastError();
 }
 
