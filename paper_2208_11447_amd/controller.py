@@ -8,7 +8,7 @@ steps) would need. The controlled solve starts its checks at the predicted m, so
 a good prediction costs two small problems and one synchronisation instead of
 one per checkpoint. The plain adaptive-m solve is both the fallback (the checks
 continue past the prediction, and a full adaptive run follows if the capped
-dimension is reached) and the judge (every accepted result passes its stopping
+dimension is reached) and the arbiter (every accepted result passes its stopping
 test).
 
 Features (16): log n_x, log n_y, log n_z (n_z = 1 in 2D), log D, log(1 + c_x),

@@ -128,7 +128,7 @@ def test_controller_trained_on_method_runs_beats_plain_adaptive():
         _, info_p, m_p, est_p, sec_p = runner.adaptive(A, b, 2, 2, 10, ctl.M_CAP, tol)
         _, info_c, m_c, est_c, sec_c, fb = ctl.controlled_solve(runner, model, spec, A, b, tol)
         if info_p.status == 0 and est_p <= tol:
-            assert info_c.status == 0 and est_c <= tol      # the judge's test holds for the controller too
+            assert info_c.status == 0 and est_c <= tol      # the arbiter's test holds for the controller too
             t_plain += sec_p
             t_ctl += sec_c
             steps_plain += m_p
