@@ -128,7 +128,10 @@ typedef struct skfab_info {
     int32_t a_format;       /* storage of A in the Arnoldi steps: 0 CSR (or no product with A),
                                1 SELL-64 with int32 columns, 2 SELL-64 with int16 offsets
                                col - row (chosen when every col - row of A lies in
-                               [-32768, 32767])                                      */
+                               [-32768, 32767]); plus 4 when the SELL-64 copy stores
+                               the values as uint8 indices into a table of A's distinct
+                               values (at most 256 of them, 0.0 counted; see
+                               skfab_set_value_table)                                */
     double eps_est;         /* max_j | ||S v_j||^2 - 1 |  (Section 4.3 monitor)        */
     double rcond_R;         /* min|R_jj| / max|R_jj| of the whitening factor         */
     double sigma;           /* spectral scale used by the quadrature                 */
@@ -225,6 +228,18 @@ skfab_status skfab_sketch_apply(skfab_ctx *ctx, int64_t n, int32_t s, int32_t ze
                                 uint64_t seed, const double *v, double *Sv,
                                 void *ws, size_t ws_bytes);
 size_t skfab_sketch_ws_bytes(int64_t n, int32_t s);
+
+/* Value-table storage of A (on by default).  When A has at most 256 distinct
+ * values (the padding value 0.0 counted), the SELL-64 copy of A made by each solve
+ * stores every entry's value as a uint8 index into a table of those values, which
+ * the step kernel holds in LDS: 1 byte per stored entry instead of the value (8 B
+ * in FP64).  The values used are the same, so the results are bitwise those of the
+ * plain form.  The conversion finds the distinct values itself (an open-addressing
+ * set in the workspace); matrices with more of them use the plain form.
+ * enable = 0 turns the table form off for later solves on this context (the plain
+ * form is then always used), 1 turns it back on.  Errors: SKFAB_ERR_ARG (null ctx,
+ * enable other than 0 or 1). */
+skfab_status skfab_set_value_table(skfab_ctx *ctx, int32_t enable);
 
 /* Kernel timing with HIP events on the context's stream (benchmark support).
  * enable = 0 turns timing off; enable = n >= 1 brackets every n-th launch of each

@@ -23,7 +23,7 @@ EXPORTED = [
     "skfab_version", "skfab_status_string", "skfab_create", "skfab_set_stream", "skfab_destroy",
     "skfab_workspace_bytes", "skfab_solve", "skfab_arnoldi", "skfab_small_problem",
     "skfab_small_workspace_bytes", "skfab_sketch_pattern", "skfab_sketch_apply", "skfab_sketch_ws_bytes",
-    "skfab_timing_enable", "skfab_timing_read",
+    "skfab_timing_enable", "skfab_timing_read", "skfab_set_value_table",
     "skfab_batch_workspace_bytes", "skfab_solve_batched", "skfab_batch_set_tuning", "skfab_batch_get_tuning",
     "skfab_batch_autotune",
     "skfab_adaptive_workspace_bytes", "skfab_solve_adaptive", "skfab_gershgorin_ws_bytes", "skfab_gershgorin",
@@ -89,6 +89,7 @@ def lib():
         "skfab_sketch_apply": (C.c_int, [P, C.c_int64, C.c_int32, C.c_int32, C.c_uint64, P, P, P, C.c_size_t]),
         "skfab_sketch_ws_bytes": (C.c_size_t, [C.c_int64, C.c_int32]),
         "skfab_timing_enable": (C.c_int, [P, C.c_int32]),
+        "skfab_set_value_table": (C.c_int, [P, C.c_int32]),
         "skfab_timing_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "skfab_batch_workspace_bytes": (C.c_int, [C.c_int32, C.POINTER(skfab_batch_problem), C.c_int32,
                                                   C.POINTER(skfab_params), C.POINTER(C.c_size_t)]),

@@ -20,7 +20,8 @@ hipError_t launch_arnoldi_check(const double* SV, const double* SAV, const doubl
 int64_t sell_scan_blocks(int64_t nslices);
 hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const double* val, int64_t N,
                                int64_t nslices, int64_t capacity, DevCtrl* ctrl, int32_t* sl_len, int64_t* sl_ptr,
-                               int64_t* bsum, int32_t* sl_col, void* sl_val, int prec, hipStream_t st);
+                               int64_t* bsum, int32_t* sl_col, void* sl_val, DictBuf* dict, int use_dict, int prec,
+                               hipStream_t st);
 hipError_t launch_normalize_basis(const void* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl,
                                   const double* eta, double* V, int prec, hipStream_t st);
 hipError_t launch_sketch_pattern(int64_t col0, int64_t ncols, int s, int zeta, uint64_t seed, int32_t* rows,
@@ -120,6 +121,9 @@ struct skfab_ctx {
     int batch_block = 1024;
     int batch_spw = 1;
     std::vector<char> batch_host;
+    // the SELL copy may store A's values as uint8 indices into a value table when A
+    // has at most 256 distinct values
+    bool value_table = true;
 };
 
 namespace {
@@ -178,7 +182,7 @@ int next_order(int l) {
 
 struct Layout {
     size_t ctrl, eta, wnorm, H, gram, colnorm2, scal, U, W, skpart, SV, SAV, Tws, K0r, T1r, Hh, Ubuf, Urhs, nodebuf,
-        qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, chk, sl_len, sl_ptr, bsum, sl_col, sl_val, total;
+        qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, chk, sl_len, sl_ptr, bsum, sl_col, sl_val, dict, total;
     int64_t ldU;
     int64_t sell_capacity;
     int lnodes;
@@ -259,6 +263,7 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
     ly.bsum = with_basis ? take((size_t)sell_scan_blocks(ly.L.nslices) * sizeof(int64_t)) : take(0);
     ly.sl_col = with_basis ? take((size_t)ly.sell_capacity * sizeof(int32_t)) : take(0);
     ly.sl_val = with_basis ? take((size_t)ly.sell_capacity * wbytes(prec)) : take(0);
+    ly.dict = with_basis ? take(sizeof(DictBuf)) : take(0);
     ly.chk = take((size_t)2 * m * d);
     ly.SV = take((size_t)s * (m + 1) * d);
     ly.SAV = take((size_t)s * m * d);
@@ -288,6 +293,7 @@ struct Ptrs {
     double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Hh, *Ubuf, *Urhs,
         *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1, *chk;
     void* sl_val;
+    DictBuf* dict;
     int* piv;
     int32_t *sl_len, *sl_col;
     int64_t *sl_ptr, *bsum;
@@ -307,6 +313,7 @@ Ptrs carve(void* ws, const Layout& ly) {
     p.piv = reinterpret_cast<int*>(b + ly.piv);
     p.chk = D(ly.chk);
     p.sl_val = b + ly.sl_val;
+    p.dict = reinterpret_cast<DictBuf*>(b + ly.dict);
     p.sl_len = reinterpret_cast<int32_t*>(b + ly.sl_len);
     p.sl_col = reinterpret_cast<int32_t*>(b + ly.sl_col);
     p.sl_ptr = reinterpret_cast<int64_t*>(b + ly.sl_ptr);
@@ -364,11 +371,12 @@ skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matri
 // arnoldi_setup (control block, SELL copy of A, step arguments), one arnoldi_step per
 // j = 0..m (j = m forms the extension only), arnoldi_tail (its sketch and eta_m).
 skfab_status arnoldi_setup(const skfab_csr* A, const double* b, const skfab_params* p, const Layout& ly,
-                           const Ptrs& w, hipStream_t st, StepArgs* out) {
+                           const Ptrs& w, bool value_table, hipStream_t st, StepArgs* out) {
     const int m = p->m, s = p->s;
     HIP_TRY(launch_init_ctrl(w.ctrl, m, st));
     HIP_TRY(launch_sell_convert(A->rowptr, A->col, static_cast<const double*>(A->val), A->n, ly.L.nslices,
-                                ly.sell_capacity, w.ctrl, w.sl_len, w.sl_ptr, w.bsum, w.sl_col, w.sl_val, p->prec, st));
+                                ly.sell_capacity, w.ctrl, w.sl_len, w.sl_ptr, w.bsum, w.sl_col, w.sl_val, w.dict,
+                                value_table ? 1 : 0, p->prec, st));
     StepArgs& a = *out;
     std::memset(&a, 0, sizeof(a));
     a.N = A->n;
@@ -380,6 +388,7 @@ skfab_status arnoldi_setup(const skfab_csr* A, const double* b, const skfab_para
     a.sl_len = w.sl_len;
     a.sl_col = w.sl_col;
     a.sl_val = w.sl_val;
+    a.sl_table = w.dict->table;
     a.nslices = ly.L.nslices;
     a.slices_per_chunk = ly.L.slices_per_chunk;
     a.rows_per_chunk = ly.L.rows_per_chunk;
@@ -436,7 +445,7 @@ skfab_status arnoldi_tail(StepArgs& a, const skfab_params* p, const Layout& ly, 
 skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, const skfab_params* p,
                          const Layout& ly, const Ptrs& w, hipStream_t st) {
     StepArgs a;
-    skfab_status r = arnoldi_setup(A, b, p, ly, w, st, &a);
+    skfab_status r = arnoldi_setup(A, b, p, ly, w, ctx->value_table, st, &a);
     if (r != SKFAB_OK) return r;
     for (int j = 0; j <= p->m; ++j) {
         r = arnoldi_step(ctx, a, p, ly, w, j, st);
@@ -545,7 +554,7 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
 }
 
 // Storage form of A used by the step kernel (skfab_info.a_format).
-int32_t a_format(const DevCtrl& c) { return c.sell_ok ? (c.col16 ? 2 : 1) : 0; }
+int32_t a_format(const DevCtrl& c) { return c.sell_ok ? (c.col16 ? 2 : 1) | (c.dict8 ? 4 : 0) : 0; }
 
 skfab_status read_info(const Ptrs& w, hipStream_t st, skfab_info* info) {
     if (!info) return SKFAB_OK;
@@ -785,7 +794,7 @@ constexpr int BATCH_SLOTS = 128;    // quadrature scratch slots per unit
 
 struct BatchProbLayout {
     int64_t N, nnz, ldU, nslices, capacity;
-    size_t sl_len, sl_ptr, bsum, sl_col, sl_val;
+    size_t sl_len, sl_ptr, bsum, sl_col, sl_val, dict;
 };
 
 struct BatchUnitLayout {
@@ -894,6 +903,7 @@ BatchLayout make_batch_layout(int32_t nprob, const skfab_batch_problem* probs, i
         q.bsum = take((size_t)sell_scan_blocks(q.nslices) * sizeof(int64_t));
         q.sl_col = take((size_t)q.capacity * sizeof(int32_t));
         q.sl_val = take((size_t)q.capacity * wbytes(p->prec));
+        q.dict = take(sizeof(DictBuf));
     }
     L.unit.resize(L.nunits);
     for (int qi = 0; qi < nprob; ++qi) {
@@ -972,6 +982,7 @@ void batch_descriptors(const BatchLayout& L, const BatchPlan& P, const skfab_bat
             a.sl_len = reinterpret_cast<const int32_t*>(dev + ql.sl_len);
             a.sl_col = reinterpret_cast<const int32_t*>(dev + ql.sl_col);
             a.sl_val = dev + ql.sl_val;
+            a.sl_table = reinterpret_cast<const DictBuf*>(dev + ql.dict)->table;
             a.nslices = ql.nslices;
             a.slices_per_chunk = (ql.nslices + P.G[qi] - 1) / P.G[qi];
             a.rows_per_chunk = (ql.N + P.G[qi] - 1) / P.G[qi];
@@ -1052,7 +1063,9 @@ skfab_status run_batch_arnoldi(skfab_ctx* ctx, const BatchLayout& L, const Batch
                                     reinterpret_cast<int32_t*>(dev + q.sl_len),
                                     reinterpret_cast<int64_t*>(dev + q.sl_ptr),
                                     reinterpret_cast<int64_t*>(dev + q.bsum),
-                                    reinterpret_cast<int32_t*>(dev + q.sl_col), dev + q.sl_val, p->prec, st));
+                                    reinterpret_cast<int32_t*>(dev + q.sl_col), dev + q.sl_val,
+                                    reinterpret_cast<DictBuf*>(dev + q.dict), ctx->value_table ? 1 : 0, p->prec,
+                                    st));
     }
     int nact = L.nprob;
     for (int j = 0; j <= jmax; ++j) {
@@ -1126,6 +1139,12 @@ skfab_status skfab_batch_workspace_bytes(int32_t nprob, const skfab_batch_proble
     skfab_status v = validate_batch(nprob, probs, nrhs, p, false);
     if (v != SKFAB_OK) return v;
     *bytes = make_batch_layout(nprob, probs, nrhs, p).total;
+    return SKFAB_OK;
+}
+
+skfab_status skfab_set_value_table(skfab_ctx* ctx, int32_t enable) {
+    if (!ctx || (enable != 0 && enable != 1)) return SKFAB_ERR_ARG;
+    ctx->value_table = enable != 0;
     return SKFAB_OK;
 }
 
@@ -1315,7 +1334,7 @@ skfab_status skfab_solve_adaptive(skfab_ctx* ctx, const skfab_csr* A, const doub
     double qtol;
     defaults(p, &l1, &l2, &lmax, &qtol);
     StepArgs a;
-    skfab_status r = arnoldi_setup(A, b, p, L.main, w, st, &a);
+    skfab_status r = arnoldi_setup(A, b, p, L.main, w, ctx->value_table, st, &a);
     if (r != SKFAB_OK) return r;
     int mprev = 0, cur = 0;
     bool broke = false;

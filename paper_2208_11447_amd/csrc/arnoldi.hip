@@ -178,9 +178,12 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     __shared__ double scratch[BLOCK / WAVE];
     __shared__ int s_ok;
     __shared__ int s_prog;  // slices finished by the block's wavefronts (main loop)
+    __shared__ WT dtab[DICT_MAX];  // the matrix's value table (uint8 form of the SELL copy)
 
     const int sell_flag = gptr(a.sctrl)->sell_ok;  // issued with the control-block loads
     const int col16 = gptr(a.sctrl)->col16;
+    const int dict8 = gptr(a.sctrl)->dict8;
+    const WT dval = (WT)(AT)gptr(a.sl_table)[threadIdx.x & (DICT_MAX - 1)];  // (written to LDS in the prologue)
     // A breakdown detected by an earlier step ends the recurrence (the step that
     // detects it still runs its prologue to write the extension column).  The test
     // is made only after every load of the prologue has been issued, so that the
@@ -264,8 +267,9 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         }
         if (stopped) return;
         if (tid < KW * KW) win[tid] = wv;
+        if (tid < DICT_MAX) dtab[tid] = dval;
         // every thread's scalar partials reduced in a fixed tree through the (not yet
-        // used) sketch-bin region of LDS (its first barrier also publishes win)
+        // used) sketch-bin region of LDS (its first barrier also publishes win and dtab)
         block_reduce_multi<NSC, BLOCK>(sv, bins, red);
         if (tid == 0) s_ok = step_coefficients<KW>(red, win, j - 1, k, bid == 0, a, coef) ? 1 : 0;
         skv = wave_sum(skv);
@@ -295,6 +299,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         }
         for (int i = tid; i < NW * 2 * s; i += BLOCK) bins[i] = 0.0;
         if (tid == 0) s_prog = 0;
+        if (tid < DICT_MAX) dtab[tid] = dval;
         __syncthreads();
     }
 
@@ -317,6 +322,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     const GAS AT* __restrict__ slv = gptr(static_cast<const AT*>(a.sl_val));
     const GAS int32_t* __restrict__ sl_col = gptr(a.sl_col);
     const GAS int16_t* __restrict__ slo = gptr(reinterpret_cast<const int16_t*>(a.sl_col));
+    const GAS uint8_t* __restrict__ sl8 = gptr(reinterpret_cast<const uint8_t*>(a.sl_val));
     const GAS int32_t* __restrict__ rowptr = gptr(a.rowptr);
     const GAS int32_t* __restrict__ colp = gptr(a.col);
     const GAS double* __restrict__ valp = gptr(a.val);
@@ -349,8 +355,9 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     const bool pre = sell && !a.extend;
     // the loop twice: once for the steps whose window is full (j >= k, every test of
     // the window length folded away), once for the first k steps
-    auto main_loop = [&](auto full_tag) {
+    auto main_loop = [&](auto full_tag, auto dict_tag) __attribute__((always_inline)) {
     constexpr bool FULL = decltype(full_tag)::value;
+    constexpr bool DICT = decltype(dict_tag)::value;  // values as uint8 indices into dtab
     const bool first = FULL ? false : first_all;
     const int nwin = FULL ? KW : nwin_all;
     int wbase = 0;
@@ -400,7 +407,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                 // gathers, then the products -- one memory round trip per batch
                 const int32_t rr = valid ? (int32_t)r : 0;  // offsets of rows beyond N are 0
                 for (int q0 = 0; q0 < len; q0 += SB) {
-                    int cc[SB];
+                    int cc[SB], vi[SB];
                     WT vv[SB], xb[SB], xu[SB][KW];
                     if (col16) {
                         // every offset and value load issued before the first offset is
@@ -409,7 +416,8 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                         for (int q = 0; q < SB; ++q) {
                             const bool in = q0 + q < len;
                             cc[q] = in ? (int32_t)slo[e0 + (int64_t)(q0 + q) * WAVE] : 0;
-                            vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
+                            if constexpr (DICT) vi[q] = in ? (int)sl8[e0 + (int64_t)(q0 + q) * WAVE] : 0;
+                            else vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
                         }
 #pragma unroll
                         for (int q = 0; q < SB; ++q) cc[q] = (q0 + q < len) ? rr + cc[q] : 0;
@@ -418,8 +426,13 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                         for (int q = 0; q < SB; ++q) {
                             const bool in = q0 + q < len;
                             cc[q] = in ? sl_col[e0 + (int64_t)(q0 + q) * WAVE] : 0;
-                            vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
+                            if constexpr (DICT) vi[q] = in ? (int)sl8[e0 + (int64_t)(q0 + q) * WAVE] : 0;
+                            else vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
                         }
+                    }
+                    if constexpr (DICT) {
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) vv[q] = (q0 + q < len) ? dtab[vi[q]] : (WT)0;
                     }
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
@@ -502,12 +515,16 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         if (pre && lane == 0) __hip_atomic_fetch_add(&s_prog, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     }
     };
-    if constexpr (KW <= 4) {  // (for the widest window the second copy would spill registers)
-        if (nwin_all == KW && !first_all) main_loop(std::integral_constant<bool, true>());
-        else main_loop(std::integral_constant<bool, false>());
-    } else {
-        main_loop(std::integral_constant<bool, false>());
-    }
+    auto run = [&](auto dict_tag) __attribute__((always_inline)) {
+        if constexpr (KW <= 4) {  // (for the widest window the second copy would spill registers)
+            if (nwin_all == KW && !first_all) main_loop(std::integral_constant<bool, true>(), dict_tag);
+            else main_loop(std::integral_constant<bool, false>(), dict_tag);
+        } else {
+            main_loop(std::integral_constant<bool, false>(), dict_tag);
+        }
+    };
+    if (dict8 && sell) run(std::integral_constant<bool, true>());
+    else run(std::integral_constant<bool, false>());
     __builtin_amdgcn_s_setprio(0);
 
     // partial sketches, bin-major; slot = chunk keeps one XCD's slots contiguous
@@ -709,12 +726,74 @@ __global__ void normalize_basis_kernel(const VT* U, int64_t ldU, int64_t N, int 
 }
 
 // ------------------------------------------------------ SELL-64 conversion
+// Value set of A (open addressing over DICT_SLOTS slots, linear probing).
+__device__ __forceinline__ int dict_hash(uint64_t bits) { return (int)((bits * 0x9E3779B97F4A7C15ull) >> 55); }
+
+// Inserts `bits` into a set in LDS: 1 if it was not there, 0 if it was, -1 if full.
+__device__ __forceinline__ int dict_insert_lds(uint64_t* keys, uint64_t bits) {
+    const int h = dict_hash(bits);
+    for (int t = 0; t < DICT_SLOTS; ++t) {
+        const int sl = (h + t) & (DICT_SLOTS - 1);
+        const uint64_t k = keys[sl];
+        if (k == bits) return 0;
+        if (k == DICT_EMPTY) {
+            const uint64_t prev = atomicCAS((unsigned long long*)&keys[sl], (unsigned long long)DICT_EMPTY,
+                                            (unsigned long long)bits);
+            if (prev == DICT_EMPTY) return 1;
+            if (prev == bits) return 0;
+        }
+    }
+    return -1;
+}
+
+// The same for the matrix's set in device memory (agent-scope atomics: blocks on
+// every XCD insert into it); counts the values in ctrl->ndict.
+__device__ __forceinline__ bool dict_insert_global(DictBuf* d, DevCtrl* ctrl, uint64_t bits) {
+    const int h = dict_hash(bits);
+    for (int t = 0; t < DICT_SLOTS; ++t) {
+        const int sl = (h + t) & (DICT_SLOTS - 1);
+        const uint64_t k = __hip_atomic_load(&d->keys[sl], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (k == bits) return true;
+        if (k == DICT_EMPTY) {
+            const uint64_t prev = atomicCAS((unsigned long long*)&d->keys[sl], (unsigned long long)DICT_EMPTY,
+                                            (unsigned long long)bits);
+            if (prev == DICT_EMPTY) {
+                atomicAdd(&ctrl->ndict, 1);
+                return true;
+            }
+            if (prev == bits) return true;
+        }
+    }
+    return false;
+}
+
+// The matrix's value set emptied, with 0.0 (the padding value) in it; one block.
+__global__ __launch_bounds__(DICT_SLOTS) void sell_dict_reset_kernel(DictBuf* d, DevCtrl* ctrl) {
+    const int t = threadIdx.x;
+    d->keys[t] = (t == dict_hash(0ull)) ? 0ull : DICT_EMPTY;
+    if (t == 0) {
+        ctrl->ndict = 1;
+        ctrl->dict_over = 0;
+        ctrl->dict8 = 0;
+    }
+}
+
 // sl_len[sl] = max row length in slice sl (one wavefront per slice); ctrl->col_wide
 // is raised when a column lies outside [row - 32768, row + 32767], i.e. when the
-// 16-bit offset form of the column indices cannot be used.
-__global__ __launch_bounds__(256) void sell_len_kernel(const int32_t* rowptr, const int32_t* col, int64_t N,
-                                                       int64_t nslices, int32_t* sl_len, DevCtrl* ctrl) {
+// 16-bit offset form of the column indices cannot be used.  With use_dict, every
+// value of A goes into the matrix's value set (through a per-block set in LDS, so
+// that only values new to the block reach device memory); ctrl->dict_over is raised
+// when the set overflows.
+__global__ __launch_bounds__(256) void sell_len_kernel(const int32_t* rowptr, const int32_t* col, const double* val,
+                                                       int64_t N, int64_t nslices, int32_t* sl_len, DevCtrl* ctrl,
+                                                       DictBuf* dict, int use_dict) {
+    __shared__ uint64_t lkeys[DICT_SLOTS];
     const int lane = threadIdx.x & 63;
+    if (use_dict) {
+        for (int t = threadIdx.x; t < DICT_SLOTS; t += 256) lkeys[t] = DICT_EMPTY;
+        __syncthreads();
+    }
+    bool over = false;
     for (int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sl < nslices; sl += (int64_t)gridDim.x * 4) {
         const int64_t r = sl * 64 + lane;
         const int e0 = (r < N) ? rowptr[r] : 0, e1 = (r < N) ? rowptr[r + 1] : 0;
@@ -723,6 +802,11 @@ __global__ __launch_bounds__(256) void sell_len_kernel(const int32_t* rowptr, co
         for (int e = e0; e < e1; ++e) {
             const int64_t d = (int64_t)col[e] - r;
             wide |= (d < -32768 || d > 32767) ? 1 : 0;
+            if (use_dict && !over) {
+                const uint64_t bits = (uint64_t)__double_as_longlong(val[e]);
+                const int ins = (bits == DICT_EMPTY) ? -1 : dict_insert_lds(lkeys, bits);
+                if (ins < 0 || (ins == 1 && !dict_insert_global(dict, ctrl, bits))) over = true;
+            }
         }
         for (int off = 32; off > 0; off >>= 1) {
             len = max(len, __shfl_xor(len, off, 64));
@@ -733,6 +817,7 @@ __global__ __launch_bounds__(256) void sell_len_kernel(const int32_t* rowptr, co
             if (wide) atomicOr(&ctrl->col_wide, 1);
         }
     }
+    if (over) atomicOr(&ctrl->dict_over, 1);
 }
 
 constexpr int SCAN_CH = 4096;  // slices per scan block
@@ -750,8 +835,10 @@ __global__ __launch_bounds__(1024) void sell_scan_sums_kernel(const int32_t* sl_
 
 // exclusive scan of the block sums (one block, sequential per thread then across)
 __global__ __launch_bounds__(1024) void sell_scan_top_kernel(int64_t* bsum, int64_t nb, int64_t capacity,
-                                                             DevCtrl* ctrl) {
+                                                             DevCtrl* ctrl, DictBuf* dict, int use_dict) {
     __shared__ int64_t part[1024];
+    __shared__ int sh_ok;
+    __shared__ int wcnt[16];
     const int64_t per = (nb + 1023) / 1024;
     const int64_t i0 = threadIdx.x * per, i1 = min(nb, i0 + per);
     int64_t t = 0;
@@ -764,10 +851,27 @@ __global__ __launch_bounds__(1024) void sell_scan_top_kernel(int64_t* bsum, int6
         ctrl->sell_total = run;
         ctrl->sell_ok = (run <= capacity) ? 1 : 0;
         ctrl->col16 = ctrl->col_wide ? 0 : 1;
+        sh_ok = (run <= capacity) ? 1 : 0;
     }
     __syncthreads();
     int64_t run = part[threadIdx.x];
     for (int64_t i = i0; i < i1; ++i) { const int64_t v = bsum[i]; bsum[i] = run; run += v; }
+    // value table: the occupied slots of the value set numbered in slot order
+    const bool use = use_dict && sh_ok && !ctrl->dict_over && ctrl->ndict <= DICT_MAX;
+    const int tid = threadIdx.x;
+    uint64_t k = DICT_EMPTY;
+    if (use && tid < DICT_SLOTS) k = dict->keys[tid];
+    const bool occ = k != DICT_EMPTY;
+    const uint64_t mask = __ballot(occ);
+    if ((tid & 63) == 0) wcnt[tid >> 6] = __popcll(mask);
+    __syncthreads();
+    if (use && tid < DICT_SLOTS) {
+        int idx = __popcll(mask & ((1ull << (tid & 63)) - 1ull));
+        for (int w = 0; w < (tid >> 6); ++w) idx += wcnt[w];
+        dict->slot_idx[tid] = occ ? idx : -1;
+        if (occ) dict->table[idx] = __longlong_as_double((long long)k);
+    }
+    if (tid == 0) ctrl->dict8 = use ? 1 : 0;
 }
 
 // sl_ptr = exclusive prefix of 64 * sl_len (block-local scan plus block offset)
@@ -802,10 +906,31 @@ template <typename AT>
 __global__ __launch_bounds__(256) void sell_fill_kernel(const int32_t* rowptr, const int32_t* col, const double* val,
                                                         int64_t N, int64_t nslices, const DevCtrl* ctrl,
                                                         const int64_t* sl_ptr, const int32_t* sl_len,
-                                                        int32_t* sl_col, AT* sl_val) {
+                                                        int32_t* sl_col, AT* sl_val, const DictBuf* dict) {
+    __shared__ uint64_t lkeys[DICT_SLOTS];
+    __shared__ int lidx[DICT_SLOTS];
     if (!ctrl->sell_ok) return;
     const bool c16 = ctrl->col16 != 0;
+    const bool d8 = ctrl->dict8 != 0;
+    if (d8) {  // (block-uniform)
+        for (int t = threadIdx.x; t < DICT_SLOTS; t += 256) {
+            lkeys[t] = dict->keys[t];
+            lidx[t] = dict->slot_idx[t];
+        }
+        __syncthreads();
+    }
+    // table index of a value (every value of A, and 0.0, is in the set)
+    auto index_of = [&](double v) -> uint8_t {
+        const uint64_t bits = (uint64_t)__double_as_longlong(v);
+        const int h = dict_hash(bits);
+        for (int t = 0; t < DICT_SLOTS; ++t) {
+            const int sl = (h + t) & (DICT_SLOTS - 1);
+            if (lkeys[sl] == bits) return (uint8_t)lidx[sl];
+        }
+        return 0;
+    };
     int16_t* sl_off = reinterpret_cast<int16_t*>(sl_col);
+    uint8_t* sl_v8 = reinterpret_cast<uint8_t*>(sl_val);
     const int lane = threadIdx.x & 63;
     for (int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sl < nslices; sl += (int64_t)gridDim.x * 4) {
         const int64_t r = sl * 64 + lane;
@@ -828,7 +953,8 @@ __global__ __launch_bounds__(256) void sell_fill_kernel(const int32_t* rowptr, c
                 if (q0 + q < len) {
                     if (c16) sl_off[o + (int64_t)(q0 + q) * 64] = (int16_t)((r < N) ? cb[q] - r : 0);
                     else sl_col[o + (int64_t)(q0 + q) * 64] = cb[q];
-                    sl_val[o + (int64_t)(q0 + q) * 64] = (AT)vb[q];
+                    if (d8) sl_v8[o + (int64_t)(q0 + q) * 64] = index_of(vb[q]);
+                    else sl_val[o + (int64_t)(q0 + q) * 64] = (AT)vb[q];
                 }
             }
         }
@@ -883,7 +1009,7 @@ int step_block_fit(int block, int s) {
     const size_t lds_budget = 156 * 1024;
     auto lds_of = [&](int bl) {
         const size_t bins = (size_t)(bl / 64) * 2 * s, red = (size_t)(2 * KMAX + 1) * (bl + 72);
-        return (bins > red ? bins : red) * sizeof(double) + (size_t)(bl / 64) * 64 * 8;
+        return (bins > red ? bins : red) * sizeof(double) + (size_t)(bl / 64) * 64 * 8 + DICT_MAX * sizeof(double);
     };
     while (block > 256 && lds_of(block) > lds_budget) block /= 2;
     return block;
@@ -956,20 +1082,23 @@ int64_t sell_scan_blocks(int64_t nslices) { return (nslices + SCAN_CH - 1) / SCA
 
 hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const double* val, int64_t N,
                                int64_t nslices, int64_t capacity, DevCtrl* ctrl, int32_t* sl_len, int64_t* sl_ptr,
-                               int64_t* bsum, int32_t* sl_col, void* sl_val, int prec, hipStream_t st) {
+                               int64_t* bsum, int32_t* sl_col, void* sl_val, DictBuf* dict, int use_dict, int prec,
+                               hipStream_t st) {
     const int64_t g64 = (nslices + 3) / 4;
     const unsigned g = (unsigned)(g64 < 65536 ? g64 : 65536);
-    hipLaunchKernelGGL(sell_len_kernel, dim3(g), dim3(256), 0, st, rowptr, col, N, nslices, sl_len, ctrl);
+    hipLaunchKernelGGL(sell_dict_reset_kernel, dim3(1), dim3(DICT_SLOTS), 0, st, dict, ctrl);
+    hipLaunchKernelGGL(sell_len_kernel, dim3(g), dim3(256), 0, st, rowptr, col, val, N, nslices, sl_len, ctrl, dict,
+                       use_dict);
     const int64_t nb = sell_scan_blocks(nslices);
     hipLaunchKernelGGL(sell_scan_sums_kernel, dim3((unsigned)nb), dim3(1024), 0, st, sl_len, nslices, bsum);
-    hipLaunchKernelGGL(sell_scan_top_kernel, dim3(1), dim3(1024), 0, st, bsum, nb, capacity, ctrl);
+    hipLaunchKernelGGL(sell_scan_top_kernel, dim3(1), dim3(1024), 0, st, bsum, nb, capacity, ctrl, dict, use_dict);
     hipLaunchKernelGGL(sell_scan_apply_kernel, dim3((unsigned)nb), dim3(1024), 0, st, sl_len, nslices, bsum, sl_ptr);
     if (prec == 0)
         hipLaunchKernelGGL(sell_fill_kernel<double>, dim3(g), dim3(256), 0, st, rowptr, col, val, N, nslices, ctrl,
-                           sl_ptr, sl_len, sl_col, static_cast<double*>(sl_val));
+                           sl_ptr, sl_len, sl_col, static_cast<double*>(sl_val), dict);
     else
         hipLaunchKernelGGL(sell_fill_kernel<float>, dim3(g), dim3(256), 0, st, rowptr, col, val, N, nslices, ctrl,
-                           sl_ptr, sl_len, sl_col, static_cast<float*>(sl_val));
+                           sl_ptr, sl_len, sl_col, static_cast<float*>(sl_val), dict);
     return hipGetLastError();
 }
 

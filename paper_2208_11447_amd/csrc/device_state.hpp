@@ -27,6 +27,23 @@ struct DevCtrl {
     int64_t sell_total; // entries of the SELL-64 copy of A (padded)
     int32_t sell_ok;    // 1: the SELL-64 copy fits the workspace and is used
     int32_t col16;      // 1: the SELL-64 copy stores column offsets col - row as int16
+    int32_t ndict;      // distinct values of A seen by the conversion (0.0 included)
+    int32_t dict_over;  // set when A has more distinct values than the value table holds
+    int32_t dict8;      // 1: the SELL-64 copy stores 8-bit indices into the value table
+    int32_t pad3;
+};
+
+// Value table of the SELL-64 copy (one per matrix): when A has at most DICT_MAX
+// distinct values (0.0, the padding value, always among them), each stored entry
+// is a uint8 index into `table`.  `keys` is the open-addressing set the conversion
+// builds (DICT_SLOTS slots, empty = DICT_EMPTY), `slot_idx` its slot -> index map.
+constexpr int DICT_MAX = 256;
+constexpr int DICT_SLOTS = 512;
+constexpr uint64_t DICT_EMPTY = ~0ull;
+struct DictBuf {
+    uint64_t keys[DICT_SLOTS];
+    int32_t slot_idx[DICT_SLOTS];
+    double table[DICT_MAX];
 };
 
 // Launch shape of the step kernel for one problem (host side): block size, grid
@@ -53,7 +70,8 @@ struct StepArgs {
     const int64_t* sl_ptr;
     const int32_t* sl_len;
     const int32_t* sl_col;
-    const void* sl_val;   // values in the precision's matrix type
+    const void* sl_val;   // values in the precision's matrix type, or uint8 table indices (ctrl->dict8)
+    const double* sl_table;  // the value table (DictBuf::table) for the uint8 form
     int64_t nslices;
     int64_t slices_per_chunk;
     int64_t rows_per_chunk;

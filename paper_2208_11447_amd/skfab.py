@@ -191,6 +191,12 @@ def skfab_sketch_apply(ctx: Context, n: int, s: int, zeta: int, seed: int, v: to
            "skfab_sketch_apply")
 
 
+def skfab_set_value_table(ctx: Context, enable: bool = True):
+    """Value-table (uint8 index) storage of A's values in the SELL copy when A has at
+    most 256 distinct values; on by default (enable=False: always the plain form)."""
+    _check(N.lib().skfab_set_value_table(ctx.handle, 1 if enable else 0), "skfab_set_value_table")
+
+
 def skfab_timing_enable(ctx: Context, enable: bool = True, stride: int = 1):
     """Event timing of every stride-th launch of each timed kernel class (off: enable=False)."""
     _check(N.lib().skfab_timing_enable(ctx.handle, int(stride) if enable else 0), "skfab_timing_enable")
