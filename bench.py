@@ -104,6 +104,15 @@ KERNEL_SOURCES = ("paper_2208_11447_amd/csrc/arnoldi.hip", "paper_2208_11447_amd
                   "paper_2208_11447_amd/csrc/device_state.hpp")
 
 
+def storage_name(a_format: int) -> str:
+    """Storage of A in the Arnoldi steps as reported by skfab_info.a_format."""
+    if a_format == 0:
+        return "csr"
+    cols = "int16_offsets" if a_format & 3 == 2 else "int32_cols"
+    vals = "uint8_value_table" if a_format & 4 else "values"
+    return f"sell64_{cols}_{vals}"
+
+
 def recorded_traffic(workload: str, prec: str, field: str = "traffic_bytes_per_launch"):
     """HBM bytes per step-kernel launch (per batch for the batched workload: field
     traffic_bytes_per_batch) from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary of
@@ -316,7 +325,9 @@ def run_batched(args):
                    + ("" if args.prec == "fp64" else f"_{args.prec}"),
                    "problems": len(probs), "rhs_per_problem": R, "solves_per_step": solves,
                    "N_range": [min(Ns), max(Ns)], "N_sum": sum(Ns), "m_range": [min(ms), max(ms)], "k": 2,
-                   "s": "2m", "zeta": 8, "prec": args.prec, "tuning": tuning, "parallelism": "single-gpu"},
+                   "s": "2m", "zeta": 8, "prec": args.prec, "tuning": tuning,
+                   "a_storage": sorted({storage_name(info[i][0].a_format) for i in range(len(probs))}),
+                   "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      # counters recorded at the autotuner's shape (1024 threads, 64 slices per wavefront)
@@ -507,7 +518,8 @@ def main():
         "config": {"workload": f"{args.workload}_{args.f}_{args.method}"
                    + ("" if args.prec == "fp64" else f"_{args.prec}"), "grid": f"{cfg['n']}^{cfg['dim']}",
                    "N": N, "nnz": nnz, "m": cfg["m"], "k": cfg["k"], "s": cfg["s"], "zeta": cfg["zeta"],
-                   "f": args.f, "method": args.method, "prec": args.prec, "parallelism": "single-gpu"},
+                   "f": args.f, "method": args.method, "prec": args.prec,
+                   "a_storage": storage_name(info.a_format), "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,

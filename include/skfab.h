@@ -229,11 +229,12 @@ skfab_status skfab_sketch_apply(skfab_ctx *ctx, int64_t n, int32_t s, int32_t ze
                                 void *ws, size_t ws_bytes);
 size_t skfab_sketch_ws_bytes(int64_t n, int32_t s);
 
-/* Value-table storage of A (on by default).  When A has at most 256 distinct
- * values (the padding value 0.0 counted), the SELL-64 copy of A made by each solve
- * stores every entry's value as a uint8 index into a table of those values, which
- * the step kernel holds in LDS: 1 byte per stored entry instead of the value (8 B
- * in FP64).  The values used are the same, so the results are bitwise those of the
+/* Value-table storage of A (on by default; FP64 form).  When A has at most 256
+ * distinct values (the padding value 0.0 counted), the SELL-64 copy of A made by
+ * each FP64 solve stores every entry's value as a uint8 index into a table of those
+ * values, which the step kernel holds in LDS: 1 byte per stored entry instead of 8.
+ * (The FP32 forms keep their 4-byte values: there the lookup costs more than it
+ * saves.)  The values used are the same, so the results are bitwise those of the
  * plain form.  The conversion finds the distinct values itself (an open-addressing
  * set in the workspace); matrices with more of them use the plain form.
  * enable = 0 turns the table form off for later solves on this context (the plain

@@ -122,7 +122,8 @@ struct skfab_ctx {
     int batch_spw = 1;
     std::vector<char> batch_host;
     // the SELL copy may store A's values as uint8 indices into a value table when A
-    // has at most 256 distinct values
+    // has at most 256 distinct values (FP64 form only: for 4-byte values the table
+    // lookup costs more than the 3 bytes per entry it saves)
     bool value_table = true;
 };
 
@@ -376,7 +377,7 @@ skfab_status arnoldi_setup(const skfab_csr* A, const double* b, const skfab_para
     HIP_TRY(launch_init_ctrl(w.ctrl, m, st));
     HIP_TRY(launch_sell_convert(A->rowptr, A->col, static_cast<const double*>(A->val), A->n, ly.L.nslices,
                                 ly.sell_capacity, w.ctrl, w.sl_len, w.sl_ptr, w.bsum, w.sl_col, w.sl_val, w.dict,
-                                value_table ? 1 : 0, p->prec, st));
+                                (value_table && p->prec == SKFAB_PREC_FP64) ? 1 : 0, p->prec, st));
     StepArgs& a = *out;
     std::memset(&a, 0, sizeof(a));
     a.N = A->n;
@@ -1064,8 +1065,8 @@ skfab_status run_batch_arnoldi(skfab_ctx* ctx, const BatchLayout& L, const Batch
                                     reinterpret_cast<int64_t*>(dev + q.sl_ptr),
                                     reinterpret_cast<int64_t*>(dev + q.bsum),
                                     reinterpret_cast<int32_t*>(dev + q.sl_col), dev + q.sl_val,
-                                    reinterpret_cast<DictBuf*>(dev + q.dict), ctx->value_table ? 1 : 0, p->prec,
-                                    st));
+                                    reinterpret_cast<DictBuf*>(dev + q.dict),
+                                    (ctx->value_table && p->prec == SKFAB_PREC_FP64) ? 1 : 0, p->prec, st));
     }
     int nact = L.nprob;
     for (int j = 0; j <= jmax; ++j) {
