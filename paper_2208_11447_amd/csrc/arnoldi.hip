@@ -794,18 +794,32 @@ __global__ __launch_bounds__(256) void sell_len_kernel(const int32_t* rowptr, co
         __syncthreads();
     }
     bool over = false;
+    uint64_t last = 0ull;  // the lane's last value found in the set (0.0 is always there)
     for (int64_t sl = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); sl < nslices; sl += (int64_t)gridDim.x * 4) {
         const int64_t r = sl * 64 + lane;
         const int e0 = (r < N) ? rowptr[r] : 0, e1 = (r < N) ? rowptr[r + 1] : 0;
         int len = e1 - e0;
         int wide = 0;
-        for (int e = e0; e < e1; ++e) {
-            const int64_t d = (int64_t)col[e] - r;
-            wide |= (d < -32768 || d > 32767) ? 1 : 0;
-            if (use_dict && !over) {
-                const uint64_t bits = (uint64_t)__double_as_longlong(val[e]);
-                const int ins = (bits == DICT_EMPTY) ? -1 : dict_insert_lds(lkeys, bits);
-                if (ins < 0 || (ins == 1 && !dict_insert_global(dict, ctrl, bits))) over = true;
+        // entries in groups of 8: all loads of a group issued before any is used
+        for (int g0 = e0; g0 < e1; g0 += 8) {
+            int cb[8];
+            uint64_t vb[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool in = g0 + q < e1;
+                cb[q] = in ? col[g0 + q] : (int)r;
+                vb[q] = (in && use_dict) ? (uint64_t)__double_as_longlong(val[g0 + q]) : 0ull;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const int64_t d = (int64_t)cb[q] - r;
+                wide |= (d < -32768 || d > 32767) ? 1 : 0;
+                const uint64_t bits = vb[q];
+                if (use_dict && !over && bits != last) {
+                    const int ins = (bits == DICT_EMPTY) ? -1 : dict_insert_lds(lkeys, bits);
+                    if (ins < 0 || (ins == 1 && !dict_insert_global(dict, ctrl, bits))) over = true;
+                    last = bits;
+                }
             }
         }
         for (int off = 32; off > 0; off >>= 1) {
