@@ -165,7 +165,7 @@ template <int KW> struct SellBatch { static constexpr int value = KW <= 2 ? 7 : 
 //
 // The body serves both the single-problem kernel and the batched one: `bid` is
 // the block's index among the G blocks of its (problem, right-hand side) pair.
-template <int KW, int ZETA, int BLOCK, typename P>
+template <int KW, int ZETA, int BLOCK, typename P, bool PREFETCH>
 __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     using VT = typename P::V;
     using WT = typename P::W;
@@ -362,11 +362,46 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     const int nwin = FULL ? KW : nwin_all;
     int wbase = 0;
     int iter = 0;
+    // metadata of the slice at loop position idx (slice index itn) from the wavefront's
+    // ring, refilled with the next 64 slices when it runs out
+    auto ring = [&](int64_t itn, int idx) {
+        if (idx - wbase == WAVE) {
+            wbase += WAVE;
+            const int64_t itl = itn + (int64_t)lane * step;
+            const int nl = (itl < it1) ? sl_len[itl] : 0;
+            const int np = (itl < it1) ? (int)(sl_ptr[itl] >> 6) : 0;
+            meta[wid][lane] = make_int2(nl, np);
+        }
+        return meta[wid][idx - wbase];
+    };
+    // Batched form, with the value table and windows up to 2 wide: the next slice's
+    // metadata and the column data of its first batch are requested while the
+    // current slice is processed, so that a slice waits for one memory round trip
+    // (its value indices travel with its gathers) instead of two.  (Measured: 2 %
+    // faster in the batched form; slower in the single-problem one, whose main
+    // loop then runs at the register limit, and slower with 8-byte values, where
+    // the loop was bound by bandwidth.  Wider windows have no registers left.)
+    constexpr bool PFC = PREFETCH && DICT && KW <= 2;
+    int lenN = 0;
+    int64_t e0N = 0;
+    int pcol[SB];
+    auto prefetch = [&](int64_t itn, int idx) {
+        const int2 md = ring(itn, idx);
+        lenN = md.x;
+        e0N = ((int64_t)md.y << 6) + lane;
+#pragma unroll
+        for (int q = 0; q < SB; ++q) {
+            if (q < lenN) pcol[q] = col16 ? (int)slo[e0N + (int64_t)q * WAVE] : sl_col[e0N + (int64_t)q * WAVE];
+            else pcol[q] = 0;
+        }
+    };
+    if (PFC && pre && it0 < it1) prefetch(it0, 0);
     for (int64_t it = it0; it < it1; it += step, ++iter) {
         const int64_t r = sell ? it * WAVE + lane : it;
         const bool valid = r < a.N;
         int len = 0;
         int64_t e0 = 0;
+        bool pf_done = !(PFC && pre) || it + step >= it1;  // the next slice's prefetch is issued
         if (pre) {
             // the four wavefronts of a SIMD share its issue slots, which go to the oldest
             // first: with equal static shares the youngest would finish last.  A
@@ -375,16 +410,14 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             const int done = __hip_atomic_load(&s_prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             if (done > iter * NW) __builtin_amdgcn_s_setprio(3);
             else __builtin_amdgcn_s_setprio(0);
-            if (iter - wbase == WAVE) {  // next window of 64 slices
-                wbase += WAVE;
-                const int64_t itl = it + (int64_t)lane * step;
-                const int nl = (itl < it1) ? sl_len[itl] : 0;
-                const int np = (itl < it1) ? (int)(sl_ptr[itl] >> 6) : 0;
-                meta[wid][lane] = make_int2(nl, np);
+            if constexpr (PFC) {
+                len = lenN;
+                e0 = e0N;
+            } else {
+                const int2 md = ring(it, iter);
+                len = md.x;
+                e0 = ((int64_t)md.y << 6) + lane;
             }
-            const int2 md = meta[wid][iter - wbase];
-            len = md.x;
-            e0 = ((int64_t)md.y << 6) + lane;
         }
         // the row's own inputs of u_j: requested before the matrix entries and used
         // only after the product, which needs u_j at the neighbours, not at the row
@@ -409,7 +442,14 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                 for (int q0 = 0; q0 < len; q0 += SB) {
                     int cc[SB], vi[SB];
                     WT vv[SB], xb[SB], xu[SB][KW];
-                    if (col16) {
+                    if (PFC && q0 == 0) {
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) {
+                            const bool in = q < len;
+                            cc[q] = in ? (col16 ? rr + pcol[q] : pcol[q]) : 0;
+                            vi[q] = in ? (int)sl8[e0 + (int64_t)q * WAVE] : 0;
+                        }
+                    } else if (col16) {
                         // every offset and value load issued before the first offset is
                         // used (converting each offset as it arrives would serialise them)
 #pragma unroll
@@ -430,7 +470,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                             else vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
                         }
                     }
-                    if constexpr (DICT) {
+                    if constexpr (DICT && !PFC) {
 #pragma unroll
                         for (int q = 0; q < SB; ++q) vv[q] = (q0 + q < len) ? dtab[vi[q]] : (WT)0;
                     }
@@ -440,6 +480,14 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
 #pragma unroll
                         for (int o = 0; o < KW; ++o) xu[q][o] = (o < nwin) ? to_w<WT>(gload(Uo[o] + cc[q])) : (WT)0;
                     }
+                    if constexpr (PFC) {
+                        if (!pf_done) {  // the next slice's column data, behind this slice's gathers
+                            prefetch(it + step, iter + 1);
+                            pf_done = true;
+                        }
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) vv[q] = (q0 + q < len) ? dtab[vi[q]] : (WT)0;
+                    }
 #pragma unroll
                     for (int q = 0; q < SB; ++q) {
                         WT x = alpha_w * xb[q];
@@ -448,6 +496,12 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                             if (o < nwin) x = fma(cf_w[o], xu[q][o], x);
                         x = to_w<WT>(Store<VT>::put(x));
                         w = fma(vv[q], x, w);
+                    }
+                }
+                if constexpr (PFC) {
+                    if (!pf_done) {  // (an empty slice)
+                        prefetch(it + step, iter + 1);
+                        pf_done = true;
                     }
                 }
             } else if (valid) {
@@ -546,7 +600,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
 
 template <int KW, int ZETA, int BLOCK, typename P>
 __global__ __launch_bounds__(BLOCK) void arnoldi_step_kernel(StepArgs a) {
-    step_body<KW, ZETA, BLOCK, P>(a, blockIdx.x);
+    step_body<KW, ZETA, BLOCK, P, false>(a, blockIdx.x);
 }
 
 // Unit (problem, right-hand side) of a block of the batched step launch.
@@ -588,7 +642,7 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_batched_kernel(const Batch
     a.scal_cur = u.scal[j & 1];
     a.skp_prev = u.skp[(j + 1) & 1];
     a.skp_cur = u.skp[j & 1];
-    step_body<KW, ZETA, BLOCK, P>(a, lk.bid);
+    step_body<KW, ZETA, BLOCK, P, true>(a, lk.bid);
 }
 
 // After the extension step m: S u_m (unnormalised) into SV[:, m_used], eta_m and
