@@ -48,6 +48,18 @@ __device__ __forceinline__ void store_nt(bf16s v, bf16s* p) { __builtin_nontempo
 #define GAS __attribute__((address_space(1)))
 template <typename T> __device__ __forceinline__ GAS T* gptr(T* p) { return (GAS T*)p; }
 template <typename T> __device__ __forceinline__ T gload(const GAS T* p) { return *p; }
+
+// Raw buffer stores: a resource covering nbytes from base (wave-uniform); the
+// hardware drops stores at byte offsets >= nbytes.  A row-guarded tail thus needs
+// no per-lane branch (guarded stores in branches were each made to wait for the
+// previous one).  Word 3 of the descriptor is the gfx9-family raw-buffer format.
+typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(void* base, int nbytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, nbytes, 0x00020000);
+}
+__device__ __forceinline__ void buf_store_f64(double v, __amdgpu_buffer_rsrc_t r, int byte_off) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, byte_off, 0, 0);
+}
 __device__ __forceinline__ bf16s gload(const GAS bf16s* p) { return bf16s{p->bits}; }
 template <typename T> __device__ __forceinline__ void store_nt(T v, GAS T* p) { __builtin_nontemporal_store(v, p); }
 __device__ __forceinline__ void store_nt(bf16s v, GAS bf16s* p) { __builtin_nontemporal_store(v.bits, &p->bits); }

@@ -174,13 +174,17 @@ __device__ __forceinline__ void qr_panel_body(double* X, int s, int c0, const De
 #pragma unroll
         for (int i = 0; i < QR_NB; ++i) Tws[l * QR_NB + i] = trow[i];
     }
+    // rows c0 .. s-1 of each panel column through a buffer resource ending at row
+    // s-1 (an empty one for columns beyond the panel): no per-lane guard
+    const int wu = __builtin_amdgcn_readfirstlane(wid);
 #pragma unroll
-    for (int q = 0; q < QR_CPW; ++q)
+    for (int q = 0; q < QR_CPW; ++q) {
+        const int c = wu * QR_CPW + q;
+        const __amdgpu_buffer_rsrc_t rs =
+            buf_rsrc(X + (int64_t)c0 + (int64_t)s * (c0 + min(c, pc - 1)), (c < pc) ? nrows * 8 : 0);
 #pragma unroll
-        for (int i = 0; i < RPW; ++i) {
-            const int c = wid * QR_CPW + q, r = lane + WAVE * i;
-            if (c < pc && r < nrows) X[(int64_t)(c0 + r) + (int64_t)s * (c0 + c)] = a[q][i];
-        }
+        for (int i = 0; i < RPW; ++i) buf_store_f64(a[q][i], rs, (lane + WAVE * i) * 8);
+    }
 }
 
 template <int RPW>
@@ -240,15 +244,15 @@ __device__ __forceinline__ void qr_update_body(double* X, int s, int c0, const D
         Z[tid] = (tid < pc) ? t : 0.0;
     }
     __syncthreads();
+    // rows beyond the column's end fall outside the buffer resource (no guard)
+    const __amdgpu_buffer_rsrc_t rs = buf_rsrc(C, nrows * 8);
 #pragma unroll
     for (int k = 0; k < RPT; ++k) {
         const int r = tid + 256 * k;
-        if (r < nrows) {
-            double t = 0.0;
+        double t = 0.0;
 #pragma unroll
-            for (int i = 0; i < QR_NB; ++i) t = fma(yv[k][i], Z[i], t);
-            C[r] = cv[k] - t;
-        }
+        for (int i = 0; i < QR_NB; ++i) t = fma(yv[k][i], Z[i], t);
+        buf_store_f64(cv[k] - t, rs, r * 8);
     }
 }
 
