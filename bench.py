@@ -330,9 +330,9 @@ def run_batched(args):
                    "parallelism": "single-gpu"},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     # counters recorded at the autotuner's shape (1024 threads, 64 slices per wavefront)
-                     "traffic": recorded_traffic(args.workload, args.prec, "traffic_bytes_per_batch")
-                     if list(tuning) == [1024, 64] else None,
+                     # counters are recorded per launch shape (null for a shape without a record)
+                     "traffic": recorded_traffic(f"{args.workload}_t{tuning[0]}x{tuning[1]}", args.prec,
+                                                 "traffic_bytes_per_batch"),
                      "kernel": "arnoldi_step_batched_kernel", "bytes_per_batch": step_bytes // args.steps,
                      "launches": n_step, "step_ms_per_batch": round(ms_step / args.steps, 3),
                      "assembly_gbs": round(asm_bytes / (ms_asm / 1e3) / 1e9, 1) if n_asm else None},
