@@ -75,6 +75,13 @@ def test_host_validation(kw, status):
     assert st == status
 
 
+def test_value_table_switch_validation():
+    """skfab_set_value_table rejects a null context before touching any device."""
+    lib = N.lib()
+    assert lib.skfab_set_value_table(None, 1) == N.SKFAB_ERR_ARG
+    assert lib.skfab_set_value_table(None, 0) == N.SKFAB_ERR_ARG
+
+
 def test_status_strings():
     lib = N.lib()
     for s in range(8):
