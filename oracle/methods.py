@@ -15,6 +15,9 @@ Functions f (the ``f`` argument):
 Readings (listed in the design notes):
   * S b is taken as ||b|| * S v_1, the first column of SV_m (Section 4's
     algorithm never sketches b itself).
+  * Extremely ill-conditioned R (remark after eq. sfom3): the numerical
+    pseudoinverse is the truncated QR one in basis order, i.e. the longest
+    prefix of the basis whose sketch has kappa_F(R_j) <= COND_MAX is used.
   * Whitened coordinates: c = Q^T S b, B = SAV R^-1, M = Q^T B.
   * Quadrature uses the spectral scaling sigma = sqrt(|theta|_min |theta|_max)
     over the eigenvalues theta of M (an exact identity for z^(-1/2)).
@@ -47,6 +50,59 @@ class Whitened:
     M: np.ndarray     # Q^T SAV R^-1
     c: np.ndarray     # Q^T S b
     Sb: np.ndarray    # S b = beta * SV[:, 0]
+
+
+# ------------------------------------------- ill-conditioned R (Section 2.1) ---
+# The remark after eq. (sFOM''') suggests a numerical pseudoinverse in place of
+# R_m^-1 when SV_m, and hence R_m, is extremely ill-conditioned.  Reading taken
+# here: the pseudoinverse is the truncated (basic) one of the QR factor in the
+# order of the Krylov basis.  The leading blocks R_j = R[:j, :j] are the QR
+# factors of the prefixes SV_j, and their condition numbers never decrease with
+# j, so the columns to drop are the trailing ones: the approximant is formed
+# from the longest prefix V_j whose sketch has a Frobenius-norm condition number
+# ||R_j||_F ||R_j^-1||_F of at most COND_MAX.  A basis that meets the bound is
+# used whole, so the remedy changes nothing for well-conditioned problems.
+COND_MAX = 1e12
+
+
+def prefix_conditions(R: np.ndarray) -> np.ndarray:
+    """kappa_F(R_j) = ||R_j||_F ||R_j^-1||_F for j = 1..m (R upper triangular).
+    R_j^-1 is the leading block of R^-1, so both norms are prefix sums over
+    columns; a zero pivot gives inf from its column on."""
+    m = R.shape[0]
+    with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
+        Rinv = sla.solve_triangular(R, np.eye(m), lower=False)
+        inv2 = np.cumsum(np.sum(Rinv ** 2, axis=0))
+        fro2 = np.cumsum(np.sum(np.triu(R) ** 2, axis=0))
+        c = np.sqrt(fro2 * inv2)
+    c[~np.isfinite(c)] = np.inf
+    return np.maximum.accumulate(c)
+
+
+def conditioned_prefix(arn: ArnoldiResult, cond_max: float = COND_MAX) -> int:
+    """Largest j with kappa_F(R_j) <= cond_max, R the QR factor of SV_m."""
+    if arn.m_used == 0:
+        return 0
+    R = np.linalg.qr(arn.SV, mode="r")
+    c = prefix_conditions(R)
+    return max(1, int(np.count_nonzero(c <= cond_max)))
+
+
+def regularize(arn: ArnoldiResult, cond_max: float = COND_MAX):
+    """The data the whitening uses: arn itself, or its conditioned prefix."""
+    mp = conditioned_prefix(arn, cond_max)
+    if mp >= arn.m_used:
+        return arn, arn.m_used
+    return _prefix(arn, mp), mp
+
+
+def _pad(y: np.ndarray, m: int) -> np.ndarray:
+    """Coefficients over the whole basis: dropped trailing vectors get 0."""
+    if y.size >= m:
+        return y
+    out = np.zeros(m)
+    out[: y.size] = y
+    return out
 
 
 def whiten(arn: ArnoldiResult) -> Whitened:
@@ -118,38 +174,51 @@ def sfom_closed(arn: ArnoldiResult, f: str, fparam: float = 0.0, poly=None) -> S
     """Closed form (sFOM''') of Algorithm 1: V_m R^-1 f(Q^T SAV R^-1) Q^T S b."""
     if arn.m_used == 0:
         return _empty(arn)
+    full = arn
+    arn, mp = regularize(full)
     w = whiten(arn)
     g = matfun_apply(w.M, w.c, f, fparam, poly)
-    y = sla.solve_triangular(w.R, g, lower=False)
-    return SolveResult(_assemble(arn, y), y, arn.m_used,
+    y = _pad(sla.solve_triangular(w.R, g, lower=False), full.m_used)
+    return SolveResult(_assemble(full, y), y, mp,
                        info=dict(rcond_R=1.0 / np.linalg.cond(w.R)))
 
 
-# Rounding floor of the adaptive test (a reading, not in the paper): when the
-# requested tolerance lies below what the node solves can resolve, the relative
-# differences of consecutive orders stop falling at some small level; an order
-# whose difference is below QUAD_FLOOR and larger than half the previous
-# difference is then accepted instead of refining up to l_max.  At the last
-# order the sequence allows (the next one would exceed l_max), a difference below
-# QUAD_FLOOR is accepted even while it is still falling: no further order exists
-# to show the floor, and the difference already bounds the change at that level.
+# Rounding floor of the adaptive test.  This is NOT part of Section 4.1's rule,
+# which refines until ||q_l1 - q_l2|| < tol: it is an addition of this
+# implementation.  When the requested tolerance lies below what the node solves
+# can resolve, the relative differences of consecutive orders stop falling at
+# the rounding level of the node solves; an order whose difference is below
+# QUAD_FLOOR and larger than half the previous difference is then accepted
+# instead of refining up to l_max.  At the last order the sequence allows (the
+# next one would exceed l_max), a difference below QUAD_FLOOR is accepted even
+# while it is still falling: no further order exists to show the floor, and the
+# difference already bounds the change at that level.  Results accepted this
+# way report ``floor=True`` in their info and the accepted difference.
 QUAD_FLOOR = 1e-10
 
 
-def _adaptive(eval_rule, tol: float, l1: int, l2: int, lmax: int):
+def _adaptive(eval_rule, tol: float, l1: int, l2: int, lmax: int, stats: dict | None = None):
     """Adaptive order loop of Section 4.1 (relative test ||q1-q2|| <= tol ||q2||),
-    with the rounding-floor acceptance described at QUAD_FLOOR."""
+    with the rounding-floor acceptance described at QUAD_FLOOR.  ``stats``
+    receives the accepted difference and whether the floor accepted it."""
     q1 = eval_rule(l1)
     q2 = eval_rule(l2)
     d_prev = np.inf
+    st = stats if stats is not None else {}
     while True:
         n2 = np.linalg.norm(q2)
         d = np.linalg.norm(q1 - q2) / n2 if n2 > 0 else (0.0 if np.linalg.norm(q1) == 0 else np.inf)
-        if d <= tol or (d <= QUAD_FLOOR and d > 0.5 * d_prev):
+        st["quad_diff"] = d
+        st["floor"] = False
+        if d <= tol:
+            return q2, l2
+        if d <= QUAD_FLOOR and d > 0.5 * d_prev:
+            st["floor"] = True
             return q2, l2
         nxt = quad.next_order(l2)
         if nxt > lmax:
             if d <= QUAD_FLOOR:
+                st["floor"] = True
                 return q2, l2
             raise QuadratureError(f"no convergence up to l = {l2}")
         q1, l1, l2, d_prev = q2, l2, nxt, d
@@ -164,12 +233,14 @@ def sfom_quad(arn: ArnoldiResult, f: str = "invsqrt", tol: float = 1e-13,
     Gauss-Chebyshev rule."""
     if arn.m_used == 0:
         return _empty(arn)
+    full = arn
+    arn, mp = regularize(full)
     w = whiten(arn)
     m = w.M.shape[0]
     if f == "inv":
         g = np.linalg.solve(w.M, w.c)
-        y = sla.solve_triangular(w.R, g, lower=False)
-        return SolveResult(_assemble(arn, y), y, arn.m_used, 1)
+        y = _pad(sla.solve_triangular(w.R, g, lower=False), full.m_used)
+        return SolveResult(_assemble(full, y), y, mp, 1)
     if f != "invsqrt":
         raise ValueError("quadrature forms support the Stieltjes functions invsqrt and inv")
     check_branch(w.M)
@@ -182,9 +253,10 @@ def sfom_quad(arn: ArnoldiResult, f: str = "invsqrt", tol: float = 1e-13,
             acc += wi * np.linalg.solve(ti * np.eye(m) + w.M / sigma, w.c)
         return acc / np.sqrt(sigma)
 
-    g, l_used = _adaptive(rule, tol, l1, l2, lmax)
-    y = sla.solve_triangular(w.R, g, lower=False)
-    return SolveResult(_assemble(arn, y), y, arn.m_used, l_used, info=dict(sigma=sigma))
+    st = {}
+    g, l_used = _adaptive(rule, tol, l1, l2, lmax, st)
+    y = _pad(sla.solve_triangular(w.R, g, lower=False), full.m_used)
+    return SolveResult(_assemble(full, y), y, mp, l_used, info=dict(sigma=sigma, **st))
 
 
 def sgmres(arn: ArnoldiResult, f: str = "invsqrt", tol: float = 1e-13,
@@ -196,12 +268,14 @@ def sgmres(arn: ArnoldiResult, f: str = "invsqrt", tol: float = 1e-13,
     quadrature_rule)."""
     if arn.m_used == 0:
         return _empty(arn)
+    full = arn
+    arn, mp = regularize(full)
     w = whiten(arn)
     if f == "inv":
         # point mass at t = 0: the textbook sketched GMRES solution of A x = b
         g = np.linalg.lstsq(w.B, w.Sb, rcond=None)[0]
-        y = sla.solve_triangular(w.R, g, lower=False)
-        return SolveResult(_assemble(arn, y), y, arn.m_used, 1)
+        y = _pad(sla.solve_triangular(w.R, g, lower=False), full.m_used)
+        return SolveResult(_assemble(full, y), y, mp, 1)
     if f != "invsqrt":
         raise ValueError("sGMRES needs a Stieltjes function (invsqrt or inv)")
     sigma = spectral_scale(w.M)
@@ -213,9 +287,10 @@ def sgmres(arn: ArnoldiResult, f: str = "invsqrt", tol: float = 1e-13,
             acc += wi * np.linalg.lstsq(ti * w.Q + w.B / sigma, w.Sb, rcond=None)[0]
         return acc / np.sqrt(sigma)
 
-    g, l_used = _adaptive(rule, tol, l1, l2, lmax)
-    y = sla.solve_triangular(w.R, g, lower=False)
-    return SolveResult(_assemble(arn, y), y, arn.m_used, l_used, info=dict(sigma=sigma))
+    st = {}
+    g, l_used = _adaptive(rule, tol, l1, l2, lmax, st)
+    y = _pad(sla.solve_triangular(w.R, g, lower=False), full.m_used)
+    return SolveResult(_assemble(full, y), y, mp, l_used, info=dict(sigma=sigma, **st))
 
 
 # ---------------------------------------------- equivalent forms (pins) ---

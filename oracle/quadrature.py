@@ -31,7 +31,9 @@ import numpy as np
 
 L1_DEFAULT = 32
 L2_DEFAULT = 45
-LMAX_DEFAULT = 4096
+# Largest order tried: 1395 is the twelfth order of the sequence from (32, 45);
+# the next one, 1972, would double the cost of the last level again.
+LMAX_DEFAULT = 1395
 
 
 def next_order(l2: int) -> int:

@@ -281,3 +281,51 @@ def test_zero_rhs_gives_zero():
     A, _, S = small_problem()
     res, _ = methods.solve(A, np.zeros(A.shape[0]), "invsqrt", 5, 2, S)
     assert np.all(res.x == 0)
+
+
+def _sgmres_integrand_unwhitened(arn, Sb):
+    """u -> (2/pi) (u^2 SV + SAV)^+ S b: the integrand of eq. (sGMRES) before any
+    whitening, after t = u^2 (the measure t^(-1/2) dt / pi of z^(-1/2) becomes
+    (2/pi) du on [0, inf))."""
+    def g(u):
+        t = u * u
+        return (2.0 / np.pi) * np.linalg.lstsq(t * arn.SV + arn.SAV, Sb, rcond=None)[0]
+    return g
+
+
+@pytest.mark.parametrize("m,k", [(12, 2), (16, 3)])
+def test_sgmres_equals_adaptive_integral_of_definition(m, k):
+    """eq. (sGMRES) as printed, V_m int (t SV_m + SAV_m)^+ dmu(t) S b, integrated by
+    a general-purpose adaptive integrator (SciPy quad_vec, no Gauss-Chebyshev rule,
+    no whitening, no spectral scaling) equals the oracle's sGMRES.  A Galerkin
+    rule in place of the least-squares one differs at the 1e-3 level here."""
+    from scipy.integrate import quad_vec
+    A, b, S = small_problem()
+    arn = arn_mod.truncated_arnoldi(A, b, m, k, S)
+    Sb = S @ b
+    val, err = quad_vec(_sgmres_integrand_unwhitened(arn, Sb), 0.0, np.inf, epsabs=0.0, epsrel=1e-13,
+                        limit=2000)
+    x_def = arn.V @ val
+    x = methods.sgmres(arn, "invsqrt").x
+    assert rel(x, x_def) < 1e-10
+    # and it is not the sketched FOM approximant (the two differ on this problem)
+    assert rel(methods.sfom_closed(arn, "invsqrt").x, x_def) > 1e-6
+
+
+def test_sgmres_node_solutions_satisfy_normal_equations():
+    """Section 3: at every shift t the sGMRES coefficients minimise ||S b - (t SV + SAV) y||,
+    so the sketched residual is orthogonal to the columns of t SV + SAV.  The oracle's
+    node solve (whitened: (t Q + B)^+ S b mapped back by R^-1) is checked on its own
+    nodes against these normal equations in unwhitened coordinates."""
+    from oracle import quadrature as quad
+    A, b, S = small_problem()
+    arn = arn_mod.truncated_arnoldi(A, b, 14, 2, S)
+    w = methods.whiten(arn)
+    sig = methods.spectral_scale(w.M)
+    t, _ = quad.gauss_chebyshev_invsqrt(45)
+    for ti in t * sig:
+        u = np.linalg.lstsq(ti * w.Q + w.B, w.Sb, rcond=None)[0]
+        y = sla.solve_triangular(w.R, u, lower=False)
+        P = ti * arn.SV + arn.SAV
+        r = w.Sb - P @ y
+        assert np.linalg.norm(P.T @ r) <= 1e-9 * np.linalg.norm(P, 2) * np.linalg.norm(w.Sb)

@@ -88,3 +88,32 @@ def test_sketch_after_orthogonalisation_caught(monkeypatch):
         return r
     monkeypatch.setattr(arn_mod, "truncated_arnoldi", bad)
     _fails(tm.test_polynomial_exactness)
+
+
+def test_galerkin_rule_in_sgmres_caught(monkeypatch):
+    """sGMRES evaluated with the sketched Galerkin node solves (the sFOM integral)
+    instead of the least-squares ones of eq. (sGMRES)."""
+    def bad(arn, f="invsqrt", tol=1e-13, **kw):
+        if f == "inv":
+            return real(arn, f, tol, **kw)
+        return methods.sfom_quad(arn, f, tol, **kw)
+    real = methods.sgmres
+    monkeypatch.setattr(methods, "sgmres", bad)
+    _fails(tm.test_sgmres_equals_adaptive_integral_of_definition, 12, 2)
+
+
+def test_remedy_dropped_caught(monkeypatch):
+    """R^-1 taken literally for an extremely ill-conditioned R (no Section 2.1 remedy)."""
+    import test_oracle_remedy as tr
+    monkeypatch.setattr(methods, "regularize", lambda arn, cond_max=methods.COND_MAX: (arn, arn.m_used))
+    data = tr.conv2d_m300.__wrapped__()
+    _fails(tr.test_truncated_k2_equals_full_orthogonalisation, data, "exp", 0.01)
+
+
+def test_remedy_keeps_ill_conditioned_columns_caught(monkeypatch):
+    """A prefix rule that keeps far too many columns (threshold near 1/u)."""
+    import test_oracle_remedy as tr
+    real = methods.regularize
+    monkeypatch.setattr(methods, "regularize", lambda arn, cond_max=methods.COND_MAX: real(arn, 1e17))
+    data = tr.conv2d_m300.__wrapped__()
+    _fails(tr.test_truncated_k2_equals_full_orthogonalisation, data, "exp", 0.01)
