@@ -48,6 +48,12 @@ def parse():
     ap.add_argument("--test-problems", type=int, default=256, help="controller: held-out problems")
     ap.add_argument("--nprob", type=int, default=64, help="problems of the batched workload")
     ap.add_argument("--no-autotune", action="store_true", help="batched form: keep the default launch shape")
+    ap.add_argument("--save-outputs", default=None, metavar="NPZ",
+                    help="batched form: save every pair's status, m_used, ||x|| and x at a fixed sample of "
+                         "entries, for the offline oracle check (--check-outputs)")
+    ap.add_argument("--check-outputs", default=None, metavar="NPZ",
+                    help="CPU only: check the saved batched outputs against the oracle (right-hand side 0 of "
+                         "every problem and every pair with a nonzero status) and print the table")
     ap.add_argument("--tuning", default=None, metavar="BLOCK,SPW",
                     help="batched form: fixed launch shape (threads per block, slices per wavefront)")
     ap.add_argument("--f", default="invsqrt", choices=["invsqrt", "inv"])
@@ -56,7 +62,8 @@ def parse():
                     help="storage/arithmetic of A, the basis and the SpMV (small problem and assembly stay FP64)")
     ap.add_argument("--no-parity", action="store_true", help="skip the full-size oracle comparison")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-steps", type=int, default=30)
+    ap.add_argument("--cpu-solves", type=int, default=3,
+                    help="full oracle solves timed for cpu_baseline (median; the first also gives the parity)")
     ap.add_argument("--no-timing-events", action="store_true")
     ap.add_argument("--timing-stride", type=int, default=8,
                     help="single-problem workloads: HIP events bracket every n-th step-kernel (and assembly) launch "
@@ -138,56 +145,35 @@ def recorded_traffic(workload: str, prec: str, field: str = "traffic_bytes_per_l
     return int(fields[field])
 
 
-def cpu_baseline(cfg, arrays, b, sample_steps):
-    """Time the oracle as it stands on a bounded sample: `sample_steps` of the m
-    truncated-Arnoldi steps on the full operator (per-step time scaled to m), the
-    oracle small problem at full m and s (its cost does not depend on N) on the
-    same family's 64^3 grid, and the sketch construction."""
+def host_threads() -> int:
+    """CPU threads this process may use: its affinity set, capped by OMP_NUM_THREADS
+    when that is set (a GPU machine gives each GPU a share of its cores)."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    env = os.environ.get("OMP_NUM_THREADS")
+    if env and env.isdigit() and int(env) > 0:
+        n = min(n, int(env))
+    return max(1, n)
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_legs(cfg, arrays, b, x_gpu, f, method, reps):
+    """The oracle as it stands, on the same workload: `reps` full solves (sketch
+    construction, m truncated-Arnoldi steps, small problem, assembly) with the BLAS
+    pool at the host's thread share.  The first solve also gives the parity of the
+    GPU result.  Returns (parity error, cpu_baseline dict or None)."""
     import numpy as np
     import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
-
-    from oracle import arnoldi as oarn
-    from oracle import methods as ometh
-    from oracle import sketch as osk
-    from workloads import convdiff_csr, gaussian_rhs
-
-    rp, col, val = arrays
-    N = rp.size - 1
-    m, k, s, zeta = cfg["m"], cfg["k"], cfg["s"], cfg["zeta"]
-    with threadpool_limits(limits=1):
-        A = sp.csr_matrix((val, col, rp), shape=(N, N))
-        t0 = time.perf_counter()
-        S = osk.sparse_sign_matrix(N, s, zeta, cfg["sketch_seed"])
-        t_sketch = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        arn = oarn.truncated_arnoldi(A, b, sample_steps, k, S)
-        t_arn = time.perf_counter() - t0
-        t0 = time.perf_counter()
-        _ = arn.V @ np.ones(arn.m_used)
-        t_asm = time.perf_counter() - t0
-        # small problem at full m on a smaller operator of the same family
-        rp2, col2, val2 = convdiff_csr(64, cfg["dim"], cfg["diffusion"], cfg["convection"])
-        N2 = rp2.size - 1
-        A2 = sp.csr_matrix((val2, col2, rp2), shape=(N2, N2))
-        S2 = osk.sparse_sign_matrix(N2, s, zeta, 0)
-        arn2 = oarn.truncated_arnoldi(A2, gaussian_rhs(N2, 0), m, k, S2)
-        t0 = time.perf_counter()
-        w = ometh.whiten(arn2)
-        g = ometh.matfun_apply(w.M, w.c, "invsqrt")
-        _ = np.linalg.solve(w.R, g)
-        t_small = time.perf_counter() - t0
-    per_solve = t_sketch + t_arn / sample_steps * m + t_asm / sample_steps * m + t_small
-    sample = (f"oracle: sketch build + {sample_steps} of {m} truncated-Arnoldi steps on the full operator "
-              f"({t_arn:.1f} s, scaled to {m} steps) + assembly scaled likewise + small problem at m={m} "
-              f"({t_small:.2f} s, 64^3 grid); single thread")
-    return {"value": 1.0 / per_solve, "unit": "solves/s", "cores": 1, "kind": "oracle", "sample": sample,
-            "sec_per_solve": per_solve}
-
-
-def oracle_parity(cfg, arrays, b, x_gpu, f, method):
-    import numpy as np
-    import scipy.sparse as sp
 
     from oracle import arnoldi as oarn
     from oracle import methods as ometh
@@ -196,15 +182,37 @@ def oracle_parity(cfg, arrays, b, x_gpu, f, method):
     rp, col, val = arrays
     N = rp.size - 1
     A = sp.csr_matrix((val, col, rp), shape=(N, N))
-    S = osk.sparse_sign_matrix(N, cfg["s"], cfg["zeta"], cfg["sketch_seed"])
-    arn = oarn.truncated_arnoldi(A, b, cfg["m"], cfg["k"], S)
-    if method == "sfom":
-        xr = ometh.sfom_closed(arn, f).x
-    elif method == "sgmres":
-        xr = ometh.sgmres(arn, f, tol=1e-13).x
-    else:
-        xr = ometh.sfom_quad(arn, f, tol=1e-13).x
-    return float(np.linalg.norm(x_gpu - xr) / np.linalg.norm(xr))
+    threads = host_threads()
+    solve = {"sfom": lambda arn: ometh.sfom_closed(arn, f),
+             "sgmres": lambda arn: ometh.sgmres(arn, f, tol=1e-13),
+             "sfom_quad": lambda arn: ometh.sfom_quad(arn, f, tol=1e-13)}[method]
+    times, t_arn, err = [], [], None
+    with threadpool_limits(limits=threads):
+        for r in range(max(1, reps)):
+            t0 = time.perf_counter()
+            S = osk.sparse_sign_matrix(N, cfg["s"], cfg["zeta"], cfg["sketch_seed"])
+            t1 = time.perf_counter()
+            arn = oarn.truncated_arnoldi(A, b, cfg["m"], cfg["k"], S)
+            t2 = time.perf_counter()
+            xr = solve(arn).x
+            times.append(time.perf_counter() - t0)
+            t_arn.append(t2 - t1)
+            if r == 0:
+                err = float(np.linalg.norm(x_gpu - xr) / np.linalg.norm(xr))
+            print(f"# oracle solve {r + 1}/{reps}: {times[-1]:.1f} s", file=sys.stderr, flush=True)
+    if reps < 1:
+        return err, None
+    med = float(np.median(times))
+    nnz = int(rp[-1])
+    arn_bytes = cfg["m"] * step_kernel_bytes(N, nnz, cfg["k"])
+    cpu = {"value": round(1.0 / med, 5), "unit": "solves/s", "cores": threads, "kind": "oracle",
+           "sample": f"median of {len(times)} full oracle solves of this workload (sketch build, "
+                     f"{cfg['m']} truncated-Arnoldi steps, small problem, assembly); NumPy/SciPy BLAS pool "
+                     f"{threads} threads, scipy.sparse products single-threaded",
+           "sec_per_solve": [round(t, 2) for t in times],
+           "arnoldi_gbs": round(arn_bytes / float(np.median(t_arn)) / 1e9, 2),
+           "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+    return err, cpu
 
 
 def batch_step_bytes(Ns, nnzs, ms, R, k, prec):
@@ -286,6 +294,8 @@ def run_batched(args):
     asm_bytes = sum(R * (PREC_BYTES[args.prec][1] * N * m + 8 * N) for N, m in zip(Ns, ms)) * n_asm
     print(f"# timed {args.steps} batches in {elapsed:.3f} s; {len(bad)} pairs with a nonzero status {bad[:4]}",
           file=sys.stderr, flush=True)
+    if args.save_outputs:
+        save_batch_outputs(args.save_outputs, probs, info, R)
     # parity on a bounded sample: the two smallest problems, first right-hand side
     parity = None
     if not args.no_parity:
@@ -308,9 +318,11 @@ def run_batched(args):
                   "tol": 1e-10 if args.prec == "fp64" else None}
         print(f"# parity vs oracle (sample): {errs}", file=sys.stderr, flush=True)
     solves = len(probs) * R
+    ok = solves - len(bad)
     out = {
         "metric": "f(A)b solves/s and SpMV+sketch HBM GB/s at rel. err 1e-8 vs FP64 oracle",
-        "value": round(solves * args.steps / elapsed, 3),
+        # pairs that end with a nonzero status are not counted as solves
+        "value": round(ok * args.steps / elapsed, 3),
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
@@ -323,7 +335,8 @@ def run_batched(args):
         "data": "synthetic",
         "config": {"workload": f"batch{len(probs)}x{R}_convdiff2d_{args.f}_{args.method}"
                    + ("" if args.prec == "fp64" else f"_{args.prec}"),
-                   "problems": len(probs), "rhs_per_problem": R, "solves_per_step": solves,
+                   "problems": len(probs), "rhs_per_problem": R, "pairs_per_step": solves,
+                   "solves_per_step": ok,
                    "N_range": [min(Ns), max(Ns)], "N_sum": sum(Ns), "m_range": [min(ms), max(ms)], "k": 2,
                    "s": "2m", "zeta": 8, "prec": args.prec, "tuning": tuning,
                    "a_storage": sorted({storage_name(info[i][0].a_format) for i in range(len(probs))}),
@@ -339,8 +352,84 @@ def run_batched(args):
         "cpu_baseline": None,
         "parity": parity,
         "nonzero_status_pairs": len(bad),
+        "nonzero_status_list": [[int(i), int(r), int(st)] for i, r, st in bad],
     }
     print(json.dumps(out), flush=True)
+
+
+SAMPLE_ENTRIES = 4096
+
+
+def sample_index(N: int):
+    """Fixed entries of a result kept by --save-outputs: evenly spaced over 0..N-1."""
+    import numpy as np
+    return np.unique(np.linspace(0, N - 1, SAMPLE_ENTRIES).astype(np.int64))
+
+
+def save_batch_outputs(path, probs, info, R):
+    import numpy as np
+    rows = []
+    for i, q in enumerate(probs):
+        idx = sample_index(q.A.n)
+        X = q.X.cpu().numpy()
+        for r in range(R):
+            rows.append((i, r, info[i][r].status, info[i][r].m_used, info[i][r].flags,
+                         float(np.linalg.norm(X[r])), X[r][idx]))
+    np.savez_compressed(path, prob=np.array([r[0] for r in rows]), rhs=np.array([r[1] for r in rows]),
+                        status=np.array([r[2] for r in rows]), m_used=np.array([r[3] for r in rows]),
+                        flags=np.array([r[4] for r in rows]), xnorm=np.array([r[5] for r in rows]),
+                        xs=np.array([np.pad(r[6], (0, SAMPLE_ENTRIES - r[6].size)) for r in rows]))
+    print(f"# saved {len(rows)} pair outputs to {path}", file=sys.stderr, flush=True)
+
+
+def check_batch_outputs(path, nprob):
+    """Oracle check of saved batched outputs (CPU): right-hand side 0 of every
+    problem, and every pair with a nonzero status, through the oracle's own run of
+    the same pair.  A pair the GPU solved is compared on the sampled entries and on
+    ||x||; a pair the GPU refused is classified by what the oracle does with it."""
+    import numpy as np
+    import scipy.sparse as sp
+
+    from oracle import arnoldi as oarn
+    from oracle import methods as ometh
+    from oracle import sketch as osk
+    from workloads import batched_problem_params, convdiff_csr
+
+    d = np.load(path)
+    params = batched_problem_params(nprob)
+    pairs = {(int(p), int(r)): k for k, (p, r) in enumerate(zip(d["prob"], d["rhs"]))}
+    todo = sorted({(p, 0) for p in range(nprob)} | {pr for pr, k in pairs.items() if d["status"][k] != 0})
+    rows = []
+    worst = 0.0
+    for (pi, r) in todo:
+        k = pairs[(pi, r)]
+        q = params[pi]
+        rp, col, val = convdiff_csr(q["n"], 2, 1.0, q["c"])
+        N = rp.size - 1
+        A = sp.csr_matrix((val, col, rp), shape=(N, N))
+        b = np.random.default_rng(q["rhs_seedseq"]).standard_normal((4, N))[r]
+        S = osk.sparse_sign_matrix(N, q["s"], 8, q["sketch_seed"])
+        arn = oarn.truncated_arnoldi(A, b, q["m"], 2, S)
+        try:
+            res = ometh.sfom_closed(arn, "invsqrt")
+            verdict, x = "ok", res.x
+        except ometh.BranchError:
+            verdict, x = "branch", None
+        gst = int(d["status"][k])
+        if x is not None and gst == 0:
+            idx = sample_index(N)
+            xs = d["xs"][k][: idx.size]
+            e = float(np.linalg.norm(xs - x[idx]) / np.linalg.norm(x[idx]))
+            en = abs(float(d["xnorm"][k]) - np.linalg.norm(x)) / np.linalg.norm(x)
+            worst = max(worst, e, en)
+            rows.append((pi, r, N, q["m"], gst, verdict, f"{e:.2e}", f"{en:.2e}", int(d["m_used"][k]), res.m_used))
+        else:
+            rows.append((pi, r, N, q["m"], gst, verdict, "-", "-", int(d["m_used"][k]),
+                         res.m_used if x is not None else "-"))
+        print(" ".join(str(v) for v in rows[-1]), flush=True)
+    agree = sum(1 for row in rows if (row[4] == 0) == (row[5] == "ok"))
+    print(json.dumps({"checked_pairs": len(rows), "status_agrees_with_oracle": agree,
+                      "max_rel_err_sampled": worst}), flush=True)
 
 
 def run_controller(args):
@@ -380,7 +469,7 @@ def run_controller(args):
     for i, spec in enumerate(ctl.random_specs(args.test_problems, seed=12)):
         A, b = spec.build()
         _, ip, mp, ep, sp_ = runner.adaptive(A, b, 2, 2, 10, ctl.M_CAP, tol)
-        _, ic, mc, ec, sc, fb = ctl.controlled_solve(runner, model, spec, A, b, tol)
+        _, ic, mc, ec, sc, fb, _ = ctl.controlled_solve(runner, model, spec, A, b, tol)
         rows.append((ip.status == 0 and ep <= tol, ic.status == 0 and ec <= tol, sp_, sc, mp, mc, fb))
         if (i + 1) % 64 == 0:
             print(f"# evaluated {i + 1} held-out problems", file=sys.stderr, flush=True)
@@ -414,6 +503,9 @@ def run_controller(args):
 
 def main():
     args = parse()
+    if args.check_outputs:
+        check_batch_outputs(args.check_outputs, args.nprob)
+        return
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
         return
@@ -490,16 +582,13 @@ def main():
           f"relres={info.arnoldi_relres:.2e}", file=sys.stderr, flush=True)
 
     parity = None
-    if not args.no_parity:
-        t = time.perf_counter()
-        err = oracle_parity(cfg, (rp, col, val), b, x_host, args.f, args.method)
-        parity = {"rel_err_vs_oracle": err, "tol": 1e-10 if args.prec == "fp64" else None, "oracle_seconds": round(time.perf_counter() - t, 1)}
-        print(f"# parity vs oracle: {err:.3e}", file=sys.stderr, flush=True)
     cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(cfg, (rp, col, val), b, args.cpu_sample_steps)
-        print(f"# cpu baseline: {cpu['sec_per_solve']:.1f} s/solve", file=sys.stderr, flush=True)
-        cpu.pop("sec_per_solve")
+    if not (args.no_parity and args.no_cpu_baseline):
+        reps = 0 if args.no_cpu_baseline else args.cpu_solves
+        err, cpu = oracle_legs(cfg, (rp, col, val), b, x_host, args.f, args.method, reps)
+        if not args.no_parity:
+            parity = {"rel_err_vs_oracle": err, "tol": 1e-10 if args.prec == "fp64" else None}
+            print(f"# parity vs oracle: {err:.3e}", file=sys.stderr, flush=True)
 
     value = args.steps / elapsed
     out = {

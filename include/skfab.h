@@ -49,7 +49,8 @@ typedef enum skfab_status {
     SKFAB_OK = 0,
     SKFAB_ERR_ARG = 1,      /* null pointer, unsupported option, bad enum value          */
     SKFAB_ERR_SHAPE = 2,    /* violates 1 <= k <= min(m, 8), m < s <= N, zeta <= s ...   */
-    SKFAB_ERR_RANK = 3,     /* R_m of SV_m = Q_m R_m numerically singular (Section 2.1)  */
+    SKFAB_ERR_RANK = 3,     /* sketched basis numerically singular from its first column,
+                               or the projected matrix singular (Section 2.1)           */
     SKFAB_ERR_BRANCH = 4,   /* projected matrix has det < 0: an eigenvalue on the branch
                                cut of z^(-1/2) (Section 2.3, sketched Ritz values)       */
     SKFAB_ERR_QUAD = 5,     /* adaptive quadrature did not converge by lmax (Section 4.1) */
@@ -61,15 +62,18 @@ typedef enum skfab_status {
  * every method; EXP and POLY are evaluated in closed form (SFOM_CLOSED only). */
 typedef enum skfab_fun {
     SKFAB_F_INVSQRT = 0,    /* z^(-1/2), principal branch                            */
-    SKFAB_F_EXP = 1,        /* exp(-fparam * z)  (rejected with SKFAB_ERR_ARG until the
-                               closed-form exponential kernel is available)           */
+    SKFAB_F_EXP = 1,        /* exp(-fparam * z), fparam >= 0: Pade [13/13] scaling and
+                               squaring of the projected matrix (SFOM_CLOSED only)    */
     SKFAB_F_INV = 2,        /* 1/z (test function)                                   */
     SKFAB_F_POLY = 3        /* sum_i poly[i] z^i, npoly coefficients (test function)  */
 } skfab_fun;
 
 typedef enum skfab_method {
-    SKFAB_SFOM_CLOSED = 0,  /* Algorithm 1, closed form (sFOM'''): f(M) evaluated to
-                               near machine precision                              */
+    SKFAB_SFOM_CLOSED = 0,  /* Algorithm 1, closed form (sFOM'''): exp by Pade [13/13],
+                               1/z and polynomials directly, z^(-1/2) by the adaptive
+                               quadrature of Section 4.1 at tol 1e-13 (accepted at the
+                               rounding floor 1e-10 when 1e-13 is out of reach of the
+                               node solves: info.flags bit 1, info.quad_diff)       */
     SKFAB_SFOM_QUAD = 1,    /* (sFOM) integral form, adaptive quadrature, quad_tol   */
     SKFAB_SGMRES_QUAD = 2   /* Algorithm 2, (sGMRES), adaptive quadrature, quad_tol   */
 } skfab_method;
@@ -118,7 +122,21 @@ typedef struct skfab_params {
     int32_t lmax;           /* largest quadrature order tried (default 1395)         */
     double quad_tol;        /* relative tolerance of the quadrature test (Section 4.1) */
     int32_t prec;           /* skfab_prec                                            */
+    double cond_max;        /* largest kappa_F(R_j) = ||R_j||_F ||R_j^-1||_F of the basis
+                               prefix the approximant is formed from (Section 2.1 remedy
+                               for an extremely ill-conditioned R, see skfab_solve);
+                               0 = the default of the precision (SKFAB_COND_MAX_FP64,
+                               SKFAB_COND_MAX_FP32, SKFAB_COND_MAX_BF16); else >= 1   */
 } skfab_params;
+
+/* Default cond_max per precision.  FP64: rounding of the whitened problem stays near
+ * u kappa <= 1e-6.  A basis stored with unit roundoff u_p cannot hold directions below
+ * u_p of the rest: kappa of its sketch levels off near 1e2..1e3 / u_p even where the
+ * exact basis is dependent, so the reduced precisions stop at 4 / u_p, below that
+ * level (u_p = 2^-24 for FP32, 2^-8 for bfloat16). */
+#define SKFAB_COND_MAX_FP64 1e10
+#define SKFAB_COND_MAX_FP32 67108864.0
+#define SKFAB_COND_MAX_BF16 1024.0
 
 /* Filled by synchronising calls (host struct). */
 typedef struct skfab_info {
@@ -133,12 +151,25 @@ typedef struct skfab_info {
                                values (at most 256 of them, 0.0 counted; see
                                skfab_set_value_table)                                */
     double eps_est;         /* max_j | ||S v_j||^2 - 1 |  (Section 4.3 monitor)        */
-    double rcond_R;         /* min|R_jj| / max|R_jj| of the whitening factor         */
+    double rcond_R;         /* 1 / kappa_F(R), R the whitening factor used (kappa_F =
+                               ||R||_F ||R^-1||_F)                                     */
     double sigma;           /* spectral scale used by the quadrature                 */
     double beta;            /* ||b||_2                                               */
     double arnoldi_relres;  /* ||S A V_m - [S V_m, S u_{m+1}] Hbar||_F / ||S A V_m||_F: the
                                Arnoldi relation checked in the sketched space          */
+    double quad_diff;       /* relative difference ||q_l1 - q_l2|| / ||q_l2|| (whitened
+                               coordinates) at the accepted quadrature order; 0 without
+                               quadrature                                              */
+    int32_t flags;          /* bit 0 (SKFAB_FLAG_TRUNCATED): the basis was cut to its
+                               conditioned prefix (Section 2.1 remedy, see skfab_solve);
+                               bit 1 (SKFAB_FLAG_QUAD_FLOOR): the quadrature order was
+                               accepted at the rounding floor, quad_diff > tol          */
+    int32_t m_basis;        /* basis length built (m, or less after a breakdown); m_used
+                               is smaller when the remedy cut the basis               */
 } skfab_info;
+
+#define SKFAB_FLAG_TRUNCATED 1
+#define SKFAB_FLAG_QUAD_FLOOR 2
 
 typedef struct skfab_ctx skfab_ctx;
 
@@ -159,25 +190,40 @@ skfab_status skfab_set_stream(skfab_ctx *ctx, void *hip_stream);
 /* Destroy a context (does not synchronise; NULL is accepted). */
 skfab_status skfab_destroy(skfab_ctx *ctx);
 
-/* Bytes of device workspace skfab_solve / skfab_arnoldi need for this problem
- * (host computation, no device work).  Errors: SKFAB_ERR_ARG, SKFAB_ERR_SHAPE. */
-skfab_status skfab_workspace_bytes(const skfab_csr *A, const skfab_params *p,
+/* Bytes of device workspace skfab_solve (with nrhs right-hand sides) and
+ * skfab_arnoldi need for this problem (host computation, no device work).
+ * Errors: SKFAB_ERR_ARG (nrhs < 1, null pointers), SKFAB_ERR_SHAPE. */
+skfab_status skfab_workspace_bytes(const skfab_csr *A, const skfab_params *p, int32_t nrhs,
                                    size_t *bytes);
 
-/* x <- approximation of f(A) b (Algorithm 1 for SFOM_*, Algorithm 2 for SGMRES).
- *   b, x     device vectors of length N (may not alias)
- *   ws       device workspace of at least skfab_workspace_bytes bytes, 256-byte aligned
- *   info     optional host struct; if non-NULL the call synchronises the stream and
- *            returns the device-detected status in info->status
+/* X[:, r] <- approximation of f(A) B[:, r], r < nrhs (Algorithm 1 for SFOM_*,
+ * Algorithm 2 for SGMRES).
+ *   b, ldb   device, N x nrhs column-major, column r at b + r ldb (ldb >= N when
+ *            nrhs > 1; ignored for nrhs = 1)
+ *   x, ldx   device, N x nrhs column-major, column r at x + r ldx; may not alias b
+ *   ws       device workspace of at least skfab_workspace_bytes(A, p, nrhs) bytes,
+ *            256-byte aligned
+ *   info     optional host array of nrhs structs; if non-NULL the call synchronises
+ *            the stream and returns the device-detected status of column r in
+ *            info[r].status
  * Steps (all on the device): draw S (implicit, hashed), k-truncated Arnoldi with the
- * sketches S v_j and S A v_j formed on the fly, whitening QR of [SV_m | SAV_m], the
- * projected matrix M = Q^T SAV R^-1, f(M) c or the quadrature of Section 4.1, the
- * coefficients y = R^-1 (...), and the assembly x = V_m y.
+ * sketches S v_j and S A v_j formed on the fly and the extension vector u_{m+1},
+ * Householder QR of the extended sketch [S V_m, S u_{m+1}] = Q_e R_e, the projected
+ * problem from the Arnoldi relation (Hessenberg pencil t R + R_e Hbar; for sFOM the
+ * matrix H_m + (R^-1 r) e_m^T of the Section 2.2 remark, similar to Q^T SAV R^-1),
+ * f of it or the quadrature of Section 4.1, and the assembly x = V_m y.
+ * Extremely ill-conditioned R (the remark after eq. sFOM''' of Section 2.1): the
+ * numerical pseudoinverse used is the truncated QR one in basis order, i.e. the
+ * approximant is formed from the longest prefix V_j of the basis whose sketch has
+ * ||R_j||_F ||R_j^-1||_F <= p->cond_max (info.m_used = j < info.m_basis, flags bit 0).
+ * nrhs > 1: for f = z^(-1/2) or 1/z with zeta = 8, k <= 4 and nrhs <= 4 the columns
+ * are solved together by the batched form (one step launch per j serves every column,
+ * same S for all); otherwise they are solved one after another in the workspace.
  * b = 0 gives x = 0.  Lucky breakdown (Section 4: division by ||w||) stops the
- * recurrence early; info->m_used reports the dimension used. */
-skfab_status skfab_solve(skfab_ctx *ctx, const skfab_csr *A, const double *b, double *x,
-                         const skfab_params *p, void *ws, size_t ws_bytes,
-                         skfab_info *info);
+ * recurrence early; info.m_used reports the dimension used. */
+skfab_status skfab_solve(skfab_ctx *ctx, const skfab_csr *A, const double *b, int64_t ldb,
+                         int32_t nrhs, double *x, int64_t ldx, const skfab_params *p,
+                         void *ws, size_t ws_bytes, skfab_info *info);
 
 /* Test hook: run only the k-truncated Arnoldi recurrence with sketches
  * (Algorithm 2, basis part) and export its state.
@@ -209,7 +255,9 @@ skfab_status skfab_small_problem(skfab_ctx *ctx, const double *SVext, const doub
 /* Workspace bytes for skfab_small_problem alone. */
 skfab_status skfab_small_workspace_bytes(const skfab_params *p, size_t *bytes);
 
-/* Test hook: the sparse-sign sketch pattern of columns [col0, col0 + ncols).
+/* Test hook: the sparse-sign sketch pattern of columns [col0, col0 + ncols): the
+ * s x N subspace embedding S of Section 1, eq. (sketch) (an epsilon-embedding of the
+ * Krylov space with high probability), drawn as a sparse sign matrix.
  * rows  device int32 [ncols * zeta]: rows[i*zeta + q] is the row of entry q of
  *       column col0 + i;  signs device int8 [ncols * zeta], +1 or -1.
  * Definition (implemented independently of the CPU reference): SplitMix64
@@ -221,7 +269,8 @@ skfab_status skfab_small_workspace_bytes(const skfab_params *p, size_t *bytes);
 skfab_status skfab_sketch_pattern(skfab_ctx *ctx, int64_t col0, int64_t ncols, int32_t s,
                                   int32_t zeta, uint64_t seed, int32_t *rows, int8_t *signs);
 
-/* Test hook: Sv <- S v for a device vector v of length n (Sv device, length s).
+/* Test hook: Sv <- S v for a device vector v of length n (Sv device, length s), the
+ * sketch of Section 1, eq. (sketch), with the pattern of skfab_sketch_pattern.
  * Deterministic (fixed reduction order).  Uses `ws` for per-block partial sums
  * (at least skfab_sketch_ws_bytes(n, s) bytes). */
 skfab_status skfab_sketch_apply(skfab_ctx *ctx, int64_t n, int32_t s, int32_t zeta,
@@ -264,11 +313,13 @@ skfab_status skfab_timing_read(skfab_ctx *ctx, int32_t kernel, double *total_ms,
  * right-hand sides of one problem share its sketch S and its copy of A). */
 typedef struct skfab_batch_problem {
     skfab_csr A;            /* device CSR, FP64 values                               */
-    const double *B;        /* device, N x nrhs column-major (column r at B + r N)   */
-    double *X;              /* device, N x nrhs column-major: the results            */
+    const double *B;        /* device, N x nrhs column-major (column r at B + r ldb) */
+    double *X;              /* device, N x nrhs column-major: the results (column r at
+                               X + r ldx)                                            */
     int32_t m;              /* Krylov dimension of this problem, 1 <= m <= 512       */
     int32_t s;              /* sketch size, m < s <= min(N, 1024)                    */
     uint64_t seed;          /* seed of this problem's sketch S                       */
+    int64_t ldb, ldx;       /* leading dimensions of B and X (0 = N; otherwise >= N)  */
 } skfab_batch_problem;
 
 /* Launch shape of the batched step kernel: threads per block (256, 512, 1024) and

@@ -62,7 +62,7 @@ class Whitened:
 # from the longest prefix V_j whose sketch has a Frobenius-norm condition number
 # ||R_j||_F ||R_j^-1||_F of at most COND_MAX.  A basis that meets the bound is
 # used whole, so the remedy changes nothing for well-conditioned problems.
-COND_MAX = 1e12
+COND_MAX = 1e10
 
 
 def prefix_conditions(R: np.ndarray) -> np.ndarray:

@@ -18,6 +18,7 @@ SKFAB_F_INVSQRT, SKFAB_F_EXP, SKFAB_F_INV, SKFAB_F_POLY = range(4)
 SKFAB_SFOM_CLOSED, SKFAB_SFOM_QUAD, SKFAB_SGMRES_QUAD = range(3)
 SKFAB_PREC_FP64, SKFAB_PREC_FP32, SKFAB_PREC_FP32_BF16BASIS = range(3)
 SKFAB_VAL_F64 = 0
+SKFAB_FLAG_TRUNCATED, SKFAB_FLAG_QUAD_FLOOR = 1, 2
 
 EXPORTED = [
     "skfab_version", "skfab_status_string", "skfab_create", "skfab_set_stream", "skfab_destroy",
@@ -40,18 +41,20 @@ class skfab_params(C.Structure):
     _fields_ = [("f", C.c_int32), ("fparam", C.c_double), ("poly", C.POINTER(C.c_double)),
                 ("npoly", C.c_int32), ("method", C.c_int32), ("m", C.c_int32), ("k", C.c_int32),
                 ("s", C.c_int32), ("zeta", C.c_int32), ("seed", C.c_uint64), ("l1", C.c_int32),
-                ("l2", C.c_int32), ("lmax", C.c_int32), ("quad_tol", C.c_double), ("prec", C.c_int32)]
+                ("l2", C.c_int32), ("lmax", C.c_int32), ("quad_tol", C.c_double), ("prec", C.c_int32),
+                ("cond_max", C.c_double)]
 
 
 class skfab_info(C.Structure):
     _fields_ = [("status", C.c_int32), ("m_used", C.c_int32), ("l_used", C.c_int32),
                 ("a_format", C.c_int32), ("eps_est", C.c_double), ("rcond_R", C.c_double),
-                ("sigma", C.c_double), ("beta", C.c_double), ("arnoldi_relres", C.c_double)]
+                ("sigma", C.c_double), ("beta", C.c_double), ("arnoldi_relres", C.c_double),
+                ("quad_diff", C.c_double), ("flags", C.c_int32), ("m_basis", C.c_int32)]
 
 
 class skfab_batch_problem(C.Structure):
     _fields_ = [("A", skfab_csr), ("B", C.c_void_p), ("X", C.c_void_p), ("m", C.c_int32), ("s", C.c_int32),
-                ("seed", C.c_uint64)]
+                ("seed", C.c_uint64), ("ldb", C.c_int64), ("ldx", C.c_int64)]
 
 
 class skfab_batch_tuning(C.Structure):
@@ -77,9 +80,10 @@ def lib():
         "skfab_create": (C.c_int, [C.POINTER(P), C.c_int32, P]),
         "skfab_set_stream": (C.c_int, [P, P]),
         "skfab_destroy": (C.c_int, [P]),
-        "skfab_workspace_bytes": (C.c_int, [C.POINTER(skfab_csr), C.POINTER(skfab_params), C.POINTER(C.c_size_t)]),
-        "skfab_solve": (C.c_int, [P, C.POINTER(skfab_csr), P, P, C.POINTER(skfab_params), P, C.c_size_t,
-                                  C.POINTER(skfab_info)]),
+        "skfab_workspace_bytes": (C.c_int, [C.POINTER(skfab_csr), C.POINTER(skfab_params), C.c_int32,
+                                             C.POINTER(C.c_size_t)]),
+        "skfab_solve": (C.c_int, [P, C.POINTER(skfab_csr), P, C.c_int64, C.c_int32, P, C.c_int64,
+                                  C.POINTER(skfab_params), P, C.c_size_t, C.POINTER(skfab_info)]),
         "skfab_arnoldi": (C.c_int, [P, C.POINTER(skfab_csr), P, C.POINTER(skfab_params), P, P, P, P, P,
                                     C.c_size_t, C.POINTER(skfab_info)]),
         "skfab_small_problem": (C.c_int, [P, P, P, C.c_double, C.POINTER(skfab_params), P, P, C.c_size_t,

@@ -205,19 +205,28 @@ def predict(runner: Runner, model: Model, feats: np.ndarray):
     return out
 
 
+def checkpoints(m0: int, m_stop: int, d: int = CHECK_D) -> int:
+    """Small problems an adaptive run from m0 evaluates before stopping at m_stop."""
+    return max(0, (m_stop - m0) // d) + 1
+
+
 def controlled_solve(runner: Runner, model: Model, spec: ProblemSpec, A, b, tol: float, feats=None):
     """Solve with the predicted configuration: checks at m_pred - d and m_pred,
     continuing every d steps up to m_pred + 6 d; a full plain adaptive-m run if
-    that does not pass.  Returns (x, info, m_stop, estimate, seconds, fallback)."""
+    that does not pass.  Returns (x, info, m_stop, estimate, seconds, fallback,
+    checks), checks = small problems evaluated (both runs on a fallback)."""
     t0 = time.perf_counter()
     if feats is None:
         feats = runner.features(spec, A, b)
     m, k, sf = predict(runner, model, feats)[0]
     m_max = min(M_CAP, m + 6 * CHECK_D)
-    x, info, m_stop, est, _ = runner.adaptive(A, b, k, sf, max(k, m - CHECK_D), m_max, tol)
+    m0 = max(k, m - CHECK_D)
+    x, info, m_stop, est, _ = runner.adaptive(A, b, k, sf, m0, m_max, tol)
+    checks = checkpoints(m0, m_stop)
     fallback = False
     if info.status != 0 or not (est <= tol):
         fallback = True
         x, info, m_stop, est, _ = runner.adaptive(A, b, 2, 2, 10, M_CAP, tol)
+        checks += checkpoints(10, m_stop)
     torch.cuda.synchronize()
-    return x, info, m_stop, est, time.perf_counter() - t0, fallback
+    return x, info, m_stop, est, time.perf_counter() - t0, fallback, checks

@@ -32,6 +32,9 @@ int sketch_apply_blocks(int64_t n);
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st);
 hipError_t launch_init_ctrl(DevCtrl* c, int m, hipStream_t st);
 hipError_t launch_qr(double* X, int s, int ncols_max, const DevCtrl* ctrl, double* Tws, hipStream_t st);
+hipError_t launch_cond_trunc(double* X, int s, int m, DevCtrl* ctrl, const double* H, double* cnd, double cmax,
+                             hipStream_t st);
+hipError_t launch_cond_trunc_batched(const SmallUnit* units, int nunits, int s, int m, double cmax, hipStream_t st);
 // launch rule of the step kernel (arnoldi.hip)
 int step_block_fit(int block, int s);
 Launch step_launch(int64_t N, int s, int k);
@@ -55,6 +58,8 @@ hipError_t launch_finish_coeffs(DevCtrl* ctrl, int m, const double* y, const dou
                                 double* ys, double* yout, hipStream_t st);
 hipError_t launch_assemble(const void* U, int64_t ldU, int64_t N, int m, const DevCtrl* ctrl, const double* ys,
                            double* x, int prec, hipStream_t st);
+hipError_t launch_norm1(const DevCtrl* ctrl, int m, const double* const* P, int count, double* norm1,
+                        hipStream_t st);
 hipError_t launch_hhat(const DevCtrl* ctrl, int m, const double* T1r, const double* X, int s, const double* H,
                        double tau, double* Ahat, double* norm1, hipStream_t st);
 hipError_t launch_combine(const DevCtrl* ctrl, int m, double a, const double* P, double b, const double* Q,
@@ -183,7 +188,7 @@ int next_order(int l) {
 
 struct Layout {
     size_t ctrl, eta, wnorm, H, gram, colnorm2, scal, U, W, skpart, SV, SAV, Tws, K0r, T1r, Hh, Ubuf, Urhs, nodebuf,
-        qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, chk, sl_len, sl_ptr, bsum, sl_col, sl_val, dict, total;
+        qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, chk, cnd, sl_len, sl_ptr, bsum, sl_col, sl_val, dict, total;
     int64_t ldU;
     int64_t sell_capacity;
     int lnodes;
@@ -266,6 +271,7 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
     ly.sl_val = with_basis ? take((size_t)ly.sell_capacity * wbytes(prec)) : take(0);
     ly.dict = with_basis ? take(sizeof(DictBuf)) : take(0);
     ly.chk = take((size_t)2 * m * d);
+    ly.cnd = take((size_t)2 * (m + 1) * d);
     ly.SV = take((size_t)s * (m + 1) * d);
     ly.SAV = take((size_t)s * m * d);
     ly.Tws = take((size_t)QR_NB_HOST * QR_NB_HOST * d);
@@ -283,7 +289,7 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
     ly.poly = take((size_t)(npoly > 0 ? npoly : 1) * d);
     ly.expbuf = take((size_t)EXP_BUFS * m * m * d);
     ly.piv = take((size_t)m * sizeof(int));
-    ly.norm1 = take(d);
+    ly.norm1 = take(6 * d);
     ly.total = off;
     return ly;
 }
@@ -292,7 +298,7 @@ struct Ptrs {
     DevCtrl* ctrl;
     void *U, *W;
     double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Hh, *Ubuf, *Urhs,
-        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1, *chk;
+        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1, *chk, *cnd;
     void* sl_val;
     DictBuf* dict;
     int* piv;
@@ -313,6 +319,7 @@ Ptrs carve(void* ws, const Layout& ly) {
     p.y0 = D(ly.y0); p.poly = D(ly.poly); p.expbuf = D(ly.expbuf); p.norm1 = D(ly.norm1);
     p.piv = reinterpret_cast<int*>(b + ly.piv);
     p.chk = D(ly.chk);
+    p.cnd = D(ly.cnd);
     p.sl_val = b + ly.sl_val;
     p.dict = reinterpret_cast<DictBuf*>(b + ly.dict);
     p.sl_len = reinterpret_cast<int32_t*>(b + ly.sl_len);
@@ -331,6 +338,14 @@ void defaults(const skfab_params* p, int* l1, int* l2, int* lmax, double* tol) {
 
 bool zeta_ok(int z) { return z == 2 || z == 4 || z == 8 || z == 16; }
 
+// Largest kappa_F of the basis prefix used (Section 2.1 remedy): the caller's, or the
+// precision's default.
+double cond_max_of(const skfab_params* p) {
+    if (p->cond_max > 0.0) return p->cond_max;
+    return p->prec == SKFAB_PREC_FP64 ? SKFAB_COND_MAX_FP64
+                                      : (p->prec == SKFAB_PREC_FP32 ? SKFAB_COND_MAX_FP32 : SKFAB_COND_MAX_BF16);
+}
+
 skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matrix) {
     if (!p) return SKFAB_ERR_ARG;
     if (need_matrix) {
@@ -340,6 +355,7 @@ skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matri
     }
     if (p->f < 0 || p->f > 3 || p->method < 0 || p->method > 2) return SKFAB_ERR_ARG;
     if (p->prec < SKFAB_PREC_FP64 || p->prec > SKFAB_PREC_FP32_BF16BASIS) return SKFAB_ERR_ARG;
+    if (!(p->cond_max == 0.0 || p->cond_max >= 1.0)) return SKFAB_ERR_ARG;
     // reduced precisions are built for the default sketch density and k <= 4
     if (p->prec != SKFAB_PREC_FP64 && (p->zeta != 8 || p->k > 4)) return SKFAB_ERR_ARG;
     if (p->m < 1 || p->m > MMAX) return SKFAB_ERR_SHAPE;
@@ -455,31 +471,50 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
     return arnoldi_tail(a, p, ly, w, st);
 }
 
-// y0 = exp(-tau H_hat) beta e_1 by [13/13] Pade scaling and squaring.  Reads ||A||_1
-// back to the host once to choose the number of squarings.
+// y0 = exp(-tau H_hat) beta e_1 by [13/13] Pade scaling and squaring.  The powers
+// A^2 .. A^6 are formed unscaled; their 1-norms come back to the host once and
+// choose the number of squarings s from alpha(A) (see csrc/expm.hip); the powers
+// are then scaled by 2^(-p s), exactly (powers of two).
 skfab_status run_expm(const skfab_params* p, const Ptrs& w, hipStream_t st) {
     const int m = p->m, s = p->s;
     double* B[EXP_BUFS];
     for (int i = 0; i < EXP_BUFS; ++i) B[i] = w.expbuf + (size_t)i * m * m;
     double *A = B[0], *A2 = B[1], *A4 = B[2], *A6 = B[3], *T = B[4], *W1 = B[5], *U = B[6], *V = B[7], *Q = B[8],
            *X2 = B[9];
-    HIP_TRY(launch_fill(w.norm1, 1, 0.0, st));
+    HIP_TRY(launch_fill(w.norm1, 6, 0.0, st));
     HIP_TRY(launch_fill(w.y0, m, 0.0, st));
     HIP_TRY(launch_hhat(w.ctrl, m, w.T1r, w.SV, s, w.H, p->fparam, A, w.norm1, st));
-    double nrm = 0.0;
-    HIP_TRY(hipMemcpyAsync(&nrm, w.norm1, sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(launch_dgemm(w.ctrl, m, A, A, 0.0, A2, st));
+    HIP_TRY(launch_dgemm(w.ctrl, m, A, A2, 0.0, T, st));    // A^3
+    HIP_TRY(launch_dgemm(w.ctrl, m, A2, A2, 0.0, A4, st));
+    HIP_TRY(launch_dgemm(w.ctrl, m, A, A4, 0.0, W1, st));   // A^5
+    HIP_TRY(launch_dgemm(w.ctrl, m, A4, A2, 0.0, A6, st));
+    {
+        const double* P[5] = {A2, T, A4, W1, A6};
+        HIP_TRY(launch_norm1(w.ctrl, m, P, 5, w.norm1 + 1, st));
+    }
+    double nrm[6] = {0, 0, 0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(nrm, w.norm1, sizeof(nrm), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    for (int q = 0; q < 6; ++q)
+        if (!std::isfinite(nrm[q])) return SKFAB_OK;  // m_used == 0 or overflow: y0 stays as initialised
+    // d_k = ||A^k||^(1/k); alpha = min over p = 1..5 of max(d_p, d_{p+1})
+    double d[7];
+    for (int k = 1; k <= 6; ++k) d[k] = std::pow(nrm[k - 1], 1.0 / k);
+    double alpha = INFINITY;
+    for (int q = 1; q <= 5; ++q) alpha = std::min(alpha, std::max(d[q], d[q + 1]));
     const double theta13 = 5.371920351148152;  // Higham (2005), Table 2.3
     int sq = 0;
-    if (std::isfinite(nrm) && nrm > theta13) sq = (int)std::ceil(std::log2(nrm / theta13));
-    if (!std::isfinite(nrm)) return SKFAB_OK;  // m_used == 0 or overflow: y0 stays as initialised
-    if (sq > 0) HIP_TRY(launch_combine(w.ctrl, m, std::ldexp(1.0, -sq), A, 0, nullptr, 0, nullptr, 0.0, A, st));
+    if (alpha > theta13) sq = (int)std::ceil(std::log2(alpha / theta13));
+    if (sq > 0) {
+        HIP_TRY(launch_combine(w.ctrl, m, std::ldexp(1.0, -sq), A, 0, nullptr, 0, nullptr, 0.0, A, st));
+        HIP_TRY(launch_combine(w.ctrl, m, std::ldexp(1.0, -2 * sq), A2, 0, nullptr, 0, nullptr, 0.0, A2, st));
+        HIP_TRY(launch_combine(w.ctrl, m, std::ldexp(1.0, -4 * sq), A4, 0, nullptr, 0, nullptr, 0.0, A4, st));
+        HIP_TRY(launch_combine(w.ctrl, m, std::ldexp(1.0, -6 * sq), A6, 0, nullptr, 0, nullptr, 0.0, A6, st));
+    }
     double c[14];
     c[0] = 1.0;
     for (int j = 0; j < 13; ++j) c[j + 1] = c[j] * (13.0 - j) / ((26.0 - j) * (j + 1.0));
-    HIP_TRY(launch_dgemm(w.ctrl, m, A, A, 0.0, A2, st));
-    HIP_TRY(launch_dgemm(w.ctrl, m, A2, A2, 0.0, A4, st));
-    HIP_TRY(launch_dgemm(w.ctrl, m, A4, A2, 0.0, A6, st));
     // U = A (A6 (c13 A6 + c11 A4 + c9 A2) + c7 A6 + c5 A4 + c3 A2 + c1 I)
     HIP_TRY(launch_combine(w.ctrl, m, c[13], A6, c[11], A4, c[9], A2, 0.0, T, st));
     HIP_TRY(launch_dgemm(w.ctrl, m, A6, T, 0.0, W1, st));
@@ -518,6 +553,8 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     const bool ls = p->method == SKFAB_SGMRES_QUAD;
     HIP_TRY(launch_arnoldi_check(w.SV, w.SAV, w.H, s, m, p->k, w.ctrl, w.chk, st));
     HIP_TRY(launch_qr(w.SV, s, m + 1, w.ctrl, w.Tws, st));
+    // Section 2.1 remedy: the longest basis prefix whose sketch is conditioned
+    HIP_TRY(launch_cond_trunc(w.SV, s, m, w.ctrl, w.H, w.cnd, cond_max_of(p), st));
     HIP_TRY(launch_pencil_setup(w.SV, s, m, p->k, w.ctrl, w.H, w.K0r, w.T1r, st));
     HIP_TRY(launch_hhat_rows(w.ctrl, m, s, w.SV, w.T1r, w.H, w.Hh, st));
     const int branch = (p->f == SKFAB_F_INVSQRT && !ls) ? 1 : 0;
@@ -557,20 +594,35 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
 // Storage form of A used by the step kernel (skfab_info.a_format).
 int32_t a_format(const DevCtrl& c) { return c.sell_ok ? (c.col16 ? 2 : 1) | (c.dict8 ? 4 : 0) : 0; }
 
+skfab_status solve_one(skfab_ctx* ctx, const skfab_csr* A, const double* b, double* x, const skfab_params* p,
+                       void* ws, size_t ws_bytes, skfab_info* info);
+bool multi_rhs_batched(const skfab_params* p, int nrhs);
+skfab_batch_problem one_problem(const skfab_csr* A, const double* b, int64_t ldb, double* x, int64_t ldx,
+                                const skfab_params* p);
+size_t batch_ws_total(int32_t nprob, const skfab_batch_problem* probs, int32_t nrhs, const skfab_params* p);
+
+// skfab_info from a control block (a_format from the control block of the SELL copy).
+void ctrl_to_info(const DevCtrl& c, int32_t aformat, skfab_info* o) {
+    o->status = c.status;
+    o->m_used = c.m_used;
+    o->l_used = c.l_used;
+    o->a_format = aformat;
+    o->eps_est = c.eps_est;
+    o->rcond_R = c.rcond;
+    o->sigma = c.sigma;
+    o->beta = c.beta;
+    o->arnoldi_relres = c.relres;
+    o->quad_diff = c.quad_diff;
+    o->flags = c.flags;
+    o->m_basis = c.m_basis;
+}
+
 skfab_status read_info(const Ptrs& w, hipStream_t st, skfab_info* info) {
     if (!info) return SKFAB_OK;
     DevCtrl c;
     HIP_TRY(hipMemcpyAsync(&c, w.ctrl, sizeof(DevCtrl), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    info->status = c.status;
-    info->m_used = c.m_used;
-    info->l_used = c.l_used;
-    info->a_format = a_format(c);
-    info->eps_est = c.eps_est;
-    info->rcond_R = c.rcond;
-    info->sigma = c.sigma;
-    info->beta = c.beta;
-    info->arnoldi_relres = c.relres;
+    ctrl_to_info(c, a_format(c), info);
     return SKFAB_OK;
 }
 
@@ -651,20 +703,51 @@ skfab_status skfab_timing_read(skfab_ctx* ctx, int32_t kernel, double* total_ms,
     return SKFAB_OK;
 }
 
-skfab_status skfab_workspace_bytes(const skfab_csr* A, const skfab_params* p, size_t* bytes) {
-    if (!bytes || !A || !p) return SKFAB_ERR_ARG;
+skfab_status skfab_workspace_bytes(const skfab_csr* A, const skfab_params* p, int32_t nrhs, size_t* bytes) {
+    if (!bytes || !A || !p || nrhs < 1) return SKFAB_ERR_ARG;
     skfab_status v = validate(A, p, false);
     if (v != SKFAB_OK) return v;
     if (A->n <= 0) return SKFAB_ERR_SHAPE;
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    *bytes = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k).total;
+    size_t total = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k).total;
+    if (nrhs > 1 && multi_rhs_batched(p, nrhs)) {
+        const skfab_batch_problem q = one_problem(A, nullptr, 0, nullptr, 0, p);
+        const size_t tb = batch_ws_total(1, &q, nrhs, p);
+        total = tb > total ? tb : total;
+    }
+    *bytes = total;
     return SKFAB_OK;
 }
 
-skfab_status skfab_solve(skfab_ctx* ctx, const skfab_csr* A, const double* b, double* x, const skfab_params* p,
-                         void* ws, size_t ws_bytes, skfab_info* info) {
+skfab_status skfab_solve(skfab_ctx* ctx, const skfab_csr* A, const double* b, int64_t ldb, int32_t nrhs, double* x,
+                         int64_t ldx, const skfab_params* p, void* ws, size_t ws_bytes, skfab_info* info) {
+    if (!ctx || !b || !x || !A || nrhs < 1) return SKFAB_ERR_ARG;
+    if (nrhs > 1 && (ldb < A->n || ldx < A->n)) return SKFAB_ERR_SHAPE;
+    if (nrhs == 1) return solve_one(ctx, A, b, x, p, ws, ws_bytes, info);
+    skfab_status v = validate(A, p, true);
+    if (v != SKFAB_OK) return v;
+    if (multi_rhs_batched(p, nrhs)) {
+        // one problem with nrhs right-hand sides: the batched form, whose step launch
+        // serves every column from the same rows of A
+        const skfab_batch_problem q = one_problem(A, b, ldb, x, ldx, p);
+        return skfab_solve_batched(ctx, 1, &q, nrhs, p, ws, ws_bytes, info);
+    }
+    // other functions / shapes: the columns one after another in the same workspace
+    for (int r = 0; r < nrhs; ++r) {
+        v = solve_one(ctx, A, b + (int64_t)r * ldb, x + (int64_t)r * ldx, p, ws, ws_bytes, info ? info + r : nullptr);
+        if (v != SKFAB_OK) return v;
+    }
+    return SKFAB_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+skfab_status solve_one(skfab_ctx* ctx, const skfab_csr* A, const double* b, double* x, const skfab_params* p,
+                       void* ws, size_t ws_bytes, skfab_info* info) {
     if (!ctx || !b || !x) return SKFAB_ERR_ARG;
     skfab_status v = validate(A, p, true);
     if (v != SKFAB_OK) return v;
@@ -686,6 +769,10 @@ skfab_status skfab_solve(skfab_ctx* ctx, const skfab_csr* A, const double* b, do
     HIP_TRY(timing_end(stop, st));
     return read_info(w, st, info);
 }
+
+}  // namespace
+
+extern "C" {
 
 skfab_status skfab_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, const skfab_params* p, double* V,
                            double* SV, double* SAV, double* H, void* ws, size_t ws_bytes, skfab_info* info) {
@@ -812,7 +899,7 @@ struct BatchLayout {
     size_t small_begin, small_end;     // contiguous per-unit small region (zero-filled per call)
     size_t small_bytes;                // bytes of one unit's small block
     // offsets inside one unit's small block
-    size_t o_eta, o_wnorm, o_H, o_gram, o_colnorm2, o_chk, o_SV, o_SAV, o_Tws, o_K0r, o_T1r, o_Hh, o_Urhs, o_qprev, o_y,
+    size_t o_eta, o_wnorm, o_H, o_gram, o_colnorm2, o_chk, o_cnd, o_SV, o_SAV, o_Tws, o_K0r, o_T1r, o_Hh, o_Urhs, o_qprev, o_y,
         o_ys, o_y0;
     size_t total;
 };
@@ -824,6 +911,7 @@ skfab_status validate_batch(int32_t nprob, const skfab_batch_problem* probs, int
     if (p->f != SKFAB_F_INVSQRT && p->f != SKFAB_F_INV) return SKFAB_ERR_ARG;
     if (p->method < 0 || p->method > 2) return SKFAB_ERR_ARG;
     if (p->prec < SKFAB_PREC_FP64 || p->prec > SKFAB_PREC_FP32_BF16BASIS) return SKFAB_ERR_ARG;
+    if (!(p->cond_max == 0.0 || p->cond_max >= 1.0)) return SKFAB_ERR_ARG;
     if (p->zeta != 8 || p->k < 1 || p->k > 4) return SKFAB_ERR_ARG;
     int l1, l2, lmax;
     double tol;
@@ -837,8 +925,30 @@ skfab_status validate_batch(int32_t nprob, const skfab_batch_problem* probs, int
         if (q.m < 1 || q.m > MMAX) return SKFAB_ERR_SHAPE;
         if (p->k > q.m) return SKFAB_ERR_SHAPE;
         if (q.s <= q.m || q.s > SMAX || q.s > q.A.n) return SKFAB_ERR_SHAPE;
+        if ((q.ldb != 0 && q.ldb < q.A.n) || (q.ldx != 0 && q.ldx < q.A.n)) return SKFAB_ERR_SHAPE;
     }
     return SKFAB_OK;
+}
+
+// Multi-RHS solves of skfab_solve go through the batched form when it covers them.
+bool multi_rhs_batched(const skfab_params* p, int nrhs) {
+    return nrhs >= 1 && nrhs <= BATCH_MAX_RHS && (p->f == SKFAB_F_INVSQRT || p->f == SKFAB_F_INV) &&
+           p->zeta == 8 && p->k >= 1 && p->k <= 4;
+}
+
+skfab_batch_problem one_problem(const skfab_csr* A, const double* b, int64_t ldb, double* x, int64_t ldx,
+                                const skfab_params* p) {
+    skfab_batch_problem q;
+    std::memset(&q, 0, sizeof(q));
+    q.A = *A;
+    q.B = b;
+    q.X = x;
+    q.m = p->m;
+    q.s = p->s;
+    q.seed = p->seed;
+    q.ldb = ldb;
+    q.ldx = ldx;
+    return q;
 }
 
 BatchLayout make_batch_layout(int32_t nprob, const skfab_batch_problem* probs, int32_t R, const skfab_params* p) {
@@ -872,6 +982,7 @@ BatchLayout make_batch_layout(int32_t nprob, const skfab_batch_problem* probs, i
     L.o_gram = sub((size_t)(mmax + 1) * KMAX * d);
     L.o_colnorm2 = sub((mmax + 1) * d);
     L.o_chk = sub((size_t)2 * mmax * d);
+    L.o_cnd = sub((size_t)2 * (mmax + 1) * d);
     L.o_SV = sub((size_t)smax * (mmax + 1) * d);
     L.o_SAV = sub((size_t)smax * mmax * d);
     L.o_Tws = sub((size_t)QR_NB_HOST * QR_NB_HOST * d);
@@ -927,6 +1038,10 @@ BatchLayout make_batch_layout(int32_t nprob, const skfab_batch_problem* probs, i
     }
     L.total = off;
     return L;
+}
+
+size_t batch_ws_total(int32_t nprob, const skfab_batch_problem* probs, int32_t nrhs, const skfab_params* p) {
+    return make_batch_layout(nprob, probs, nrhs, p).total;
 }
 
 // Step-kernel blocks of a problem with `nslices` SELL slices: about `spw` slices per
@@ -987,7 +1102,7 @@ void batch_descriptors(const BatchLayout& L, const BatchPlan& P, const skfab_bat
             a.nslices = ql.nslices;
             a.slices_per_chunk = (ql.nslices + P.G[qi] - 1) / P.G[qi];
             a.rows_per_chunk = (ql.N + P.G[qi] - 1) / P.G[qi];
-            a.b = q.B + (int64_t)r * ql.N;
+            a.b = q.B + (int64_t)r * (q.ldb > 0 ? q.ldb : ql.N);
             a.U = dev + ul.U;
             a.SV = reinterpret_cast<double*>(sb + L.o_SV);
             a.SAV = reinterpret_cast<double*>(sb + L.o_SAV);
@@ -1022,6 +1137,7 @@ void batch_descriptors(const BatchLayout& L, const BatchPlan& P, const skfab_bat
             m.eta = a.eta;
             m.colnorm2 = reinterpret_cast<double*>(sb + L.o_colnorm2);
             m.chk = reinterpret_cast<double*>(sb + L.o_chk);
+            m.cnd = reinterpret_cast<double*>(sb + L.o_cnd);
             m.Tws = reinterpret_cast<double*>(sb + L.o_Tws);
             m.K0r = reinterpret_cast<double*>(sb + L.o_K0r);
             m.T1r = reinterpret_cast<double*>(sb + L.o_T1r);
@@ -1036,7 +1152,7 @@ void batch_descriptors(const BatchLayout& L, const BatchPlan& P, const skfab_bat
             m.U = a.U;
             m.ldU = ql.ldU;
             m.N = ql.N;
-            m.x = q.X + (int64_t)r * ql.N;
+            m.x = q.X + (int64_t)r * (q.ldx > 0 ? q.ldx : ql.N);
             m.m = q.m;
             m.pad = 0;
         }
@@ -1092,6 +1208,7 @@ skfab_status run_batch_small(const BatchLayout& L, const skfab_params* p, char* 
     HIP_TRY(launch_arnoldi_tail_batched(su, sm, n, s, m, st));
     HIP_TRY(launch_arnoldi_check_batched(sm, n, s, m, p->k, st));
     HIP_TRY(launch_qr_batched(sm, n, s, m + 1, st));
+    HIP_TRY(launch_cond_trunc_batched(sm, n, s, m, cond_max_of(p), st));
     HIP_TRY(launch_pencil_setup_batched(sm, n, s, m, p->k, st));
     HIP_TRY(launch_hhat_rows_batched(sm, n, m, s, st));
     const int branch = (p->f == SKFAB_F_INVSQRT && !ls) ? 1 : 0;
@@ -1192,17 +1309,8 @@ skfab_status skfab_solve_batched(skfab_ctx* ctx, int32_t nprob, const skfab_batc
     for (int qi = 0; qi < L.nprob; ++qi) {
         const int pi = L.order[qi];
         for (int rr = 0; rr < L.R; ++rr) {
-            const DevCtrl& cc = c[qi * L.R + rr];
-            skfab_info& o = info[pi * L.R + rr];
-            o.status = cc.status;
-            o.m_used = cc.m_used;
-            o.l_used = cc.l_used;
-            o.a_format = a_format(c[qi * L.R]);  // the problem's SELL flags sit in its first unit
-            o.eps_est = cc.eps_est;
-            o.rcond_R = cc.rcond;
-            o.sigma = cc.sigma;
-            o.beta = cc.beta;
-            o.arnoldi_relres = cc.relres;
+            // the problem's SELL flags sit in its first unit
+            ctrl_to_info(c[qi * L.R + rr], a_format(c[qi * L.R]), &info[pi * L.R + rr]);
         }
     }
     return SKFAB_OK;
@@ -1288,17 +1396,7 @@ AdaptiveLayout make_adaptive_layout(const skfab_csr* A, const skfab_params* p) {
     return L;
 }
 
-void fill_info(const DevCtrl& c, skfab_info* info) {
-    info->status = c.status;
-    info->m_used = c.m_used;
-    info->l_used = c.l_used;
-    info->a_format = a_format(c);
-    info->eps_est = c.eps_est;
-    info->rcond_R = c.rcond;
-    info->sigma = c.sigma;
-    info->beta = c.beta;
-    info->arnoldi_relres = c.relres;
-}
+void fill_info(const DevCtrl& c, skfab_info* info) { ctrl_to_info(c, a_format(c), info); }
 
 }  // namespace
 

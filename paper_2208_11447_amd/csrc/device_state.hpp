@@ -15,22 +15,23 @@ struct DevCtrl {
     int32_t converged;  // quadrature convergence flag
     int32_t l_prev;     // order of the rule held in qprev
     int32_t col_wide;   // set by the SELL conversion when some |col - row| exceeds the int16 range
-    int32_t pad;
+    int32_t flags;      // bit 0: basis truncated to its conditioned prefix (Section 2.1 remedy);
+                        // bit 1: quadrature order accepted at the rounding floor, not at tol
     double beta;        // ||b||
     double sigma;       // spectral scale of the quadrature
     double eps_est;     // max_j | ||S v_j||^2 - 1 |
-    double rcond;       // min |R_jj| / max |R_jj|
+    double rcond;       // 1 / kappa_F(R) of the whitening factor used
     double logdet;      // log |det H_hat|
     double relres;      // ||S A V - [S V, S u_{m+1}] Hbar||_F / ||S A V||_F (Arnoldi relation check)
     double qdiff_prev;  // relative difference of the last two quadrature orders tested
-    double pad2;
+    double quad_diff;   // relative difference at the accepted quadrature order
     int64_t sell_total; // entries of the SELL-64 copy of A (padded)
     int32_t sell_ok;    // 1: the SELL-64 copy fits the workspace and is used
     int32_t col16;      // 1: the SELL-64 copy stores column offsets col - row as int16
     int32_t ndict;      // distinct values of A seen by the conversion (0.0 included)
     int32_t dict_over;  // set when A has more distinct values than the value table holds
     int32_t dict8;      // 1: the SELL-64 copy stores 8-bit indices into the value table
-    int32_t pad3;
+    int32_t m_basis;    // basis length built (m_used before the conditioning truncation)
 };
 
 // Value table of the SELL-64 copy (one per matrix): when A has at most DICT_MAX
@@ -114,6 +115,7 @@ struct BatchStepUnit {
 struct SmallUnit {
     DevCtrl* ctrl;
     double *SV, *SAV, *H, *eta, *colnorm2, *chk, *Tws, *K0r, *T1r, *Hh, *Ubuf, *Urhs, *nodebuf, *qprev, *y0, *ys, *y;
+    double* cnd;  // [2 (m_max + 1)] column norms of R^-1 and of R (conditioning test)
     const void* U;
     int64_t ldU, N;
     double* x;

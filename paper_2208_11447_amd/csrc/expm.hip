@@ -4,11 +4,18 @@
 //
 // exp of the dense m x m matrix uses scaling and squaring with the [13/13] Pade
 // approximant (Higham, SIAM J. Matrix Anal. Appl. 26 (2005)): A <- A / 2^s with
-// ||A||_1 <= theta_13, U = A (A6 (c13 A6 + c11 A4 + c9 A2) + c7 A6 + c5 A4 + c3 A2 + c1 I),
+// alpha(A) <= theta_13, U = A (A6 (c13 A6 + c11 A4 + c9 A2) + c7 A6 + c5 A4 + c3 A2 + c1 I),
 // V = A6 (c12 A6 + c10 A4 + c8 A2) + c6 A6 + c4 A4 + c2 A2 + c0 I, X = (V - U)^-1 (V + U),
-// then s squarings.  Dense products use an LDS-tiled FP64 GEMM; the Pade solve
-// an LU factorisation with partial pivoting (one block) and one wavefront per
-// right-hand-side column.
+// then s squarings.  The scaling uses alpha(A) = min_p max(||A^p||^(1/p),
+// ||A^(p+1)||^(1/(p+1))) over p(p-1) <= 27 instead of ||A||: the backward-error
+// series of the [13/13] approximant starts at x^27, and Al-Mohy & Higham (SIAM J.
+// Matrix Anal. Appl. 31 (2009), Thm. 4.2) bound such a series at A by its
+// absolute-coefficient series at alpha_p(A).  For the projected matrix of a basis
+// with a well-conditioned prefix cut from a dependent tail, ||A|| is dominated by
+// one large last column while the powers are not, and scaling by ||A|| would square
+// many times over and amplify the rounding of each product.  Dense products use an
+// LDS-tiled FP64 GEMM; the Pade solve an LU factorisation with partial pivoting
+// (one block) and one wavefront per right-hand-side column.
 #include "common.hpp"
 #include "device_state.hpp"
 
@@ -193,6 +200,24 @@ __global__ __launch_bounds__(256) void lu_solve_cols_kernel(const DevCtrl* ctrl,
     }
 }
 
+// ||P_q||_1 of the mu x mu matrices P_q (ld m) into norm1[q], one block each.
+struct NormArgs {
+    const double* P[6];
+};
+__global__ __launch_bounds__(256) void norm1_kernel(const DevCtrl* ctrl, int m, NormArgs a, double* norm1) {
+    __shared__ double scratch[4];
+    const int mu = ctrl->m_used;
+    const double* P = a.P[blockIdx.x];
+    double mx = 0.0;
+    for (int j = threadIdx.x; j < mu; j += blockDim.x) {
+        double c = 0.0;
+        for (int i = 0; i < mu; ++i) c += fabs(P[i + (int64_t)m * j]);
+        mx = fmax(mx, c);
+    }
+    mx = block_max(mx, scratch);
+    if (threadIdx.x == 0) norm1[blockIdx.x] = mx;
+}
+
 // y[i] = beta * X[i, 0]
 __global__ void first_column_kernel(const DevCtrl* ctrl, const double* X, const double* eta, double* y) {
     const int mu = ctrl->m_used;
@@ -227,6 +252,14 @@ hipError_t launch_lu(DevCtrl* ctrl, int m, double* Q, int* piv, hipStream_t st) 
 hipError_t launch_lu_solve_cols(const DevCtrl* ctrl, int m, const double* LU, const int* piv, double* P,
                                 hipStream_t st) {
     hipLaunchKernelGGL(lu_solve_cols_kernel, dim3((m + 3) / 4), dim3(256), 0, st, ctrl, m, LU, piv, P);
+    return hipGetLastError();
+}
+
+hipError_t launch_norm1(const DevCtrl* ctrl, int m, const double* const* P, int count, double* norm1,
+                        hipStream_t st) {
+    NormArgs a;
+    for (int q = 0; q < 6; ++q) a.P[q] = q < count ? P[q] : nullptr;
+    hipLaunchKernelGGL(norm1_kernel, dim3(count), dim3(256), 0, st, ctrl, m, a, norm1);
     return hipGetLastError();
 }
 

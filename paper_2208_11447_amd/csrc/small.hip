@@ -46,6 +46,9 @@ __device__ __forceinline__ void init_ctrl_body(DevCtrl* c, int m) {
         c->beta = 0.0; c->sigma = 1.0; c->eps_est = 0.0; c->rcond = 0.0; c->logdet = 0.0;
         c->qdiff_prev = INFINITY;
         c->col_wide = 0;
+        c->flags = 0;
+        c->quad_diff = 0.0;
+        c->m_basis = m;
     }
 }
 
@@ -360,6 +363,166 @@ __device__ __forceinline__ void dist_set(double (&v)[QM], int i, double x) {
         if (q == i / WAVE && lane == i % WAVE) v[q] = x;
 }
 
+// ------------------------------------------------- conditioning of R (Section 2.1)
+// The remark after eq. (sFOM''') suggests a numerical pseudoinverse in place of
+// R_m^-1 when SV_m, and so R_m, is extremely ill-conditioned.  The one used here
+// is the truncated QR one in the order of the Krylov basis: the leading blocks
+// R_j = R[:j, :j] are the QR factors of the prefixes SV_j (the same Householder
+// steps), kappa_F(R_j) = ||R_j||_F ||R_j^-1||_F never decreases with j, and the
+// approximant is formed from the longest prefix with kappa_F(R_j) <= cmax.
+// R_j^-1 is the leading block of R^-1, so one inverse gives every prefix: column
+// c of R^-1 (support rows 0..c) is a back substitution, one wavefront per column.
+// The prefix then looks to the rest of the small problem exactly like a run of
+// j steps: its extension column S u_{j+1} = h_{j+1,j} S v_{j+1} is, after the first
+// j reflectors, h_{j+1,j} times rows 0..j of the factored column j.
+constexpr int RC_NT = 256;  // wavefronts per block of the column kernel: 4
+
+// cnd[c] = ||R^-1 e_c||^2, cnd[m + 1 + c] = ||R[:c+1, c]||^2 for c < mu.
+template <int QM>
+__device__ __forceinline__ void rinv_col_body(int c, const double* __restrict__ X, int s,
+                                              const DevCtrl* ctrl, int m, double* __restrict__ cnd) {
+    const int mu = ctrl->m_used;
+    if (c >= mu) return;
+    const int lane = threadIdx.x & 63;
+    double r[QM], dinv[QM];
+    double g = 0.0;
+#pragma unroll
+    for (int q = 0; q < QM; ++q) {
+        const int i = lane + WAVE * q;
+        r[q] = (i == c) ? 1.0 : 0.0;
+        dinv[q] = (i <= c) ? 1.0 / X[i + (int64_t)s * i] : 0.0;
+        const double v = (i <= c) ? X[i + (int64_t)s * c] : 0.0;
+        g = fma(v, v, g);
+    }
+    // x = R^-1 e_c, columns of R from c down to 0, BF columns in flight
+    constexpr int BF = 4;
+    double cb[BF][QM];
+#pragma unroll
+    for (int f = 0; f < BF; ++f) {
+        const int col = c - f;
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int i = lane + WAVE * q;
+            cb[f][q] = (col >= 0 && i < col) ? X[i + (int64_t)s * col] : 0.0;
+        }
+    }
+    for (int l = c; l >= 0; --l) {
+        const double xl = dist_get(r, l) * dist_get(dinv, l);
+        dist_set(r, l, xl);
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int i = lane + WAVE * q;
+            if (i < l) r[q] = fma(-cb[0][q], xl, r[q]);
+        }
+#pragma unroll
+        for (int f = 0; f + 1 < BF; ++f)
+#pragma unroll
+            for (int q = 0; q < QM; ++q) cb[f][q] = cb[f + 1][q];
+        const int col = l - BF;
+#pragma unroll
+        for (int q = 0; q < QM; ++q) {
+            const int i = lane + WAVE * q;
+            cb[BF - 1][q] = (col >= 0 && i < col) ? X[i + (int64_t)s * col] : 0.0;
+        }
+    }
+    double n = 0.0;
+#pragma unroll
+    for (int q = 0; q < QM; ++q)
+        if (lane + WAVE * q <= c) n = fma(r[q], r[q], n);
+    n = wave_sum(n);
+    g = wave_sum(g);
+    if (lane == 0) {
+        cnd[c] = n;
+        cnd[m + 1 + c] = g;
+    }
+}
+
+template <int QM>
+__global__ __launch_bounds__(RC_NT) void rinv_col_kernel(const double* X, int s, const DevCtrl* ctrl, int m,
+                                                         double* cnd) {
+    rinv_col_body<QM>(blockIdx.x * (RC_NT / WAVE) + (threadIdx.x >> 6), X, s, ctrl, m, cnd);
+}
+
+template <int QM>
+__global__ __launch_bounds__(RC_NT) void rinv_col_batched_kernel(const SmallUnit* __restrict__ units, int s, int m) {
+    const SmallUnit& u = units[blockIdx.y];
+    rinv_col_body<QM>(blockIdx.x * (RC_NT / WAVE) + (threadIdx.x >> 6), u.SV, s, u.ctrl, m, u.cnd);
+}
+
+// The prefix: kappa_F(R_j) from the prefix sums of cnd (fixed order: per-lane
+// chunks, then an exclusive scan of the 64 chunk sums by lane 0), j' = the number of
+// prefixes within cmax.  rcond reports 1 / kappa_F of the factor used.  If
+// j' < mu, column j' of X becomes the extension column of the j'-step problem and
+// m_used drops to j' (flag bit 0).  One wavefront.
+__device__ __forceinline__ void cond_trunc_body(DevCtrl* ctrl, double* X, int s, const double* H, int64_t ldh,
+                                                int m, const double* cnd, double cmax) {
+    __shared__ double fsum[WAVE + 1], gsum[WAVE + 1];
+    __shared__ int cnt[WAVE];
+    __shared__ double kap[WAVE];
+    const int mu = ctrl->m_used;
+    if (mu == 0) return;
+    const int lane = threadIdx.x;
+    const int per = (mu + WAVE - 1) / WAVE;
+    const int c0 = min(lane * per, mu), c1 = min(c0 + per, mu);
+    auto fin = [](double v) { return (v <= 1.7976931348623157e308) ? v : INFINITY; };  // NaN -> inf
+    double fs = 0.0, gs = 0.0;
+    for (int c = c0; c < c1; ++c) { fs += fin(cnd[c]); gs += fin(cnd[m + 1 + c]); }
+    fsum[lane + 1] = fs;
+    gsum[lane + 1] = gs;
+    __syncthreads();
+    if (lane == 0) {
+        fsum[0] = 0.0; gsum[0] = 0.0;
+        for (int i = 1; i <= WAVE; ++i) { fsum[i] += fsum[i - 1]; gsum[i] += gsum[i - 1]; }
+    }
+    __syncthreads();
+    double F = fsum[lane], G = gsum[lane];
+    int n = 0;
+    double klast = 0.0;
+    for (int c = c0; c < c1; ++c) {
+        F += fin(cnd[c]);
+        G += fin(cnd[m + 1 + c]);
+        const double k = sqrt(F * G);
+        if (k <= cmax) { ++n; klast = k; }
+    }
+    cnt[lane] = n;
+    kap[lane] = klast;
+    __syncthreads();
+    if (lane == 0) {
+        int mp = 0;
+        double kp = 0.0;
+        for (int i = 0; i < WAVE; ++i) {
+            if (cnt[i] > 0) kp = kap[i];
+            mp += cnt[i];
+        }
+        ctrl->m_basis = mu;
+        ctrl->rcond = (mp > 0 && kp > 0.0) ? 1.0 / kp : 0.0;
+        if (mp == 0) {
+            if (ctrl->status == 0) ctrl->status = 3;  // SKFAB_ERR_RANK: R_11 = 0
+        } else if (mp < mu) {
+            ctrl->m_used = mp;
+            ctrl->flags |= 1;
+        }
+        cnt[0] = mp;
+    }
+    __syncthreads();
+    const int mp = cnt[0];
+    if (mp > 0 && mp < mu) {
+        const double h = H[mp + ldh * (mp - 1)];
+        for (int i = lane; i <= mp; i += WAVE) X[i + (int64_t)s * mp] *= h;
+    }
+}
+
+__global__ __launch_bounds__(64) void cond_trunc_kernel(DevCtrl* ctrl, double* X, int s, const double* H, int m,
+                                                        const double* cnd, double cmax) {
+    cond_trunc_body(ctrl, X, s, H, m + 1, m, cnd, cmax);
+}
+
+__global__ __launch_bounds__(64) void cond_trunc_batched_kernel(const SmallUnit* __restrict__ units, int s, int m,
+                                                                double cmax) {
+    const SmallUnit& u = units[blockIdx.y];
+    cond_trunc_body(u.ctrl, u.SV, s, u.H, m + 1, m, u.cnd, cmax);
+}
+
 // ------------------------------------------------------------- H_hat rows
 // H_hat = H_mu + x e_mu^T with x = R^-1 r, r = R_e[:mu, mu] (the extension column
 // of the QR'd sketch): the projected matrix of the sketched FOM in the basis V_m
@@ -628,7 +791,7 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
 
 // Node 0 (a = 0): log|det H_hat| and its sign (square case), the spectral scale
 // sigma = |det H_hat|^(1/mu) (geometric mean of the moduli of the sketched Ritz
-// values), rcond of R, the branch check for z^(-1/2) (a negative determinant means
+// values), the branch check for z^(-1/2) (a negative determinant means
 // an odd number of negative real eigenvalues), and -- for f = 1/z -- the solution
 // itself (H_hat y = beta e_1, or the least-squares pencil problem for sGMRES).
 template <int QM>
@@ -639,23 +802,6 @@ __device__ __forceinline__ void pencil_scalars_body(int m, int s, const double* 
     const int mu = ctrl_c->m_used;
     if (mu == 0) return;
     const int lane = threadIdx.x;
-    // R diagonal statistics (rank test)
-    double rmin = 1e308, rmax = 0.0;
-    double dg[QM];
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        const int j = lane + 64 * q;
-        dg[q] = (j < mu) ? X[j + (int64_t)s * j] : 1.0;
-    }
-#pragma unroll
-    for (int q = 0; q < QM; ++q) {
-        if (lane + 64 * q < mu) {
-            rmin = fmin(rmin, fabs(dg[q]));
-            rmax = fmax(rmax, fabs(dg[q]));
-        }
-    }
-    rmax = wave_max(rmax);
-    rmin = -wave_max(-rmin);
     const double beta = eta[0];
     double ld = 0.0, sg = 1.0;
     if (is_ls) {
@@ -670,8 +816,6 @@ __device__ __forceinline__ void pencil_scalars_body(int m, int s, const double* 
     }
     if (lane == 0) {
         ctrl->beta = beta;
-        ctrl->rcond = (rmax > 0.0) ? rmin / rmax : 0.0;
-        if (!(rmin > 2.220446049250313e-16 * rmax)) ctrl->status = 3;  // SKFAB_ERR_RANK
         if (!is_ls) {
             const double lg = ld / mu;
             ctrl->logdet = ld;
@@ -899,8 +1043,7 @@ __global__ __launch_bounds__(BAND_NT) void quad_level_band_batched_kernel(const 
     quad_level_band_body<KB>(u.ctrl, grp, u.Hh, u.Ubuf, u.nodebuf, m, u.eta);
 }
 
-// Square case of the pencil scalars with the band elimination: beta, the rank
-// test on diag(R), H_hat y0 = beta e_1 (lane 0), log|det H_hat|, sigma and the
+// Square case of the pencil scalars with the band elimination: beta, H_hat y0 = beta e_1 (lane 0), log|det H_hat|, sigma and the
 // sign of det H_hat for the branch test.  One wavefront.
 template <int KB>
 __device__ __forceinline__ void pencil_scalars_band_body(int m, int s, const double* X, DevCtrl* ctrl,
@@ -913,14 +1056,8 @@ __device__ __forceinline__ void pencil_scalars_band_body(int m, int s, const dou
     if (mu == 0) return;
     const int lane = threadIdx.x;
     (void)Ubuf;
-    double rmin = 1e308, rmax = 0.0;
-    for (int j = lane; j < mu; j += WAVE) {
-        const double dg = fabs(X[j + (int64_t)s * j]);
-        rmin = fmin(rmin, dg);
-        rmax = fmax(rmax, dg);
-    }
-    rmax = wave_max(rmax);
-    rmin = -wave_max(-rmin);
+    (void)X;
+    (void)s;
     load_band<KB>(Hh, m, mu, Bs, Ls);
     __syncthreads();
     const double beta = eta[0];
@@ -934,8 +1071,6 @@ __device__ __forceinline__ void pencil_scalars_band_body(int m, int s, const dou
     const double ld = -wave_sum_fast(lu);
     if (lane == 0) {
         ctrl->beta = beta;
-        ctrl->rcond = (rmax > 0.0) ? rmin / rmax : 0.0;
-        if (!(rmin > 2.220446049250313e-16 * rmax)) ctrl->status = 3;  // SKFAB_ERR_RANK
         const double lg = ld / mu;
         ctrl->logdet = ld;
         ctrl->sigma = exp(lg);
@@ -1035,8 +1170,8 @@ __device__ __forceinline__ void quad_reduce_body(DevCtrl* ctrl, const QuadGroup&
     __syncthreads();
     int acc_lev = -1;
     int last = grp.nlev - 1;
-    bool bad = false;
-    double dprev = ctrl->qdiff_prev;
+    bool bad = false, floor_acc = false;
+    double dprev = ctrl->qdiff_prev, dacc = 0.0;
     for (int lev = 0; lev < grp.nlev; ++lev) {
         if (grp.first && lev == 0) continue;
         if (!isfinite(nd[lev]) || !isfinite(nc[lev])) { bad = true; last = lev; break; }
@@ -1045,7 +1180,12 @@ __device__ __forceinline__ void quad_reduce_body(DevCtrl* ctrl, const QuadGroup&
         // below QUAD_FLOOR at the final order of the sequence
         const double d = (nc[lev] > 0.0) ? sqrt(nd[lev] / nc[lev]) : (nd[lev] > 0.0 ? INFINITY : 0.0);
         const bool final_order = grp.last && lev == grp.nlev - 1;
-        if (d <= tol || (d <= QUAD_FLOOR && (d > 0.5 * dprev || final_order))) { acc_lev = lev; break; }
+        if (d <= tol || (d <= QUAD_FLOOR && (d > 0.5 * dprev || final_order))) {
+            acc_lev = lev;
+            dacc = d;
+            floor_acc = d > tol;
+            break;
+        }
         dprev = d;
     }
     if (acc_lev >= 0) {
@@ -1054,7 +1194,12 @@ __device__ __forceinline__ void quad_reduce_body(DevCtrl* ctrl, const QuadGroup&
         for (int jj = threadIdx.x; jj < mu; jj += 1024) qprev[jj] = qs[last + 1][jj];
     }
     if (threadIdx.x == 0) {
-        if (acc_lev >= 0) { ctrl->converged = 1; ctrl->l_used = grp.lev_l[acc_lev]; }
+        if (acc_lev >= 0) {
+            ctrl->converged = 1;
+            ctrl->l_used = grp.lev_l[acc_lev];
+            ctrl->quad_diff = dacc;
+            if (floor_acc) ctrl->flags |= 2;
+        }
         else { ctrl->l_prev = grp.lev_l[last]; ctrl->qdiff_prev = dprev; }
         if (bad) ctrl->status = 5;
     }
@@ -1327,6 +1472,31 @@ hipError_t launch_assemble(const void* U, int64_t ldU, int64_t N, int m, const D
 // Every unit uses the common leading dimensions m (= m_max) and s (= s_max).
 hipError_t launch_init_ctrl_batched(const SmallUnit* units, int nunits, hipStream_t st) {
     hipLaunchKernelGGL(init_ctrl_batched_kernel, dim3(1, nunits), dim3(64), 0, st, units);
+    return hipGetLastError();
+}
+
+hipError_t launch_cond_trunc(double* X, int s, int m, DevCtrl* ctrl, const double* H, double* cnd, double cmax,
+                             hipStream_t st) {
+    const int blocks = (m + RC_NT / WAVE - 1) / (RC_NT / WAVE);
+    if (m <= 256)
+        hipLaunchKernelGGL(rinv_col_kernel<4>, dim3(blocks), dim3(RC_NT), 0, st, X, s, ctrl, m, cnd);
+    else
+        hipLaunchKernelGGL(rinv_col_kernel<8>, dim3(blocks), dim3(RC_NT), 0, st, X, s, ctrl, m, cnd);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cond_trunc_kernel, dim3(1), dim3(64), 0, st, ctrl, X, s, H, m, cnd, cmax);
+    return hipGetLastError();
+}
+
+hipError_t launch_cond_trunc_batched(const SmallUnit* units, int nunits, int s, int m, double cmax, hipStream_t st) {
+    const int blocks = (m + RC_NT / WAVE - 1) / (RC_NT / WAVE);
+    if (m <= 256)
+        hipLaunchKernelGGL(rinv_col_batched_kernel<4>, dim3(blocks, nunits), dim3(RC_NT), 0, st, units, s, m);
+    else
+        hipLaunchKernelGGL(rinv_col_batched_kernel<8>, dim3(blocks, nunits), dim3(RC_NT), 0, st, units, s, m);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cond_trunc_batched_kernel, dim3(1, nunits), dim3(64), 0, st, units, s, m, cmax);
     return hipGetLastError();
 }
 

@@ -70,7 +70,7 @@ class CSR:
 
 
 def make_params(f="invsqrt", m=50, k=2, s=200, zeta=8, seed=0, method="sfom", fparam=0.0, poly=None,
-                l1=32, l2=45, lmax=1395, quad_tol=1e-13, prec="fp64") -> N.skfab_params:
+                l1=32, l2=45, lmax=1395, quad_tol=1e-13, prec="fp64", cond_max=0.0) -> N.skfab_params:
     p = N.skfab_params()
     p.f = FUNCS[f] if isinstance(f, str) else int(f)
     p.fparam = float(fparam)
@@ -78,6 +78,7 @@ def make_params(f="invsqrt", m=50, k=2, s=200, zeta=8, seed=0, method="sfom", fp
     p.m, p.k, p.s, p.zeta, p.seed = int(m), int(k), int(s), int(zeta), int(seed)
     p.l1, p.l2, p.lmax, p.quad_tol = int(l1), int(l2), int(lmax), float(quad_tol)
     p.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
+    p.cond_max = float(cond_max)
     if poly is not None:
         arr = (C.c_double * len(poly))(*[float(c) for c in poly])
         p.poly = C.cast(arr, C.POINTER(C.c_double))
@@ -119,13 +120,14 @@ def skfab_version() -> int:
     return N.lib().skfab_version()
 
 
-def skfab_workspace_bytes(A: CSR | int, p: N.skfab_params) -> int:
+def skfab_workspace_bytes(A: CSR | int, p: N.skfab_params, nrhs: int = 1) -> int:
     if isinstance(A, CSR):
         csr = N.skfab_csr(A.n, A.col.numel(), None, None, None, N.SKFAB_VAL_F64)
     else:
         csr = N.skfab_csr(int(A), 0, None, None, None, N.SKFAB_VAL_F64)
     out = C.c_size_t()
-    _check(N.lib().skfab_workspace_bytes(C.byref(csr), C.byref(p), C.byref(out)), "skfab_workspace_bytes")
+    _check(N.lib().skfab_workspace_bytes(C.byref(csr), C.byref(p), int(nrhs), C.byref(out)),
+           "skfab_workspace_bytes")
     return out.value
 
 
@@ -136,14 +138,22 @@ def alloc_workspace(nbytes: int, device=None) -> torch.Tensor:
 
 def skfab_solve(ctx: Context, A: CSR, b: torch.Tensor, x: torch.Tensor, p: N.skfab_params,
                 ws: torch.Tensor, want_info: bool = True):
+    """x <- f(A) b.  b, x: (N,) tensors (one right-hand side; returns one skfab_info)
+    or (nrhs, N) tensors (row r = column r of the C ABI's column-major N x nrhs;
+    returns a list of nrhs skfab_info)."""
     _require_device(b, torch.float64, "b")
     _require_device(x, torch.float64, "x")
+    if b.shape != x.shape or b.dim() not in (1, 2) or b.shape[-1] != A.n:
+        raise ValueError("b and x must both be (N,) or (nrhs, N) tensors of the matrix's size")
+    nrhs = 1 if b.dim() == 1 else int(b.shape[0])
     csr = A.c_struct()
-    info = N.skfab_info() if want_info else None
-    st = N.lib().skfab_solve(ctx.handle, C.byref(csr), _ptr(b), _ptr(x), C.byref(p), _ptr(ws), ws.numel(),
-                             C.byref(info) if info is not None else None)
+    info = (N.skfab_info * nrhs)() if want_info else None
+    st = N.lib().skfab_solve(ctx.handle, C.byref(csr), _ptr(b), A.n, nrhs, _ptr(x), A.n, C.byref(p), _ptr(ws),
+                             ws.numel(), info)
     _check(st, "skfab_solve")
-    return info
+    if info is None:
+        return None
+    return info[0] if b.dim() == 1 else [info[r] for r in range(nrhs)]
 
 
 def skfab_arnoldi(ctx: Context, A: CSR, b: torch.Tensor, p: N.skfab_params, V=None, SV=None, SAV=None, H=None,

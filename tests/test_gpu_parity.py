@@ -13,6 +13,7 @@ import torch
 from gpu_common import (ctx, problem, device_csr, dev, gpu_solve, gpu_arnoldi, oracle_run, rel, log)
 from oracle import methods as ometh
 from oracle import sketch as osk
+from paper_2208_11447_amd import _native as N
 from paper_2208_11447_amd import skfab as sk
 
 pytestmark = pytest.mark.gpu
@@ -106,11 +107,9 @@ def test_high_quadrature_orders_match():
 def test_solve_parity_m300(method):
     """Krylov dimension above 256: the small-problem kernels in their wider
     register form (up to 512 rows: QR panels, H_hat rows, node solves, pencil),
-    2D 200x200 grid, convection 200, m=300, k=2, s=600, f = z^(-1/2).  (The
-    sketched basis stays well conditioned here, cond(R) ~ 10; on a 100x100 grid
-    with convection 60 the truncated basis is numerically dependent at m=300,
-    cond(R) ~ 1e16, and H_hat built from R then has a real eigenvalue on the
-    negative axis: the branch status is the right answer there.)"""
+    2D 200x200 grid, convection 200, m=300, k=2, s=600, f = z^(-1/2).  The
+    sketched basis stays well conditioned here (no truncation); the numerically
+    dependent case is test_ill_conditioned_basis_remedy."""
     A, b, arrs = problem(200, c=200.0, seed=7)
     m, k, s = 300, 2, 600
     x, info = gpu_solve(arrs, b, f="invsqrt", m=m, k=k, s=s, method=method, quad_tol=1e-13)
@@ -256,3 +255,72 @@ def test_timing_stride_counts_launches():
     assert torch.equal(x0, x1)
     with pytest.raises(RuntimeError):
         sk.skfab_timing_enable(c, True, stride=-2)
+
+
+@pytest.mark.parametrize("method", ["sfom", "sfom_quad", "sgmres"])
+def test_ill_conditioned_basis_remedy(method):
+    """2D 100x100 grid, convection 60, m = 300, k = 2, s = 600: the truncated basis
+    is numerically dependent (cond(SV_m) ~ 1e16).  Section 2.1's remedy on both
+    sides (longest prefix with kappa_F(R_j) <= 1e10): every method agrees with the
+    oracle, and the result with the fully orthogonalised oracle run (k = m)."""
+    A, b, arrs = problem(100, c=60.0, seed=3)
+    m, k, s = 300, 2, 600
+    log(f"ill-conditioned basis m={m} method={method}")
+    x, info = gpu_solve(arrs, b, f="invsqrt", m=m, k=k, s=s, method=method, quad_tol=1e-13)
+    arn, _ = oracle_run(A, b, m, k, s)
+    ref = {"sfom": ometh.sfom_closed, "sgmres": ometh.sgmres, "sfom_quad": ometh.sfom_quad}[method]
+    r = ref(arn, "invsqrt") if method == "sfom" else ref(arn, "invsqrt", tol=1e-13)
+    err = rel(x, r.x) if info.status == 0 else float("nan")
+    log(f"  status={info.status} m_used={info.m_used}/{info.m_basis} (oracle {r.m_used}) flags={info.flags} "
+        f"rcond={info.rcond_R:.2e} l_used={info.l_used} quad_diff={info.quad_diff:.2e} err={err:.3e}")
+    assert np.linalg.cond(arn.SV) > 1e14
+    assert info.status == 0
+    assert info.flags & N.SKFAB_FLAG_TRUNCATED and info.m_used < m and info.m_basis == m
+    assert 1.0 / info.rcond_R <= 1e10
+    assert err < FP64_TOL
+
+
+@pytest.mark.parametrize("f,tau,nrhs", [("invsqrt", 0.0, 3), ("inv", 0.0, 4), ("exp", 1e-3, 2)])
+def test_multi_rhs_solve(f, tau, nrhs):
+    """skfab_solve with nrhs columns (ld = N): each column equals the single-column
+    solve (the batched form for z^(-1/2) and 1/z, to rounding; the column loop for
+    exp, bitwise) and the oracle."""
+    A, b0, arrs = problem(60, seed=1)
+    Nn = A.shape[0]
+    m, k, s = 30, 2, 120
+    B = np.stack([np.random.default_rng(10 + r).standard_normal(Nn) for r in range(nrhs)])
+    Ad = device_csr(arrs)
+    p = sk.make_params(f=f, fparam=tau, m=m, k=k, s=s, method="sfom")
+    ws = sk.alloc_workspace(sk.skfab_workspace_bytes(Ad, p, nrhs))
+    Bd = dev(B)
+    X = torch.zeros_like(Bd)
+    log(f"multi-rhs f={f} nrhs={nrhs}")
+    infos = sk.skfab_solve(ctx(), Ad, Bd, X, p, ws)
+    torch.cuda.synchronize()
+    Xh = X.cpu().numpy()
+    for r in range(nrhs):
+        assert infos[r].status == 0 and infos[r].m_used == m
+        x1, _ = gpu_solve(arrs, B[r], f=f, fparam=tau, m=m, k=k, s=s, method="sfom")
+        arn, _ = oracle_run(A, B[r], m, k, s)
+        e_or = rel(Xh[r], ometh.sfom_closed(arn, f, tau).x)
+        e_1 = rel(Xh[r], x1)
+        log(f"  column {r}: vs single solve {e_1:.2e}, vs oracle {e_or:.2e}")
+        assert e_or < FP64_TOL
+        if f == "exp":
+            assert np.array_equal(Xh[r], x1)
+        else:
+            assert e_1 < 1e-12
+
+
+def test_quadrature_reporting():
+    """info.quad_diff is the accepted relative difference: at most tol unless the
+    rounding-floor flag is set, and then at most the floor (1e-10)."""
+    A, b, arrs = problem(80, c=40.0, seed=5)
+    for method, tol in (("sfom_quad", 1e-8), ("sgmres", 1e-8), ("sfom", 1e-13)):
+        x, info = gpu_solve(arrs, b, f="invsqrt", m=40, k=2, s=160, method=method, quad_tol=tol)
+        log(f"quad reporting {method}: l_used={info.l_used} quad_diff={info.quad_diff:.2e} flags={info.flags}")
+        assert info.status == 0 and info.l_used >= 45
+        if info.flags & N.SKFAB_FLAG_QUAD_FLOOR:
+            assert tol < info.quad_diff <= 1e-10
+        else:
+            assert 0.0 <= info.quad_diff <= tol

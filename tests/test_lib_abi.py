@@ -44,8 +44,20 @@ def _params(**kw):
 def _ws(n, **kw):
     csr = N.skfab_csr(n, 5 * n, None, None, None, 0)
     out = C.c_size_t()
-    st = N.lib().skfab_workspace_bytes(C.byref(csr), C.byref(_params(**kw)), C.byref(out))
+    st = N.lib().skfab_workspace_bytes(C.byref(csr), C.byref(_params(**kw)), 1, C.byref(out))
     return st, out.value
+
+
+def test_workspace_multi_rhs():
+    """nrhs > 1 through the batched form needs at least the room of nrhs bases;
+    nrhs < 1 is refused."""
+    csr = N.skfab_csr(100_000, 500_000, None, None, None, 0)
+    out1, out4 = C.c_size_t(), C.c_size_t()
+    p = _params(m=100, s=200)
+    assert N.lib().skfab_workspace_bytes(C.byref(csr), C.byref(p), 1, C.byref(out1)) == N.SKFAB_OK
+    assert N.lib().skfab_workspace_bytes(C.byref(csr), C.byref(p), 4, C.byref(out4)) == N.SKFAB_OK
+    assert out4.value >= 4 * 100_000 * 100 * 8 > out1.value
+    assert N.lib().skfab_workspace_bytes(C.byref(csr), C.byref(p), 0, C.byref(out1)) == N.SKFAB_ERR_ARG
 
 
 def test_workspace_sizes_grow_with_problem():
