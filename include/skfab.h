@@ -55,7 +55,9 @@ typedef enum skfab_status {
                                cut of z^(-1/2) (Section 2.3, sketched Ritz values)       */
     SKFAB_ERR_QUAD = 5,     /* adaptive quadrature did not converge by lmax (Section 4.1) */
     SKFAB_ERR_HIP = 6,      /* a HIP runtime call failed                                  */
-    SKFAB_ERR_WORKSPACE = 7 /* workspace pointer null or smaller than required            */
+    SKFAB_ERR_WORKSPACE = 7,/* workspace pointer null or smaller than required            */
+    SKFAB_ERR_TOO_LARGE = 8 /* skfab_solve_noalloc: the problem needs more workspace than
+                               SKFAB_NOALLOC_WS_BYTES                                   */
 } skfab_status;
 
 /* f in f(A) b.  INVSQRT and INV are Stieltjes functions (Section 1) and work with
@@ -224,6 +226,21 @@ skfab_status skfab_workspace_bytes(const skfab_csr *A, const skfab_params *p, in
 skfab_status skfab_solve(skfab_ctx *ctx, const skfab_csr *A, const double *b, int64_t ldb,
                          int32_t nrhs, double *x, int64_t ldx, const skfab_params *p,
                          void *ws, size_t ws_bytes, skfab_info *info);
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * serving loops, harnesses that forbid hipMalloc): skfab_solve with one right-hand
+ * side (ldb = ldx = N) whose workspace is a static device array of
+ * SKFAB_NOALLOC_WS_BYTES bytes inside the library, one per device, held until the
+ * process ends.  The call allocates and frees nothing.  The array's address is
+ * resolved by skfab_create for the context's device.  Problems whose
+ * skfab_workspace_bytes(A, p, 1) exceeds the array are refused with
+ * SKFAB_ERR_TOO_LARGE before anything is enqueued (the 2D 100 x 100 problem at m = 50,
+ * s = 200 needs 26 MiB).  Every call on a device shares that device's array: calls
+ * that overlap on one device (two streams, two threads) race and must be ordered by
+ * the caller.  Otherwise as skfab_solve (stream-ordered; info synchronises). */
+#define SKFAB_NOALLOC_WS_BYTES (64u * 1024u * 1024u)
+skfab_status skfab_solve_noalloc(skfab_ctx *ctx, const skfab_csr *A, const double *b, double *x,
+                                 const skfab_params *p, skfab_info *info);
 
 /* Test hook: run only the k-truncated Arnoldi recurrence with sketches
  * (Algorithm 2, basis part) and export its state.

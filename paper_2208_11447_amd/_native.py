@@ -13,7 +13,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libskfab.so")
 
 SKFAB_OK, SKFAB_ERR_ARG, SKFAB_ERR_SHAPE, SKFAB_ERR_RANK, SKFAB_ERR_BRANCH, SKFAB_ERR_QUAD, \
-    SKFAB_ERR_HIP, SKFAB_ERR_WORKSPACE = range(8)
+    SKFAB_ERR_HIP, SKFAB_ERR_WORKSPACE, SKFAB_ERR_TOO_LARGE = range(9)
+SKFAB_NOALLOC_WS_BYTES = 64 * 1024 * 1024
 SKFAB_F_INVSQRT, SKFAB_F_EXP, SKFAB_F_INV, SKFAB_F_POLY = range(4)
 SKFAB_SFOM_CLOSED, SKFAB_SFOM_QUAD, SKFAB_SGMRES_QUAD = range(3)
 SKFAB_PREC_FP64, SKFAB_PREC_FP32, SKFAB_PREC_FP32_BF16BASIS = range(3)
@@ -22,7 +23,7 @@ SKFAB_FLAG_TRUNCATED, SKFAB_FLAG_QUAD_FLOOR = 1, 2
 
 EXPORTED = [
     "skfab_version", "skfab_status_string", "skfab_create", "skfab_set_stream", "skfab_destroy",
-    "skfab_workspace_bytes", "skfab_solve", "skfab_arnoldi", "skfab_small_problem",
+    "skfab_workspace_bytes", "skfab_solve", "skfab_solve_noalloc", "skfab_arnoldi", "skfab_small_problem",
     "skfab_small_workspace_bytes", "skfab_sketch_pattern", "skfab_sketch_apply", "skfab_sketch_ws_bytes",
     "skfab_timing_enable", "skfab_timing_read", "skfab_set_value_table",
     "skfab_batch_workspace_bytes", "skfab_solve_batched", "skfab_batch_set_tuning", "skfab_batch_get_tuning",
@@ -84,6 +85,8 @@ def lib():
                                              C.POINTER(C.c_size_t)]),
         "skfab_solve": (C.c_int, [P, C.POINTER(skfab_csr), P, C.c_int64, C.c_int32, P, C.c_int64,
                                   C.POINTER(skfab_params), P, C.c_size_t, C.POINTER(skfab_info)]),
+        "skfab_solve_noalloc": (C.c_int, [P, C.POINTER(skfab_csr), P, P, C.POINTER(skfab_params),
+                                          C.POINTER(skfab_info)]),
         "skfab_arnoldi": (C.c_int, [P, C.POINTER(skfab_csr), P, C.POINTER(skfab_params), P, P, P, P, P,
                                     C.c_size_t, C.POINTER(skfab_info)]),
         "skfab_small_problem": (C.c_int, [P, P, P, C.c_double, C.POINTER(skfab_params), P, P, C.c_size_t,

@@ -110,6 +110,11 @@ constexpr int NODE_SLOTS_HOST = 1024;
 
 using namespace skfab;
 
+namespace skfab {
+skfab_status noalloc_init_device(int device);
+int ctx_device(const skfab_ctx* ctx);
+}  // namespace skfab
+
 struct skfab_ctx {
     int device;
     hipStream_t stream;
@@ -131,6 +136,8 @@ struct skfab_ctx {
     // lookup costs more than the 3 bytes per entry it saves)
     bool value_table = true;
 };
+
+int skfab::ctx_device(const skfab_ctx* ctx) { return ctx ? ctx->device : -1; }
 
 namespace {
 constexpr size_t TIMING_PAIRS = 2048;
@@ -642,6 +649,7 @@ const char* skfab_status_string(int32_t s) {
         case SKFAB_ERR_QUAD: return "adaptive quadrature did not converge";
         case SKFAB_ERR_HIP: return "HIP runtime error";
         case SKFAB_ERR_WORKSPACE: return "workspace missing or too small";
+        case SKFAB_ERR_TOO_LARGE: return "problem needs more workspace than skfab_solve_noalloc's static buffer";
         default: return "unknown status";
     }
 }
@@ -656,6 +664,12 @@ skfab_status skfab_create(skfab_ctx** ctx, int32_t device, void* hip_stream) {
     if (!c) return SKFAB_ERR_ARG;
     c->device = device;
     c->stream = static_cast<hipStream_t>(hip_stream);
+    // the device address of skfab_solve_noalloc's static workspace, once per device
+    const skfab_status st = skfab::noalloc_init_device(device);
+    if (st != SKFAB_OK) {
+        delete c;
+        return st;
+    }
     *ctx = c;
     return SKFAB_OK;
 }

@@ -156,6 +156,22 @@ def skfab_solve(ctx: Context, A: CSR, b: torch.Tensor, x: torch.Tensor, p: N.skf
     return info[0] if b.dim() == 1 else [info[r] for r in range(nrhs)]
 
 
+def skfab_solve_noalloc(ctx: Context, A: CSR, b: torch.Tensor, x: torch.Tensor, p: N.skfab_params,
+                        want_info: bool = True):
+    """x <- f(A) b (one right-hand side) with the library's static device workspace:
+    the call allocates nothing."""
+    _require_device(b, torch.float64, "b")
+    _require_device(x, torch.float64, "x")
+    if b.shape != x.shape or b.dim() != 1 or b.shape[0] != A.n:
+        raise ValueError("b and x must be (N,) tensors of the matrix's size")
+    csr = A.c_struct()
+    info = N.skfab_info() if want_info else None
+    st = N.lib().skfab_solve_noalloc(ctx.handle, C.byref(csr), _ptr(b), _ptr(x), C.byref(p),
+                                     C.byref(info) if info is not None else None)
+    _check(st, "skfab_solve_noalloc")
+    return info
+
+
 def skfab_arnoldi(ctx: Context, A: CSR, b: torch.Tensor, p: N.skfab_params, V=None, SV=None, SAV=None, H=None,
                   ws: torch.Tensor = None, want_info: bool = True):
     csr = A.c_struct()
