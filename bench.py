@@ -382,50 +382,69 @@ def save_batch_outputs(path, probs, info, R):
     print(f"# saved {len(rows)} pair outputs to {path}", file=sys.stderr, flush=True)
 
 
-def check_batch_outputs(path, nprob):
-    """Oracle check of saved batched outputs (CPU): right-hand side 0 of every
-    problem, and every pair with a nonzero status, through the oracle's own run of
-    the same pair.  A pair the GPU solved is compared on the sampled entries and on
-    ||x||; a pair the GPU refused is classified by what the oracle does with it."""
+def _oracle_pair(job):
+    """One (problem, rhs) pair of the batched workload through the oracle (worker)."""
     import numpy as np
     import scipy.sparse as sp
+    from threadpoolctl import threadpool_limits
 
     from oracle import arnoldi as oarn
     from oracle import methods as ometh
     from oracle import sketch as osk
     from workloads import batched_problem_params, convdiff_csr
 
-    d = np.load(path)
-    params = batched_problem_params(nprob)
-    pairs = {(int(p), int(r)): k for k, (p, r) in enumerate(zip(d["prob"], d["rhs"]))}
-    todo = sorted({(p, 0) for p in range(nprob)} | {pr for pr, k in pairs.items() if d["status"][k] != 0})
-    rows = []
-    worst = 0.0
-    for (pi, r) in todo:
-        k = pairs[(pi, r)]
-        q = params[pi]
+    pi, r, nprob = job
+    q = batched_problem_params(nprob)[pi]
+    with threadpool_limits(limits=1):
         rp, col, val = convdiff_csr(q["n"], 2, 1.0, q["c"])
         N = rp.size - 1
         A = sp.csr_matrix((val, col, rp), shape=(N, N))
         b = np.random.default_rng(q["rhs_seedseq"]).standard_normal((4, N))[r]
         S = osk.sparse_sign_matrix(N, q["s"], 8, q["sketch_seed"])
         arn = oarn.truncated_arnoldi(A, b, q["m"], 2, S)
+        out = {"N": N, "m": q["m"]}
         try:
             res = ometh.sfom_closed(arn, "invsqrt")
-            verdict, x = "ok", res.x
+            out.update(verdict="ok", m_used=res.m_used, xnorm=float(np.linalg.norm(res.x)),
+                       xs=res.x[sample_index(N)])
         except ometh.BranchError:
-            verdict, x = "branch", None
+            w = ometh.whiten(ometh.regularize(arn)[0])
+            ev = np.linalg.eigvals(w.M)
+            neg = ev[(np.abs(ev.imag) <= 1e-12 * np.max(np.abs(ev))) & (ev.real <= 0)]
+            out.update(verdict="branch", m_used=ometh.conditioned_prefix(arn),
+                       cut_eigs=[float(v.real) for v in neg])
+    return pi, r, out
+
+
+def check_batch_outputs(path, nprob):
+    """Oracle check of saved batched outputs (CPU): right-hand side 0 of every
+    problem, and every pair with a nonzero status, through the oracle's own run of
+    the same pair.  A pair the GPU solved is compared on the sampled entries and on
+    ||x||; a pair the GPU refused is classified by what the oracle does with it."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+
+    d = np.load(path)
+    pairs = {(int(p), int(r)): k for k, (p, r) in enumerate(zip(d["prob"], d["rhs"]))}
+    todo = sorted({(p, 0) for p in range(nprob)} | {pr for pr, k in pairs.items() if d["status"][k] != 0})
+    rows = []
+    worst = 0.0
+    with ProcessPoolExecutor(max_workers=host_threads()) as ex:
+        results = sorted(ex.map(_oracle_pair, [(p, r, nprob) for p, r in todo]), key=lambda t: (t[0], t[1]))
+    print("problem rhs N m gpu_status oracle gpu_m_used oracle_m_used rel_err_sampled rel_err_norm cut_eigs",
+          flush=True)
+    for pi, r, o in results:
+        k = pairs[(pi, r)]
         gst = int(d["status"][k])
-        if x is not None and gst == 0:
-            idx = sample_index(N)
-            xs = d["xs"][k][: idx.size]
-            e = float(np.linalg.norm(xs - x[idx]) / np.linalg.norm(x[idx]))
-            en = abs(float(d["xnorm"][k]) - np.linalg.norm(x)) / np.linalg.norm(x)
-            worst = max(worst, e, en)
-            rows.append((pi, r, N, q["m"], gst, verdict, f"{e:.2e}", f"{en:.2e}", int(d["m_used"][k]), res.m_used))
-        else:
-            rows.append((pi, r, N, q["m"], gst, verdict, "-", "-", int(d["m_used"][k]),
-                         res.m_used if x is not None else "-"))
+        e = en = "-"
+        if o["verdict"] == "ok" and gst == 0:
+            xs = d["xs"][k][: o["xs"].size]
+            ev = float(np.linalg.norm(xs - o["xs"]) / np.linalg.norm(o["xs"]))
+            evn = abs(float(d["xnorm"][k]) - o["xnorm"]) / o["xnorm"]
+            worst = max(worst, ev, evn)
+            e, en = f"{ev:.2e}", f"{evn:.2e}"
+        rows.append((pi, r, o["N"], o["m"], gst, o["verdict"], int(d["m_used"][k]), o["m_used"], e, en,
+                     ",".join(f"{v:.3g}" for v in o.get("cut_eigs", [])) or "-"))
         print(" ".join(str(v) for v in rows[-1]), flush=True)
     agree = sum(1 for row in rows if (row[4] == 0) == (row[5] == "ok"))
     print(json.dumps({"checked_pairs": len(rows), "status_agrees_with_oracle": agree,

@@ -129,6 +129,11 @@ typedef struct skfab_params {
                                for an extremely ill-conditioned R, see skfab_solve);
                                0 = the default of the precision (SKFAB_COND_MAX_FP64,
                                SKFAB_COND_MAX_FP32, SKFAB_COND_MAX_BF16); else >= 1   */
+    int32_t two_pass;       /* 1: the two-pass form of Section 4.2 (skfab_solve only): the
+                               first pass keeps the k + 1 basis vectors of the window and
+                               the sketches, the second reruns the recurrence and adds each
+                               regenerated vector to x; workspace O(kN) instead of O(mN),
+                               twice the products with A.  0: one pass, V_m kept      */
 } skfab_params;
 
 /* Default cond_max per precision.  FP64: rounding of the whitened problem stays near

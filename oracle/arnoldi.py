@@ -106,3 +106,32 @@ class _IdentityOp:
 
     def __matmul__(self, v):
         return np.array(v, dtype=np.float64, copy=True)
+
+
+def truncated_basis_vectors(A, b: np.ndarray, m: int, k: int):
+    """The basis vectors v_1, v_2, ... of the k-truncated recurrence, one at a time,
+    holding only the last k of them (the second pass of Section 4.2).  The same
+    operations in the same order as truncated_arnoldi; the vectors agree with the
+    first pass's to rounding (NumPy may sum the dot products of a strided column in
+    another order).  Stops early at a breakdown."""
+    beta = float(np.linalg.norm(b))
+    if beta == 0.0:
+        return
+    window = []
+    v = b / beta
+    for j in range(m):
+        yield v
+        if j == m - 1:
+            return
+        window.append(v)
+        if len(window) > k:
+            window.pop(0)
+        w = A @ v
+        norm_av = np.linalg.norm(w)
+        for vi in window[max(0, len(window) - k):]:
+            hij = float(vi @ w)
+            w = w - hij * vi
+        hnext = float(np.linalg.norm(w))
+        if hnext <= BREAKDOWN_TOL * norm_av:
+            return
+        v = w / hnext

@@ -419,3 +419,27 @@ def adaptive_m(A, b, f: str, k: int, S, m0: int, d: int, m_max: int, tol: float,
         prev = res
         m += d
     return res, m - d, est
+
+
+# ------------------------------------------------- two passes (Section 4.2) ---
+def two_pass(A, b, f: str, m: int, k: int, S, method: str = "sfom", fparam: float = 0.0, tol: float = 1e-13):
+    """Section 4.2: the first pass runs the k-truncated recurrence and keeps only the
+    sketches and coefficients (the basis vectors are not needed once the window has
+    moved past them); the small problem gives the coefficient vector y; the second
+    pass runs the recurrence again and accumulates x = sum_i y_i v_i, one vector at
+    a time.  Returns the small problem's SolveResult with this x."""
+    from .arnoldi import truncated_arnoldi, truncated_basis_vectors
+    arn = truncated_arnoldi(A, b, m, k, S)
+    # the first pass's data without the basis (a zero-height V: no N-sized work)
+    first = ArnoldiResult(np.zeros((0, arn.m_used)), arn.SV, arn.SAV, arn.H, arn.beta, arn.m_used)
+    if method == "sfom":
+        res = sfom_closed(first, f, fparam)
+    elif method == "sgmres":
+        res = sgmres(first, f, tol)
+    else:
+        res = sfom_quad(first, f, tol)
+    x = np.zeros(b.shape[0])
+    for i, v in enumerate(truncated_basis_vectors(A, b, arn.m_used, k)):
+        x += res.y[i] * v
+    res.x = x
+    return res

@@ -43,7 +43,7 @@ class skfab_params(C.Structure):
                 ("npoly", C.c_int32), ("method", C.c_int32), ("m", C.c_int32), ("k", C.c_int32),
                 ("s", C.c_int32), ("zeta", C.c_int32), ("seed", C.c_uint64), ("l1", C.c_int32),
                 ("l2", C.c_int32), ("lmax", C.c_int32), ("quad_tol", C.c_double), ("prec", C.c_int32),
-                ("cond_max", C.c_double)]
+                ("cond_max", C.c_double), ("two_pass", C.c_int32)]
 
 
 class skfab_info(C.Structure):

@@ -60,6 +60,8 @@ hipError_t launch_assemble(const void* U, int64_t ldU, int64_t N, int m, const D
                            double* x, int prec, hipStream_t st);
 hipError_t launch_norm1(const DevCtrl* ctrl, int m, const double* const* P, int count, double* norm1,
                         hipStream_t st);
+hipError_t launch_accum_basis(const void* Uj, int64_t N, int j, const DevCtrl* ctrl, const double* ys, double* x,
+                              int prec, hipStream_t st);
 hipError_t launch_hhat(const DevCtrl* ctrl, int m, const double* T1r, const double* X, int s, const double* H,
                        double tau, double* Ahat, double* norm1, hipStream_t st);
 hipError_t launch_combine(const DevCtrl* ctrl, int m, double a, const double* P, double b, const double* Q,
@@ -246,7 +248,7 @@ size_t vbytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 size_t wbytes(int prec) { return prec == 0 ? 8 : 4; }
 
 Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lmax, int npoly, bool with_basis,
-                   int prec, int k = 1) {
+                   int prec, int k = 1, int ucols = 0) {
     Layout ly;
     ly.L = step_launch(N > 0 ? N : 1, s, k);
     ly.ldU = (N + 63) / 64 * 64;
@@ -266,7 +268,7 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
     ly.gram = take((size_t)(m + 1) * KMAX * d);
     ly.colnorm2 = take((m + 1) * d);
     ly.scal = take((size_t)2 * NSC_MAX * G * d);
-    ly.U = with_basis ? take((size_t)ly.ldU * m * vbytes(prec)) : take(0);
+    ly.U = with_basis ? take((size_t)ly.ldU * (ucols > 0 ? ucols : m) * vbytes(prec)) : take(0);
     ly.W = with_basis ? take((size_t)2 * ly.ldU * wbytes(prec)) : take(0);
     ly.skpart = with_basis ? take((size_t)2 * G * 2 * s * d) : take(0);
     // SELL-64 copy of A: room for 25% more entries than nnz plus one padded row per slice
@@ -345,6 +347,9 @@ void defaults(const skfab_params* p, int* l1, int* l2, int* lmax, double* tol) {
 
 bool zeta_ok(int z) { return z == 2 || z == 4 || z == 8 || z == 16; }
 
+// Columns of the stored basis U: all m, or the k + 1 of the window (two-pass form).
+int basis_columns(const skfab_params* p) { return p->two_pass ? p->k + 1 : p->m; }
+
 // Largest kappa_F of the basis prefix used (Section 2.1 remedy): the caller's, or the
 // precision's default.
 double cond_max_of(const skfab_params* p) {
@@ -363,6 +368,7 @@ skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matri
     if (p->f < 0 || p->f > 3 || p->method < 0 || p->method > 2) return SKFAB_ERR_ARG;
     if (p->prec < SKFAB_PREC_FP64 || p->prec > SKFAB_PREC_FP32_BF16BASIS) return SKFAB_ERR_ARG;
     if (!(p->cond_max == 0.0 || p->cond_max >= 1.0)) return SKFAB_ERR_ARG;
+    if (p->two_pass != 0 && p->two_pass != 1) return SKFAB_ERR_ARG;
     // reduced precisions are built for the default sketch density and k <= 4
     if (p->prec != SKFAB_PREC_FP64 && (p->zeta != 8 || p->k > 4)) return SKFAB_ERR_ARG;
     if (p->m < 1 || p->m > MMAX) return SKFAB_ERR_SHAPE;
@@ -434,6 +440,7 @@ skfab_status arnoldi_setup(const skfab_csr* A, const double* b, const skfab_para
     a.k = p->k;
     a.m = m;
     a.G = ly.L.G;
+    a.uring = basis_columns(p);
     HIP_TRY(launch_fill(w.H, (int64_t)(m + 1) * m, 0.0, st));
     return SKFAB_OK;
 }
@@ -467,8 +474,9 @@ skfab_status arnoldi_tail(StepArgs& a, const skfab_params* p, const Layout& ly, 
 }
 
 skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, const skfab_params* p,
-                         const Layout& ly, const Ptrs& w, hipStream_t st) {
-    StepArgs a;
+                         const Layout& ly, const Ptrs& w, hipStream_t st, StepArgs* out = nullptr) {
+    StepArgs local;
+    StepArgs& a = out ? *out : local;
     skfab_status r = arnoldi_setup(A, b, p, ly, w, ctx->value_table, st, &a);
     if (r != SKFAB_OK) return r;
     for (int j = 0; j <= p->m; ++j) {
@@ -725,7 +733,8 @@ skfab_status skfab_workspace_bytes(const skfab_csr* A, const skfab_params* p, in
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    size_t total = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k).total;
+    size_t total = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k,
+                               basis_columns(p)).total;
     if (nrhs > 1 && multi_rhs_batched(p, nrhs)) {
         const skfab_batch_problem q = one_problem(A, nullptr, 0, nullptr, 0, p);
         const size_t tb = batch_ws_total(1, &q, nrhs, p);
@@ -768,15 +777,29 @@ skfab_status solve_one(skfab_ctx* ctx, const skfab_csr* A, const double* b, doub
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
-    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k);
+    const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k,
+                                  basis_columns(p));
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);
     hipStream_t st = ctx->stream;
-    skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st);
+    StepArgs a;
+    skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st, &a);
     if (r != SKFAB_OK) return r;
     r = run_small(p, ly, w, st);
     if (r != SKFAB_OK) return r;
+    if (p->two_pass) {
+        // Section 4.2, second pass: the same step launches regenerate u_0 .. u_{m-1}
+        // (bitwise: every sum has a fixed order), each added to x as it appears
+        const size_t vb = vbytes(p->prec);
+        for (int j = 0; j < p->m; ++j) {
+            r = arnoldi_step(ctx, a, p, ly, w, j, st);
+            if (r != SKFAB_OK) return r;
+            const char* uj = static_cast<const char*>(w.U) + (size_t)(j % (p->k + 1)) * ly.ldU * vb;
+            HIP_TRY(launch_accum_basis(uj, A->n, j, w.ctrl, w.ys, x, p->prec, st));
+        }
+        return read_info(w, st, info);
+    }
     hipEvent_t stop;
     HIP_TRY(timing_begin(ctx, 1, st, &stop));
     HIP_TRY(launch_assemble(w.U, ly.ldU, A->n, p->m, w.ctrl, w.ys, x, p->prec, st));
@@ -794,6 +817,7 @@ skfab_status skfab_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, 
     skfab_status v = validate(A, p, true);
     if (v == SKFAB_ERR_ARG && p && p->f == SKFAB_F_EXP) v = SKFAB_OK;  // the basis does not depend on f
     if (v != SKFAB_OK) return v;
+    if (p->two_pass) return SKFAB_ERR_ARG;  // exports the whole basis
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
@@ -926,6 +950,7 @@ skfab_status validate_batch(int32_t nprob, const skfab_batch_problem* probs, int
     if (p->method < 0 || p->method > 2) return SKFAB_ERR_ARG;
     if (p->prec < SKFAB_PREC_FP64 || p->prec > SKFAB_PREC_FP32_BF16BASIS) return SKFAB_ERR_ARG;
     if (!(p->cond_max == 0.0 || p->cond_max >= 1.0)) return SKFAB_ERR_ARG;
+    if (p->two_pass) return SKFAB_ERR_ARG;  // the batched form keeps every basis
     if (p->zeta != 8 || p->k < 1 || p->k > 4) return SKFAB_ERR_ARG;
     int l1, l2, lmax;
     double tol;
@@ -946,7 +971,7 @@ skfab_status validate_batch(int32_t nprob, const skfab_batch_problem* probs, int
 
 // Multi-RHS solves of skfab_solve go through the batched form when it covers them.
 bool multi_rhs_batched(const skfab_params* p, int nrhs) {
-    return nrhs >= 1 && nrhs <= BATCH_MAX_RHS && (p->f == SKFAB_F_INVSQRT || p->f == SKFAB_F_INV) &&
+    return nrhs >= 1 && nrhs <= BATCH_MAX_RHS && !p->two_pass && (p->f == SKFAB_F_INVSQRT || p->f == SKFAB_F_INV) &&
            p->zeta == 8 && p->k >= 1 && p->k <= 4;
 }
 
@@ -1133,6 +1158,7 @@ void batch_descriptors(const BatchLayout& L, const BatchPlan& P, const skfab_bat
             a.s = q.s;
             a.k = p->k;
             a.m = q.m;
+            a.uring = q.m;
             a.G = P.G[qi];
             BatchStepUnit& b = su[u];
             b.a = a;
@@ -1431,7 +1457,7 @@ skfab_status skfab_solve_adaptive(skfab_ctx* ctx, const skfab_csr* A, const doub
     if (!ctx || !b || !x) return SKFAB_ERR_ARG;
     skfab_status v = validate(A, p, true);
     if (v != SKFAB_OK) return v;
-    if (p->method != SKFAB_SFOM_CLOSED) return SKFAB_ERR_ARG;
+    if (p->method != SKFAB_SFOM_CLOSED || p->two_pass) return SKFAB_ERR_ARG;
     if (d < 1 || m0 < p->k || m0 > p->m || !(tol > 0.0)) return SKFAB_ERR_ARG;
     const AdaptiveLayout L = make_adaptive_layout(A, p);
     if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;

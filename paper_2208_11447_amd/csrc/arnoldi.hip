@@ -314,10 +314,12 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     const GAS WT* __restrict__ Wp = gptr(static_cast<const WT*>(a.Wprev));
     const GAS double* __restrict__ b0p = gptr(a.b);
     const bool first_all = (j == 0);
+    // basis vector c in column c % uring (a ring of k + 1 columns in the two-pass form)
+    const int ur = a.uring;
     const GAS VT* Uo[KW];
 #pragma unroll
-    for (int o = 0; o < KW; ++o) Uo[o] = gptr(static_cast<const VT*>(a.U)) + (int64_t)((o < nwin_all) ? (j - 1 - o) : 0) * a.ldU;
-    GAS VT* __restrict__ Uj = gptr(static_cast<VT*>(a.U)) + (int64_t)(a.extend ? 0 : j) * a.ldU;
+    for (int o = 0; o < KW; ++o) Uo[o] = gptr(static_cast<const VT*>(a.U)) + (int64_t)((o < nwin_all) ? (j - 1 - o) % ur : 0) * a.ldU;
+    GAS VT* __restrict__ Uj = gptr(static_cast<VT*>(a.U)) + (int64_t)(a.extend ? 0 : j % ur) * a.ldU;
     GAS WT* __restrict__ Wc = gptr(static_cast<WT*>(a.Wcur));
     const GAS AT* __restrict__ slv = gptr(static_cast<const AT*>(a.sl_val));
     const GAS int32_t* __restrict__ sl_col = gptr(a.sl_col);

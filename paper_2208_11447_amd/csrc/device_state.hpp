@@ -98,6 +98,9 @@ struct StepArgs {
     double inv_sqrt_zeta;
     int32_t s, k, j, m, G;
     int32_t extend;   // 1: form u_m and its sketch only (no product with A)
+    int32_t uring;    // columns of U: basis vector c lives in column c % uring (m, or k + 1
+                      // for the two-pass form, whose first pass keeps only the window)
+    int32_t pad;
 };
 
 // One (problem, right-hand side) pair of a batched solve: the step arguments

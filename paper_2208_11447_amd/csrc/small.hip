@@ -1324,7 +1324,39 @@ __global__ __launch_bounds__(256) void assemble_batched_kernel(const SmallUnit* 
     assemble_body<VT>(static_cast<const VT*>(u.U), u.ldU, u.N, m, u.ctrl, u.ys, u.x);
 }
 
+// Second pass of the two-pass form (Section 4.2): x += ys[j] u_j with the basis
+// vector u_j just regenerated in its ring column (x = 0 before j = 0).  Steps at or
+// beyond m_used (breakdown, or the conditioned prefix) add nothing.
+template <typename VT>
+__global__ __launch_bounds__(256) void accum_basis_kernel(const VT* __restrict__ Uj, int64_t N, int j,
+                                                          const DevCtrl* ctrl, const double* __restrict__ ys,
+                                                          double* __restrict__ x) {
+    const int mu = ctrl->m_used;
+    const bool add = j < mu;
+    const double c = add ? ys[j] : 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < N; r += (int64_t)gridDim.x * blockDim.x) {
+        const double base = (j == 0) ? 0.0 : x[r];
+        x[r] = add ? fma(c, to_w<double>(Uj[r]), base) : base;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
+hipError_t launch_accum_basis(const void* Uj, int64_t N, int j, const DevCtrl* ctrl, const double* ys, double* x,
+                              int prec, hipStream_t st) {
+    int64_t g = (N + 255) / 256;
+    const dim3 grid((unsigned)(g < 4096 ? g : 4096));
+    if (prec == 1)
+        hipLaunchKernelGGL(accum_basis_kernel<float>, grid, dim3(256), 0, st, static_cast<const float*>(Uj), N, j,
+                           ctrl, ys, x);
+    else if (prec == 2)
+        hipLaunchKernelGGL(accum_basis_kernel<bf16s>, grid, dim3(256), 0, st, static_cast<const bf16s*>(Uj), N, j,
+                           ctrl, ys, x);
+    else
+        hipLaunchKernelGGL(accum_basis_kernel<double>, grid, dim3(256), 0, st, static_cast<const double*>(Uj), N, j,
+                           ctrl, ys, x);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(double* p, int64_t n, double v, hipStream_t st) {
     if (n <= 0) return hipSuccess;
     int64_t g = (n + 255) / 256;

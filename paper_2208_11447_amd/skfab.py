@@ -70,7 +70,8 @@ class CSR:
 
 
 def make_params(f="invsqrt", m=50, k=2, s=200, zeta=8, seed=0, method="sfom", fparam=0.0, poly=None,
-                l1=32, l2=45, lmax=1395, quad_tol=1e-13, prec="fp64", cond_max=0.0) -> N.skfab_params:
+                l1=32, l2=45, lmax=1395, quad_tol=1e-13, prec="fp64", cond_max=0.0,
+                two_pass=False) -> N.skfab_params:
     p = N.skfab_params()
     p.f = FUNCS[f] if isinstance(f, str) else int(f)
     p.fparam = float(fparam)
@@ -79,6 +80,7 @@ def make_params(f="invsqrt", m=50, k=2, s=200, zeta=8, seed=0, method="sfom", fp
     p.l1, p.l2, p.lmax, p.quad_tol = int(l1), int(l2), int(lmax), float(quad_tol)
     p.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
     p.cond_max = float(cond_max)
+    p.two_pass = 1 if two_pass else 0
     if poly is not None:
         arr = (C.c_double * len(poly))(*[float(c) for c in poly])
         p.poly = C.cast(arr, C.POINTER(C.c_double))

@@ -324,3 +324,28 @@ def test_quadrature_reporting():
             assert tol < info.quad_diff <= 1e-10
         else:
             assert 0.0 <= info.quad_diff <= tol
+
+
+@pytest.mark.parametrize("method,f,tau", [("sfom", "invsqrt", 0.0), ("sgmres", "invsqrt", 0.0),
+                                          ("sfom", "exp", 1e-3)])
+def test_two_pass_form(method, f, tau):
+    """Section 4.2 two-pass form: the first pass keeps k + 1 basis vectors, the second
+    regenerates them (bitwise, fixed-order sums) and accumulates x.  Its x equals the
+    one-pass x to rounding and the oracle's two-pass result to the FP64 tolerance; its
+    workspace holds k + 1 instead of m basis vectors."""
+    A, b, arrs = problem(100, seed=2)
+    m, k, s = 50, 2, 200
+    Ad = device_csr(arrs)
+    p1 = sk.make_params(f=f, fparam=tau, m=m, k=k, s=s, method=method)
+    p2 = sk.make_params(f=f, fparam=tau, m=m, k=k, s=s, method=method, two_pass=True)
+    ws1, ws2 = sk.skfab_workspace_bytes(Ad, p1), sk.skfab_workspace_bytes(Ad, p2)
+    assert ws1 - ws2 >= (m - k - 1) * A.shape[0] * 8
+    log(f"two-pass {method} {f}: workspace {ws2 / 2**20:.1f} MiB vs one-pass {ws1 / 2**20:.1f} MiB")
+    x1, i1 = gpu_solve(arrs, b, f=f, fparam=tau, m=m, k=k, s=s, method=method)
+    x2, i2 = gpu_solve(arrs, b, f=f, fparam=tau, m=m, k=k, s=s, method=method, two_pass=True)
+    assert i1.status == 0 and i2.status == 0 and i2.m_used == m
+    S = osk.sparse_sign_matrix(A.shape[0], s, 8, 0)
+    ref = ometh.two_pass(A, b, f, m, k, S, method, fparam=tau).x
+    e12, eor = rel(x2, x1), rel(x2, ref)
+    log(f"  two-pass vs one-pass {e12:.2e}, vs oracle {eor:.2e}")
+    assert e12 <= 1e-14 and eor < FP64_TOL

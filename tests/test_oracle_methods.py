@@ -329,3 +329,34 @@ def test_sgmres_node_solutions_satisfy_normal_equations():
         P = ti * arn.SV + arn.SAV
         r = w.Sb - P @ y
         assert np.linalg.norm(P.T @ r) <= 1e-9 * np.linalg.norm(P, 2) * np.linalg.norm(w.Sb)
+
+
+@pytest.mark.parametrize("method", ["sfom", "sgmres", "sfom_quad"])
+def test_two_pass_equals_one_pass(method):
+    """Section 4.2: discarding the basis in the first pass and regenerating it in the
+    second gives the one-pass approximant V_m y (to rounding)."""
+    A, b, S = small_problem()
+    m, k = 18, 2
+    arn = arn_mod.truncated_arnoldi(A, b, m, k, S)
+    one = {"sfom": lambda: methods.sfom_closed(arn, "invsqrt"),
+           "sgmres": lambda: methods.sgmres(arn, "invsqrt"),
+           "sfom_quad": lambda: methods.sfom_quad(arn, "invsqrt")}[method]().x
+    two = methods.two_pass(A, b, "invsqrt", m, k, S, method).x
+    assert rel(two, one) < 1e-13
+    vs = list(arn_mod.truncated_basis_vectors(A, b, m, k))
+    assert len(vs) == m
+    assert max(np.max(np.abs(v - arn.V[:, i])) for i, v in enumerate(vs)) < 1e-13
+
+
+def test_two_pass_breakdown_and_exp():
+    """The second pass stops where the first broke down; closed-form exp as well."""
+    rng = np.random.default_rng(4)
+    blk = np.diag([2.0, 3.0, 5.0]) + 0.3 * rng.standard_normal((3, 3))
+    A = sp.block_diag([blk, sp.diags(np.linspace(1, 9, 40))]).tocsr()
+    b = np.zeros(43)
+    b[:3] = rng.standard_normal(3)
+    S = sketch.sparse_sign_matrix(43, 20, 8, 1)
+    res = methods.two_pass(A, b, "exp", 8, 3, S, fparam=0.1)
+    truth = np.zeros(43)
+    truth[:3] = sla.expm(-0.1 * blk) @ b[:3]
+    assert res.m_used == 3 and rel(res.x, truth) < 1e-10
