@@ -94,6 +94,18 @@ typedef enum skfab_prec {
                                       multiplied by A and sketched                      */
 } skfab_prec;
 
+/* Sketch S of the method (the s x N subspace embedding of Section 1, eq. sketch). */
+typedef enum skfab_sketch {
+    SKFAB_SKETCH_SPARSE_SIGN = 0,  /* zeta nonzeros +-1/sqrt(zeta) per column, drawn by a
+                                      counter-based hash inside the step kernel (see
+                                      skfab_sketch_pattern); never stored              */
+    SKFAB_SKETCH_SRDCT = 1         /* subsampled randomized DCT S = sqrt(N/s) P F E of
+                                      Section 5.1: E = diag(srdct_signs), F the orthonormal
+                                      DCT-II, P the srdct_rows of F E; applied to the
+                                      stored basis after the recurrence (FP64 matrix
+                                      cores); workspace + 8 s N bytes                 */
+} skfab_sketch;
+
 typedef enum skfab_valtype {
     SKFAB_VAL_F64 = 0
 } skfab_valtype;
@@ -129,6 +141,11 @@ typedef struct skfab_params {
                                for an extremely ill-conditioned R, see skfab_solve);
                                0 = the default of the precision (SKFAB_COND_MAX_FP64,
                                SKFAB_COND_MAX_FP32, SKFAB_COND_MAX_BF16); else >= 1   */
+    int32_t sketch;         /* skfab_sketch (default 0: sparse sign).  SRDCT: skfab_solve
+                               with one pass only; zeta and seed are not used           */
+    const int8_t *srdct_signs;  /* SRDCT: DEVICE int8[N], the +-1 diagonal of E          */
+    const int32_t *srdct_rows;  /* SRDCT: DEVICE int32[s], the rows of F E kept by P,
+                               distinct, in [0, N); the draws are the caller's          */
     int32_t two_pass;       /* 1: the two-pass form of Section 4.2 (skfab_solve only): the
                                first pass keeps the k + 1 basis vectors of the window and
                                the sketches, the second reruns the recurrence and adds each
@@ -299,6 +316,18 @@ skfab_status skfab_sketch_apply(skfab_ctx *ctx, int64_t n, int32_t s, int32_t ze
                                 uint64_t seed, const double *v, double *Sv,
                                 void *ws, size_t ws_bytes);
 size_t skfab_sketch_ws_bytes(int64_t n, int32_t s);
+
+/* Test hook: SV <- S V for the SRDCT sketch S = sqrt(N/s) P F E (Section 5.1): V device
+ * n x ncols column-major (ld ldv >= n), SV device s x ncols (ld s); signs (int8[n], +-1)
+ * and rows (int32[s], distinct, in [0, n)) device arrays.  The contraction used by
+ * skfab_solve with SKFAB_SKETCH_SRDCT (F_P formed in ws, then FP64 matrix cores, partial
+ * tiles summed in a fixed order).  ws: skfab_srdct_ws_bytes(n, s, ncols) bytes.
+ * Errors: SKFAB_ERR_ARG (null pointers), SKFAB_ERR_SHAPE (s > n, ldv < n, sizes < 1),
+ * SKFAB_ERR_WORKSPACE. */
+size_t skfab_srdct_ws_bytes(int64_t n, int32_t s, int32_t ncols);
+skfab_status skfab_srdct_apply(skfab_ctx *ctx, int64_t n, int32_t s, const int8_t *signs,
+                               const int32_t *rows, const double *V, int64_t ldv, int32_t ncols,
+                               double *SV, void *ws, size_t ws_bytes);
 
 /* Value-table storage of A (on by default; FP64 form).  When A has at most 256
  * distinct values (the padding value 0.0 counted), the SELL-64 copy of A made by

@@ -125,3 +125,23 @@ def sparse_sign_matrix(N: int, s: int, zeta: int = 8, seed: int = 0) -> sp.csc_m
 def apply_sketch(S, v: np.ndarray) -> np.ndarray:
     """S @ v (plain sparse product)."""
     return S @ v
+
+
+# ------------------------------------------------------------ SRDCT (Section 5.1)
+def dct_matrix(N: int, rows=None) -> np.ndarray:
+    """Rows of the orthonormal DCT-II matrix F (N x N): F[k, i] = c_k cos(pi k (2i + 1)
+    / (2N)), c_0 = sqrt(1/N), c_k = sqrt(2/N) for k >= 1.  The angle is reduced
+    exactly in integers: k (2i + 1) mod 4N."""
+    k = np.arange(N, dtype=np.int64) if rows is None else np.asarray(rows, dtype=np.int64)
+    i = np.arange(N, dtype=np.int64)
+    q = (k[:, None] * (2 * i[None, :] + 1)) % (4 * N)
+    c = np.where(k == 0, np.sqrt(1.0 / N), np.sqrt(2.0 / N))
+    return c[:, None] * np.cos(np.pi * q / (2.0 * N))
+
+
+def srdct_matrix(N: int, signs: np.ndarray, rows: np.ndarray) -> np.ndarray:
+    """S = sqrt(N/s) P F E as a dense s x N matrix (E = diag(signs), P selects
+    `rows` of F E).  The factor sqrt(N/s) makes E ||S v||^2 = ||v||^2 over the
+    uniform choice of the s rows."""
+    s = len(rows)
+    return np.sqrt(N / s) * dct_matrix(N, rows) * np.asarray(signs, dtype=np.float64)[None, :]

@@ -20,12 +20,13 @@ SKFAB_SFOM_CLOSED, SKFAB_SFOM_QUAD, SKFAB_SGMRES_QUAD = range(3)
 SKFAB_PREC_FP64, SKFAB_PREC_FP32, SKFAB_PREC_FP32_BF16BASIS = range(3)
 SKFAB_VAL_F64 = 0
 SKFAB_FLAG_TRUNCATED, SKFAB_FLAG_QUAD_FLOOR = 1, 2
+SKFAB_SKETCH_SPARSE_SIGN, SKFAB_SKETCH_SRDCT = 0, 1
 
 EXPORTED = [
     "skfab_version", "skfab_status_string", "skfab_create", "skfab_set_stream", "skfab_destroy",
     "skfab_workspace_bytes", "skfab_solve", "skfab_solve_noalloc", "skfab_arnoldi", "skfab_small_problem",
     "skfab_small_workspace_bytes", "skfab_sketch_pattern", "skfab_sketch_apply", "skfab_sketch_ws_bytes",
-    "skfab_timing_enable", "skfab_timing_read", "skfab_set_value_table",
+    "skfab_timing_enable", "skfab_timing_read", "skfab_set_value_table", "skfab_srdct_ws_bytes", "skfab_srdct_apply",
     "skfab_batch_workspace_bytes", "skfab_solve_batched", "skfab_batch_set_tuning", "skfab_batch_get_tuning",
     "skfab_batch_autotune",
     "skfab_adaptive_workspace_bytes", "skfab_solve_adaptive", "skfab_gershgorin_ws_bytes", "skfab_gershgorin",
@@ -43,7 +44,8 @@ class skfab_params(C.Structure):
                 ("npoly", C.c_int32), ("method", C.c_int32), ("m", C.c_int32), ("k", C.c_int32),
                 ("s", C.c_int32), ("zeta", C.c_int32), ("seed", C.c_uint64), ("l1", C.c_int32),
                 ("l2", C.c_int32), ("lmax", C.c_int32), ("quad_tol", C.c_double), ("prec", C.c_int32),
-                ("cond_max", C.c_double), ("two_pass", C.c_int32)]
+                ("cond_max", C.c_double), ("sketch", C.c_int32), ("srdct_signs", C.c_void_p),
+                ("srdct_rows", C.c_void_p), ("two_pass", C.c_int32)]
 
 
 class skfab_info(C.Structure):
@@ -96,6 +98,8 @@ def lib():
         "skfab_sketch_apply": (C.c_int, [P, C.c_int64, C.c_int32, C.c_int32, C.c_uint64, P, P, P, C.c_size_t]),
         "skfab_sketch_ws_bytes": (C.c_size_t, [C.c_int64, C.c_int32]),
         "skfab_timing_enable": (C.c_int, [P, C.c_int32]),
+        "skfab_srdct_ws_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32]),
+        "skfab_srdct_apply": (C.c_int, [P, C.c_int64, C.c_int32, P, P, P, C.c_int64, C.c_int32, P, P, C.c_size_t]),
         "skfab_set_value_table": (C.c_int, [P, C.c_int32]),
         "skfab_timing_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "skfab_batch_workspace_bytes": (C.c_int, [C.c_int32, C.POINTER(skfab_batch_problem), C.c_int32,

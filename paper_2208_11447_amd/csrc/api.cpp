@@ -62,6 +62,13 @@ hipError_t launch_norm1(const DevCtrl* ctrl, int m, const double* const* P, int 
                         hipStream_t st);
 hipError_t launch_accum_basis(const void* Uj, int64_t N, int j, const DevCtrl* ctrl, const double* ys, double* x,
                               int prec, hipStream_t st);
+hipError_t launch_colnorm(const double* SV, int s, int m, const DevCtrl* ctrl, double* colnorm2, hipStream_t st);
+size_t srdct_part_doubles(int s, int64_t N, int ncols);
+hipError_t launch_srdct_matrix(int s, int64_t N, const int8_t* signs, const int32_t* rows, double* FP,
+                               hipStream_t st);
+hipError_t launch_srdct_sketch(const double* FP, int s, int64_t N, const void* U, int64_t ldU, int ncols, int prec,
+                               double* part, const DevCtrl* ctrl, const double* eta, double* SV, int64_t ldS,
+                               hipStream_t st);
 hipError_t launch_hhat(const DevCtrl* ctrl, int m, const double* T1r, const double* X, int s, const double* H,
                        double tau, double* Ahat, double* norm1, hipStream_t st);
 hipError_t launch_combine(const DevCtrl* ctrl, int m, double a, const double* P, double b, const double* Q,
@@ -197,7 +204,7 @@ int next_order(int l) {
 
 struct Layout {
     size_t ctrl, eta, wnorm, H, gram, colnorm2, scal, U, W, skpart, SV, SAV, Tws, K0r, T1r, Hh, Ubuf, Urhs, nodebuf,
-        qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, chk, cnd, sl_len, sl_ptr, bsum, sl_col, sl_val, dict, total;
+        qprev, qcur, y, ys, y0, poly, expbuf, piv, norm1, chk, cnd, srfp, srpart, sl_len, sl_ptr, bsum, sl_col, sl_val, dict, total;
     int64_t ldU;
     int64_t sell_capacity;
     int lnodes;
@@ -248,7 +255,7 @@ size_t vbytes(int prec) { return prec == 0 ? 8 : (prec == 1 ? 4 : 2); }
 size_t wbytes(int prec) { return prec == 0 ? 8 : 4; }
 
 Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lmax, int npoly, bool with_basis,
-                   int prec, int k = 1, int ucols = 0) {
+                   int prec, int k = 1, int ucols = 0, bool srdct = false) {
     Layout ly;
     ly.L = step_launch(N > 0 ? N : 1, s, k);
     ly.ldU = (N + 63) / 64 * 64;
@@ -281,6 +288,9 @@ Layout make_layout(int64_t N, int64_t nnz, int m, int s, int l1, int l2, int lma
     ly.dict = with_basis ? take(sizeof(DictBuf)) : take(0);
     ly.chk = take((size_t)2 * m * d);
     ly.cnd = take((size_t)2 * (m + 1) * d);
+    // SRDCT sketch: F_P (s x N) and the partial tiles of the contraction
+    ly.srfp = (srdct && with_basis) ? take((size_t)s * N * d) : take(0);
+    ly.srpart = (srdct && with_basis) ? take(srdct_part_doubles(s, N, m + 1) * d) : take(0);
     ly.SV = take((size_t)s * (m + 1) * d);
     ly.SAV = take((size_t)s * m * d);
     ly.Tws = take((size_t)QR_NB_HOST * QR_NB_HOST * d);
@@ -307,7 +317,7 @@ struct Ptrs {
     DevCtrl* ctrl;
     void *U, *W;
     double *eta, *wnorm, *H, *gram, *colnorm2, *scal, *skpart, *SV, *SAV, *Tws, *K0r, *T1r, *Hh, *Ubuf, *Urhs,
-        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1, *chk, *cnd;
+        *nodebuf, *qprev, *qcur, *y, *ys, *y0, *poly, *expbuf, *norm1, *chk, *cnd, *srfp, *srpart;
     void* sl_val;
     DictBuf* dict;
     int* piv;
@@ -329,6 +339,8 @@ Ptrs carve(void* ws, const Layout& ly) {
     p.piv = reinterpret_cast<int*>(b + ly.piv);
     p.chk = D(ly.chk);
     p.cnd = D(ly.cnd);
+    p.srfp = D(ly.srfp);
+    p.srpart = D(ly.srpart);
     p.sl_val = b + ly.sl_val;
     p.dict = reinterpret_cast<DictBuf*>(b + ly.dict);
     p.sl_len = reinterpret_cast<int32_t*>(b + ly.sl_len);
@@ -348,7 +360,10 @@ void defaults(const skfab_params* p, int* l1, int* l2, int* lmax, double* tol) {
 bool zeta_ok(int z) { return z == 2 || z == 4 || z == 8 || z == 16; }
 
 // Columns of the stored basis U: all m, or the k + 1 of the window (two-pass form).
-int basis_columns(const skfab_params* p) { return p->two_pass ? p->k + 1 : p->m; }
+int basis_columns(const skfab_params* p) {
+    if (p->sketch == SKFAB_SKETCH_SRDCT) return p->m + 1;  // u_{m+1} kept for the sketch
+    return p->two_pass ? p->k + 1 : p->m;
+}
 
 // Largest kappa_F of the basis prefix used (Section 2.1 remedy): the caller's, or the
 // precision's default.
@@ -369,13 +384,19 @@ skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matri
     if (p->prec < SKFAB_PREC_FP64 || p->prec > SKFAB_PREC_FP32_BF16BASIS) return SKFAB_ERR_ARG;
     if (!(p->cond_max == 0.0 || p->cond_max >= 1.0)) return SKFAB_ERR_ARG;
     if (p->two_pass != 0 && p->two_pass != 1) return SKFAB_ERR_ARG;
+    if (p->sketch != SKFAB_SKETCH_SPARSE_SIGN && p->sketch != SKFAB_SKETCH_SRDCT) return SKFAB_ERR_ARG;
+    if (p->sketch == SKFAB_SKETCH_SRDCT) {
+        // the SRDCT sketch is applied to the stored basis: one pass only
+        if (p->two_pass) return SKFAB_ERR_ARG;
+        if (need_matrix && (!p->srdct_signs || !p->srdct_rows)) return SKFAB_ERR_ARG;
+    }
     // reduced precisions are built for the default sketch density and k <= 4
     if (p->prec != SKFAB_PREC_FP64 && (p->zeta != 8 || p->k > 4)) return SKFAB_ERR_ARG;
     if (p->m < 1 || p->m > MMAX) return SKFAB_ERR_SHAPE;
     if (p->k < 1 || p->k > KMAX || p->k > p->m) return SKFAB_ERR_SHAPE;
     if (p->s <= p->m || p->s > SMAX) return SKFAB_ERR_SHAPE;
     if (need_matrix && p->s > A->n) return SKFAB_ERR_SHAPE;
-    if (!zeta_ok(p->zeta) || p->zeta > p->s) return SKFAB_ERR_SHAPE;
+    if (p->sketch == SKFAB_SKETCH_SPARSE_SIGN && (!zeta_ok(p->zeta) || p->zeta > p->s)) return SKFAB_ERR_SHAPE;
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
@@ -441,6 +462,8 @@ skfab_status arnoldi_setup(const skfab_csr* A, const double* b, const skfab_para
     a.m = m;
     a.G = ly.L.G;
     a.uring = basis_columns(p);
+    a.nosketch = p->sketch == SKFAB_SKETCH_SRDCT ? 1 : 0;
+    a.keep_ext = a.nosketch;
     HIP_TRY(launch_fill(w.H, (int64_t)(m + 1) * m, 0.0, st));
     return SKFAB_OK;
 }
@@ -566,7 +589,8 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     defaults(p, &l1, &l2, &lmax, &tol);
     if (p->method == SKFAB_SFOM_CLOSED) tol = 1e-13;
     const bool ls = p->method == SKFAB_SGMRES_QUAD;
-    HIP_TRY(launch_arnoldi_check(w.SV, w.SAV, w.H, s, m, p->k, w.ctrl, w.chk, st));
+    if (p->sketch == SKFAB_SKETCH_SPARSE_SIGN)  // (the SRDCT path forms no S A V_m)
+        HIP_TRY(launch_arnoldi_check(w.SV, w.SAV, w.H, s, m, p->k, w.ctrl, w.chk, st));
     HIP_TRY(launch_qr(w.SV, s, m + 1, w.ctrl, w.Tws, st));
     // Section 2.1 remedy: the longest basis prefix whose sketch is conditioned
     HIP_TRY(launch_cond_trunc(w.SV, s, m, w.ctrl, w.H, w.cnd, cond_max_of(p), st));
@@ -734,7 +758,7 @@ skfab_status skfab_workspace_bytes(const skfab_csr* A, const skfab_params* p, in
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
     size_t total = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k,
-                               basis_columns(p)).total;
+                               basis_columns(p), p->sketch == SKFAB_SKETCH_SRDCT).total;
     if (nrhs > 1 && multi_rhs_batched(p, nrhs)) {
         const skfab_batch_problem q = one_problem(A, nullptr, 0, nullptr, 0, p);
         const size_t tb = batch_ws_total(1, &q, nrhs, p);
@@ -778,14 +802,22 @@ skfab_status solve_one(skfab_ctx* ctx, const skfab_csr* A, const double* b, doub
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
     const Layout ly = make_layout(A->n, A->nnz, p->m, p->s, l1, l2, lmax, p->npoly, true, p->prec, p->k,
-                                  basis_columns(p));
+                                  basis_columns(p), p->sketch == SKFAB_SKETCH_SRDCT);
     if (!ws || ws_bytes < ly.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);
     hipStream_t st = ctx->stream;
+    const bool srdct = p->sketch == SKFAB_SKETCH_SRDCT;
+    if (srdct) HIP_TRY(launch_srdct_matrix(p->s, A->n, p->srdct_signs, p->srdct_rows, w.srfp, st));
     StepArgs a;
     skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st, &a);
     if (r != SKFAB_OK) return r;
+    if (srdct) {
+        // [S v_1 .. S v_m, S u_{m+1}]: the stored basis times F_P (FP64 matrix cores)
+        HIP_TRY(launch_srdct_sketch(w.srfp, p->s, A->n, w.U, ly.ldU, p->m + 1, p->prec, w.srpart, w.ctrl, w.eta,
+                                    w.SV, p->s, st));
+        HIP_TRY(launch_colnorm(w.SV, p->s, p->m, w.ctrl, w.colnorm2, st));
+    }
     r = run_small(p, ly, w, st);
     if (r != SKFAB_OK) return r;
     if (p->two_pass) {
@@ -817,7 +849,7 @@ skfab_status skfab_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, 
     skfab_status v = validate(A, p, true);
     if (v == SKFAB_ERR_ARG && p && p->f == SKFAB_F_EXP) v = SKFAB_OK;  // the basis does not depend on f
     if (v != SKFAB_OK) return v;
-    if (p->two_pass) return SKFAB_ERR_ARG;  // exports the whole basis
+    if (p->two_pass || p->sketch != SKFAB_SKETCH_SPARSE_SIGN) return SKFAB_ERR_ARG;  // hook of the fused sketch
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
@@ -951,6 +983,7 @@ skfab_status validate_batch(int32_t nprob, const skfab_batch_problem* probs, int
     if (p->prec < SKFAB_PREC_FP64 || p->prec > SKFAB_PREC_FP32_BF16BASIS) return SKFAB_ERR_ARG;
     if (!(p->cond_max == 0.0 || p->cond_max >= 1.0)) return SKFAB_ERR_ARG;
     if (p->two_pass) return SKFAB_ERR_ARG;  // the batched form keeps every basis
+    if (p->sketch != SKFAB_SKETCH_SPARSE_SIGN) return SKFAB_ERR_ARG;
     if (p->zeta != 8 || p->k < 1 || p->k > 4) return SKFAB_ERR_ARG;
     int l1, l2, lmax;
     double tol;
@@ -971,7 +1004,8 @@ skfab_status validate_batch(int32_t nprob, const skfab_batch_problem* probs, int
 
 // Multi-RHS solves of skfab_solve go through the batched form when it covers them.
 bool multi_rhs_batched(const skfab_params* p, int nrhs) {
-    return nrhs >= 1 && nrhs <= BATCH_MAX_RHS && !p->two_pass && (p->f == SKFAB_F_INVSQRT || p->f == SKFAB_F_INV) &&
+    return nrhs >= 1 && nrhs <= BATCH_MAX_RHS && !p->two_pass && p->sketch == SKFAB_SKETCH_SPARSE_SIGN &&
+           (p->f == SKFAB_F_INVSQRT || p->f == SKFAB_F_INV) &&
            p->zeta == 8 && p->k >= 1 && p->k <= 4;
 }
 
@@ -1300,6 +1334,25 @@ skfab_status skfab_batch_workspace_bytes(int32_t nprob, const skfab_batch_proble
     return SKFAB_OK;
 }
 
+size_t skfab_srdct_ws_bytes(int64_t n, int32_t s, int32_t ncols) {
+    if (n < 1 || s < 1 || ncols < 1) return 0;
+    return align_up((size_t)s * n * sizeof(double)) + align_up(srdct_part_doubles(s, n, ncols) * sizeof(double));
+}
+
+skfab_status skfab_srdct_apply(skfab_ctx* ctx, int64_t n, int32_t s, const int8_t* signs, const int32_t* rows,
+                               const double* V, int64_t ldv, int32_t ncols, double* SV, void* ws, size_t ws_bytes) {
+    if (!ctx || !signs || !rows || !V || !SV) return SKFAB_ERR_ARG;
+    if (n < 1 || s < 1 || s > n || ncols < 1 || ldv < n) return SKFAB_ERR_SHAPE;
+    const size_t need = skfab_srdct_ws_bytes(n, s, ncols);
+    if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;
+    if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
+    double* FP = static_cast<double*>(ws);
+    double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + align_up((size_t)s * n * sizeof(double)));
+    HIP_TRY(launch_srdct_matrix(s, n, signs, rows, FP, ctx->stream));
+    HIP_TRY(launch_srdct_sketch(FP, s, n, V, ldv, ncols, 0, part, nullptr, nullptr, SV, s, ctx->stream));
+    return SKFAB_OK;
+}
+
 skfab_status skfab_set_value_table(skfab_ctx* ctx, int32_t enable) {
     if (!ctx || (enable != 0 && enable != 1)) return SKFAB_ERR_ARG;
     ctx->value_table = enable != 0;
@@ -1457,7 +1510,7 @@ skfab_status skfab_solve_adaptive(skfab_ctx* ctx, const skfab_csr* A, const doub
     if (!ctx || !b || !x) return SKFAB_ERR_ARG;
     skfab_status v = validate(A, p, true);
     if (v != SKFAB_OK) return v;
-    if (p->method != SKFAB_SFOM_CLOSED || p->two_pass) return SKFAB_ERR_ARG;
+    if (p->method != SKFAB_SFOM_CLOSED || p->two_pass || p->sketch != SKFAB_SKETCH_SPARSE_SIGN) return SKFAB_ERR_ARG;
     if (d < 1 || m0 < p->k || m0 > p->m || !(tol > 0.0)) return SKFAB_ERR_ARG;
     const AdaptiveLayout L = make_adaptive_layout(A, p);
     if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) % ALIGN) != 0) return SKFAB_ERR_WORKSPACE;

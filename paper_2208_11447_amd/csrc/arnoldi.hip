@@ -319,7 +319,9 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
     const GAS VT* Uo[KW];
 #pragma unroll
     for (int o = 0; o < KW; ++o) Uo[o] = gptr(static_cast<const VT*>(a.U)) + (int64_t)((o < nwin_all) ? (j - 1 - o) % ur : 0) * a.ldU;
-    GAS VT* __restrict__ Uj = gptr(static_cast<VT*>(a.U)) + (int64_t)(a.extend ? 0 : j % ur) * a.ldU;
+    GAS VT* __restrict__ Uj = gptr(static_cast<VT*>(a.U)) + (int64_t)(j % ur) * a.ldU;
+    const bool store_u = !a.extend || a.keep_ext;
+    const bool sketch = !a.nosketch;
     GAS WT* __restrict__ Wc = gptr(static_cast<WT*>(a.Wcur));
     const GAS AT* __restrict__ slv = gptr(static_cast<const AT*>(a.sl_val));
     const GAS int32_t* __restrict__ sl_col = gptr(a.sl_col);
@@ -542,10 +544,8 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         }
         const VT us = Store<VT>::put(u);
         u = to_w<WT>(us);  // the stored value is the one used everywhere
-        if (!a.extend && valid) {
-            store_nt(us, &Uj[r]);
-            store_nt(w, &Wc[r]);
-        }
+        if (store_u && valid) store_nt(us, &Uj[r]);
+        if (!a.extend && valid) store_nt(w, &Wc[r]);
         if (valid) {
             const double ud = (double)u, wd = (double)w;
             acc_uu = fma(ud, ud, acc_uu);
@@ -558,14 +558,16 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                     acc_ul[o] = fma(ud, (double)uo[o], acc_ul[o]);
                 }
             }
-            int rows[ZETA];
-            double sg[ZETA];
-            sketch_column<ZETA>(a.seed, (uint64_t)r, s, rows, sg);
+            if (sketch) {
+                int rows[ZETA];
+                double sg[ZETA];
+                sketch_column<ZETA>(a.seed, (uint64_t)r, s, rows, sg);
 #pragma unroll
-            for (int q = 0; q < ZETA; ++q) lds_add(binV + rows[q], sg[q] * ud);
-            if (!a.extend) {
+                for (int q = 0; q < ZETA; ++q) lds_add(binV + rows[q], sg[q] * ud);
+                if (!a.extend) {
 #pragma unroll
-                for (int q = 0; q < ZETA; ++q) lds_add(binAV + rows[q], sg[q] * wd);
+                    for (int q = 0; q < ZETA; ++q) lds_add(binAV + rows[q], sg[q] * wd);
+                }
             }
         }
         if (pre && lane == 0) __hip_atomic_fetch_add(&s_prog, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -1120,6 +1122,11 @@ hipError_t launch_arnoldi_tail(const StepArgs& a, double* colnorm2, hipStream_t 
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(colnorm_kernel, dim3((a.m + 3) / 4), dim3(256), 0, st, a.SV, a.s, a.m, a.ctrl, colnorm2);
+    return hipGetLastError();
+}
+
+hipError_t launch_colnorm(const double* SV, int s, int m, const DevCtrl* ctrl, double* colnorm2, hipStream_t st) {
+    hipLaunchKernelGGL(colnorm_kernel, dim3((m + 3) / 4), dim3(256), 0, st, SV, s, m, ctrl, colnorm2);
     return hipGetLastError();
 }
 

@@ -99,7 +99,11 @@ struct StepArgs {
     int32_t s, k, j, m, G;
     int32_t extend;   // 1: form u_m and its sketch only (no product with A)
     int32_t uring;    // columns of U: basis vector c lives in column c % uring (m, or k + 1
-                      // for the two-pass form, whose first pass keeps only the window)
+                      // for the two-pass form, whose first pass keeps only the window; m + 1
+                      // with keep_ext)
+    int32_t nosketch; // 1: no sparse-sign sketch in the step (the SRDCT sketch is applied to
+                      // the stored basis afterwards)
+    int32_t keep_ext; // 1: the extension pass stores u_m in column m % uring
     int32_t pad;
 };
 

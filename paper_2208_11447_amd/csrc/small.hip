@@ -48,6 +48,7 @@ __device__ __forceinline__ void init_ctrl_body(DevCtrl* c, int m) {
         c->col_wide = 0;
         c->flags = 0;
         c->quad_diff = 0.0;
+        c->relres = -1.0;  // set by the Arnoldi-relation check (sparse-sign sketch only)
         c->m_basis = m;
     }
 }

@@ -71,7 +71,9 @@ class CSR:
 
 def make_params(f="invsqrt", m=50, k=2, s=200, zeta=8, seed=0, method="sfom", fparam=0.0, poly=None,
                 l1=32, l2=45, lmax=1395, quad_tol=1e-13, prec="fp64", cond_max=0.0,
-                two_pass=False) -> N.skfab_params:
+                two_pass=False, srdct=None) -> N.skfab_params:
+    """Method parameters.  srdct: None for the sparse-sign sketch, or (signs, rows) device
+    tensors (int8[N], int32[s]) of the SRDCT sketch (kept alive by the returned struct)."""
     p = N.skfab_params()
     p.f = FUNCS[f] if isinstance(f, str) else int(f)
     p.fparam = float(fparam)
@@ -81,6 +83,16 @@ def make_params(f="invsqrt", m=50, k=2, s=200, zeta=8, seed=0, method="sfom", fp
     p.prec = PRECS[prec] if isinstance(prec, str) else int(prec)
     p.cond_max = float(cond_max)
     p.two_pass = 1 if two_pass else 0
+    if srdct is not None:
+        signs, rows = srdct
+        _require_device(signs, torch.int8, "srdct signs")
+        _require_device(rows, torch.int32, "srdct rows")
+        p.sketch = N.SKFAB_SKETCH_SRDCT
+        p.srdct_signs = signs.data_ptr()
+        p.srdct_rows = rows.data_ptr()
+        p._srdct_keepalive = (signs, rows)
+    else:
+        p.sketch = N.SKFAB_SKETCH_SPARSE_SIGN
     if poly is not None:
         arr = (C.c_double * len(poly))(*[float(c) for c in poly])
         p.poly = C.cast(arr, C.POINTER(C.c_double))
@@ -217,6 +229,26 @@ def skfab_sketch_apply(ctx: Context, n: int, s: int, zeta: int, seed: int, v: to
     _require_device(Sv, torch.float64, "Sv")
     _check(N.lib().skfab_sketch_apply(ctx.handle, n, s, zeta, seed, _ptr(v), _ptr(Sv), _ptr(ws), ws.numel()),
            "skfab_sketch_apply")
+
+
+def skfab_srdct_ws_bytes(n: int, s: int, ncols: int) -> int:
+    return N.lib().skfab_srdct_ws_bytes(int(n), int(s), int(ncols))
+
+
+def skfab_srdct_apply(ctx: Context, signs: torch.Tensor, rows: torch.Tensor, V: torch.Tensor, SV: torch.Tensor,
+                      ws: torch.Tensor):
+    """SV <- S V for the SRDCT sketch; V: (ncols, n) tensor (row c = column c of the C ABI's
+    column-major n x ncols), SV: (ncols, s)."""
+    _require_device(signs, torch.int8, "signs")
+    _require_device(rows, torch.int32, "rows")
+    _require_device(V, torch.float64, "V")
+    _require_device(SV, torch.float64, "SV")
+    ncols, n = V.shape
+    s = rows.numel()
+    if SV.shape != (ncols, s) or signs.numel() != n:
+        raise ValueError("shapes: V (ncols, n), SV (ncols, s), signs (n,), rows (s,)")
+    _check(N.lib().skfab_srdct_apply(ctx.handle, n, s, _ptr(signs), _ptr(rows), _ptr(V), n, ncols, _ptr(SV),
+                                     _ptr(ws), ws.numel()), "skfab_srdct_apply")
 
 
 def skfab_set_value_table(ctx: Context, enable: bool = True):

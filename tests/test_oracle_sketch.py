@@ -101,3 +101,41 @@ def test_seed_changes_pattern():
     assert not np.array_equal(r0, r1)
     r0b, _ = sketch.sparse_sign_pattern(100, 50, 8, seed=0, cols=np.arange(40, 60))
     assert np.array_equal(r0[40:60], r0b)
+
+
+# ------------------------------------------------------------------ SRDCT
+def test_dct_matrix_matches_library_and_is_orthogonal():
+    """F of the SRDCT sketch is the orthonormal DCT-II: SciPy's transform of the unit
+    vectors, and F F^T = I."""
+    import scipy.fft
+    N = 37
+    F = sketch.dct_matrix(N)
+    ref = scipy.fft.dct(np.eye(N), type=2, norm="ortho", axis=0)
+    assert np.max(np.abs(F - ref)) < 1e-14
+    assert np.max(np.abs(F @ F.T - np.eye(N))) < 1e-13
+
+
+def test_srdct_expected_norm_and_rows():
+    """E ||S v||^2 = ||v||^2 over the choice of rows: the average over all N rows of
+    (N/s) s (F E v)_k^2 / N is ||v||^2 exactly (Parseval); S picks the drawn rows."""
+    from workloads import srdct_draws
+    N, s = 200, 40
+    signs, rows = srdct_draws(N, s, 3)
+    v = np.random.default_rng(1).standard_normal(N)
+    S = sketch.srdct_matrix(N, signs, rows)
+    z = sketch.dct_matrix(N) @ (signs * v)
+    assert np.isclose(np.sum(z ** 2), v @ v, rtol=1e-13)           # Parseval
+    assert np.allclose(S @ v, np.sqrt(N / s) * z[rows], rtol=1e-12, atol=1e-14)
+    mc = np.mean([np.sum((sketch.srdct_matrix(N, *srdct_draws(N, s, t)) @ v) ** 2) for t in range(300)])
+    assert abs(mc / (v @ v) - 1) < 0.05
+
+
+def test_srdct_embedding_distortion():
+    """Distortion of the SRDCT embedding on a random 10-dimensional subspace with
+    s = 200, N = 2000: well below 1 (an epsilon-subspace embedding, eq. sketch)."""
+    from workloads import srdct_draws
+    N, s, d = 2000, 200, 10
+    U, _ = np.linalg.qr(np.random.default_rng(2).standard_normal((N, d)))
+    signs, rows = srdct_draws(N, s, 5)
+    sv = np.linalg.svd(sketch.srdct_matrix(N, signs, rows) @ U, compute_uv=False)
+    assert np.max(np.abs(sv ** 2 - 1)) < 0.7

@@ -7,6 +7,7 @@ of the sketched Krylov method itself.
 from .convdiff import convdiff_csr, convdiff_spectrum_bounds, grid_coefficients
 from .rhs import gaussian_rhs, ones_rhs
 from .configs import CONFIGS, config, batched_problem_params
+from .srdct import srdct_draws
 
 __all__ = [
     "convdiff_csr",
@@ -17,4 +18,5 @@ __all__ = [
     "CONFIGS",
     "config",
     "batched_problem_params",
+    "srdct_draws",
 ]

@@ -21,6 +21,12 @@ CONFIGS = {
     "convdiff2d_n100_m200_fp32": dict(
         n=100, dim=2, diffusion=1.0, convection=50.0, rhs_seed=0, sketch_seed=0,
         m=200, k=2, s=400, zeta=8, funcs=("invsqrt", "exp"), methods=("sfom",)),
+    # the paper's convection-diffusion experiment (Section 5.1): 100x100 grid, diffusion
+    # 1e-3, unit convection in direction [1, -1] (C (+) C^T), b = ones / ||ones||, k = 4,
+    # s = 2 m_max = 400, Krylov dimensions up to 200; sketch: SRDCT or sparse sign
+    "paper51_convdiff2d_n100": dict(
+        n=100, dim=2, diffusion=1e-3, convection=1.0, paper_direction=True, rhs="ones", sketch_seed=0,
+        m=200, k=4, s=400, zeta=8, funcs=("invsqrt",), methods=("sfom", "sfom_quad", "sgmres")),
     "convdiff2d_n100_m300_fp32": dict(
         n=100, dim=2, diffusion=1.0, convection=50.0, rhs_seed=0, sketch_seed=0,
         m=300, k=2, s=600, zeta=8, funcs=("invsqrt", "exp"), methods=("sfom",)),
