@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="convdiff3d_n128_m200",
                     help="a single-problem workload, 'batch64x4' for the batched form (64 problems x 4 rhs), "
-                         "or 'controller' for the learned controller against plain adaptive-m")
+                         "'controller' for the learned controller against plain adaptive-m, or 'paper51' for "
+                         "the convergence table of the paper's convection-diffusion experiment")
     ap.add_argument("--train-problems", type=int, default=2500,
                     help="controller: training problems (4 method runs each)")
     ap.add_argument("--test-problems", type=int, default=256, help="controller: held-out problems")
@@ -451,6 +452,80 @@ def check_batch_outputs(path, nprob):
                       "max_rel_err_sampled": worst}), flush=True)
 
 
+def run_paper51(args):
+    """The paper's convection-diffusion experiment (Section 5.1): 100 x 100 grid,
+    diffusion 1e-3, unit convection in direction [1, -1], b = ones / ||ones||, k = 4,
+    s = 400, f = z^(-1/2).  For m = 10, 20, ..., 200 and both sketches (the paper's
+    SRDCT and the sparse sign of the other workloads) the device solves with sketched
+    FOM in closed form, sketched FOM by quadrature and sketched GMRES; errors against
+    the reference A^(-1/2) b (sparse direct quadrature, no Krylov space) beside the
+    error of the best approximation from K_m(A, b) (orthogonal projection)."""
+    import numpy as np
+    import scipy.sparse as sp
+    import torch
+
+    from oracle import arnoldi as oarn
+    from oracle import methods as ometh
+    from oracle import reference
+    from oracle import sketch as osk
+    from paper_2208_11447_amd import skfab as sk
+    from workloads import config, convdiff_csr, ones_rhs, srdct_draws
+
+    cfg = config("paper51_convdiff2d_n100")
+    rp, col, val = convdiff_csr(cfg["n"], 2, cfg["diffusion"], cfg["convection"], paper_direction=True)
+    N = rp.size - 1
+    A = sp.csr_matrix((val, col, rp), shape=(N, N))
+    b = ones_rhs(N)
+    t0 = time.perf_counter()
+    truth = reference.invsqrt_apply(A, b, tol=1e-13)
+    print(f"# reference A^(-1/2) b in {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+    full = oarn.full_arnoldi(A, b, cfg["m"])
+    Q, _ = np.linalg.qr(full.V)
+    nt = np.linalg.norm(truth)
+    ms = list(range(10, cfg["m"] + 1, 10))
+    best = {m: float(np.linalg.norm(truth - Q[:, :m] @ (Q[:, :m].T @ truth)) / nt) for m in ms}
+    Ad = sk.CSR.from_numpy(rp, col, val)
+    bd = torch.as_tensor(b, device="cuda")
+    x = torch.empty_like(bd)
+    ctx = sk.Context(0)
+    signs, rows = srdct_draws(N, cfg["s"], cfg["sketch_seed"])
+    sketches = {"srdct": (torch.as_tensor(signs, device="cuda"), torch.as_tensor(rows, device="cuda")),
+                "sparse_sign": None}
+    table = []
+    for m in ms:
+        row = {"m": m, "best": best[m]}
+        for name, sr in sketches.items():
+            # sFOM by quadrature at the tolerance of the paper's experiments (1e-7, Section 5.3)
+            for method, qtol in (("sfom", 1e-13), ("sfom_quad", 1e-7), ("sgmres", 1e-13)):
+                p = sk.make_params(f="invsqrt", m=m, k=cfg["k"], s=cfg["s"], zeta=cfg["zeta"], seed=cfg["sketch_seed"],
+                                   method=method, quad_tol=qtol, srdct=sr)
+                ws = sk.alloc_workspace(sk.skfab_workspace_bytes(Ad, p))
+                info = sk.skfab_solve(ctx, Ad, bd, x, p, ws)
+                e = float(np.linalg.norm(x.cpu().numpy() - truth) / nt) if info.status == 0 else None
+                row[f"{name}_{method}"] = e
+                row[f"{name}_{method}_status"] = int(info.status)
+                if method == "sfom":
+                    row[f"{name}_m_used"] = int(info.m_used)
+                if method == "sfom_quad":
+                    row[f"{name}_sfom_quad_l"] = int(info.l_used)
+                    xq = x.cpu().numpy()
+            # the closed form by a dense matrix function (the oracle: Schur square root of
+            # the projected matrix), for the same sketch, against the device's quadrature
+            S = osk.srdct_matrix(N, signs, rows) if sr is not None else osk.sparse_sign_matrix(N, cfg["s"], 8,
+                                                                                               cfg["sketch_seed"])
+            xo = ometh.sfom_closed(oarn.truncated_arnoldi(A, b, m, cfg["k"], S), "invsqrt").x
+            row[f"{name}_quad_vs_dense_closed"] = float(np.linalg.norm(xq - xo) / np.linalg.norm(xo))
+        table.append(row)
+        print("# " + json.dumps(row), file=sys.stderr, flush=True)
+    # closed form and quadrature of sketched FOM coincide (the paper's observation)
+    gap = max(r[f"{n}_quad_vs_dense_closed"] for r in table for n in sketches)
+    out = {"metric": "relative error of f(A)b approximants vs m (Section 5.1 convection-diffusion)",
+           "config": {"workload": "paper51_convdiff2d_n100", "N": N, "k": cfg["k"], "s": cfg["s"],
+                      "f": "invsqrt", "rhs": "ones/||ones||", "sketches": list(sketches)},
+           "max_rel_gap_sfom_quad_tol1e-7_vs_dense_closed_form": gap, "table": table}
+    print(json.dumps(out), flush=True)
+
+
 def run_controller(args):
     """The learned controller: labels from 4 adaptive-m runs per training problem
     ((k, s/m) in {2, 4} x {2, 4}, tol 1e-8), full-batch training on the device
@@ -544,6 +619,9 @@ def main():
         return
     if args.workload == "controller":
         run_controller(args)
+        return
+    if args.workload == "paper51":
+        run_paper51(args)
         return
     cfg = config(args.workload)
     rp, col, val = convdiff_csr(cfg["n"], cfg["dim"], cfg["diffusion"], cfg["convection"])

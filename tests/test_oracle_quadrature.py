@@ -110,3 +110,19 @@ def test_adaptive_fast_decrease_is_not_stagnation():
     rule, orders = _rule_from_diffs([1e-2, 1e-6, 1e-11, 1e-12, 9e-14])
     _, l = _adaptive(rule, 1e-13, 32, 45, 10_000)
     assert l == orders[5]
+
+
+def test_reference_invsqrt_matches_dense():
+    """The sparse-direct reference A^(-1/2) b equals the dense Schur square root on a
+    small grid of the paper's operator family."""
+    import scipy.linalg as sla
+    import scipy.sparse as sp
+    from oracle import reference
+    from workloads import convdiff_csr, ones_rhs
+    rp, col, val = convdiff_csr(12, 2, 1e-3, 1.0, paper_direction=True)
+    N = rp.size - 1
+    A = sp.csr_matrix((val, col, rp), shape=(N, N))
+    b = ones_rhs(N)
+    ref = np.real(np.linalg.solve(sla.sqrtm(A.toarray()), b))
+    x = reference.invsqrt_apply(A, b, tol=1e-13)
+    assert np.linalg.norm(x - ref) / np.linalg.norm(ref) < 1e-11
