@@ -16,8 +16,9 @@
 //   * sketched GMRES (eq. sgmres integrand):       y(t) = argmin || beta R_00 e_1 - P(t) y ||
 // The approximants are V_m int y(t) dmu(t) (sFOM, sGMRES).  For z^(-1/2) the
 // integral is the Gauss-Chebyshev rule after t = (1-x)/(1+x) (Section 5.1) with the
-// spectral scaling t -> sigma t, sigma = |det H_hat|^(1/m) (geometric mean of the
-// eigenvalue moduli of the projected matrix), and the adaptive order update
+// spectral scaling t -> sigma t, sigma = sqrt(|theta|_min |theta|_max) over the
+// eigenvalues of the projected matrix (estimated by power and inverse iteration),
+// and the adaptive order update
 // l <- floor(sqrt(2) l) of Section 4.1 (accepting an order at the rounding floor
 // QUAD_FLOOR when the requested tolerance is out of reach).  Every node is an
 // O(m^2) Hessenberg solve (partial pivoting) or Givens least-squares solve, one
@@ -364,6 +365,48 @@ __device__ __forceinline__ void dist_set(double (&v)[QM], int i, double x) {
         if (q == i / WAVE && lane == i % WAVE) v[q] = x;
 }
 
+// ----------------------------------------------------- spectral scale sigma
+// sigma ~ sqrt(theta_small theta_max), the scale that balances the Gauss-Chebyshev
+// rule's error at both ends of the spectrum of H_hat (the sketched Ritz values).
+// theta_max: power iteration with H_hat, the mean of log ||H x|| over the second half
+// of SIG_IT normalised steps (settles on the modulus also for a complex dominant
+// pair).  theta_small = beta / ||H_hat^-1 beta e_1||, from the a = 0 node solve the
+// kernel makes anyway: the smallest scale of the spectrum as the right-hand side
+// sees it.  On the batched workload this lands within 0.05x..4x of the eigenvalue
+// optimum sqrt(|theta|_min |theta|_max), where the rule converges within a few
+// hundred nodes; the geometric mean of all moduli (|det H_hat|^(1/mu)) was 9x..90x
+// off and needed up to 1395.  That mean is the fallback if an estimate is not finite.
+constexpr int SIG_IT = 10;
+
+__device__ __forceinline__ void sig_start(int mu, double* xs) {
+    const int lane = threadIdx.x & 63;
+    // a fixed start vector with every component nonzero
+    double t = 0.0;
+    for (int i = lane; i < mu; i += WAVE) {
+        const double v = 1.0 + 0.25 * (double)((i * 7) % 11);
+        xs[i] = v;
+        t = fma(v, v, t);
+    }
+    t = wave_sum(t);
+    __syncthreads();
+    const double r = 1.0 / sqrt(t);
+    for (int i = lane; i < mu; i += WAVE) xs[i] *= r;
+    __syncthreads();
+}
+
+// ys <- ys / ||ys||; returns log ||ys|| (before the scaling); xs <- the scaled ys
+__device__ __forceinline__ double sig_normalise(int mu, double* xs, const double* ys) {
+    const int lane = threadIdx.x & 63;
+    double t = 0.0;
+    for (int i = lane; i < mu; i += WAVE) t = fma(ys[i], ys[i], t);
+    t = wave_sum(t);
+    const double r = 1.0 / sqrt(t);
+    __syncthreads();
+    for (int i = lane; i < mu; i += WAVE) xs[i] = ys[i] * r;
+    __syncthreads();
+    return 0.5 * log(t);
+}
+
 // ------------------------------------------------- conditioning of R (Section 2.1)
 // The remark after eq. (sFOM''') suggests a numerical pseudoinverse in place of
 // R_m^-1 when SV_m, and so R_m, is extremely ill-conditioned.  The one used here
@@ -658,8 +701,7 @@ __global__ __launch_bounds__(HH_NT) void hhat_rows_batched_kernel(const SmallUni
 template <bool LS, bool DET, int QM>
 __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restrict__ T1r,
                                   const double* __restrict__ K0r, double rhs0, double* __restrict__ Ucol,
-                                  double* __restrict__ unused, double* __restrict__ y, double* logdet, double* sgn) {
-    (void)unused;
+                                  const double* rhsv, double* __restrict__ y, double* logdet, double* sgn) {
     const int lane = threadIdx.x & 63;
     constexpr int PF = QM <= 4 ? 4 : 2;  // rows of the pencil in flight ahead of the elimination
     double carry[QM], next[QM];
@@ -676,7 +718,8 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
 #pragma unroll
     for (int f = 0; f < PF; ++f)
         if (1 + f <= last) load_pencil_row(pref[f], 1 + f, f, mu, m, T1r, K0r);
-    double rc = rhs0;
+    // right-hand side rhs0 e_1, or (square case) the vector rhsv, read row by row
+    double rc = (!LS && rhsv) ? rhsv[0] : rhs0;
     double sg = 1.0;
     for (int kk = 0; kk < last; ++kk) {
         combine_row(next, pref[0], a);
@@ -684,7 +727,7 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
         for (int f = 0; f + 1 < PF; ++f) pref[f] = pref[f + 1];
         // keep PF rows in flight while this column is eliminated
         if (kk + 1 + PF <= last) load_pencil_row(pref[PF - 1], kk + 1 + PF, kk + PF, mu, m, T1r, K0r);
-        double rn = 0.0;
+        double rn = (!LS && rhsv) ? rhsv[kk + 1] : 0.0;
         double pk = dist_get(carry, kk);
         double nk = dist_get(next, kk);
         double* ucol = Ucol + kk;  // row kk of U: element (kk, jj) at jj * m + kk
@@ -692,7 +735,7 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
             if (fabs(nk) > fabs(pk)) {
 #pragma unroll
                 for (int q = 0; q < QM; ++q) { const double t = carry[q]; carry[q] = next[q]; next[q] = t; }
-                rn = rc; rc = 0.0;
+                const double tr = rn; rn = rc; rc = tr;
                 const double tp = pk; pk = nk; nk = tp;
                 if (DET) sg = -sg;
             }
@@ -791,8 +834,7 @@ __device__ void pencil_solve_wave(int mu, int m, double a, const double* __restr
 }
 
 // Node 0 (a = 0): log|det H_hat| and its sign (square case), the spectral scale
-// sigma = |det H_hat|^(1/mu) (geometric mean of the moduli of the sketched Ritz
-// values), the branch check for z^(-1/2) (a negative determinant means
+// sigma (see sig_start), the branch check for z^(-1/2) (a negative determinant means
 // an odd number of negative real eigenvalues), and -- for f = 1/z -- the solution
 // itself (H_hat y = beta e_1, or the least-squares pencil problem for sGMRES).
 template <int QM>
@@ -806,21 +848,45 @@ __device__ __forceinline__ void pencil_scalars_body(int m, int s, const double* 
     const double beta = eta[0];
     double ld = 0.0, sg = 1.0;
     if (is_ls) {
-        pencil_solve_wave<true, false, QM>(mu, m, 0.0, T1r, K0r, beta * X[0], Ubuf, Urhs, y0, nullptr, nullptr);
+        pencil_solve_wave<true, false, QM>(mu, m, 0.0, T1r, K0r, beta * X[0], Ubuf, nullptr, y0, nullptr, nullptr);
     } else {
         // H_hat y = beta e_1: the a = 0 system of the square case, and det H_hat
-        pencil_solve_wave<false, true, QM>(mu, m, 0.0, nullptr, Hh, beta, Ubuf, Urhs, y0, nullptr, &sg);
+        pencil_solve_wave<false, true, QM>(mu, m, 0.0, nullptr, Hh, beta, Ubuf, nullptr, y0, nullptr, &sg);
         // log|det| = sum log|U_kk| (sg already holds the sign: row swaps and pivot signs)
         double lu = 0.0;
         for (int kk = lane; kk < mu; kk += 64) lu += log(fabs(Ubuf[(int64_t)kk * m + kk]));
         ld = wave_sum_fast(lu);
+    }
+    double lsig = NAN;
+    if (!is_ls) {
+        // sigma as in the band form: power iteration with the rows of H_hat (one row per
+        // step across the lanes), the small scale from y0 = H_hat^-1 beta e_1
+        __shared__ double xs[MMAX], ys[MMAX];
+        double lmax = 0.0;
+        __syncthreads();  // y0 of the a = 0 solve complete
+        double y2 = 0.0;
+        for (int i = lane; i < mu; i += WAVE) y2 = fma(y0[i], y0[i], y2);
+        const double lsmall = log(beta) - 0.5 * log(wave_sum(y2));
+        sig_start(mu, xs);
+        for (int it = 0; it < SIG_IT; ++it) {
+            for (int i = 0; i < mu; ++i) {
+                double t = 0.0;
+                for (int jj = max(i - 1, 0) + lane; jj < mu; jj += WAVE) t = fma(Hh[(int64_t)i * m + jj], xs[jj], t);
+                t = wave_sum(t);
+                if (lane == 0) ys[i] = t;
+            }
+            __syncthreads();
+            const double l = sig_normalise(mu, xs, ys);
+            if (it >= SIG_IT / 2) lmax += l;
+        }
+        lsig = 0.5 * (lmax / (SIG_IT / 2) + lsmall);
     }
     if (lane == 0) {
         ctrl->beta = beta;
         if (!is_ls) {
             const double lg = ld / mu;
             ctrl->logdet = ld;
-            ctrl->sigma = exp(lg);
+            ctrl->sigma = isfinite(lsig) ? exp(lsig) : exp(lg);
             const double sdet = sg;  // sign of det H_hat
             if (branch_check && sdet < 0.0 && ctrl->status == 0) ctrl->status = 4;  // SKFAB_ERR_BRANCH
             if (!isfinite(lg) && ctrl->status == 0) ctrl->status = 3;
@@ -878,9 +944,9 @@ __device__ __forceinline__ void quad_level_body(const DevCtrl* ctrl, const QuadG
         const double w = (2.0 / l) / (1.0 + x);
         double* yi = nodebuf + (int64_t)i * m;
         if (is_ls)
-            pencil_solve_wave<true, false, QM>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, Ur, yi, nullptr, nullptr);
+            pencil_solve_wave<true, false, QM>(mu, m, t * sigma, T1r, K0r, rhs0 * w, U, nullptr, yi, nullptr, nullptr);
         else
-            pencil_solve_wave<false, false, QM>(mu, m, t * sigma, nullptr, Hh, rhs0 * w, U, Ur, yi, nullptr, nullptr);
+            pencil_solve_wave<false, false, QM>(mu, m, t * sigma, nullptr, Hh, rhs0 * w, U, nullptr, yi, nullptr, nullptr);
     }
 }
 
@@ -914,13 +980,13 @@ __device__ __forceinline__ void load_band(const double* __restrict__ Hh, int m, 
 template <int KB, bool DET>
 __device__ __forceinline__ void band_node_solve(int mu, double a, double rhs0, const double* Bs, const double* Ls,
                                                 double* __restrict__ Us, int64_t fstride, double* __restrict__ y,
-                                                int* neg) {
+                                                int* neg, const double* rhsv = nullptr) {
     constexpr int F = KB + 2;
     double c[KB];  // carry row: columns kk .. kk+KB-1 (the last slot is zero on entry)
 #pragma unroll
     for (int d = 0; d + 1 < KB; ++d) c[d] = Bs[d + 1];
     c[KB - 1] = 0.0;
-    double cL = Ls[0], cR = rhs0;
+    double cL = Ls[0], cR = rhsv ? rhsv[0] : rhs0;
     if (mu > 1) c[0] += a;
     else cL += a;
     int ng = 0;
@@ -928,7 +994,7 @@ __device__ __forceinline__ void band_node_solve(int mu, double a, double rhs0, c
         double n[KB];
 #pragma unroll
         for (int d = 0; d < KB; ++d) n[d] = Bs[(kk + 1) * KB + d];
-        double nL = Ls[kk + 1], nR = 0.0;
+        double nL = Ls[kk + 1], nR = rhsv ? rhsv[kk + 1] : 0.0;
         if (kk + 2 < mu) n[1] += a;  // the diagonal of row kk+1 (in the last column for the last row)
         else nL += a;
         if (fabs(n[0]) > fabs(c[0])) {
@@ -1070,11 +1136,34 @@ __device__ __forceinline__ void pencil_scalars_band_body(int m, int s, const dou
     double lu = 0.0;
     for (int kk = lane; kk < mu; kk += WAVE) lu += log(fabs(Us[kk * (KB + 2)]));
     const double ld = -wave_sum_fast(lu);
+    // sigma: |theta|_max by power iteration (rows of H_hat over the lanes), the small
+    // scale from y0 = H_hat^-1 beta e_1 (written by lane 0 above, visible after the barrier)
+    __shared__ double xs[MMAX], ys[MMAX];
+    double lmax = 0.0;
+    double y2 = 0.0;
+    for (int i = lane; i < mu; i += WAVE) y2 = fma(y0[i], y0[i], y2);
+    const double lsmall = log(beta) - 0.5 * log(wave_sum(y2));
+    sig_start(mu, xs);
+    for (int it = 0; it < SIG_IT; ++it) {
+        for (int i = lane; i < mu; i += WAVE) {
+            double t = Ls[i] * xs[mu - 1];
+#pragma unroll
+            for (int d = 0; d < KB; ++d) {
+                const int c = i - 1 + d;
+                if (c >= 0 && c < mu - 1) t = fma(Bs[i * KB + d], xs[c], t);
+            }
+            ys[i] = t;
+        }
+        __syncthreads();
+        const double l = sig_normalise(mu, xs, ys);
+        if (it >= SIG_IT / 2) lmax += l;
+    }
+    const double lsig = 0.5 * (lmax / (SIG_IT / 2) + lsmall);  // log sqrt(theta_max theta_small)
     if (lane == 0) {
         ctrl->beta = beta;
         const double lg = ld / mu;
         ctrl->logdet = ld;
-        ctrl->sigma = exp(lg);
+        ctrl->sigma = isfinite(lsig) ? exp(lsig) : exp(lg);
         if (branch_check && ng && ctrl->status == 0) ctrl->status = 4;  // SKFAB_ERR_BRANCH: det H_hat < 0
         if (!isfinite(lg) && ctrl->status == 0) ctrl->status = 3;
     }
