@@ -74,7 +74,123 @@ def parse():
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB (5 times) and report its GB/s; "
                          "used to scale rocprofv3 FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--summarize", default=None, choices=["trace", "counters"],
+                    help="CPU only: write a text summary of rocprofv3 CSV output (-f csv): 'trace' from one "
+                         "--kernel-trace --stats run, 'counters' from four --pmc runs (FETCH_SIZE, WRITE_SIZE of "
+                         "the workload, then of the copy calibration); see --prof-dirs")
+    ap.add_argument("--prof-dirs", default="", help="comma-separated rocprofv3 output folders (-d)")
+    ap.add_argument("--prof-json", default=None, help="the JSON line bench.py printed in the profiled run")
+    ap.add_argument("--prof-copy-json", default=None,
+                    help="the JSON line of the --copy-calibration run profiled for the counter scale")
+    ap.add_argument("--prof-title", default="", help="summary title line")
+    ap.add_argument("--prof-cmd", action="append", default=[], help="command(s) that made the output")
+    ap.add_argument("--prof-out", default=None, help="summary file to write")
     return ap.parse_args()
+
+
+def _prof_rows(root: str, suffix: str):
+    """Rows of every rocprofv3 CSV file under `root` whose name ends in `suffix`."""
+    import csv
+    import glob
+    rows = []
+    for path in sorted(glob.glob(os.path.join(root, "**", f"*{suffix}"), recursive=True)):
+        with open(path, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no *{suffix} under {root}")
+    return rows
+
+
+def _kernel_sha() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def _counter_means(root: str, counter: str):
+    """{kernel name: (dispatches, mean counter value per dispatch)} of one --pmc run."""
+    acc = {}
+    for r in _prof_rows(root, "counter_collection.csv"):
+        if r.get("Counter_Name") != counter:
+            continue
+        name = r["Kernel_Name"]
+        n, t = acc.get(name, (0, 0.0))
+        acc[name] = (n + 1, t + float(r["Counter_Value"]))
+    return {k: (n, t / n) for k, (n, t) in acc.items()}
+
+
+def summarize_profile(args):
+    """Text summary of rocprofv3 CSV output for profiles/ (see --summarize)."""
+    dirs = [d for d in args.prof_dirs.split(",") if d]
+    run = {}
+    if args.prof_json:
+        with open(args.prof_json) as fh:
+            run = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+    roof = run.get("roofline", {})
+    lines = [f"# {args.prof_title}"] + [f"# command: {c}" for c in args.prof_cmd]
+    lines.append(f"# kernel sources sha256 ({', '.join(os.path.basename(r) for r in KERNEL_SOURCES)}): "
+                 f"{_kernel_sha()}")
+    if args.summarize == "trace":
+        rows = _prof_rows(dirs[0], "kernel_stats.csv")
+        rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+        total = sum(float(r["TotalDurationNs"]) for r in rows)
+        if run:
+            lines.append(f"# bench line of the same run: value {run.get('value')} {run.get('unit')}, "
+                         f"ms_per_step {run.get('ms_per_step')}, step kernel by HIP events "
+                         f"{roof.get('mean_launch_us', roof.get('step_ms_per_batch'))} "
+                         f"{'us per launch' if 'mean_launch_us' in roof else 'ms per batch'}")
+        lines.append("# columns: kernel, calls, total, mean, share of GPU time")
+        for r in rows:
+            t = float(r["TotalDurationNs"])
+            name = r["Name"][:90]
+            lines.append(f"{name:<92s}{int(r['Calls']):>7d}  {t / 1e6:>10.3f} ms  {float(r['AverageNs']) / 1e3:>10.2f} us"
+                         f"  {100 * t / total:>6.2f} %")
+    else:
+        fetch, write, cfetch, cwrite = (_counter_means(dirs[0], "FETCH_SIZE"), _counter_means(dirs[1], "WRITE_SIZE"),
+                                        _counter_means(dirs[2], "FETCH_SIZE"), _counter_means(dirs[3], "WRITE_SIZE"))
+        # the calibration copy: the dispatch with the most bytes in each calibration run
+        cf = max(v for _, v in cfetch.values())
+        cw = max(v for _, v in cwrite.values())
+        with open(args.prof_copy_json) as fh:
+            cj = json.loads([ln for ln in fh if ln.startswith("{")][-1])
+        step = [k for k in fetch if "arnoldi_step" in k]
+        if len(step) != 1:
+            raise SystemExit(f"expected one step kernel, found {step}")
+        kname = step[0]
+        nd, fk = fetch[kname]
+        _, wk = write[kname]
+        lines.append(f"# calibration: device copy reading {cj['copy_bytes_read']} B and writing "
+                     f"{cj['copy_bytes_written']} B: FETCH_SIZE {cf:.1f} KiB, WRITE_SIZE {cw:.1f} KiB per dispatch")
+        fs = cj["copy_bytes_read"] / 1024 / cf
+        ws_ = cj["copy_bytes_written"] / 1024 / cw
+        lines += [f"fetch_scale: {fs:.4f}", f"write_scale: {ws_:.4f}", f"kernel: {kname}", f"dispatches: {nd}",
+                  f"fetch_kib_per_dispatch: {fk:.1f}", f"write_kib_per_dispatch: {wk:.1f}"]
+        per_dispatch = 1024 * (fk * fs + wk * ws_)
+        if "bytes_per_batch" in roof:
+            per_batch_launches = roof["launches"] / run["steps"]
+            batches = nd / per_batch_launches
+            traffic = per_dispatch * nd / batches
+            alg = roof["bytes_per_batch"]
+            lines += [f"batches: {batches:.2f}", f"traffic_bytes_per_batch: {int(traffic)}",
+                      f"algorithmic_bytes_per_batch: {alg}"]
+        else:
+            traffic = per_dispatch
+            alg = roof["bytes_per_launch"]
+            lines += [f"traffic_bytes_per_launch: {int(traffic)}", f"algorithmic_bytes_per_launch: {alg}"]
+        lines += [f"traffic_over_algorithmic: {traffic / alg:.4f}", f"source_sha256: {_kernel_sha()}",
+                  "# other kernels of the same runs (mean KiB per dispatch, unscaled): FETCH_SIZE / WRITE_SIZE"]
+        for k in sorted(fetch, key=lambda k: -fetch[k][0] * fetch[k][1])[:12]:
+            if k == kname:
+                continue
+            lines.append(f"#   {k[:86]:<88s}{fetch[k][0]:>6d}  {fetch[k][1]:>12.1f}  {write.get(k, (0, 0.0))[1]:>12.1f}")
+    text = "\n".join(lines) + "\n"
+    if args.prof_out:
+        with open(args.prof_out, "w") as fh:
+            fh.write(text)
+    print(text, end="")
 
 
 def copy_calibration(gib: float):
@@ -599,6 +715,9 @@ def main():
     args = parse()
     if args.check_outputs:
         check_batch_outputs(args.check_outputs, args.nprob)
+        return
+    if args.summarize:
+        summarize_profile(args)
         return
     if args.copy_calibration > 0:
         copy_calibration(args.copy_calibration)
