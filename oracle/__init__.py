@@ -20,6 +20,8 @@ step, in NumPy/SciPy double precision:
                    (sFOM) and (sGMRES), the equivalent forms used as pins, and
                    the sketched stopping estimate and the adaptive-m loop
                    (Section 4.3),
+* ``contour``    - the parabolic contour rule for exp(-tau z): sketched GMRES
+                   and sketched FOM by Cauchy's integral (Sections 4.1, 5.2),
 * ``features``   - Gershgorin bounds (controller features),
 * ``mlp``        - the controller network, its loss gradient and Adam step.
 
@@ -27,4 +29,4 @@ Parity status: every function here is pinned by a CPU test against values the
 paper prints or against mathematics it fixes (closed forms, invariants,
 special cases); see tests/test_oracle_*.py.
 """
-from . import sketch, arnoldi, quadrature, methods, features, mlp  # noqa: F401
+from . import sketch, arnoldi, quadrature, methods, contour, features, mlp  # noqa: F401
