@@ -61,11 +61,19 @@ typedef enum skfab_status {
 } skfab_status;
 
 /* f in f(A) b.  INVSQRT and INV are Stieltjes functions (Section 1) and work with
- * every method; EXP and POLY are evaluated in closed form (SFOM_CLOSED only). */
+ * every method; POLY is evaluated in closed form (SFOM_CLOSED only); EXP in closed
+ * form (SFOM_CLOSED) or, with SGMRES_QUAD, by the contour rule of Sections 4.1 and
+ * 5.2 (fparam > 0, m <= 200). */
 typedef enum skfab_fun {
     SKFAB_F_INVSQRT = 0,    /* z^(-1/2), principal branch                            */
     SKFAB_F_EXP = 1,        /* exp(-fparam * z), fparam >= 0: Pade [13/13] scaling and
-                               squaring of the projected matrix (SFOM_CLOSED only)    */
+                               squaring of the projected matrix (SFOM_CLOSED); sketched
+                               GMRES (SGMRES_QUAD, fparam > 0) by Cauchy's integral over
+                               a parabola a + i theta - c theta^2 around the negated
+                               sketched Ritz values (eigenvalues of H_hat by a
+                               Hessenberg QR iteration on the device), trapezoidal rule
+                               with K = 32, 64, ..., 1024 intervals under the test of
+                               Section 4.1 at quad_tol (info.l_used = K + 1)            */
     SKFAB_F_INV = 2,        /* 1/z (test function)                                   */
     SKFAB_F_POLY = 3        /* sum_i poly[i] z^i, npoly coefficients (test function)  */
 } skfab_fun;
@@ -77,7 +85,9 @@ typedef enum skfab_method {
                                rounding floor 1e-10 when 1e-13 is out of reach of the
                                node solves: info.flags bit 1, info.quad_diff)       */
     SKFAB_SFOM_QUAD = 1,    /* (sFOM) integral form, adaptive quadrature, quad_tol   */
-    SKFAB_SGMRES_QUAD = 2   /* Algorithm 2, (sGMRES), adaptive quadrature, quad_tol   */
+    SKFAB_SGMRES_QUAD = 2   /* Algorithm 2, (sGMRES), adaptive quadrature, quad_tol
+                               (Gauss-Chebyshev for the Stieltjes functions, the
+                               contour rule for EXP)                                   */
 } skfab_method;
 
 /* Precision of the Krylov recurrence (spec precision extension).  In every

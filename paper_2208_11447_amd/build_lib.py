@@ -11,7 +11,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libskfab.so")
 SOURCES = ["arnoldi.hip", "sketch.hip", "small.hip", "expm.hip", "adaptive.hip", "control.hip", "noalloc.hip",
-           "srdct.hip", "api.cpp"]
+           "srdct.hip", "contour.hip", "api.cpp"]
 ARCH = os.environ.get("SKFAB_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

@@ -49,6 +49,10 @@ hipError_t launch_pencil_scalars(int m, int s, const double* X, DevCtrl* ctrl, c
 hipError_t launch_quad_group(const DevCtrl* ctrl, const QuadGroup& g, const double* T1r, const double* K0r,
                              const double* Hh, double* Ubuf, double* Urhs, double* nodebuf, int m, int is_ls,
                              const double* X, const double* eta, int k, hipStream_t st);
+hipError_t launch_contour_setup(DevCtrl* ctrl, int m, const double* Hh, double tau, double* ritz, hipStream_t st);
+hipError_t launch_contour_level(const DevCtrl* ctrl, const QuadGroup& g, double tau, const double* T1r,
+                                const double* K0r, double* Ubuf, double* nodebuf, int m, const double* X,
+                                const double* eta, hipStream_t st);
 hipError_t launch_quad_reduce(DevCtrl* ctrl, const QuadGroup& g, const double* nodebuf, int m, double tol,
                               const double* T1r, double* qprev, double* y, hipStream_t st);
 hipError_t launch_quad_fail(DevCtrl* ctrl, hipStream_t st);
@@ -244,9 +248,33 @@ std::vector<QuadGroup> quad_groups(int l1, int l2, int lmax) {
     return out;
 }
 
+// Trapezoidal levels of the contour rule (K = CT_KFIRST, 2 CT_KFIRST, ..., CT_KMAX
+// intervals, K + 1 nodes each), packed like quad_groups.
+std::vector<QuadGroup> contour_groups() {
+    std::vector<QuadGroup> out;
+    QuadGroup g;
+    std::memset(&g, 0, sizeof(g));
+    g.first = 1;
+    for (int K = CT_KFIRST; K <= CT_KMAX; K *= 2) {
+        const int l = K + 1;
+        if (g.nlev > 0 && (g.total + l > NODE_SLOTS_HOST || g.nlev == MAX_GROUP_LEVELS)) {
+            out.push_back(g);
+            std::memset(&g, 0, sizeof(g));
+        }
+        g.lev_l[g.nlev] = l;
+        g.lev_off[g.nlev] = g.total;
+        g.total += l;
+        g.nlev += 1;
+    }
+    if (g.nlev > 0) out.push_back(g);
+    if (!out.empty()) out.back().last = 1;
+    return out;
+}
+
 int max_level_nodes(int l1, int l2, int lmax) {
     int mx = 0;
     for (const QuadGroup& g : quad_groups(l1, l2, lmax)) mx = g.total > mx ? g.total : mx;
+    for (const QuadGroup& g : contour_groups()) mx = g.total > mx ? g.total : mx;
     return mx;
 }
 
@@ -406,8 +434,10 @@ skfab_status validate(const skfab_csr* A, const skfab_params* p, bool need_matri
         if (p->method != SKFAB_SFOM_CLOSED) return SKFAB_ERR_ARG;
     }
     if (p->f == SKFAB_F_EXP) {
-        if (p->method != SKFAB_SFOM_CLOSED) return SKFAB_ERR_ARG;
         if (!(p->fparam >= 0.0)) return SKFAB_ERR_ARG;
+        if (p->method == SKFAB_SFOM_QUAD) return SKFAB_ERR_ARG;
+        // sketched GMRES by the contour rule: tau > 0 (the integrand's decay), m <= CT_NMAX
+        if (p->method == SKFAB_SGMRES_QUAD && (!(p->fparam > 0.0) || p->m > CT_NMAX)) return SKFAB_ERR_ARG;
     }
     return SKFAB_OK;
 }
@@ -610,6 +640,18 @@ skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, h
     if (p->f == SKFAB_F_POLY) {
         HIP_TRY(hipMemcpyAsync(w.poly, p->poly, sizeof(double) * p->npoly, hipMemcpyHostToDevice, st));
         HIP_TRY(launch_poly(w.ctrl, m, w.T1r, w.K0r, w.eta, w.poly, p->npoly, w.y0, st));
+        HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
+        return SKFAB_OK;
+    }
+    if (p->f == SKFAB_F_EXP && ls) {
+        // sketched GMRES by the contour rule (Sections 4.1, 5.2): Ritz values and the
+        // parabola, then trapezoidal levels under the Section 4.1 test
+        HIP_TRY(launch_contour_setup(w.ctrl, m, w.Hh, p->fparam, w.expbuf, st));
+        for (const QuadGroup& g : contour_groups()) {
+            HIP_TRY(launch_contour_level(w.ctrl, g, p->fparam, w.T1r, w.K0r, w.Ubuf, w.nodebuf, m, w.SV, w.eta, st));
+            HIP_TRY(launch_quad_reduce(w.ctrl, g, w.nodebuf, m, tol, w.T1r, w.qprev, w.y0, st));
+        }
+        HIP_TRY(launch_quad_fail(w.ctrl, st));
         HIP_TRY(launch_finish_coeffs(w.ctrl, m, w.y0, w.eta, w.colnorm2, w.ys, w.y, st));
         return SKFAB_OK;
     }

@@ -9,6 +9,10 @@ constexpr int WAVE = 64;
 constexpr int KMAX = 8;                 // largest truncation length of the fused step
 constexpr int NSC_MAX = 2 * KMAX + 1;   // partial scalars per Arnoldi step
 constexpr int MMAX = 512;               // largest Krylov dimension
+constexpr int CT_NMAX = 200;            // largest Krylov dimension of the contour form (exp, sGMRES)
+constexpr int NODE_SLOTS_CT = 512;      // concurrent complex node solves (2 m^2 doubles of scratch each)
+constexpr int CT_KFIRST = 32;           // trapezoidal levels K = 32, 64, ..., CT_KMAX intervals
+constexpr int CT_KMAX = 1024;
 constexpr int SMAX = 1024;              // largest sketch size
 constexpr int STEP_GMAX_1024 = 256;     // step-kernel blocks at most, per 1024 threads of block size
 constexpr double BREAKDOWN_TOL = 1e-14; // lucky-breakdown threshold on h_{j+1,j} / ||A v_j||

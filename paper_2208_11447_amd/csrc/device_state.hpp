@@ -32,6 +32,7 @@ struct DevCtrl {
     int32_t dict_over;  // set when A has more distinct values than the value table holds
     int32_t dict8;      // 1: the SELL-64 copy stores 8-bit indices into the value table
     int32_t m_basis;    // basis length built (m_used before the conditioning truncation)
+    double ct_a, ct_c, ct_tmax;  // contour t(theta) = a + i theta - c theta^2, |theta| <= tmax (exp, sGMRES)
 };
 
 // Value table of the SELL-64 copy (one per matrix): when A has at most DICT_MAX

@@ -51,6 +51,7 @@ __device__ __forceinline__ void init_ctrl_body(DevCtrl* c, int m) {
         c->quad_diff = 0.0;
         c->relres = -1.0;  // set by the Arnoldi-relation check (sparse-sign sketch only)
         c->m_basis = m;
+        c->ct_a = 0.0; c->ct_c = 0.0; c->ct_tmax = 0.0;
     }
 }
 
