@@ -57,7 +57,11 @@ def parse():
                          "every problem and every pair with a nonzero status) and print the table")
     ap.add_argument("--tuning", default=None, metavar="BLOCK,SPW",
                     help="batched form: fixed launch shape (threads per block, slices per wavefront)")
-    ap.add_argument("--f", default="invsqrt", choices=["invsqrt", "inv"])
+    ap.add_argument("--f", default="invsqrt", choices=["invsqrt", "inv", "exp"],
+                    help="f(z): z^(-1/2), 1/z, or exp(-tau z) (sfom: closed form; sgmres: contour rule)")
+    ap.add_argument("--tau", type=float, default=1e-2, help="tau of f(z) = exp(-tau z)")
+    ap.add_argument("--quad-tol", type=float, default=1e-13,
+                    help="tolerance of the adaptive quadrature (Section 4.1 test) for sfom_quad and sgmres")
     ap.add_argument("--method", default="sfom", choices=["sfom", "sfom_quad", "sgmres"])
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16basis"],
                     help="storage/arithmetic of A, the basis and the SpMV (small problem and assembly stay FP64)")
@@ -283,7 +287,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def oracle_legs(cfg, arrays, b, x_gpu, f, method, reps):
+def oracle_legs(cfg, arrays, b, x_gpu, f, method, reps, tau=0.0, quad_tol=1e-13):
     """The oracle as it stands, on the same workload: `reps` full solves (sketch
     construction, m truncated-Arnoldi steps, small problem, assembly) with the BLAS
     pool at the host's thread share.  The first solve also gives the parity of the
@@ -300,8 +304,10 @@ def oracle_legs(cfg, arrays, b, x_gpu, f, method, reps):
     N = rp.size - 1
     A = sp.csr_matrix((val, col, rp), shape=(N, N))
     threads = host_threads()
-    solve = {"sfom": lambda arn: ometh.sfom_closed(arn, f),
-             "sgmres": lambda arn: ometh.sgmres(arn, f, tol=1e-13),
+    from oracle import contour as ocont
+    solve = {"sfom": lambda arn: ometh.sfom_closed(arn, f, tau),
+             "sgmres": (lambda arn: ocont.sgmres_contour(arn, tau, tol=quad_tol)) if f == "exp"
+             else (lambda arn: ometh.sgmres(arn, f, tol=quad_tol)),
              "sfom_quad": lambda arn: ometh.sfom_quad(arn, f, tol=1e-13)}[method]
     times, t_arn, err = [], [], None
     with threadpool_limits(limits=threads):
@@ -752,7 +758,8 @@ def main():
     bd = torch.as_tensor(b, device=dev)
     x = torch.empty_like(bd)
     p = sk.make_params(f=args.f, m=cfg["m"], k=cfg["k"], s=cfg["s"], zeta=cfg["zeta"], seed=cfg["sketch_seed"],
-                       method=args.method, quad_tol=1e-13, prec=args.prec)
+                       method=args.method, quad_tol=args.quad_tol, prec=args.prec,
+                       fparam=args.tau if args.f == "exp" else 0.0)
     ws = sk.alloc_workspace(sk.skfab_workspace_bytes(A, p), device=dev)
     ctx = sk.Context(0)
     print(f"# workload {args.workload}: N={N} nnz={nnz} m={cfg['m']} k={cfg['k']} s={cfg['s']} "
@@ -801,7 +808,8 @@ def main():
     cpu = None
     if not (args.no_parity and args.no_cpu_baseline):
         reps = 0 if args.no_cpu_baseline else args.cpu_solves
-        err, cpu = oracle_legs(cfg, (rp, col, val), b, x_host, args.f, args.method, reps)
+        err, cpu = oracle_legs(cfg, (rp, col, val), b, x_host, args.f, args.method, reps,
+                               tau=args.tau if args.f == "exp" else 0.0, quad_tol=args.quad_tol)
         if not args.no_parity:
             parity = {"rel_err_vs_oracle": err, "tol": 1e-10 if args.prec == "fp64" else None}
             print(f"# parity vs oracle: {err:.3e}", file=sys.stderr, flush=True)
@@ -824,10 +832,13 @@ def main():
                    + ("" if args.prec == "fp64" else f"_{args.prec}"), "grid": f"{cfg['n']}^{cfg['dim']}",
                    "N": N, "nnz": nnz, "m": cfg["m"], "k": cfg["k"], "s": cfg["s"], "zeta": cfg["zeta"],
                    "f": args.f, "method": args.method, "prec": args.prec,
+                   **({"tau": args.tau} if args.f == "exp" else {}),
                    "a_storage": storage_name(info.a_format), "parallelism": "single-gpu"},
         "roofline": roof,
         "cpu_baseline": cpu,
         "parity": parity,
+        "small_problem": {"status": int(info.status), "m_used": int(info.m_used), "quad_order": int(info.l_used),
+                          "quad_diff": float(info.quad_diff), "flags": int(info.flags)},
     }
     print(json.dumps(out), flush=True)
 

@@ -107,12 +107,22 @@ __device__ bool hqr_eigs(double* Hs, double* bul, int n, double* __restrict__ wr
     const double eps = 2.3e-16;
     int hi = n - 1, its = 0, total = 0;
     while (hi >= 0) {
-        // start l of the unreduced block that ends at hi
-        int l = hi;
-        for (; l > 0; --l) {
-            double sd = fabs(g(l - 1, l - 1)) + fabs(g(l, l));
-            if (sd == 0.0) sd = nrm;
-            if (fabs(g(l, l - 1)) <= eps * sd) break;
+        // start l of the unreduced block that ends at hi: the largest l in 1..hi with a
+        // negligible H[l][l-1] (0 if none), 64 candidates per pass
+        int l = 0;
+        for (int top = hi; top > 0; top -= WAVE) {
+            const int c = top - lane;
+            bool small = false;
+            if (c > 0) {
+                double sd = fabs(g(c - 1, c - 1)) + fabs(g(c, c));
+                if (sd == 0.0) sd = nrm;
+                small = fabs(g(c, c - 1)) <= eps * sd;
+            }
+            const unsigned long long hit = __ballot(small);
+            if (hit) {
+                l = top - (__ffsll((long long)hit) - 1);
+                break;
+            }
         }
         __syncthreads();
         if (l > 0 && lane == 0) *hq_at(Hs, bul, l, l - 1, n) = 0.0;
@@ -178,7 +188,8 @@ __device__ bool hqr_eigs(double* Hs, double* bul, int n, double* __restrict__ wr
             if (nx == 0.0) continue;
             const double alpha = (x >= 0.0) ? -nx : nx;
             const double v0 = x - alpha;
-            const double u1 = y / v0, u2 = three ? z / v0 : 0.0;
+            const double rv0 = 1.0 / v0;
+            const double u1 = y * rv0, u2 = three ? z * rv0 : 0.0;
             const double beta = 2.0 / (1.0 + u1 * u1 + u2 * u2);
             // from the left: rows k..k+2, columns max(l, k-1)..hi
             for (int j = max(l, k - 1) + lane; j <= hi; j += WAVE) {
