@@ -443,3 +443,47 @@ def two_pass(A, b, f: str, m: int, k: int, S, method: str = "sfom", fparam: floa
         x += res.y[i] * v
     res.x = x
     return res
+
+
+# ------------------------------------------------- s-adaptivity (Section 6)
+EPS_MAX_DEFAULT = 0.5
+
+
+def solve_reckless(A, b, f: str, m: int, k: int, s0: int, s_max: int, eps_max: float = EPS_MAX_DEFAULT,
+                   zeta: int = 8, seed: int = 0, method: str = "sfom", fparam: float = 0.0, tol: float = 1e-13):
+    """The 'responsibly reckless' choice of the sketch size that the conclusions
+    propose: start with an optimistic s, monitor the computation, and redo it with
+    a larger s when s turns out to be too small.  Reading: s is too small when the
+    solve fails numerically (a sketched Ritz value on the branch cut, or a
+    quadrature that does not converge) or when the Section 4.3 monitor
+    max_j | ||S v_j||^2 - 1 | over the basis in use exceeds eps_max; the redo
+    doubles s (capped at s_max; S is redrawn from the same seed).  Returns
+    (SolveResult, s_used, trail) with trail = [(s, outcome, eps), ...]."""
+    from . import arnoldi as oarn
+    from . import sketch as osk
+    N = A.shape[0]
+    trail = []
+    s = s0
+    while True:
+        S = osk.sparse_sign_matrix(N, s, zeta, seed)
+        arn = oarn.truncated_arnoldi(A, b, m, k, S)
+        used, mp = regularize(arn)
+        eps = float(np.max(np.abs(np.sum(used.SV ** 2, axis=0) - 1.0))) if mp > 0 else 0.0
+        res, outcome = None, "ok"
+        try:
+            if method == "sfom":
+                res = sfom_closed(arn, f, fparam)
+            elif method == "sfom_quad":
+                res = sfom_quad(arn, f, tol=tol)
+            else:
+                res = sgmres(arn, f, tol=tol)
+        except BranchError:
+            outcome = "branch"
+        except QuadratureError:
+            outcome = "quad"
+        if outcome == "ok" and eps > eps_max:
+            outcome = "eps"
+        trail.append((s, outcome, eps))
+        if outcome == "ok" or s >= s_max:
+            return res, s, trail
+        s = min(2 * s, s_max)
