@@ -55,6 +55,10 @@ def parse():
     ap.add_argument("--check-outputs", default=None, metavar="NPZ",
                     help="CPU only: check the saved batched outputs against the oracle (right-hand side 0 of "
                          "every problem and every pair with a nonzero status) and print the table")
+    ap.add_argument("--reckless", action="store_true",
+                    help="batched form: after the timed batches, re-solve every refused pair with "
+                         "skfab_solve_reckless (s doubled from 4m up to min(8m, 1024) while the solve fails or the "
+                         "embedding monitor exceeds 0.5) and report how many it recovers")
     ap.add_argument("--tuning", default=None, metavar="BLOCK,SPW",
                     help="batched form: fixed launch shape (threads per block, slices per wavefront)")
     ap.add_argument("--f", default="invsqrt", choices=["invsqrt", "inv", "exp"],
@@ -417,8 +421,34 @@ def run_batched(args):
     asm_bytes = sum(R * (PREC_BYTES[args.prec][1] * N * m + 8 * N) for N, m in zip(Ns, ms)) * n_asm
     print(f"# timed {args.steps} batches in {elapsed:.3f} s; {len(bad)} pairs with a nonzero status {bad[:4]}",
           file=sys.stderr, flush=True)
+    reck = None
+    if args.reckless and bad:
+        # the sketch size chosen by the computation for the pairs the batch refused
+        s_cap = lambda i: min(4 * probs[i].s, 1024)  # (the library's largest sketch)
+        s_mx = max(s_cap(i) for i, _, _ in bad)
+        pr = sk.make_params(f=args.f, m=max(ms), k=2, zeta=8, s=s_mx, method=args.method, quad_tol=1e-13,
+                            prec=args.prec)
+        big = max(range(len(probs)), key=lambda i: Ns[i])
+        wsr = sk.alloc_workspace(sk.skfab_workspace_bytes(probs[big].A, pr))
+        rec, used, t0 = 0, [], time.perf_counter()
+        for i, r, _ in bad:
+            pq = sk.make_params(f=args.f, m=probs[i].m, k=2, zeta=8, s=2 * probs[i].s, seed=probs[i].seed,
+                                method=args.method, quad_tol=1e-13, prec=args.prec)
+            xr = torch.empty_like(probs[i].B[r])
+            inf_r, s_u = sk.skfab_solve_reckless(ctx, probs[i].A, probs[i].B[r].contiguous(), xr, pq,
+                                                 s_cap(i), 0.5, wsr)
+            used.append([int(i), int(r), int(s_u), int(inf_r.status)])
+            if inf_r.status == 0:
+                rec += 1
+                probs[i].X[r].copy_(xr)
+                info[i][r] = inf_r
+        torch.cuda.synchronize()
+        reck = {"recovered": rec, "refused": len(bad), "seconds": round(time.perf_counter() - t0, 3),
+                "s_start": "4m", "s_max": "min(8m, 1024)", "eps_max": 0.5, "pairs": used}
+        print(f"# reckless s: {rec} of {len(bad)} refused pairs recovered", file=sys.stderr, flush=True)
     if args.save_outputs:
-        save_batch_outputs(args.save_outputs, probs, info, R)
+        s_used = {(p_[0], p_[1]): p_[2] for p_ in reck["pairs"]} if reck else None
+        save_batch_outputs(args.save_outputs, probs, info, R, s_used)
     # parity on a bounded sample: the two smallest problems, first right-hand side
     parity = None
     if not args.no_parity:
@@ -475,6 +505,7 @@ def run_batched(args):
         "cpu_baseline": None,
         "parity": parity,
         "nonzero_status_pairs": len(bad),
+        "reckless_s": reck,
         "nonzero_status_list": [[int(i), int(r), int(st)] for i, r, st in bad],
     }
     print(json.dumps(out), flush=True)
@@ -489,7 +520,10 @@ def sample_index(N: int):
     return np.unique(np.linspace(0, N - 1, SAMPLE_ENTRIES).astype(np.int64))
 
 
-def save_batch_outputs(path, probs, info, R):
+def save_batch_outputs(path, probs, info, R, s_used=None):
+    """Every pair's status, m_used, flags, ||x||, x at the sample entries and the
+    sketch size its result used (s_used: {(problem, rhs): s} for the pairs the
+    s-adaptive solve redid, else the problem's s)."""
     import numpy as np
     rows = []
     for i, q in enumerate(probs):
@@ -497,8 +531,9 @@ def save_batch_outputs(path, probs, info, R):
         X = q.X.cpu().numpy()
         for r in range(R):
             rows.append((i, r, info[i][r].status, info[i][r].m_used, info[i][r].flags,
-                         float(np.linalg.norm(X[r])), X[r][idx]))
+                         float(np.linalg.norm(X[r])), X[r][idx], (s_used or {}).get((i, r), q.s)))
     np.savez_compressed(path, prob=np.array([r[0] for r in rows]), rhs=np.array([r[1] for r in rows]),
+                        s=np.array([r[7] for r in rows]),
                         status=np.array([r[2] for r in rows]), m_used=np.array([r[3] for r in rows]),
                         flags=np.array([r[4] for r in rows]), xnorm=np.array([r[5] for r in rows]),
                         xs=np.array([np.pad(r[6], (0, SAMPLE_ENTRIES - r[6].size)) for r in rows]))
@@ -516,16 +551,16 @@ def _oracle_pair(job):
     from oracle import sketch as osk
     from workloads import batched_problem_params, convdiff_csr
 
-    pi, r, nprob = job
+    pi, r, nprob, s = job
     q = batched_problem_params(nprob)[pi]
     with threadpool_limits(limits=1):
         rp, col, val = convdiff_csr(q["n"], 2, 1.0, q["c"])
         N = rp.size - 1
         A = sp.csr_matrix((val, col, rp), shape=(N, N))
         b = np.random.default_rng(q["rhs_seedseq"]).standard_normal((4, N))[r]
-        S = osk.sparse_sign_matrix(N, q["s"], 8, q["sketch_seed"])
+        S = osk.sparse_sign_matrix(N, s, 8, q["sketch_seed"])
         arn = oarn.truncated_arnoldi(A, b, q["m"], 2, S)
-        out = {"N": N, "m": q["m"]}
+        out = {"N": N, "m": q["m"], "s": s}
         try:
             res = ometh.sfom_closed(arn, "invsqrt")
             out.update(verdict="ok", m_used=res.m_used, xnorm=float(np.linalg.norm(res.x)),
@@ -541,20 +576,27 @@ def _oracle_pair(job):
 
 def check_batch_outputs(path, nprob):
     """Oracle check of saved batched outputs (CPU): right-hand side 0 of every
-    problem, and every pair with a nonzero status, through the oracle's own run of
-    the same pair.  A pair the GPU solved is compared on the sampled entries and on
-    ||x||; a pair the GPU refused is classified by what the oracle does with it."""
+    problem, every pair with a nonzero status and every pair the s-adaptive solve
+    redid, through the oracle's own run of the same pair at the sketch size the
+    saved result used.  A pair the GPU solved is compared on the sampled entries
+    and on ||x||; a pair the GPU refused is classified by what the oracle does
+    with it."""
     import numpy as np
     from concurrent.futures import ProcessPoolExecutor
 
     d = np.load(path)
+    from workloads import batched_problem_params
+    qs = batched_problem_params(nprob)
     pairs = {(int(p), int(r)): k for k, (p, r) in enumerate(zip(d["prob"], d["rhs"]))}
-    todo = sorted({(p, 0) for p in range(nprob)} | {pr for pr, k in pairs.items() if d["status"][k] != 0})
+    s_of = {pr: (int(d["s"][k]) if "s" in d else qs[pr[0]]["s"]) for pr, k in pairs.items()}
+    todo = sorted({(p, 0) for p in range(nprob)} | {pr for pr, k in pairs.items() if d["status"][k] != 0}
+                  | {pr for pr in pairs if s_of[pr] != qs[pr[0]]["s"]})
     rows = []
     worst = 0.0
     with ProcessPoolExecutor(max_workers=host_threads()) as ex:
-        results = sorted(ex.map(_oracle_pair, [(p, r, nprob) for p, r in todo]), key=lambda t: (t[0], t[1]))
-    print("problem rhs N m gpu_status oracle gpu_m_used oracle_m_used rel_err_sampled rel_err_norm cut_eigs",
+        results = sorted(ex.map(_oracle_pair, [(p, r, nprob, s_of[(p, r)]) for p, r in todo]),
+                         key=lambda t: (t[0], t[1]))
+    print("problem rhs N m s gpu_status oracle gpu_m_used oracle_m_used rel_err_sampled rel_err_norm cut_eigs",
           flush=True)
     for pi, r, o in results:
         k = pairs[(pi, r)]
@@ -566,10 +608,10 @@ def check_batch_outputs(path, nprob):
             evn = abs(float(d["xnorm"][k]) - o["xnorm"]) / o["xnorm"]
             worst = max(worst, ev, evn)
             e, en = f"{ev:.2e}", f"{evn:.2e}"
-        rows.append((pi, r, o["N"], o["m"], gst, o["verdict"], int(d["m_used"][k]), o["m_used"], e, en,
+        rows.append((pi, r, o["N"], o["m"], o["s"], gst, o["verdict"], int(d["m_used"][k]), o["m_used"], e, en,
                      ",".join(f"{v:.3g}" for v in o.get("cut_eigs", [])) or "-"))
         print(" ".join(str(v) for v in rows[-1]), flush=True)
-    agree = sum(1 for row in rows if (row[4] == 0) == (row[5] == "ok"))
+    agree = sum(1 for row in rows if (row[5] == 0) == (row[6] == "ok"))
     print(json.dumps({"checked_pairs": len(rows), "status_agrees_with_oracle": agree,
                       "max_rel_err_sampled": worst}), flush=True)
 

@@ -259,6 +259,22 @@ skfab_status skfab_solve(skfab_ctx *ctx, const skfab_csr *A, const double *b, in
                          int32_t nrhs, double *x, int64_t ldx, const skfab_params *p,
                          void *ws, size_t ws_bytes, skfab_info *info);
 
+/* Sketch size chosen by the computation (the conclusions' "responsibly reckless"
+ * approach, Section 6): solve with the optimistic p->s first; if the solve fails
+ * numerically (info.status nonzero: a sketched Ritz value on the branch cut, a
+ * quadrature that does not converge, a singular factor) or the Section 4.3 monitor
+ * info.eps_est = max_j | ||S v_j||^2 - 1 | exceeds eps_max, s was too small: the
+ * solve is redone with 2 s (S redrawn from the same seed), up to s_max.  One right-
+ * hand side; sparse-sign sketch, one-pass form.  ws must hold
+ * skfab_workspace_bytes(A, p with s = s_max, 1).  On return x and info are those of
+ * the last attempt, *s_used its sketch size (s_max with a nonzero info.status when
+ * no attempt succeeded).  Every attempt synchronises to read its info.  Errors:
+ * SKFAB_ERR_ARG (null pointers, eps_max <= 0, s_max < p->s, two-pass or SRDCT),
+ * the shape checks of skfab_solve at s = s_max, SKFAB_ERR_WORKSPACE. */
+skfab_status skfab_solve_reckless(skfab_ctx *ctx, const skfab_csr *A, const double *b, double *x,
+                                  const skfab_params *p, int32_t s_max, double eps_max, void *ws,
+                                  size_t ws_bytes, skfab_info *info, int32_t *s_used);
+
 /* For callers that cannot allocate device memory (code under HIP graph capture,
  * serving loops, harnesses that forbid hipMalloc): skfab_solve with one right-hand
  * side (ldb = ldx = N) whose workspace is a static device array of

@@ -24,7 +24,8 @@ SKFAB_SKETCH_SPARSE_SIGN, SKFAB_SKETCH_SRDCT = 0, 1
 
 EXPORTED = [
     "skfab_version", "skfab_status_string", "skfab_create", "skfab_set_stream", "skfab_destroy",
-    "skfab_workspace_bytes", "skfab_solve", "skfab_solve_noalloc", "skfab_arnoldi", "skfab_small_problem",
+    "skfab_workspace_bytes", "skfab_solve", "skfab_solve_noalloc", "skfab_solve_reckless", "skfab_arnoldi",
+    "skfab_small_problem",
     "skfab_small_workspace_bytes", "skfab_sketch_pattern", "skfab_sketch_apply", "skfab_sketch_ws_bytes",
     "skfab_timing_enable", "skfab_timing_read", "skfab_set_value_table", "skfab_srdct_ws_bytes", "skfab_srdct_apply",
     "skfab_batch_workspace_bytes", "skfab_solve_batched", "skfab_batch_set_tuning", "skfab_batch_get_tuning",
@@ -89,6 +90,9 @@ def lib():
                                   C.POINTER(skfab_params), P, C.c_size_t, C.POINTER(skfab_info)]),
         "skfab_solve_noalloc": (C.c_int, [P, C.POINTER(skfab_csr), P, P, C.POINTER(skfab_params),
                                           C.POINTER(skfab_info)]),
+        "skfab_solve_reckless": (C.c_int, [P, C.POINTER(skfab_csr), P, P, C.POINTER(skfab_params), C.c_int32,
+                                           C.c_double, P, C.c_size_t, C.POINTER(skfab_info),
+                                           C.POINTER(C.c_int32)]),
         "skfab_arnoldi": (C.c_int, [P, C.POINTER(skfab_csr), P, C.POINTER(skfab_params), P, P, P, P, P,
                                     C.c_size_t, C.POINTER(skfab_info)]),
         "skfab_small_problem": (C.c_int, [P, P, P, C.c_double, C.POINTER(skfab_params), P, P, C.c_size_t,

@@ -831,6 +831,32 @@ skfab_status skfab_solve(skfab_ctx* ctx, const skfab_csr* A, const double* b, in
     return SKFAB_OK;
 }
 
+skfab_status skfab_solve_reckless(skfab_ctx* ctx, const skfab_csr* A, const double* b, double* x,
+                                  const skfab_params* p, int32_t s_max, double eps_max, void* ws, size_t ws_bytes,
+                                  skfab_info* info, int32_t* s_used) {
+    if (!ctx || !A || !b || !x || !p || !info) return SKFAB_ERR_ARG;
+    if (!(eps_max > 0.0) || s_max < p->s || p->two_pass || p->sketch != SKFAB_SKETCH_SPARSE_SIGN) return SKFAB_ERR_ARG;
+    skfab_params q = *p;
+    q.s = s_max;  // the largest attempt must fit (shape and workspace) before the first runs
+    skfab_status v = validate(A, &q, true);
+    if (v != SKFAB_OK) return v;
+    size_t need = 0;
+    v = skfab_workspace_bytes(A, &q, 1, &need);
+    if (v != SKFAB_OK) return v;
+    if (!ws || ws_bytes < need) return SKFAB_ERR_WORKSPACE;
+    int32_t s = p->s;
+    for (;;) {
+        q.s = s;
+        v = solve_one(ctx, A, b, x, &q, ws, ws_bytes, info);
+        if (v != SKFAB_OK) return v;
+        const bool ok = info->status == SKFAB_OK && info->eps_est <= eps_max;
+        if (ok || s >= s_max) break;
+        s = (2 * (int64_t)s < s_max) ? 2 * s : s_max;
+    }
+    if (s_used) *s_used = s;
+    return SKFAB_OK;
+}
+
 }  // extern "C"
 
 namespace {

@@ -186,6 +186,24 @@ def skfab_solve_noalloc(ctx: Context, A: CSR, b: torch.Tensor, x: torch.Tensor, 
     return info
 
 
+def skfab_solve_reckless(ctx: Context, A: CSR, b: torch.Tensor, x: torch.Tensor, p: N.skfab_params, s_max: int,
+                         eps_max: float, ws: torch.Tensor):
+    """x <- f(A) b with the sketch size chosen by the computation: p.s first, doubled
+    (up to s_max) while the solve fails or the embedding monitor exceeds eps_max.
+    Returns (info, s_used); ws must hold the workspace of the s = s_max solve."""
+    _require_device(b, torch.float64, "b")
+    _require_device(x, torch.float64, "x")
+    if b.shape != x.shape or b.dim() != 1 or b.shape[0] != A.n:
+        raise ValueError("b and x must be (N,) tensors of the matrix's size")
+    csr = A.c_struct()
+    info = N.skfab_info()
+    s_used = C.c_int32(0)
+    st = N.lib().skfab_solve_reckless(ctx.handle, C.byref(csr), _ptr(b), _ptr(x), C.byref(p), int(s_max),
+                                      float(eps_max), _ptr(ws), ws.numel(), C.byref(info), C.byref(s_used))
+    _check(st, "skfab_solve_reckless")
+    return info, s_used.value
+
+
 def skfab_arnoldi(ctx: Context, A: CSR, b: torch.Tensor, p: N.skfab_params, V=None, SV=None, SAV=None, H=None,
                   ws: torch.Tensor = None, want_info: bool = True):
     csr = A.c_struct()

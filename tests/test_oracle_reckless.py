@@ -32,7 +32,8 @@ def batch_pair(pi, r):
 
 def test_reckless_recovers_branch_failure():
     A, b, q = batch_pair(7, 1)
-    res, s_used, trail = ometh.solve_reckless(A, b, "invsqrt", q["m"], 2, q["s"], 4 * q["s"], seed=q["sketch_seed"])
+    res, s_used, trail = ometh.solve_reckless(A, b, "invsqrt", q["m"], 2, q["s"], min(4 * q["s"], 1024),
+                                              seed=q["sketch_seed"])
     assert [t[1] for t in trail] == ["branch", "ok"]
     assert s_used == 2 * q["s"]
     S = osk.sparse_sign_matrix(A.shape[0], s_used, 8, q["sketch_seed"])
