@@ -70,6 +70,9 @@ def parse():
     ap.add_argument("--prec", default="fp64", choices=["fp64", "fp32", "bf16basis"],
                     help="storage/arithmetic of A, the basis and the SpMV (small problem and assembly stay FP64)")
     ap.add_argument("--no-parity", action="store_true", help="skip the full-size oracle comparison")
+    ap.add_argument("--plain-values", action="store_true",
+                    help="single-problem workloads: store A's values in the SELL copy as they are, not as "
+                         "indices into a table of its distinct values")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-solves", type=int, default=3,
                     help="full oracle solves timed for cpu_baseline (median; the first also gives the parity)")
@@ -804,6 +807,8 @@ def main():
                        fparam=args.tau if args.f == "exp" else 0.0)
     ws = sk.alloc_workspace(sk.skfab_workspace_bytes(A, p), device=dev)
     ctx = sk.Context(0)
+    if args.plain_values:
+        sk.skfab_set_value_table(ctx, False)
     print(f"# workload {args.workload}: N={N} nnz={nnz} m={cfg['m']} k={cfg['k']} s={cfg['s']} "
           f"f={args.f} method={args.method} prec={args.prec}", file=sys.stderr, flush=True)
 

@@ -53,6 +53,10 @@ constexpr double CT_KAPPA_MAX = 0.25;
 // Balancing by powers of two (a diagonal similarity, exact) comes first: the last
 // column of H_hat can be orders of magnitude larger than the band.
 constexpr int CT_HQR_CAP = CT_NMAX + (CT_NMAX - 1) * (CT_NMAX + 2) / 2;
+// Threads of the eigenvalue kernel: every wavefront takes the same (uniform)
+// decisions from the same LDS values; the row and column updates of a reflector
+// are spread over all of them, one entry per thread (n <= CT_NMAX < HQ_NT).
+constexpr int HQ_NT = 256;
 
 __device__ __forceinline__ int hq_off(int i, int n) { return (i == 0) ? 0 : n + (i - 1) * (2 * n - i + 2) / 2; }
 
@@ -75,6 +79,7 @@ __device__ void hq_balance(double* Hs, double* bul, int n) {
                 if (q != i) r += fabs(*hq_at(Hs, bul, i, q, n));
             c = wave_sum(c);
             r = wave_sum(r);
+            __syncthreads();  // every wavefront has its sums before any scaling
             if (c == 0.0 || r == 0.0) continue;
             double gg = 0.5 * r, f = 1.0;
             const double s = c + r;
@@ -84,9 +89,9 @@ __device__ void hq_balance(double* Hs, double* bul, int n) {
             if ((c + r) / f < 0.95 * s) {
                 done = false;
                 const double fi = 1.0 / f;
-                for (int q = (i > 0 ? i - 1 : 0) + lane; q < n; q += WAVE) *hq_at(Hs, bul, i, q, n) *= fi;
+                for (int q = (i > 0 ? i - 1 : 0) + (int)threadIdx.x; q < n; q += HQ_NT) *hq_at(Hs, bul, i, q, n) *= fi;
                 __syncthreads();
-                for (int q = lane; q < min(i + 2, n); q += WAVE) *hq_at(Hs, bul, q, i, n) *= f;
+                for (int q = threadIdx.x; q < min(i + 2, n); q += HQ_NT) *hq_at(Hs, bul, q, i, n) *= f;
             }
             __syncthreads();
         }
@@ -125,10 +130,10 @@ __device__ bool hqr_eigs(double* Hs, double* bul, int n, double* __restrict__ wr
             }
         }
         __syncthreads();
-        if (l > 0 && lane == 0) *hq_at(Hs, bul, l, l - 1, n) = 0.0;
+        if (l > 0 && threadIdx.x == 0) *hq_at(Hs, bul, l, l - 1, n) = 0.0;
         __syncthreads();
         if (l == hi) {
-            if (lane == 0) { wr[hi] = g(hi, hi); wi[hi] = 0.0; }
+            if (threadIdx.x == 0) { wr[hi] = g(hi, hi); wi[hi] = 0.0; }
             --hi;
             its = 0;
             continue;
@@ -137,7 +142,7 @@ __device__ bool hqr_eigs(double* Hs, double* bul, int n, double* __restrict__ wr
             // 2 x 2 block [[p, q], [r, s]]
             const double p = g(hi - 1, hi - 1), q = g(hi - 1, hi), r = g(hi, hi - 1), s = g(hi, hi);
             const double hm = 0.5 * (p - s), disc = hm * hm + q * r;
-            if (lane == 0) {
+            if (threadIdx.x == 0) {
                 if (disc >= 0.0) {
                     const double z = hm + copysign(sqrt(disc), hm);
                     wr[hi - 1] = s + z;
@@ -191,10 +196,17 @@ __device__ bool hqr_eigs(double* Hs, double* bul, int n, double* __restrict__ wr
             const double rv0 = 1.0 / v0;
             const double u1 = y * rv0, u2 = three ? z * rv0 : 0.0;
             const double beta = 2.0 / (1.0 + u1 * u1 + u2 * u2);
-            // from the left: rows k..k+2, columns max(l, k-1)..hi
-            for (int j = max(l, k - 1) + lane; j <= hi; j += WAVE) {
+            // from the left: rows k..k+2, columns max(l, k-1)..hi; column k-1 (k > l) is the
+            // annihilated bulge, written exactly: (alpha, 0, 0)
+            for (int j = max(l, k - 1) + (int)threadIdx.x; j <= hi; j += HQ_NT) {
                 double* p0 = hq_at(Hs, bul, k, j, n);
                 double* p1 = hq_at(Hs, bul, k + 1, j, n);
+                if (j == k - 1) {
+                    *p0 = alpha;
+                    *p1 = 0.0;
+                    if (three) *hq_at(Hs, bul, k + 2, j, n) = 0.0;
+                    continue;
+                }
                 const double r0 = *p0, r1 = *p1;
                 const double r2 = three ? *hq_at(Hs, bul, k + 2, j, n) : 0.0;
                 const double d = beta * (r0 + u1 * r1 + u2 * r2);
@@ -203,15 +215,9 @@ __device__ bool hqr_eigs(double* Hs, double* bul, int n, double* __restrict__ wr
                 if (three) *hq_at(Hs, bul, k + 2, j, n) = r2 - d * u2;
             }
             __syncthreads();
-            if (k > l && lane == 0) {  // the annihilated bulge, exactly
-                *hq_at(Hs, bul, k, k - 1, n) = alpha;
-                *hq_at(Hs, bul, k + 1, k - 1, n) = 0.0;
-                if (three) *hq_at(Hs, bul, k + 2, k - 1, n) = 0.0;
-            }
-            __syncthreads();
             // from the right: columns k..k+2, rows l..min(k+3, hi)
             const int rl = min(k + 3, hi);
-            for (int i = l + lane; i <= rl; i += WAVE) {
+            for (int i = l + (int)threadIdx.x; i <= rl; i += HQ_NT) {
                 double* p0 = hq_at(Hs, bul, i, k, n);
                 double* p1 = hq_at(Hs, bul, i, k + 1, n);
                 const double c0 = *p0, c1 = *p1;
@@ -230,18 +236,18 @@ __device__ bool hqr_eigs(double* Hs, double* bul, int n, double* __restrict__ wr
 // One block of one wavefront: the Ritz values (eigenvalues of H_hat, row-major,
 // ld m) into ritz[0..mu) (real parts) and ritz[m..m+mu) (imaginary parts), then
 // the parabola into the control block (sigma = 1: the rule carries its own scale).
-__global__ __launch_bounds__(64) void contour_setup_kernel(DevCtrl* ctrl, int m, const double* __restrict__ Hh,
+__global__ __launch_bounds__(HQ_NT) void contour_setup_kernel(DevCtrl* ctrl, int m, const double* __restrict__ Hh,
                                                             double tau, double* __restrict__ ritz) {
     __shared__ double Hs[CT_HQR_CAP];
     __shared__ double bul[3];
     if (ctrl->status != 0) return;
     const int mu = ctrl->m_used;
     if (mu == 0) return;
-    const int lane = threadIdx.x;
-    if (lane < 3) bul[lane] = 0.0;
+    const int lane = threadIdx.x & 63;
+    if (threadIdx.x < 3) bul[threadIdx.x] = 0.0;
     for (int i = 0; i < mu; ++i)
-        for (int j = (i > 0 ? i - 1 : 0) + lane; j < mu; j += WAVE) Hs[hq_off(i, mu) + j - (i > 0 ? i - 1 : 0)] =
-            Hh[(int64_t)i * m + j];
+        for (int j = (i > 0 ? i - 1 : 0) + (int)threadIdx.x; j < mu; j += HQ_NT)
+            Hs[hq_off(i, mu) + j - (i > 0 ? i - 1 : 0)] = Hh[(int64_t)i * m + j];
     __syncthreads();
     hq_balance(Hs, bul, mu);
     double* wr = ritz;
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(64) void contour_setup_kernel(DevCtrl* ctrl, int m,
     __threadfence_block();
     __syncthreads();
     if (!ok) {
-        if (lane == 0) ctrl->status = 5;  // no contour: the eigenvalue iteration did not converge
+        if (threadIdx.x == 0) ctrl->status = 5;  // no contour: the eigenvalue iteration did not converge
         return;
     }
     // the parabola (comment at the top of the file)
@@ -264,7 +270,7 @@ __global__ __launch_bounds__(64) void contour_setup_kernel(DevCtrl* ctrl, int m,
         if (re >= top - CT_L && im != 0.0) kap = fmin(kap, (alpha - re) / (2.0 * im * im));
     }
     kap = wave_min(kap);
-    if (lane == 0) {
+    if (threadIdx.x == 0) {
         const double vmax = sqrt((alpha - top + CT_L) / kap);
         ctrl->ct_a = alpha / tau;
         ctrl->ct_c = kap * tau;
@@ -412,7 +418,7 @@ __global__ __launch_bounds__(256) void contour_level_kernel(const DevCtrl* ctrl,
 }
 
 hipError_t launch_contour_setup(DevCtrl* ctrl, int m, const double* Hh, double tau, double* ritz, hipStream_t st) {
-    hipLaunchKernelGGL(contour_setup_kernel, dim3(1), dim3(64), 0, st, ctrl, m, Hh, tau, ritz);
+    hipLaunchKernelGGL(contour_setup_kernel, dim3(1), dim3(HQ_NT), 0, st, ctrl, m, Hh, tau, ritz);
     return hipGetLastError();
 }
 
