@@ -81,10 +81,30 @@ def test_workspace_sizes_grow_with_problem():
     (dict(f=7), N.SKFAB_ERR_ARG),
     (dict(method=1, f=3), N.SKFAB_ERR_ARG),    # polynomial needs the closed form
     (dict(l1=45, l2=32), N.SKFAB_ERR_ARG),
+    (dict(f=1, method=2, fparam=0.0), N.SKFAB_ERR_ARG),           # contour form needs tau > 0
+    (dict(f=1, method=2, fparam=0.01, m=201, s=402), N.SKFAB_ERR_ARG),  # ... and m <= 200
+    (dict(f=1, method=1, fparam=0.01), N.SKFAB_ERR_ARG),          # no sFOM-quadrature form for exp
 ])
 def test_host_validation(kw, status):
     st, _ = _ws(10_000, **kw)
     assert st == status
+
+
+def test_contour_form_accepted():
+    """exp with sketched GMRES (the contour rule) passes host validation."""
+    st, nbytes = _ws(10_000, f=1, method=2, fparam=0.01, m=50, s=200)
+    assert st == N.SKFAB_OK and nbytes > 0
+
+
+def test_reckless_host_validation():
+    """skfab_solve_reckless rejects null arguments before touching any device."""
+    lib = N.lib()
+    info = N.skfab_info()
+    used = C.c_int32(0)
+    p = N.skfab_params()
+    assert lib.skfab_solve_reckless(None, None, None, None, C.byref(p), 400, 0.5, None, 0, C.byref(info),
+                                    C.byref(used)) == N.SKFAB_ERR_ARG
+    assert lib.skfab_solve_reckless(None, None, None, None, None, 400, 0.5, None, 0, None, None) == N.SKFAB_ERR_ARG
 
 
 def test_value_table_switch_validation():
