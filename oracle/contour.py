@@ -104,9 +104,9 @@ def resolvent_rule(A: np.ndarray, b: np.ndarray, tau: float, a: float, c: float,
     return acc
 
 
-def _contour_solve(arn: ArnoldiResult, tau: float, node, tol: float, kmax: int):
+def _contour_solve(arn: ArnoldiResult, tau: float, node, tol: float, kmax: int, cond_max: float):
     full = arn
-    arn, mp = M_.regularize(full)
+    arn, mp = M_.regularize(full, cond_max)
     w = M_.whiten(arn)
     theta = np.linalg.eigvals(w.M)
     a, c, tmax = parabola(theta, tau)
@@ -144,7 +144,8 @@ def _contour_solve(arn: ArnoldiResult, tau: float, node, tol: float, kmax: int):
                           info=dict(a=a, c=c, theta_max=tmax, ritz=theta, **st))
 
 
-def sgmres_contour(arn: ArnoldiResult, tau: float, tol: float = 1e-13, kmax: int = K_MAX) -> M_.SolveResult:
+def sgmres_contour(arn: ArnoldiResult, tau: float, tol: float = 1e-13, kmax: int = K_MAX,
+                   cond_max: float = M_.COND_MAX) -> M_.SolveResult:
     """Sketched GMRES approximant (eq. sGMRES) to exp(-tau A) b: at each node the
     least-squares solution of min ||S b - (t Q + B) g|| (complex t), whitened."""
     if arn.m_used == 0:
@@ -153,10 +154,11 @@ def sgmres_contour(arn: ArnoldiResult, tau: float, tol: float = 1e-13, kmax: int
     def node(w, t):
         return np.linalg.lstsq(t * w.Q + w.B, w.Sb.astype(np.complex128), rcond=None)[0]
 
-    return _contour_solve(arn, tau, node, tol, kmax)
+    return _contour_solve(arn, tau, node, tol, kmax, cond_max)
 
 
-def sfom_contour(arn: ArnoldiResult, tau: float, tol: float = 1e-13, kmax: int = K_MAX) -> M_.SolveResult:
+def sfom_contour(arn: ArnoldiResult, tau: float, tol: float = 1e-13, kmax: int = K_MAX,
+                 cond_max: float = M_.COND_MAX) -> M_.SolveResult:
     """Sketched FOM approximant by the same contour rule: (t I + M) g = c at each
     node.  Equals the closed form exp(-tau M) c up to the quadrature error."""
     if arn.m_used == 0:
@@ -165,4 +167,4 @@ def sfom_contour(arn: ArnoldiResult, tau: float, tol: float = 1e-13, kmax: int =
     def node(w, t):
         return np.linalg.solve(t * np.eye(w.M.shape[0]) + w.M, w.c.astype(np.complex128))
 
-    return _contour_solve(arn, tau, node, tol, kmax)
+    return _contour_solve(arn, tau, node, tol, kmax, cond_max)

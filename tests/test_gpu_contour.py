@@ -70,3 +70,57 @@ def test_sgmres_exp_contour_refusals():
                dict(fparam=1e-2, m=30, s=60, method="sfom_quad")):
         with pytest.raises(sk.SkfabError):
             gpu_solve(arrs, b, f="exp", k=2, **kw)
+
+
+def test_sgmres_exp_contour_lucky_breakdown():
+    """b in an A-invariant subspace of dimension 3 (k = 3): the recurrence stops at
+    m_used = 3, the sketched GMRES problem is solved exactly at every node, and the
+    contour rule reproduces exp(-tau A) b (dense expm of the 3 x 3 block)."""
+    import scipy.sparse as sp
+    rng = np.random.default_rng(0)
+    blk = np.diag([2.0, 5.0, 9.0]) + 0.5 * rng.standard_normal((3, 3))
+    rest = sp.diags(np.linspace(1.0, 9.0, 197))
+    A = sp.block_diag([blk, rest]).tocsr()
+    A.sort_indices()
+    b = np.zeros(200)
+    b[:3] = rng.standard_normal(3)
+    arrs = (A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data)
+    tau = 0.3
+    x, info = gpu_solve(arrs, b, f="exp", fparam=tau, m=8, k=3, s=40, method="sgmres", quad_tol=1e-12)
+    truth = np.zeros(200)
+    truth[:3] = sla.expm(-tau * blk) @ b[:3]
+    log(f"breakdown: m_used={info.m_used} nodes={info.l_used} rel err {rel(x, truth):.2e}")
+    assert info.status == 0 and info.m_used == 3
+    assert rel(x, truth) < 1e-10
+
+
+def test_sgmres_exp_contour_strong_convection():
+    """m = 200 on a 100 x 100 grid with strong convection (the largest m of the
+    contour form): the device agrees with the oracle."""
+    A, b, arrs = problem(100, 2, 60.0, seed=7)
+    tau, m, k, s = 2e-3, 200, 2, 400
+    x, info = gpu_solve(arrs, b, f="exp", fparam=tau, m=m, k=k, s=s, method="sgmres", quad_tol=1e-12, seed=2)
+    arn, _ = oracle_run(A, b, m, k, s, seed=2)
+    r = C.sgmres_contour(arn, tau, tol=1e-12)
+    e = rel(x, r.x)
+    log(f"strong convection: m_used={info.m_used} nodes={info.l_used} (oracle {r.l_used}) vs oracle {e:.2e}")
+    assert info.status == 0 and info.m_used == r.m_used
+    assert e < 1e-9
+
+
+def test_sgmres_exp_contour_conditioned_prefix():
+    """The Section 2.1 remedy ahead of the contour rule: with cond_max = 300 the
+    basis of the previous case is truncated to its conditioned prefix, to the same
+    length on both sides, and the contour rule on that prefix agrees with the
+    oracle's."""
+    A, b, arrs = problem(100, 2, 60.0, seed=7)
+    tau, m, k, s = 2e-3, 200, 2, 400
+    x, info = gpu_solve(arrs, b, f="exp", fparam=tau, m=m, k=k, s=s, method="sgmres", quad_tol=1e-12, seed=2,
+                        cond_max=300.0)
+    arn, _ = oracle_run(A, b, m, k, s, seed=2)
+    r = C.sgmres_contour(arn, tau, tol=1e-12, cond_max=300.0)
+    e = rel(x, r.x)
+    log(f"prefix: m_used={info.m_used} (oracle {r.m_used}) of {info.m_basis}, flags={info.flags} "
+        f"nodes={info.l_used} (oracle {r.l_used}) vs oracle {e:.2e}")
+    assert info.status == 0 and info.flags & 1 and info.m_used == r.m_used < m
+    assert e < 1e-9
