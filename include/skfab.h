@@ -368,6 +368,16 @@ skfab_status skfab_srdct_apply(skfab_ctx *ctx, int64_t n, int32_t s, const int8_
  * enable other than 0 or 1). */
 skfab_status skfab_set_value_table(skfab_ctx *ctx, int32_t enable);
 
+/* Arnoldi relation check.  The small problem builds the projected matrix from the
+ * Arnoldi relation of the k-truncated recurrence (the pencil t R + R_e Hbar; the
+ * paper's eq. (arnoldi_relation) with the sketch applied), so S A V_m is not needed
+ * to solve.  With enable = 1 the step kernels also sketch A u_j into S A V_m and
+ * every solve checks the relation: info.arnoldi_relres = ||S A V_m - [S V_m,
+ * S u_{m+1}] Hbar||_F / ||S A V_m||_F.  Off (the default) saves 8 of the 16 sketch
+ * scatter-adds per row and step; info.arnoldi_relres is then -1.  skfab_arnoldi always
+ * forms S A V_m.  Errors: SKFAB_ERR_ARG (null ctx, enable other than 0 or 1). */
+skfab_status skfab_set_arnoldi_check(skfab_ctx *ctx, int32_t enable);
+
 /* Kernel timing with HIP events on the context's stream (benchmark support).
  * enable = 0 turns timing off; enable = n >= 1 brackets every n-th launch of each
  * timed kernel class with a pair of events (n = 1: every launch; a larger n keeps

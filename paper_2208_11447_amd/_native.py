@@ -27,7 +27,8 @@ EXPORTED = [
     "skfab_workspace_bytes", "skfab_solve", "skfab_solve_noalloc", "skfab_solve_reckless", "skfab_arnoldi",
     "skfab_small_problem",
     "skfab_small_workspace_bytes", "skfab_sketch_pattern", "skfab_sketch_apply", "skfab_sketch_ws_bytes",
-    "skfab_timing_enable", "skfab_timing_read", "skfab_set_value_table", "skfab_srdct_ws_bytes", "skfab_srdct_apply",
+    "skfab_timing_enable", "skfab_timing_read", "skfab_set_value_table", "skfab_set_arnoldi_check", "skfab_srdct_ws_bytes",
+    "skfab_srdct_apply",
     "skfab_batch_workspace_bytes", "skfab_solve_batched", "skfab_batch_set_tuning", "skfab_batch_get_tuning",
     "skfab_batch_autotune",
     "skfab_adaptive_workspace_bytes", "skfab_solve_adaptive", "skfab_gershgorin_ws_bytes", "skfab_gershgorin",
@@ -105,6 +106,7 @@ def lib():
         "skfab_srdct_ws_bytes": (C.c_size_t, [C.c_int64, C.c_int32, C.c_int32]),
         "skfab_srdct_apply": (C.c_int, [P, C.c_int64, C.c_int32, P, P, P, C.c_int64, C.c_int32, P, P, C.c_size_t]),
         "skfab_set_value_table": (C.c_int, [P, C.c_int32]),
+        "skfab_set_arnoldi_check": (C.c_int, [P, C.c_int32]),
         "skfab_timing_read": (C.c_int, [P, C.c_int32, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
         "skfab_batch_workspace_bytes": (C.c_int, [C.c_int32, C.POINTER(skfab_batch_problem), C.c_int32,
                                                   C.POINTER(skfab_params), C.POINTER(C.c_size_t)]),

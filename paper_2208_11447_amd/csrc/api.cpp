@@ -148,6 +148,9 @@ struct skfab_ctx {
     // has at most 256 distinct values (FP64 form only: for 4-byte values the table
     // lookup costs more than the 3 bytes per entry it saves)
     bool value_table = true;
+    // the step kernels also sketch A u_j (S A V_m) and the small problem checks the
+    // Arnoldi relation against it (info.arnoldi_relres); off: neither (relres -1)
+    bool arnoldi_check = false;
 };
 
 int skfab::ctx_device(const skfab_ctx* ctx) { return ctx ? ctx->device : -1; }
@@ -527,11 +530,13 @@ skfab_status arnoldi_tail(StepArgs& a, const skfab_params* p, const Layout& ly, 
 }
 
 skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, const skfab_params* p,
-                         const Layout& ly, const Ptrs& w, hipStream_t st, StepArgs* out = nullptr) {
+                         const Layout& ly, const Ptrs& w, hipStream_t st, StepArgs* out = nullptr,
+                         bool sav = false) {
     StepArgs local;
     StepArgs& a = out ? *out : local;
     skfab_status r = arnoldi_setup(A, b, p, ly, w, ctx->value_table, st, &a);
     if (r != SKFAB_OK) return r;
+    a.sav = sav ? 1 : 0;
     for (int j = 0; j <= p->m; ++j) {
         r = arnoldi_step(ctx, a, p, ly, w, j, st);
         if (r != SKFAB_OK) return r;
@@ -612,14 +617,15 @@ skfab_status run_expm(const skfab_params* p, const Ptrs& w, hipStream_t st) {
 }
 
 // Small problem and coefficients y (unnormalised-basis coefficients in w.ys).
-skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, hipStream_t st) {
+skfab_status run_small(const skfab_params* p, const Layout& ly, const Ptrs& w, hipStream_t st,
+                       bool check = false) {
     const int m = p->m, s = p->s;
     int l1, l2, lmax;
     double tol;
     defaults(p, &l1, &l2, &lmax, &tol);
     if (p->method == SKFAB_SFOM_CLOSED) tol = 1e-13;
     const bool ls = p->method == SKFAB_SGMRES_QUAD;
-    if (p->sketch == SKFAB_SKETCH_SPARSE_SIGN)  // (the SRDCT path forms no S A V_m)
+    if (check && p->sketch == SKFAB_SKETCH_SPARSE_SIGN)  // (the SRDCT path forms no S A V_m)
         HIP_TRY(launch_arnoldi_check(w.SV, w.SAV, w.H, s, m, p->k, w.ctrl, w.chk, st));
     HIP_TRY(launch_qr(w.SV, s, m + 1, w.ctrl, w.Tws, st));
     // Section 2.1 remedy: the longest basis prefix whose sketch is conditioned
@@ -878,7 +884,7 @@ skfab_status solve_one(skfab_ctx* ctx, const skfab_csr* A, const double* b, doub
     const bool srdct = p->sketch == SKFAB_SKETCH_SRDCT;
     if (srdct) HIP_TRY(launch_srdct_matrix(p->s, A->n, p->srdct_signs, p->srdct_rows, w.srfp, st));
     StepArgs a;
-    skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st, &a);
+    skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st, &a, ctx->arnoldi_check);
     if (r != SKFAB_OK) return r;
     if (srdct) {
         // [S v_1 .. S v_m, S u_{m+1}]: the stored basis times F_P (FP64 matrix cores)
@@ -886,7 +892,7 @@ skfab_status solve_one(skfab_ctx* ctx, const skfab_csr* A, const double* b, doub
                                     w.SV, p->s, st));
         HIP_TRY(launch_colnorm(w.SV, p->s, p->m, w.ctrl, w.colnorm2, st));
     }
-    r = run_small(p, ly, w, st);
+    r = run_small(p, ly, w, st, ctx->arnoldi_check);
     if (r != SKFAB_OK) return r;
     if (p->two_pass) {
         // Section 4.2, second pass: the same step launches regenerate u_0 .. u_{m-1}
@@ -926,7 +932,7 @@ skfab_status skfab_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, 
     if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
     const Ptrs w = carve(ws, ly);
     hipStream_t st = ctx->stream;
-    skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st);
+    skfab_status r = run_arnoldi(ctx, A, b, p, ly, w, st, nullptr, true);  // SAV is exported
     if (r != SKFAB_OK) return r;
     const int m = p->m, s = p->s;
     if (V) HIP_TRY(launch_normalize_basis(w.U, ly.ldU, A->n, m, w.ctrl, w.eta, V, p->prec, st));
@@ -975,7 +981,7 @@ skfab_status skfab_small_problem(skfab_ctx* ctx, const double* SVext, const doub
     // SAV is not an input here: the Arnoldi-relation check is skipped (relres = 0)
     HIP_TRY(launch_fill(w.SAV, (int64_t)s * m, 0.0, st));
     skfab_params q = *p;
-    skfab_status r = run_small(&q, ly, w, st);
+    skfab_status r = run_small(&q, ly, w, st, true);  // the caller supplies S A V_m
     if (r != SKFAB_OK) return r;
     // run_small leaves y / eta in ys; with eta_j = 1 for j >= 1 only ys[0] differs
     HIP_TRY(hipMemcpyAsync(y, w.y, sizeof(double) * m, hipMemcpyDeviceToDevice, st));
@@ -1214,7 +1220,7 @@ BatchPlan batch_plan(const BatchLayout& L, int block, int spw) {
 
 // Host images of the unit descriptors and the base table, for a launch plan.
 void batch_descriptors(const BatchLayout& L, const BatchPlan& P, const skfab_batch_problem* probs,
-                       const skfab_params* p, char* dev, std::vector<char>& host) {
+                       const skfab_params* p, char* dev, std::vector<char>& host, bool sav) {
     host.assign(L.base + (size_t)(L.nprob + 1) * sizeof(int), 0);
     BatchStepUnit* su = reinterpret_cast<BatchStepUnit*>(host.data() + L.steps);
     SmallUnit* sm = reinterpret_cast<SmallUnit*>(host.data() + L.smalls);
@@ -1247,6 +1253,7 @@ void batch_descriptors(const BatchLayout& L, const BatchPlan& P, const skfab_bat
             a.U = dev + ul.U;
             a.SV = reinterpret_cast<double*>(sb + L.o_SV);
             a.SAV = reinterpret_cast<double*>(sb + L.o_SAV);
+            a.sav = sav ? 1 : 0;
             a.ctrl = ctrl + u;
             a.sctrl = ctrl + qi * L.R;  // the SELL copy is converted once per problem
             a.eta = reinterpret_cast<double*>(sb + L.o_eta);
@@ -1338,7 +1345,8 @@ skfab_status run_batch_arnoldi(skfab_ctx* ctx, const BatchLayout& L, const Batch
     return SKFAB_OK;
 }
 
-skfab_status run_batch_small(const BatchLayout& L, const skfab_params* p, char* dev, hipStream_t st) {
+skfab_status run_batch_small(const BatchLayout& L, const skfab_params* p, char* dev, hipStream_t st,
+                             bool check) {
     const SmallUnit* sm = reinterpret_cast<const SmallUnit*>(dev + L.smalls);
     const BatchStepUnit* su = reinterpret_cast<const BatchStepUnit*>(dev + L.steps);
     const int n = L.nunits, m = L.mmax, s = L.smax;
@@ -1348,7 +1356,7 @@ skfab_status run_batch_small(const BatchLayout& L, const skfab_params* p, char* 
     if (p->method == SKFAB_SFOM_CLOSED) tol = 1e-13;
     const bool ls = p->method == SKFAB_SGMRES_QUAD;
     HIP_TRY(launch_arnoldi_tail_batched(su, sm, n, s, m, st));
-    HIP_TRY(launch_arnoldi_check_batched(sm, n, s, m, p->k, st));
+    if (check) HIP_TRY(launch_arnoldi_check_batched(sm, n, s, m, p->k, st));
     HIP_TRY(launch_qr_batched(sm, n, s, m + 1, st));
     HIP_TRY(launch_cond_trunc_batched(sm, n, s, m, cond_max_of(p), st));
     HIP_TRY(launch_pencil_setup_batched(sm, n, s, m, p->k, st));
@@ -1383,7 +1391,7 @@ skfab_status batch_prepare(skfab_ctx* ctx, int32_t nprob, const skfab_batch_prob
 
 skfab_status batch_upload(skfab_ctx* ctx, const BatchLayout& L, const BatchPlan& P, const skfab_batch_problem* probs,
                           const skfab_params* p, char* dev) {
-    batch_descriptors(L, P, probs, p, dev, ctx->batch_host);
+    batch_descriptors(L, P, probs, p, dev, ctx->batch_host, ctx->arnoldi_check);
     HIP_TRY(hipMemcpyAsync(dev + L.steps, ctx->batch_host.data() + L.steps, ctx->batch_host.size() - L.steps,
                            hipMemcpyHostToDevice, ctx->stream));
     return SKFAB_OK;
@@ -1418,6 +1426,12 @@ skfab_status skfab_srdct_apply(skfab_ctx* ctx, int64_t n, int32_t s, const int8_
     double* part = reinterpret_cast<double*>(static_cast<char*>(ws) + align_up((size_t)s * n * sizeof(double)));
     HIP_TRY(launch_srdct_matrix(s, n, signs, rows, FP, ctx->stream));
     HIP_TRY(launch_srdct_sketch(FP, s, n, V, ldv, ncols, 0, part, nullptr, nullptr, SV, s, ctx->stream));
+    return SKFAB_OK;
+}
+
+skfab_status skfab_set_arnoldi_check(skfab_ctx* ctx, int32_t enable) {
+    if (!ctx || (enable != 0 && enable != 1)) return SKFAB_ERR_ARG;
+    ctx->arnoldi_check = enable != 0;
     return SKFAB_OK;
 }
 
@@ -1456,7 +1470,7 @@ skfab_status skfab_solve_batched(skfab_ctx* ctx, int32_t nprob, const skfab_batc
     if (r != SKFAB_OK) return r;
     r = run_batch_arnoldi(ctx, L, P, probs, p, dev, block, L.mmax, st);
     if (r != SKFAB_OK) return r;
-    r = run_batch_small(L, p, dev, st);
+    r = run_batch_small(L, p, dev, st, ctx->arnoldi_check);
     if (r != SKFAB_OK) return r;
     const SmallUnit* sm = reinterpret_cast<const SmallUnit*>(dev + L.smalls);
     hipEvent_t stop;

@@ -241,7 +241,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
             }
         }
         const double wv = window_value<KW>(a, j - 1, tid);  // nonzero for tid < KW^2 only
-        const int nb = 2 * s;
+        const int nb = a.sav ? 2 * s : s;  // bins of S u_{j-1} (and of S A u_{j-1})
         const int b0 = (bid * nb) / G;        // bid nb <= 1024 * 2048: 32-bit arithmetic
         const int b1 = ((bid + 1) * nb) / G;
         // sketch partial sums of this block's bins (one wavefront per bin)
@@ -289,7 +289,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
         if (b1 - b0 > NW)
             reduce_prev_sketch_tail<BLOCK>(a.skp_prev, G, s, a.ldS, j - 1, b0 + NW, b1,
                                            ok ? a.inv_sqrt_zeta / eta_p : a.inv_sqrt_zeta,
-                                           a.inv_sqrt_zeta / eta_p, ok, a.SV, a.SAV);
+                                           a.inv_sqrt_zeta / eta_p, ok && a.sav, a.SV, a.SAV);
         if (!ok) return;
     } else {
         if (stopped) return;
@@ -564,7 +564,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
                 sketch_column<ZETA>(a.seed, (uint64_t)r, s, rows, sg);
 #pragma unroll
                 for (int q = 0; q < ZETA; ++q) lds_add(binV + rows[q], sg[q] * ud);
-                if (!a.extend) {
+                if (!a.extend && a.sav) {
 #pragma unroll
                     for (int q = 0; q < ZETA; ++q) lds_add(binAV + rows[q], sg[q] * wd);
                 }
@@ -587,7 +587,7 @@ __device__ __forceinline__ void step_body(StepArgs a, const int bid) {
 
     // partial sketches, bin-major; slot = chunk keeps one XCD's slots contiguous
     __syncthreads();
-    for (int i = tid; i < 2 * s; i += BLOCK) {
+    for (int i = tid; i < (a.sav ? 2 * s : s); i += BLOCK) {
         double t = 0.0;
         for (int wv = 0; wv < NW; ++wv) t += bins[wv * 2 * s + i];
         gptr(a.skp_cur)[(int64_t)i * G + chunk] = t;

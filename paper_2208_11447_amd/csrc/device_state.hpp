@@ -105,7 +105,7 @@ struct StepArgs {
     int32_t nosketch; // 1: no sparse-sign sketch in the step (the SRDCT sketch is applied to
                       // the stored basis afterwards)
     int32_t keep_ext; // 1: the extension pass stores u_m in column m % uring
-    int32_t pad;
+    int32_t sav;      // 1: also sketch A u_j (S A V_m, read only by the Arnoldi relation check)
 };
 
 // One (problem, right-hand side) pair of a batched solve: the step arguments

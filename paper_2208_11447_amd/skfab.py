@@ -269,6 +269,12 @@ def skfab_srdct_apply(ctx: Context, signs: torch.Tensor, rows: torch.Tensor, V: 
                                      _ptr(ws), ws.numel()), "skfab_srdct_apply")
 
 
+def skfab_set_arnoldi_check(ctx: Context, enable: bool = True):
+    """Sketch A u_j as well and report the Arnoldi relation residual in
+    info.arnoldi_relres (off by default: -1)."""
+    _check(N.lib().skfab_set_arnoldi_check(ctx.handle, 1 if enable else 0), "skfab_set_arnoldi_check")
+
+
 def skfab_set_value_table(ctx: Context, enable: bool = True):
     """Value-table (uint8 index) storage of A's values in the SELL copy when A has at
     most 256 distinct values; on by default (enable=False: always the plain form)."""

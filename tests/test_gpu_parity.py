@@ -127,7 +127,11 @@ def test_solve_parity_convdiff2d_n100(method, f):
     """2D convection-diffusion, 100x100 grid, m=50, k=2, s=200, zeta=8."""
     log(f"solve parity 2D n=100 method={method} f={f}")
     A, b, arrs = problem(100)
-    x, info = gpu_solve(arrs, b, f=f, m=50, k=2, s=200, method=method, quad_tol=1e-13)
+    sk.skfab_set_arnoldi_check(ctx(), True)  # S A V_m sketched too; relres reported
+    try:
+        x, info = gpu_solve(arrs, b, f=f, m=50, k=2, s=200, method=method, quad_tol=1e-13)
+    finally:
+        sk.skfab_set_arnoldi_check(ctx(), False)
     assert info.status == 0 and info.m_used == 50
     arn, _ = oracle_run(A, b, 50, 2, 200)
     ref = {"sfom": ometh.sfom_closed, "sgmres": ometh.sgmres, "sfom_quad": ometh.sfom_quad}[method]
@@ -349,3 +353,22 @@ def test_two_pass_form(method, f, tau):
     e12, eor = rel(x2, x1), rel(x2, ref)
     log(f"  two-pass vs one-pass {e12:.2e}, vs oracle {eor:.2e}")
     assert e12 <= 1e-14 and eor < FP64_TOL
+
+
+@pytest.mark.parametrize("method", ["sfom", "sgmres"])
+def test_arnoldi_check_switch(method):
+    """The Arnoldi relation check (skfab_set_arnoldi_check) only adds the sketch of
+    A u_j and the residual: x is bitwise the same with it on and off, relres is
+    below 1e-12 with it and -1 without."""
+    _, b, arrs = problem(60)
+    kw = dict(f="invsqrt", m=40, k=2, s=160, method=method, quad_tol=1e-13)
+    x0, i0 = gpu_solve(arrs, b, **kw)
+    sk.skfab_set_arnoldi_check(ctx(), True)
+    try:
+        x1, i1 = gpu_solve(arrs, b, **kw)
+    finally:
+        sk.skfab_set_arnoldi_check(ctx(), False)
+    log(f"relres off {i0.arnoldi_relres}, on {i1.arnoldi_relres:.2e}")
+    assert i0.status == 0 and i1.status == 0
+    assert np.array_equal(x0, x1)
+    assert i0.arnoldi_relres == -1.0 and 0.0 <= i1.arnoldi_relres < 1e-12
