@@ -56,7 +56,7 @@ from .arnoldi import ArnoldiResult
 L_DECAY = 45.0
 KAPPA_MAX = 0.25
 K_FIRST = 32
-K_MAX = 4096
+K_MAX = 1024  # the largest level the library evaluates
 
 
 def parabola(theta: np.ndarray, tau: float):
