@@ -78,9 +78,9 @@ def parse():
                     help="full oracle solves timed for cpu_baseline (median; the first also gives the parity)")
     ap.add_argument("--no-timing-events", action="store_true")
     ap.add_argument("--timing-stride", type=int, default=8,
-                    help="single-problem workloads: HIP events bracket every n-th step-kernel (and assembly) launch "
-                         "of the timed region; "
-                         "the events cost a few microseconds of queue time each, so timing every launch "
+                    help="single-problem workloads: HIP events bracket every n-th assembly launch of the timed "
+                         "region (the step launches of each solve are timed as one run, every one counted); "
+                         "the events cost a few microseconds of queue time each, so timing every isolated launch "
                          "would lower the solves/s figure they are quoted with")
     ap.add_argument("--copy-calibration", type=float, default=0.0, metavar="GIB",
                     help="only run a plain device copy of this many GiB (5 times) and report its GB/s; "
@@ -843,7 +843,8 @@ def main():
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(args.workload, args.prec),
                 "kernel": "arnoldi_step_kernel", "bytes_per_launch": nbytes,
                 "mean_launch_us": round(per_launch_s * 1e6, 2), "launches": n_step,
-                "timed_every": args.timing_stride,
+                "timed": "every step launch j < m of every timed solve: one event pair per solve's run of m "
+                         "launches (gaps between launches included)",
                 "assembly_gbs": round((PREC_BYTES[args.prec][1] * N * cfg["m"] + 8 * N) / (ms_asm / 1e3 / max(n_asm, 1)) / 1e9, 1)
                 if n_asm else None}
     x_host = x.cpu().numpy()

@@ -379,11 +379,16 @@ skfab_status skfab_set_value_table(skfab_ctx *ctx, int32_t enable);
 skfab_status skfab_set_arnoldi_check(skfab_ctx *ctx, int32_t enable);
 
 /* Kernel timing with HIP events on the context's stream (benchmark support).
- * enable = 0 turns timing off; enable = n >= 1 brackets every n-th launch of each
- * timed kernel class with a pair of events (n = 1: every launch; a larger n keeps
- * the events' own cost out of most launches); negative values are rejected with
- * SKFAB_ERR_ARG.  skfab_timing_read synchronises the stream and returns the summed
- * event durations and the count of timed launches since the last read (then resets).
+ * enable = 0 turns timing off; enable = n >= 1 turns it on.  A run of consecutive
+ * launches of a timed kernel class -- the step launches j = 0 .. m-1 of a solve's
+ * recurrence, the step launches of a batched solve -- is bracketed by one pair of
+ * events and all its launches count (the interval includes the gaps between them);
+ * launches that come one at a time (the assembly, the second pass of the two-pass
+ * form, the checkpointed recurrence of the adaptive solve) are bracketed every n-th
+ * (n = 1: every one; a larger n keeps the events' own cost out of most of them).
+ * Negative values are rejected with SKFAB_ERR_ARG.  skfab_timing_read synchronises
+ * the stream and returns the summed event durations and the count of timed launches
+ * since the last read (then resets).
  *   kernel 0: the fused Arnoldi step kernel (SpMV + orthogonalisation dots +
  *             sparse-sign sketches), kernel 1: the assembly x = V_m y.
  * Events are host runtime objects created by skfab_timing_enable; no device

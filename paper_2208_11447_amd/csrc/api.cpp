@@ -131,11 +131,14 @@ int ctx_device(const skfab_ctx* ctx);
 struct skfab_ctx {
     int device;
     hipStream_t stream;
-    // optional per-launch timing of kernel classes (0: Arnoldi step, 1: assembly)
+    // optional timing of kernel classes (0: Arnoldi step, 1: assembly): a run of
+    // consecutive launches of a class as one interval, isolated launches every
+    // stride-th one
     bool timing = false;
-    int32_t stride = 1;             // every stride-th launch of a class is timed
-    int64_t tick[2] = {0, 0};       // launches of each class seen while enabled
+    int32_t stride = 1;             // every stride-th isolated launch of a class is timed
+    int64_t tick[2] = {0, 0};       // isolated launches of each class seen while enabled
     std::vector<hipEvent_t> ev[2];  // start/stop pairs, flattened
+    std::vector<int32_t> nl[2];     // launches covered by each pair
     size_t used[2] = {0, 0};
     double acc_ms[2] = {0.0, 0.0};
     int64_t count[2] = {0, 0};
@@ -168,28 +171,48 @@ hipError_t timing_flush(skfab_ctx* ctx, int c) {
         e = hipEventElapsedTime(&ms, ctx->ev[c][2 * i], ctx->ev[c][2 * i + 1]);
         if (e != hipSuccess) return e;
         ctx->acc_ms[c] += ms;
-        ctx->count[c] += 1;
+        ctx->count[c] += ctx->nl[c][i];
     }
     ctx->used[c] = 0;
     return hipSuccess;
 }
 
-// Event pair for the next timed launch of class c (nullptr pair when disabled).
-hipError_t timing_begin(skfab_ctx* ctx, int c, hipStream_t st, hipEvent_t* stop) {
-    *stop = nullptr;
+// An open interval of class c (stop == nullptr: not timed).
+struct Span {
+    hipEvent_t stop = nullptr;
+    int c = 0;
+    size_t i = 0;
+};
+
+// Opens the interval of the next launch of class c, or with run = true of a run of
+// consecutive launches of class c (always timed: one pair of events for the whole
+// run keeps the events' own cost out of the per-launch mean).  Intervals of one
+// class do not nest.
+hipError_t timing_begin(skfab_ctx* ctx, int c, hipStream_t st, Span* sp, bool run = false) {
+    sp->stop = nullptr;
     if (!ctx || !ctx->timing) return hipSuccess;
-    if (ctx->tick[c]++ % ctx->stride != 0) return hipSuccess;
+    if (!run && ctx->tick[c]++ % ctx->stride != 0) return hipSuccess;
     if (ctx->used[c] == TIMING_PAIRS) {
         hipError_t e = timing_flush(ctx, c);
         if (e != hipSuccess) return e;
     }
     const size_t i = ctx->used[c]++;
-    *stop = ctx->ev[c][2 * i + 1];
+    sp->stop = ctx->ev[c][2 * i + 1];
+    sp->c = c;
+    sp->i = i;
     return hipEventRecord(ctx->ev[c][2 * i], st);
 }
 
-hipError_t timing_end(hipEvent_t stop, hipStream_t st) {
-    return stop ? hipEventRecord(stop, st) : hipSuccess;
+// Closes the interval; it counts as `launches` launches of its class.
+hipError_t timing_end(skfab_ctx* ctx, const Span& sp, hipStream_t st, int launches = 1) {
+    if (!sp.stop) return hipSuccess;
+    ctx->nl[sp.c][sp.i] = launches;
+    return hipEventRecord(sp.stop, st);
+}
+
+// Drops an interval that will not be closed (a launch of the run failed).
+void timing_cancel(skfab_ctx* ctx, const Span& sp) {
+    if (sp.stop && ctx->used[sp.c] == sp.i + 1) --ctx->used[sp.c];
 }
 }  // namespace
 
@@ -501,8 +524,10 @@ skfab_status arnoldi_setup(const skfab_csr* A, const double* b, const skfab_para
     return SKFAB_OK;
 }
 
+// One step launch.  time_each: the launch is timed on its own (every stride-th);
+// false inside a run that the caller times as a whole.
 skfab_status arnoldi_step(skfab_ctx* ctx, StepArgs& a, const skfab_params* p, const Layout& ly, const Ptrs& w,
-                          int j, hipStream_t st) {
+                          int j, hipStream_t st, bool time_each = true) {
     const int64_t nsc = (int64_t)NSC_MAX * ly.L.G;
     const int64_t nsk = (int64_t)2 * p->s * ly.L.G;
     a.j = j;
@@ -513,11 +538,11 @@ skfab_status arnoldi_step(skfab_ctx* ctx, StepArgs& a, const skfab_params* p, co
     a.scal_cur = w.scal + (j & 1) * nsc;
     a.skp_prev = w.skpart + ((j + 1) & 1) * nsk;
     a.skp_cur = w.skpart + (j & 1) * nsk;
-    hipEvent_t stop;
-    const bool timed = j < p->m;  // the extension pass has no product with A
-    if (timed) HIP_TRY(timing_begin(ctx, 0, st, &stop));
+    Span sp;
+    const bool timed = time_each && j < p->m;  // the extension pass has no product with A
+    if (timed) HIP_TRY(timing_begin(ctx, 0, st, &sp));
     HIP_TRY(launch_arnoldi_step(a, p->zeta, ly.L.block, p->prec, st));
-    if (timed) HIP_TRY(timing_end(stop, st));
+    if (timed) HIP_TRY(timing_end(ctx, sp, st));
     return SKFAB_OK;
 }
 
@@ -537,10 +562,20 @@ skfab_status run_arnoldi(skfab_ctx* ctx, const skfab_csr* A, const double* b, co
     skfab_status r = arnoldi_setup(A, b, p, ly, w, ctx->value_table, st, &a);
     if (r != SKFAB_OK) return r;
     a.sav = sav ? 1 : 0;
-    for (int j = 0; j <= p->m; ++j) {
-        r = arnoldi_step(ctx, a, p, ly, w, j, st);
-        if (r != SKFAB_OK) return r;
+    // steps 0 .. m-1 (each with its product by A) are timed as one run; the
+    // extension pass j = m is not timed
+    Span sp;
+    HIP_TRY(timing_begin(ctx, 0, st, &sp, true));
+    for (int j = 0; j < p->m; ++j) {
+        r = arnoldi_step(ctx, a, p, ly, w, j, st, false);
+        if (r != SKFAB_OK) {
+            timing_cancel(ctx, sp);
+            return r;
+        }
     }
+    HIP_TRY(timing_end(ctx, sp, st, p->m));
+    r = arnoldi_step(ctx, a, p, ly, w, p->m, st, false);
+    if (r != SKFAB_OK) return r;
     return arnoldi_tail(a, p, ly, w, st);
 }
 
@@ -775,6 +810,7 @@ skfab_status skfab_timing_enable(skfab_ctx* ctx, int32_t enable) {
         if (hipSetDevice(ctx->device) != hipSuccess) return SKFAB_ERR_HIP;
         for (int c = 0; c < 2; ++c) {
             ctx->ev[c].resize(2 * TIMING_PAIRS);
+            ctx->nl[c].assign(TIMING_PAIRS, 1);
             for (auto& e : ctx->ev[c]) HIP_TRY(hipEventCreate(&e));
         }
     }
@@ -906,10 +942,10 @@ skfab_status solve_one(skfab_ctx* ctx, const skfab_csr* A, const double* b, doub
         }
         return read_info(w, st, info);
     }
-    hipEvent_t stop;
-    HIP_TRY(timing_begin(ctx, 1, st, &stop));
+    Span sp;
+    HIP_TRY(timing_begin(ctx, 1, st, &sp));
     HIP_TRY(launch_assemble(w.U, ly.ldU, A->n, p->m, w.ctrl, w.ys, x, p->prec, st));
-    HIP_TRY(timing_end(stop, st));
+    HIP_TRY(timing_end(ctx, sp, st));
     return read_info(w, st, info);
 }
 
@@ -1334,14 +1370,22 @@ skfab_status run_batch_arnoldi(skfab_ctx* ctx, const BatchLayout& L, const Batch
                                     (ctx->value_table && p->prec == SKFAB_PREC_FP64) ? 1 : 0, p->prec, st));
     }
     int nact = L.nprob;
+    // the step launches follow one another with nothing between them: one run
+    Span sp;
+    HIP_TRY(timing_begin(ctx, 0, st, &sp, true));
+    int nlaunch = 0;
     for (int j = 0; j <= jmax; ++j) {
         while (nact > 0 && probs[L.order[nact - 1]].m < j) --nact;
         if (nact == 0) break;
-        hipEvent_t stop;
-        HIP_TRY(timing_begin(ctx, 0, st, &stop));
-        HIP_TRY(launch_arnoldi_step_batched(su, base, nact, L.R, j, p->k, P.base[nact], block, L.smax, p->prec, st));
-        HIP_TRY(timing_end(stop, st));
+        const hipError_t e =
+            launch_arnoldi_step_batched(su, base, nact, L.R, j, p->k, P.base[nact], block, L.smax, p->prec, st);
+        if (e != hipSuccess) {
+            timing_cancel(ctx, sp);
+            return SKFAB_ERR_HIP;
+        }
+        ++nlaunch;
     }
+    HIP_TRY(timing_end(ctx, sp, st, nlaunch));
     return SKFAB_OK;
 }
 
@@ -1473,10 +1517,10 @@ skfab_status skfab_solve_batched(skfab_ctx* ctx, int32_t nprob, const skfab_batc
     r = run_batch_small(L, p, dev, st, ctx->arnoldi_check);
     if (r != SKFAB_OK) return r;
     const SmallUnit* sm = reinterpret_cast<const SmallUnit*>(dev + L.smalls);
-    hipEvent_t stop;
-    HIP_TRY(timing_begin(ctx, 1, st, &stop));
+    Span sp;
+    HIP_TRY(timing_begin(ctx, 1, st, &sp));
     HIP_TRY(launch_assemble_batched(sm, L.nunits, L.nmax, L.mmax, p->prec, st));
-    HIP_TRY(timing_end(stop, st));
+    HIP_TRY(timing_end(ctx, sp, st));
     if (!info) return SKFAB_OK;
     std::vector<DevCtrl> c(L.nunits);
     HIP_TRY(hipMemcpyAsync(c.data(), dev + L.ctrl, sizeof(DevCtrl) * L.nunits, hipMemcpyDeviceToHost, st));

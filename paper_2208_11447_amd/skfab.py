@@ -282,7 +282,8 @@ def skfab_set_value_table(ctx: Context, enable: bool = True):
 
 
 def skfab_timing_enable(ctx: Context, enable: bool = True, stride: int = 1):
-    """Event timing of every stride-th launch of each timed kernel class (off: enable=False)."""
+    """Event timing of the timed kernel classes (off: enable=False): runs of consecutive
+    step launches as one interval each, isolated launches every stride-th."""
     _check(N.lib().skfab_timing_enable(ctx.handle, int(stride) if enable else 0), "skfab_timing_enable")
 
 

@@ -233,30 +233,36 @@ def test_seed_matters_and_zeta():
 
 
 def test_timing_stride_counts_launches():
-    """skfab_timing_enable(n): every n-th step launch is timed (counts add up over
-    solves), n = 1 times them all, a negative n is refused; timing leaves x unchanged."""
+    """Event timing: the recurrence of a solve (step launches j = 0 .. m-1) is one
+    timed run whose launches all count, whatever the stride; launches timed one by
+    one (here the second pass of the two-pass form) follow skfab_timing_enable(n):
+    every n-th.  A negative n is refused; timing leaves x unchanged."""
     A, b, arrs = problem(30)
     m = 20
     Ad = device_csr(arrs)
-    p = sk.make_params(m=m, k=2, s=80)
-    ws = sk.alloc_workspace(sk.skfab_workspace_bytes(Ad, p))
     bd = dev(b)
-    x0 = torch.empty_like(bd)
-    x1 = torch.empty_like(bd)
     c = ctx()
-    sk.skfab_solve(c, Ad, bd, x0, p, ws, want_info=False)
-    for stride, solves in ((1, 2), (3, 3)):
-        sk.skfab_timing_enable(c, True, stride=stride)
-        sk.skfab_timing_read(c, 0)
-        for _ in range(solves):
-            sk.skfab_solve(c, Ad, bd, x1, p, ws, want_info=False)
-        ms, n = sk.skfab_timing_read(c, 0)
-        sk.skfab_timing_enable(c, False)
-        launches = solves * m  # step launches j = 0 .. m-1 are timed (the extension pass is not)
-        assert n == (launches + stride - 1) // stride, (stride, n)
-        assert ms > 0.0
-    torch.cuda.synchronize()
-    assert torch.equal(x0, x1)
+    for two_pass in (False, True):
+        p = sk.make_params(m=m, k=2, s=80, two_pass=two_pass)
+        ws = sk.alloc_workspace(sk.skfab_workspace_bytes(Ad, p))
+        x0 = torch.empty_like(bd)
+        x1 = torch.empty_like(bd)
+        sk.skfab_solve(c, Ad, bd, x0, p, ws, want_info=False)
+        for stride, solves in ((1, 2), (3, 3)):
+            sk.skfab_timing_enable(c, True, stride=stride)
+            sk.skfab_timing_read(c, 0)
+            for _ in range(solves):
+                sk.skfab_solve(c, Ad, bd, x1, p, ws, want_info=False)
+            ms, n = sk.skfab_timing_read(c, 0)
+            sk.skfab_timing_enable(c, False)
+            want = solves * m  # the runs (the extension pass j = m is not timed)
+            if two_pass:  # second-pass launches j = 0 .. m-1, one by one
+                want += (solves * m + stride - 1) // stride
+            log(f"two_pass={two_pass} stride={stride} solves={solves}: {n} launches, {ms:.3f} ms")
+            assert n == want, (two_pass, stride, n, want)
+            assert ms > 0.0
+        torch.cuda.synchronize()
+        assert torch.equal(x0, x1)
     with pytest.raises(RuntimeError):
         sk.skfab_timing_enable(c, True, stride=-2)
 
