@@ -142,3 +142,29 @@ def test_batched_autotune_keeps_results(batch):
                 assert rel(X1[i], X0[i]) < 1e-12
     finally:
         sk.skfab_batch_set_tuning(c, *saved)
+
+
+def test_batched_timing_counts_step_launches(batch):
+    """Event timing of a batched solve: its step launches j = 0 .. max m form one
+    timed run, every launch counted, and the assembly one timed launch; the
+    result is bitwise the untimed one."""
+    _, probs = batch
+    X0, _ = run_batch(probs, f="invsqrt", k=2)
+    c = ctx()
+    p = sk.make_params(f="invsqrt", k=2)
+    ws = sk.alloc_workspace(sk.skfab_batch_workspace_bytes(probs, p))
+    sk.skfab_timing_enable(c, True, stride=1)
+    sk.skfab_timing_read(c, 0)
+    sk.skfab_timing_read(c, 1)
+    sk.skfab_solve_batched(c, probs, p, ws, want_info=False)
+    ms0, n0 = sk.skfab_timing_read(c, 0)
+    ms1, n1 = sk.skfab_timing_read(c, 1)
+    sk.skfab_timing_enable(c, False)
+    torch.cuda.synchronize()
+    X1 = [q.X.cpu().numpy() for q in probs]
+    mmax = max(q.m for q in probs)
+    log(f"batched timing: {n0} step launches in {ms0:.3f} ms, {n1} assembly launch in {ms1:.3f} ms")
+    assert n0 == mmax + 1 and ms0 > 0.0
+    assert n1 == 1 and ms1 > 0.0
+    for a, b in zip(X0, X1):
+        assert np.array_equal(a, b)
