@@ -59,8 +59,9 @@ def parse():
                     help="batched form: after the timed batches, re-solve every refused pair with "
                          "skfab_solve_reckless (s doubled from 4m up to min(8m, 1024) while the solve fails or the "
                          "embedding monitor exceeds 0.5) and report how many it recovers")
-    ap.add_argument("--tuning", default=None, metavar="BLOCK,SPW",
-                    help="batched form: fixed launch shape (threads per block, slices per wavefront)")
+    ap.add_argument("--tuning", default=None, metavar="BLOCK,SPW[,PACKED]",
+                    help="batched form: fixed launch shape (threads per block, slices per wavefront, and 1 / 0 "
+                         "for the packed form or not, default 0)")
     ap.add_argument("--f", default="invsqrt", choices=["invsqrt", "inv", "exp"],
                     help="f(z): z^(-1/2), 1/z, or exp(-tau z) (sfom: closed form; sgmres: contour rule)")
     ap.add_argument("--tau", type=float, default=1e-2, help="tau of f(z) = exp(-tau z)")
@@ -393,14 +394,17 @@ def run_batched(args):
           f"workspace {nbytes / 2**30:.1f} GiB, prec {args.prec}", file=sys.stderr, flush=True)
     tuning = None
     if args.tuning:
-        blk, spw = (int(v) for v in args.tuning.split(","))
-        sk.skfab_batch_set_tuning(ctx, blk, spw)
-        tuning = (blk, spw)
+        vals = [int(v) for v in args.tuning.split(",")]
+        blk, spw, packed = vals[0], vals[1], bool(vals[2]) if len(vals) > 2 else False
+        sk.skfab_batch_set_tuning(ctx, blk, spw, packed)
+        tuning = (blk, spw, packed)
     elif not args.no_autotune:
         t = time.perf_counter()
         tuning = sk.skfab_batch_autotune(ctx, probs, p, ws, steps=4)
-        print(f"# autotuned launch shape: block {tuning[0]}, {tuning[1]} slices per wavefront "
-              f"({time.perf_counter() - t:.1f} s)", file=sys.stderr, flush=True)
+        print(f"# autotuned launch shape: block {tuning[0]}, {tuning[1]} slices per wavefront, packed form "
+              f"{tuning[2]} ({time.perf_counter() - t:.1f} s)", file=sys.stderr, flush=True)
+    else:
+        tuning = sk.skfab_batch_get_tuning(ctx)
     info = sk.skfab_solve_batched(ctx, probs, p, ws)
     bad = [(i, r, info[i][r].status) for i in range(len(probs)) for r in range(R) if info[i][r].status != 0]
     for _ in range(args.warmup):
@@ -500,9 +504,11 @@ def run_batched(args):
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      # counters are recorded per launch shape (null for a shape without a record)
-                     "traffic": recorded_traffic(f"{args.workload}_t{tuning[0]}x{tuning[1]}", args.prec,
+                     "traffic": recorded_traffic(f"{args.workload}_t{tuning[0]}x{tuning[1]}"
+                                                 + ("p" if tuning[2] else ""), args.prec,
                                                  "traffic_bytes_per_batch"),
-                     "kernel": "arnoldi_step_batched_kernel", "bytes_per_batch": step_bytes // args.steps,
+                     "kernel": ("arnoldi_step_packed_kernel + arnoldi_step_batched_kernel" if tuning and tuning[2]
+                                else "arnoldi_step_batched_kernel"), "bytes_per_batch": step_bytes // args.steps,
                      "launches": n_step, "step_ms_per_batch": round(ms_step / args.steps, 3),
                      "assembly_gbs": round(asm_bytes / (ms_asm / 1e3) / 1e9, 1) if n_asm else None},
         "cpu_baseline": None,

@@ -419,10 +419,18 @@ typedef struct skfab_batch_problem {
  * (problem, right-hand side) pair, a multiple of 8 and at most 256).  A block size
  * whose per-wave sketch bins (2 s_max doubles each) would not fit the CU's LDS is
  * lowered by halving for the call (the stored tuning is kept); the autotuner skips
- * such sizes. */
+ * such sizes.  packed = 1 runs, where it applies, the packed form of the step
+ * (default 0; the autotuner tries both): one block per chunk of a problem's rows
+ * carries all its right-hand sides, so a row's column offsets, value indices and
+ * sketch hash are read or computed once for all of them.  It applies to k = 2,
+ * 512-thread blocks, the steps 2 <= j < m of each problem, with the Arnoldi
+ * relation check off and the sketch bins of its eight wavefronts (nrhs s_max
+ * doubles each) within the LDS; the results are bitwise those of the per-unit
+ * form. */
 typedef struct skfab_batch_tuning {
     int32_t block;
     int32_t slices_per_wave;
+    int32_t packed;         /* 0 or 1 */
 } skfab_batch_tuning;
 
 /* Device workspace bytes of skfab_solve_batched / skfab_batch_autotune (host only;
@@ -443,14 +451,17 @@ skfab_status skfab_solve_batched(skfab_ctx *ctx, int32_t nprob, const skfab_batc
                                  int32_t nrhs, const skfab_params *p, void *ws, size_t ws_bytes,
                                  skfab_info *info);
 
-/* Set / read the context's launch shape for batched solves. */
+/* Set / read the context's launch shape for batched solves.  Errors: SKFAB_ERR_ARG
+ * (null argument, block other than 256/512/1024, slices_per_wave outside 1..64,
+ * packed other than 0 or 1). */
 skfab_status skfab_batch_set_tuning(skfab_ctx *ctx, const skfab_batch_tuning *t);
 skfab_status skfab_batch_get_tuning(skfab_ctx *ctx, skfab_batch_tuning *t);
 
 /* Autotuner: times the batched step kernel on this batch for every candidate
- * shape (block 256/512/1024 x 1/2/4/.../64 slices per wavefront) over `steps` Arnoldi
- * steps (after an untimed first step), keeps the fastest in the context and
- * returns it in *chosen (may be NULL).  Overwrites the workspace; synchronises. */
+ * shape (block 256/512/1024 x 1/2/4/.../64 slices per wavefront, and the packed form
+ * with 512-thread blocks where it applies) over `steps` Arnoldi steps (after an
+ * untimed first step), keeps the fastest in the context and returns it in *chosen
+ * (may be NULL).  Overwrites the workspace; synchronises. */
 skfab_status skfab_batch_autotune(skfab_ctx *ctx, int32_t nprob, const skfab_batch_problem *probs,
                                   int32_t nrhs, const skfab_params *p, void *ws, size_t ws_bytes,
                                   int32_t steps, skfab_batch_tuning *chosen);

@@ -63,7 +63,7 @@ class skfab_batch_problem(C.Structure):
 
 
 class skfab_batch_tuning(C.Structure):
-    _fields_ = [("block", C.c_int32), ("slices_per_wave", C.c_int32)]
+    _fields_ = [("block", C.c_int32), ("slices_per_wave", C.c_int32), ("packed", C.c_int32)]
 
 
 _lib = None

@@ -84,7 +84,10 @@ hipError_t launch_lu_solve_cols(const DevCtrl* ctrl, int m, const double* LU, co
                                 hipStream_t st);
 hipError_t launch_first_column(const DevCtrl* ctrl, const double* X, const double* eta, double* y, hipStream_t st);
 hipError_t launch_arnoldi_step_batched(const BatchStepUnit* units, const int* base, int nact, int R, int j, int k,
-                                       int grid, int block, int smax, int prec, hipStream_t st);
+                                       int g0, int grid, int block, int smax, int prec, hipStream_t st);
+size_t packed_step_lds(int block, int R, int smax);
+hipError_t launch_arnoldi_step_packed(const BatchStepUnit* units, const int* base, int nprob, int R, int j, int grid,
+                                      int smax, int prec, hipStream_t st);
 hipError_t launch_arnoldi_tail_batched(const BatchStepUnit* units, const SmallUnit* small, int nunits, int smax,
                                        int mmax, hipStream_t st);
 hipError_t launch_arnoldi_check_batched(const SmallUnit* small, int nunits, int smax, int mmax, int k,
@@ -146,6 +149,11 @@ struct skfab_ctx {
     // unit descriptors (kept alive until the next batched call has synchronised)
     int batch_block = 1024;
     int batch_spw = 1;
+    // the packed form of the batched step (one block per chunk for all of a
+    // problem's right-hand sides) where it applies: k = 2, 512-thread blocks, the
+    // steps 2 <= j < m, the Arnoldi relation check off, its bins within the LDS.
+    // Off unless set or chosen by the autotuner: in FP64 its registers spill.
+    bool batch_packed = false;
     std::vector<char> batch_host;
     // the SELL copy may store A's values as uint8 indices into a value table when A
     // has at most 256 distinct values (FP64 form only: for 4-byte values the table
@@ -1347,6 +1355,36 @@ void batch_descriptors(const BatchLayout& L, const BatchPlan& P, const skfab_bat
 
 // Arnoldi part of a batch: control blocks, SELL copies, then one launch per step j
 // over every (problem, rhs) with m_p >= j (the last is the extension pass).
+// Step j of a batched solve over the first nact problems (by decreasing m): the
+// problems short of their m in the packed form where it applies (a launch of
+// P.base[nfull] / R blocks), the others -- and every problem at j < 2 -- in the
+// per-unit form.  Both forms keep the same data layout and give the same results.
+hipError_t batch_step(const skfab_ctx* ctx, const BatchLayout& L, const BatchPlan& P,
+                      const skfab_batch_problem* probs, const skfab_params* p, const BatchStepUnit* su,
+                      const int* base, int nact, int j, int block, hipStream_t st, int* nlaunch) {
+    int nfull = 0;
+    if (ctx->batch_packed && p->k == 2 && !ctx->arnoldi_check && j >= 2 && block == PACKED_BLOCK &&
+        packed_step_lds(block, L.R, L.smax) > 0) {
+        nfull = nact;
+        while (nfull > 0 && probs[L.order[nfull - 1]].m <= j) --nfull;
+        // the packed kernel addresses vector entries by 32-bit byte offsets
+        for (int qi = 0; qi < nfull; ++qi)
+            if (L.prob[L.order[qi]].N >= ((int64_t)1 << 29)) nfull = 0;
+    }
+    if (nfull > 0) {
+        hipError_t e = launch_arnoldi_step_packed(su, base, nfull, L.R, j, P.base[nfull] / L.R, L.smax, p->prec, st);
+        if (e != hipSuccess) return e;
+        ++*nlaunch;
+    }
+    if (nact > nfull) {
+        hipError_t e = launch_arnoldi_step_batched(su, base, nact, L.R, j, p->k, P.base[nfull],
+                                                   P.base[nact] - P.base[nfull], block, L.smax, p->prec, st);
+        if (e != hipSuccess) return e;
+        ++*nlaunch;
+    }
+    return hipSuccess;
+}
+
 skfab_status run_batch_arnoldi(skfab_ctx* ctx, const BatchLayout& L, const BatchPlan& P,
                                const skfab_batch_problem* probs, const skfab_params* p, char* dev, int block,
                                int jmax, hipStream_t st) {
@@ -1377,13 +1415,11 @@ skfab_status run_batch_arnoldi(skfab_ctx* ctx, const BatchLayout& L, const Batch
     for (int j = 0; j <= jmax; ++j) {
         while (nact > 0 && probs[L.order[nact - 1]].m < j) --nact;
         if (nact == 0) break;
-        const hipError_t e =
-            launch_arnoldi_step_batched(su, base, nact, L.R, j, p->k, P.base[nact], block, L.smax, p->prec, st);
+        const hipError_t e = batch_step(ctx, L, P, probs, p, su, base, nact, j, block, st, &nlaunch);
         if (e != hipSuccess) {
             timing_cancel(ctx, sp);
             return SKFAB_ERR_HIP;
         }
-        ++nlaunch;
     }
     HIP_TRY(timing_end(ctx, sp, st, nlaunch));
     return SKFAB_OK;
@@ -1489,8 +1525,10 @@ skfab_status skfab_batch_set_tuning(skfab_ctx* ctx, const skfab_batch_tuning* t)
     if (!ctx || !t) return SKFAB_ERR_ARG;
     if (t->block != 256 && t->block != 512 && t->block != 1024) return SKFAB_ERR_ARG;
     if (t->slices_per_wave < 1 || t->slices_per_wave > 64) return SKFAB_ERR_ARG;
+    if (t->packed != 0 && t->packed != 1) return SKFAB_ERR_ARG;
     ctx->batch_block = t->block;
     ctx->batch_spw = t->slices_per_wave;
+    ctx->batch_packed = t->packed != 0;
     return SKFAB_OK;
 }
 
@@ -1498,6 +1536,7 @@ skfab_status skfab_batch_get_tuning(skfab_ctx* ctx, skfab_batch_tuning* t) {
     if (!ctx || !t) return SKFAB_ERR_ARG;
     t->block = ctx->batch_block;
     t->slices_per_wave = ctx->batch_spw;
+    t->packed = ctx->batch_packed ? 1 : 0;
     return SKFAB_OK;
 }
 
@@ -1551,11 +1590,18 @@ skfab_status skfab_batch_autotune(skfab_ctx* ctx, int32_t nprob, const skfab_bat
     const int spws[7] = {1, 2, 4, 8, 16, 32, 64};
     float best = 1e30f;
     int bb = ctx->batch_block, bs = ctx->batch_spw;
-    const bool timing = ctx->timing;
+    bool bp = ctx->batch_packed;
+    const bool timing = ctx->timing, packed0 = ctx->batch_packed;
     ctx->timing = false;
-    for (int bi = 0; bi < 3 && r == SKFAB_OK; ++bi) {
+    // candidates: block x slices per wave, and for 512-thread blocks also the packed
+    // form (timed over the same steps; it applies from step 2 on)
+    for (int ci = 0; ci < 4 * 7 && r == SKFAB_OK; ++ci) {
+        const int bi = (ci / 7 < 3) ? ci / 7 : 1, si = ci % 7;
+        const bool packed = ci >= 3 * 7;
+        if (packed && (p->k != 2 || packed_step_lds(blocks[bi], L.R, L.smax) == 0)) continue;
         if (step_block_fit(blocks[bi], L.smax) != blocks[bi]) continue;  // bins do not fit LDS
-        for (int si = 0; si < 7 && r == SKFAB_OK; ++si) {
+        ctx->batch_packed = packed;
+        {
             const BatchPlan P = batch_plan(L, blocks[bi], spws[si]);
             // the step launches of a candidate time j = 1 .. steps (j = 0 has no
             // previous step to reduce and is run untimed first)
@@ -1567,27 +1613,31 @@ skfab_status skfab_batch_autotune(skfab_ctx* ctx, int32_t nprob, const skfab_bat
             if (hipEventRecord(e0, st) != hipSuccess) { r = SKFAB_ERR_HIP; break; }
             const BatchStepUnit* su = reinterpret_cast<const BatchStepUnit*>(dev + L.steps);
             const int* base = reinterpret_cast<const int*>(dev + L.base);
-            int nact = L.nprob;
+            int nact = L.nprob, nl = 0;
             for (int j = 1; j <= steps; ++j) {
                 while (nact > 0 && probs[L.order[nact - 1]].m < j) --nact;
                 if (nact == 0) break;
-                if (launch_arnoldi_step_batched(su, base, nact, L.R, j, p->k, P.base[nact], blocks[bi], L.smax,
-                                                p->prec, st) != hipSuccess) { r = SKFAB_ERR_HIP; break; }
+                if (batch_step(ctx, L, P, probs, p, su, base, nact, j, blocks[bi], st, &nl) != hipSuccess) {
+                    r = SKFAB_ERR_HIP;
+                    break;
+                }
             }
             if (r != SKFAB_OK) break;
             float ms = 0.f;
             if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
                 hipEventElapsedTime(&ms, e0, e1) != hipSuccess) { r = SKFAB_ERR_HIP; break; }
-            if (ms < best) { best = ms; bb = blocks[bi]; bs = spws[si]; }
+            if (ms < best) { best = ms; bb = blocks[bi]; bs = spws[si]; bp = packed; }
         }
     }
     ctx->timing = timing;
+    ctx->batch_packed = packed0;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (r != SKFAB_OK) return r;
     ctx->batch_block = bb;
     ctx->batch_spw = bs;
-    if (chosen) { chosen->block = bb; chosen->slices_per_wave = bs; }
+    ctx->batch_packed = bp;
+    if (chosen) { chosen->block = bb; chosen->slices_per_wave = bs; chosen->packed = bp ? 1 : 0; }
     return SKFAB_OK;
 }
 

@@ -634,8 +634,8 @@ __device__ __forceinline__ BatchLookup batch_lookup(const int* __restrict__ base
 template <int KW, int ZETA, int BLOCK, typename P>
 __global__ __launch_bounds__(BLOCK) void arnoldi_step_batched_kernel(const BatchStepUnit* __restrict__ units,
                                                                      const int* __restrict__ base, int nact, int R,
-                                                                     int j) {
-    const BatchLookup lk = batch_lookup(base, nact, R, blockIdx.x);
+                                                                     int j, int g0) {
+    const BatchLookup lk = batch_lookup(base, nact, R, g0 + (int)blockIdx.x);
     const BatchStepUnit& u = units[lk.unit];
     StepArgs a = u.a;
     a.j = j;
@@ -647,6 +647,382 @@ __global__ __launch_bounds__(BLOCK) void arnoldi_step_batched_kernel(const Batch
     a.skp_prev = u.skp[(j + 1) & 1];
     a.skp_cur = u.skp[j & 1];
     step_body<KW, ZETA, BLOCK, P, true>(a, lk.bid);
+}
+
+// ------------------------------------------- batched step: all right-hand sides
+// One block serves chunk `bid` of problem q for all R of its right-hand sides
+// (units q R .. q R + R - 1): a slice's metadata, column offsets and value
+// indices, and a row's sketch hash, are loaded or computed once for all of them,
+// and each wavefront has the gathers of every right-hand side in flight at once.
+// For the steps 2 <= j < m with k = 2 (full window, no extension pass, no sketch
+// of A u_j), SELL form of A.  Chunks, per-wavefront slices, bins, partials and the
+// order of every sum are those of the per-unit form (step_body), so the two forms
+// agree bit for bit and may alternate from step to step.  A block takes the LDS of
+// R sets of bins, [NW][R][s] doubles (R <= RM).
+// Load / store at element i of a uniform (per-block) base through a 32-bit byte
+// offset: the global instructions then take the base in scalar registers and only
+// the offset in a vector register (the host keeps 8 N below 2^32 for this form).
+template <typename T>
+__device__ __forceinline__ T ld_off(const GAS T* base, uint32_t i) {
+    return gload(reinterpret_cast<const GAS T*>(reinterpret_cast<const GAS char*>(base) + i * (uint32_t)sizeof(T)));
+}
+template <typename T>
+__device__ __forceinline__ void st_off(GAS T* base, uint32_t i, T v) {
+    store_nt(v, reinterpret_cast<GAS T*>(reinterpret_cast<GAS char*>(base) + i * (uint32_t)sizeof(T)));
+}
+
+template <int ZETA, int BLOCK, typename P, int RM>
+__global__ __launch_bounds__(BLOCK) void arnoldi_step_packed_kernel(const BatchStepUnit* __restrict__ units,
+                                                                    const int* __restrict__ base, int nprob, int R,
+                                                                    int j) {
+    using VT = typename P::V;
+    using WT = typename P::W;
+    using AT = typename P::A;
+    constexpr int KW = 2;
+    constexpr int NSC = 2 * KW + 1;
+    constexpr int NW = BLOCK / WAVE;
+    constexpr int SB = 5;  // entries per load batch (the gathers of RM units must fit the registers)
+    extern __shared__ double bins[];  // [NW][R][s]; the reductions' scratch before and after the loop
+    __shared__ double red[RM * NSC];
+    __shared__ double coef[RM][KMAX + 2];
+    __shared__ double win[RM][KW * KW];
+    __shared__ int2 meta[NW][WAVE];
+    __shared__ int s_ok[RM];
+    __shared__ int s_prog;
+    __shared__ WT dtab[DICT_MAX];
+
+    // problem of this block: base[q] = R x (blocks of the problems before q)
+    const int g = blockIdx.x;
+    int lo = 0, hi = nprob;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (base[mid] <= g * R) lo = mid; else hi = mid;
+    }
+    const int bid = g - base[lo] / R;
+    const BatchStepUnit* __restrict__ un = units + (int64_t)lo * R;
+    const StepArgs& a0 = un[0].a;  // fields shared by the problem's units
+    const int sell_flag = gptr(a0.sctrl)->sell_ok;
+    const int col16 = gptr(a0.sctrl)->col16;
+    const int dict8 = gptr(a0.sctrl)->dict8;
+    const WT dval = (WT)(AT)gptr(a0.sl_table)[threadIdx.x & (DICT_MAX - 1)];
+    const int k = a0.k, s = a0.s, G = a0.G;
+    const int64_t N = a0.N, ldS = a0.ldS;
+    const uint64_t seed = a0.seed;
+    const double isz = a0.inv_sqrt_zeta;
+    const int tid = threadIdx.x, lane = tid & (WAVE - 1), wid = tid / WAVE;
+    const int p = j - 1;  // the step whose reductions this block finishes
+
+    const int chunk = xcd_chunk(bid, G);
+    const int64_t sl0 = (int64_t)chunk * a0.slices_per_chunk + wid;
+    const int64_t sl1 = min(a0.nslices, (int64_t)(chunk + 1) * a0.slices_per_chunk);
+    const int64_t itl0 = sl0 + (int64_t)lane * NW;
+    const bool win_in = itl0 < sl1;
+    const int64_t itl0c = win_in ? itl0 : 0;
+    const GAS int32_t* __restrict__ sl_len = gptr(a0.sl_len);
+    const GAS int64_t* __restrict__ sl_ptr = gptr(a0.sl_ptr);
+    const int wlen = sl_len[itl0c];
+    const int64_t wptr = sl_ptr[itl0c];
+
+    // ------------------------------------------------ prologue, every unit
+    constexpr int GM = STEP_GMAX_1024 * (1024 / BLOCK);
+    constexpr int GPT = (GM + BLOCK - 1) / BLOCK;
+    constexpr int GPL = (GM + WAVE - 1) / WAVE;
+    bool stopped[RM];
+    double sv[RM * NSC];
+    double skv[RM];
+    const int b0 = (bid * s) / G, b1 = ((bid + 1) * s) / G;
+    const int mybin = (b0 + wid < b1) ? b0 + wid : -1;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const bool in = r < R;
+        const BatchStepUnit& u = un[in ? r : 0];
+        const GAS DevCtrl* cr = gptr(u.a.ctrl);
+        stopped[r] = !in || (cr->stop && cr->m_used < j - 1);
+        const GAS double* sp = gptr(u.scal[(j + 1) & 1]);
+        double ld[NSC][GPT];
+#pragma unroll
+        for (int q = 0; q < GPT; ++q) {
+            const int gg = tid + q * BLOCK, gc = (gg < G) ? gg : 0;
+#pragma unroll
+            for (int sc = 0; sc < NSC; ++sc) ld[sc][q] = sp[(int64_t)sc * G + gc];
+        }
+#pragma unroll
+        for (int sc = 0; sc < NSC; ++sc) {
+            double t = 0.0;
+#pragma unroll
+            for (int q = 0; q < GPT; ++q) t = fma((tid + q * BLOCK < G) ? 1.0 : 0.0, ld[sc][q], t);
+            sv[r * NSC + sc] = t;
+        }
+        const double wv = window_value<KW>(u.a, p, tid & (KW * KW - 1));
+        if (tid < KW * KW) win[r][tid] = wv;
+        double t0 = 0.0, t1 = 0.0;
+        if (mybin >= 0) {
+            const GAS double* src = gptr(u.skp[(j + 1) & 1]) + (int64_t)mybin * G;
+            double lb[GPL];
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                const int gg = lane + q * WAVE;
+                lb[q] = src[(gg < G) ? gg : 0];
+            }
+#pragma unroll
+            for (int q = 0; q < GPL; ++q) {
+                const double mk = (lane + q * WAVE < G) ? 1.0 : 0.0;
+                if (q & 1) t1 = fma(mk, lb[q], t1);
+                else t0 = fma(mk, lb[q], t0);
+            }
+        }
+        skv[r] = t0 + t1;
+    }
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) any |= !stopped[r];
+    if (!any) return;
+    if (tid < DICT_MAX) dtab[tid] = dval;
+    block_reduce_multi<RM * NSC, BLOCK>(sv, bins, red);
+    if (tid < RM) {  // thread r: the coefficients of unit r
+        const int r = tid;
+        bool st = true;
+#pragma unroll
+        for (int q = 0; q < RM; ++q)
+            if (q == r) st = stopped[q];
+        bool ok = false;
+        if (!st) ok = step_coefficients<KW>(red + r * NSC, win[r], p, k, bid == 0, un[r].a, coef[r]);
+        s_ok[r] = ok ? 1 : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < RM; ++r) skv[r] = wave_sum(skv[r]);
+    if (wid > 0)
+        for (int i = tid - WAVE; i < NW * R * s; i += BLOCK - WAVE) bins[i] = 0.0;
+    if (tid == WAVE) s_prog = 0;
+    __syncthreads();
+    bool act[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        act[r] = !stopped[r] && s_ok[r] != 0;
+        if (stopped[r]) continue;
+        const BatchStepUnit& u = un[r];
+        const double eta_p = coef[r][KMAX + 1];
+        const bool ok = s_ok[r] != 0;
+        if (mybin >= 0 && lane == 0) gptr(u.a.SV)[(int64_t)p * ldS + mybin] = skv[r] * (ok ? isz / eta_p : isz);
+        if (b1 - b0 > NW)
+            reduce_prev_sketch_tail<BLOCK>(u.skp[(j + 1) & 1], G, s, ldS, p, b0 + NW, b1,
+                                           ok ? isz / eta_p : isz, isz / eta_p, false, u.a.SV, u.a.SAV);
+    }
+    bool anyact = false;
+#pragma unroll
+    for (int r = 0; r < RM; ++r) anyact |= act[r];
+    if (!anyact) return;
+
+    // ------------------------------------------------ main loop
+    meta[wid][lane] = win_in ? make_int2(wlen, (int)(wptr >> 6)) : make_int2(0, 0);
+    double alpha[RM];
+    WT alpha_w[RM], cf_w[RM][KW];
+    const GAS WT* Wp[RM];
+    const GAS VT* Uo[RM][KW];
+    GAS VT* Uj[RM];
+    GAS WT* Wc[RM];
+    double* binV[RM];
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        const BatchStepUnit& u = un[act[r] ? r : 0];
+        alpha[r] = coef[r][0];
+        alpha_w[r] = (WT)alpha[r];
+#pragma unroll
+        for (int o = 0; o < KW; ++o) cf_w[r][o] = (WT)coef[r][1 + o];
+        Wp[r] = gptr(static_cast<const WT*>(u.W[(j + 1) & 1]));
+        Wc[r] = gptr(static_cast<WT*>(u.W[j & 1]));
+        const int ur = u.a.uring;
+#pragma unroll
+        for (int o = 0; o < KW; ++o)
+            Uo[r][o] = gptr(static_cast<const VT*>(u.a.U)) + (int64_t)((j - 1 - o) % ur) * u.a.ldU;
+        Uj[r] = gptr(static_cast<VT*>(u.a.U)) + (int64_t)(j % ur) * u.a.ldU;
+        binV[r] = bins + (wid * R + r) * s;
+    }
+    const GAS AT* __restrict__ slv = gptr(static_cast<const AT*>(a0.sl_val));
+    const GAS int32_t* __restrict__ sl_col = gptr(a0.sl_col);
+    const GAS int16_t* __restrict__ slo = gptr(reinterpret_cast<const int16_t*>(a0.sl_col));
+    const GAS uint8_t* __restrict__ sl8 = gptr(reinterpret_cast<const uint8_t*>(a0.sl_val));
+    const GAS int32_t* __restrict__ rowptr = gptr(a0.rowptr);
+    const GAS int32_t* __restrict__ colp = gptr(a0.col);
+    const GAS double* __restrict__ valp = gptr(a0.val);
+
+    double acc[RM][NSC];
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int i = 0; i < NSC; ++i) acc[r][i] = 0.0;
+
+    const bool sell = sell_flag != 0;
+    int64_t it0, it1, step;
+    if (sell) {
+        it0 = sl0;
+        it1 = sl1;
+        step = NW;
+    } else {
+        const int64_t r_begin = (int64_t)chunk * a0.rows_per_chunk;
+        it0 = r_begin + tid;
+        it1 = min(N, r_begin + a0.rows_per_chunk);
+        step = BLOCK;
+    }
+    auto main_loop = [&](auto dict_tag) __attribute__((always_inline)) {
+        constexpr bool DICT = decltype(dict_tag)::value;
+        int wbase = 0, iter = 0;
+        auto ring = [&](int64_t itn, int idx) {
+            if (idx - wbase == WAVE) {
+                wbase += WAVE;
+                const int64_t itl = itn + (int64_t)lane * step;
+                const int nl = (itl < it1) ? sl_len[itl] : 0;
+                const int np = (itl < it1) ? (int)(sl_ptr[itl] >> 6) : 0;
+                meta[wid][lane] = make_int2(nl, np);
+            }
+            return meta[wid][idx - wbase];
+        };
+        for (int64_t it = it0; it < it1; it += step, ++iter) {
+            const int64_t rw = sell ? it * WAVE + lane : it;
+            const bool valid = rw < N;
+            int len = 0;
+            int64_t e0 = 0;
+            if (sell) {
+                const int done = __hip_atomic_load(&s_prog, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                if (done > iter * NW) __builtin_amdgcn_s_setprio(3);
+                else __builtin_amdgcn_s_setprio(0);
+                const int2 md = ring(it, iter);
+                len = md.x;
+                e0 = ((int64_t)md.y << 6) + lane;
+            }
+            WT wrow[RM];
+            VT urow[RM][KW];
+#pragma unroll
+            for (int r = 0; r < RM; ++r) {
+                wrow[r] = (WT)0;
+                if (valid && act[r]) {
+                    wrow[r] = ld_off(Wp[r], (uint32_t)rw);
+#pragma unroll
+                    for (int o = 0; o < KW; ++o) urow[r][o] = ld_off(Uo[r][o], (uint32_t)rw);
+                }
+            }
+            WT w[RM];
+#pragma unroll
+            for (int r = 0; r < RM; ++r) w[r] = (WT)0;
+            if (sell) {
+                const int32_t rr = valid ? (int32_t)rw : 0;
+                for (int q0 = 0; q0 < len; q0 += SB) {
+                    int cc[SB], vi[SB];
+                    WT vv[SB];
+#pragma unroll
+                    for (int q = 0; q < SB; ++q) {
+                        const bool in = q0 + q < len;
+                        cc[q] = in ? (col16 ? (int32_t)slo[e0 + (int64_t)(q0 + q) * WAVE]
+                                            : sl_col[e0 + (int64_t)(q0 + q) * WAVE]) : 0;
+                        if constexpr (DICT) vi[q] = in ? (int)sl8[e0 + (int64_t)(q0 + q) * WAVE] : 0;
+                        else vv[q] = in ? (WT)slv[e0 + (int64_t)(q0 + q) * WAVE] : (WT)0;
+                    }
+                    if (col16) {
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) cc[q] = (q0 + q < len) ? rr + cc[q] : 0;
+                    }
+                    if constexpr (DICT) {
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) vv[q] = (q0 + q < len) ? dtab[vi[q]] : (WT)0;
+                    }
+                    WT xb[RM][SB], xu[RM][SB][KW];
+#pragma unroll
+                    for (int r = 0; r < RM; ++r) {
+                        if (!act[r]) continue;
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) {
+                            xb[r][q] = ld_off(Wp[r], (uint32_t)cc[q]);
+#pragma unroll
+                            for (int o = 0; o < KW; ++o) xu[r][q][o] = to_w<WT>(ld_off(Uo[r][o], (uint32_t)cc[q]));
+                        }
+                    }
+#pragma unroll
+                    for (int r = 0; r < RM; ++r) {
+                        if (!act[r]) continue;
+#pragma unroll
+                        for (int q = 0; q < SB; ++q) {
+                            WT x = alpha_w[r] * xb[r][q];
+#pragma unroll
+                            for (int o = 0; o < KW; ++o) x = fma(cf_w[r][o], xu[r][q][o], x);
+                            x = to_w<WT>(Store<VT>::put(x));
+                            w[r] = fma(vv[q], x, w[r]);
+                        }
+                    }
+                }
+            } else if (valid) {
+                const int e0r = rowptr[rw], e1r = rowptr[rw + 1];
+                for (int e = e0r; e < e1r; ++e) {
+                    const int c = colp[e];
+                    const WT av = (WT)valp[e];
+#pragma unroll
+                    for (int r = 0; r < RM; ++r) {
+                        if (!act[r]) continue;
+                        WT x = alpha_w[r] * Wp[r][c];
+#pragma unroll
+                        for (int o = 0; o < KW; ++o) x = fma(cf_w[r][o], to_w<WT>(gload(Uo[r][o] + c)), x);
+                        x = to_w<WT>(Store<VT>::put(x));
+                        w[r] = fma(av, x, w[r]);
+                    }
+                }
+            }
+            if (valid) {
+                int rows[ZETA];
+                double sg[ZETA];
+                sketch_column<ZETA>(seed, (uint64_t)rw, s, rows, sg);
+#pragma unroll
+                for (int r = 0; r < RM; ++r) {
+                    if (!act[r]) continue;
+                    WT u = alpha_w[r] * wrow[r];
+                    WT uo[KW];
+#pragma unroll
+                    for (int o = 0; o < KW; ++o) {
+                        uo[o] = to_w<WT>(urow[r][o]);
+                        u = fma(cf_w[r][o], uo[o], u);
+                    }
+                    const VT us = Store<VT>::put(u);
+                    u = to_w<WT>(us);
+                    st_off(Uj[r], (uint32_t)rw, us);
+                    st_off(Wc[r], (uint32_t)rw, w[r]);
+                    const double ud = (double)u, wd = (double)w[r];
+                    acc[r][0] = fma(ud, ud, acc[r][0]);
+                    acc[r][1] = fma(ud, wd, acc[r][1]);
+                    acc[r][2] = fma(wd, wd, acc[r][2]);
+                    acc[r][3] = fma((double)uo[0], wd, acc[r][3]);
+                    acc[r][4] = fma(ud, (double)uo[0], acc[r][4]);
+#pragma unroll
+                    for (int q = 0; q < ZETA; ++q) lds_add(binV[r] + rows[q], sg[q] * ud);
+                }
+            }
+            if (sell && lane == 0) __hip_atomic_fetch_add(&s_prog, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    };
+    if (dict8 && sell) main_loop(std::integral_constant<bool, true>());
+    else main_loop(std::integral_constant<bool, false>());
+    __builtin_amdgcn_s_setprio(0);
+
+    // ------------------------------------------------ epilogue, every unit
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < RM; ++r) {
+        if (!act[r]) continue;
+        GAS double* dst = gptr(un[r].skp[j & 1]);
+        for (int i = tid; i < s; i += BLOCK) {
+            double t = 0.0;
+            for (int wv = 0; wv < NW; ++wv) t += bins[(wv * R + r) * s + i];
+            dst[(int64_t)i * G + chunk] = t;
+        }
+    }
+    double vals[RM * NSC];
+#pragma unroll
+    for (int r = 0; r < RM; ++r)
+#pragma unroll
+        for (int i = 0; i < NSC; ++i) vals[r * NSC + i] = acc[r][i];
+    __syncthreads();
+    block_reduce_multi<RM * NSC, BLOCK>(vals, bins, red);
+    if (tid < RM * NSC) {
+        const int r = tid / NSC, i = tid % NSC;
+        if (act[r]) gptr(un[r].scal[j & 1])[(int64_t)i * G + bid] = red[tid];
+    }
 }
 
 // After the extension step m: S u_m (unnormalised) into SV[:, m_used], eta_m and
@@ -1183,40 +1559,71 @@ hipError_t launch_sell_convert(const int32_t* rowptr, const int32_t* col, const 
 // ------------------------------------------------------- batched launchers
 template <int KW, int ZETA, typename P>
 static hipError_t launch_step_batched_t(const BatchStepUnit* units, const int* base, int nact, int R, int j,
-                                        int grid, int block, int smax, hipStream_t st) {
+                                        int g0, int grid, int block, int smax, hipStream_t st) {
     const size_t bins = (size_t)(block / WAVE) * 2 * smax;
     const size_t red = (size_t)(2 * KW + 1) * (block + 72);
     const size_t lds = (bins > red ? bins : red) * sizeof(double);
     if (block == 1024)
         hipLaunchKernelGGL((arnoldi_step_batched_kernel<KW, ZETA, 1024, P>), dim3(grid), dim3(1024), lds, st, units,
-                           base, nact, R, j);
+                           base, nact, R, j, g0);
     else if (block == 512)
         hipLaunchKernelGGL((arnoldi_step_batched_kernel<KW, ZETA, 512, P>), dim3(grid), dim3(512), lds, st, units,
-                           base, nact, R, j);
+                           base, nact, R, j, g0);
     else
         hipLaunchKernelGGL((arnoldi_step_batched_kernel<KW, ZETA, 256, P>), dim3(grid), dim3(256), lds, st, units,
-                           base, nact, R, j);
+                           base, nact, R, j, g0);
     return hipGetLastError();
 }
 
 template <typename P>
 static hipError_t launch_step_batched_p(const BatchStepUnit* units, const int* base, int nact, int R, int j, int k,
-                                        int grid, int block, int smax, hipStream_t st) {
+                                        int g0, int grid, int block, int smax, hipStream_t st) {
     switch (k) {
-        case 1: return launch_step_batched_t<1, 8, P>(units, base, nact, R, j, grid, block, smax, st);
-        case 2: return launch_step_batched_t<2, 8, P>(units, base, nact, R, j, grid, block, smax, st);
-        case 3: return launch_step_batched_t<3, 8, P>(units, base, nact, R, j, grid, block, smax, st);
-        default: return launch_step_batched_t<4, 8, P>(units, base, nact, R, j, grid, block, smax, st);
+        case 1: return launch_step_batched_t<1, 8, P>(units, base, nact, R, j, g0, grid, block, smax, st);
+        case 2: return launch_step_batched_t<2, 8, P>(units, base, nact, R, j, g0, grid, block, smax, st);
+        case 3: return launch_step_batched_t<3, 8, P>(units, base, nact, R, j, g0, grid, block, smax, st);
+        default: return launch_step_batched_t<4, 8, P>(units, base, nact, R, j, g0, grid, block, smax, st);
     }
 }
 
-// Batched step launch (sketch density 8, k <= 4): `grid` blocks, the first nact
-// problems (by decreasing m) active.
+// Batched step launch (sketch density 8, k <= 4), per-unit form: `grid` blocks
+// starting at block g0 of the launch plan, the first nact problems (by decreasing
+// m) active.
 hipError_t launch_arnoldi_step_batched(const BatchStepUnit* units, const int* base, int nact, int R, int j, int k,
-                                       int grid, int block, int smax, int prec, hipStream_t st) {
-    if (prec == 1) return launch_step_batched_p<PrecF32>(units, base, nact, R, j, k, grid, block, smax, st);
-    if (prec == 2) return launch_step_batched_p<PrecBF16>(units, base, nact, R, j, k, grid, block, smax, st);
-    return launch_step_batched_p<PrecF64>(units, base, nact, R, j, k, grid, block, smax, st);
+                                       int g0, int grid, int block, int smax, int prec, hipStream_t st) {
+    if (prec == 1) return launch_step_batched_p<PrecF32>(units, base, nact, R, j, k, g0, grid, block, smax, st);
+    if (prec == 2) return launch_step_batched_p<PrecBF16>(units, base, nact, R, j, k, g0, grid, block, smax, st);
+    return launch_step_batched_p<PrecF64>(units, base, nact, R, j, k, g0, grid, block, smax, st);
+}
+
+// LDS of the packed form's block (dynamic part: R sets of bins per wavefront, or
+// the reductions' scratch), or 0 when it does not fit beside the static part.
+size_t packed_step_lds(int block, int R, int smax) {
+    constexpr int RM = PACKED_RMAX, NSC = 5;
+    if (block != PACKED_BLOCK || R < 1 || R > RM) return 0;
+    const size_t bins = (size_t)(block / WAVE) * R * smax;
+    const size_t red = (size_t)RM * NSC * (block + 72);
+    const size_t lds = (bins > red ? bins : red) * sizeof(double);
+    const size_t stat = (size_t)(block / WAVE) * WAVE * 8 + DICT_MAX * sizeof(double) + 1024;
+    return (lds + stat <= 156 * 1024) ? lds : 0;
+}
+
+// Batched step launch, packed form (k = 2, 2 <= j < m of every problem in the
+// first nprob): one block per chunk of a problem for all its R right-hand sides.
+hipError_t launch_arnoldi_step_packed(const BatchStepUnit* units, const int* base, int nprob, int R, int j, int grid,
+                                      int smax, int prec, hipStream_t st) {
+    const size_t lds = packed_step_lds(PACKED_BLOCK, R, smax);
+    if (lds == 0) return hipErrorInvalidValue;
+    if (prec == 1)
+        hipLaunchKernelGGL((arnoldi_step_packed_kernel<8, PACKED_BLOCK, PrecF32, PACKED_RMAX>), dim3(grid),
+                           dim3(PACKED_BLOCK), lds, st, units, base, nprob, R, j);
+    else if (prec == 2)
+        hipLaunchKernelGGL((arnoldi_step_packed_kernel<8, PACKED_BLOCK, PrecBF16, PACKED_RMAX>), dim3(grid),
+                           dim3(PACKED_BLOCK), lds, st, units, base, nprob, R, j);
+    else
+        hipLaunchKernelGGL((arnoldi_step_packed_kernel<8, PACKED_BLOCK, PrecF64, PACKED_RMAX>), dim3(grid),
+                           dim3(PACKED_BLOCK), lds, st, units, base, nprob, R, j);
+    return hipGetLastError();
 }
 
 hipError_t launch_arnoldi_tail_batched(const BatchStepUnit* units, const SmallUnit* small, int nunits, int smax,

@@ -15,6 +15,8 @@ constexpr int CT_KFIRST = 32;           // trapezoidal levels K = 32, 64, ..., C
 constexpr int CT_KMAX = 1024;
 constexpr int SMAX = 1024;              // largest sketch size
 constexpr int STEP_GMAX_1024 = 256;     // step-kernel blocks at most, per 1024 threads of block size
+constexpr int PACKED_BLOCK = 512;       // threads per block of the batched step's packed form
+constexpr int PACKED_RMAX = 4;          // right-hand sides per problem that the packed form carries
 constexpr double BREAKDOWN_TOL = 1e-14; // lucky-breakdown threshold on h_{j+1,j} / ||A v_j||
 
 // ------------------------------------------------------------ precisions

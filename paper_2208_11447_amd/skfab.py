@@ -354,25 +354,27 @@ def skfab_solve_batched(ctx: Context, probs, p: N.skfab_params, ws: torch.Tensor
     return [[info[i * nr + r] for r in range(nr)] for i in range(len(probs))]
 
 
-def skfab_batch_set_tuning(ctx: Context, block: int, slices_per_wave: int):
-    t = N.skfab_batch_tuning(int(block), int(slices_per_wave))
+def skfab_batch_set_tuning(ctx: Context, block: int, slices_per_wave: int, packed: bool = False):
+    t = N.skfab_batch_tuning(int(block), int(slices_per_wave), 1 if packed else 0)
     _check(N.lib().skfab_batch_set_tuning(ctx.handle, C.byref(t)), "skfab_batch_set_tuning")
 
 
 def skfab_batch_get_tuning(ctx: Context):
+    """(block, slices_per_wave, packed) of the context's batched step launches."""
     t = N.skfab_batch_tuning()
     _check(N.lib().skfab_batch_get_tuning(ctx.handle, C.byref(t)), "skfab_batch_get_tuning")
-    return t.block, t.slices_per_wave
+    return t.block, t.slices_per_wave, bool(t.packed)
 
 
 def skfab_batch_autotune(ctx: Context, probs, p: N.skfab_params, ws: torch.Tensor, steps: int = 4):
-    """Time every launch shape of the batched step kernel on this batch; keeps and
-    returns the fastest (block, slices_per_wave)."""
+    """Time every launch shape of the batched step kernel on this batch (and the
+    packed form for 512-thread blocks); keeps and returns the fastest
+    (block, slices_per_wave, packed)."""
     nr = _nrhs(probs)
     t = N.skfab_batch_tuning()
     _check(N.lib().skfab_batch_autotune(ctx.handle, len(probs), _batch_array(probs), nr, C.byref(p), _ptr(ws),
                                         ws.numel(), int(steps), C.byref(t)), "skfab_batch_autotune")
-    return t.block, t.slices_per_wave
+    return t.block, t.slices_per_wave, bool(t.packed)
 
 
 # -------------------------------------------------------------- adaptive m

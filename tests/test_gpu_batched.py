@@ -130,12 +130,13 @@ def test_batched_autotune_keeps_results(batch):
     saved = sk.skfab_batch_get_tuning(c)
     try:
         X0, _ = run_batch(probs, f="invsqrt", k=2)
-        block, spw = sk.skfab_batch_autotune(c, probs, p, ws, steps=3)
+        block, spw, packed = sk.skfab_batch_autotune(c, probs, p, ws, steps=3)
         assert block in (256, 512, 1024) and spw in (1, 2, 4, 8, 16, 32, 64)
-        assert sk.skfab_batch_get_tuning(c) == (block, spw)
-        log(f"autotuned launch shape on the test batch: block {block}, {spw} slices per wavefront")
-        for blk, s in ((256, 2), (512, 8), (block, spw)):
-            sk.skfab_batch_set_tuning(c, blk, s)
+        assert not packed or block == 512
+        assert sk.skfab_batch_get_tuning(c) == (block, spw, packed)
+        log(f"autotuned launch shape on the test batch: block {block}, {spw} slices per wavefront, packed {packed}")
+        for blk, s, pk in ((256, 2, True), (512, 8, False), (512, 8, True), (block, spw, packed)):
+            sk.skfab_batch_set_tuning(c, blk, s, pk)
             X1, info = run_batch(probs, f="invsqrt", k=2)
             for i in range(len(probs)):
                 assert all(info[i][r].status == 0 for r in range(NRHS))
@@ -149,8 +150,17 @@ def test_batched_timing_counts_step_launches(batch):
     timed run, every launch counted, and the assembly one timed launch; the
     result is bitwise the untimed one."""
     _, probs = batch
-    X0, _ = run_batch(probs, f="invsqrt", k=2)
     c = ctx()
+    saved = sk.skfab_batch_get_tuning(c)
+    sk.skfab_batch_set_tuning(c, saved[0], saved[1], False)  # one launch per step
+    try:
+        _timed_batch(probs, c)
+    finally:
+        sk.skfab_batch_set_tuning(c, *saved)
+
+
+def _timed_batch(probs, c):
+    X0, _ = run_batch(probs, f="invsqrt", k=2)
     p = sk.make_params(f="invsqrt", k=2)
     ws = sk.alloc_workspace(sk.skfab_batch_workspace_bytes(probs, p))
     sk.skfab_timing_enable(c, True, stride=1)
@@ -168,3 +178,76 @@ def test_batched_timing_counts_step_launches(batch):
     assert n1 == 1 and ms1 > 0.0
     for a, b in zip(X0, X1):
         assert np.array_equal(a, b)
+
+
+def _with_tuning(c, block, spw, packed, fn):
+    saved = sk.skfab_batch_get_tuning(c)
+    sk.skfab_batch_set_tuning(c, block, spw, packed)
+    try:
+        return fn()
+    finally:
+        sk.skfab_batch_set_tuning(c, *saved)
+
+
+@pytest.mark.parametrize("nrhs,prec", [(3, "fp64"), (4, "fp64"), (1, "fp64"), (4, "fp32")])
+def test_batched_packed_form_is_bitwise_per_unit_form(nrhs, prec):
+    """The packed form of the batched step (one block per chunk for all of a
+    problem's right-hand sides, steps 2 <= j < m, 512-thread blocks) gives X bit
+    for bit equal to the per-unit form at the same launch shape, and the oracle's
+    result per pair."""
+    hosts, probs = build_batch(nrhs=nrhs, seed0=300)
+    c = ctx()
+    X = {}
+    for packed in (False, True):
+        X[packed], info = _with_tuning(c, 512, 4, packed, lambda: run_batch(probs, f="invsqrt", k=2, prec=prec))
+        for i, q in enumerate(probs):
+            assert all(info[i][r].status == 0 and info[i][r].m_used == q.m for r in range(nrhs))
+    for i in range(len(probs)):
+        assert np.array_equal(X[True][i], X[False][i]), i
+    if prec == "fp64":
+        worst = 0.0
+        for i, ((A, B, _), q) in enumerate(zip(hosts, probs)):
+            for r in range(nrhs):
+                arn, _ = oracle_run(A, B[:, r], q.m, 2, q.s, seed=q.seed)
+                worst = max(worst, rel(X[True][i][r], ometh.sfom_closed(arn, "invsqrt").x))
+        log(f"packed form, {nrhs} rhs: bitwise the per-unit form; worst rel. err vs oracle {worst:.2e}")
+        assert worst < 1e-10
+
+
+def test_batched_packed_form_with_a_breakdown():
+    """Right-hand side 1 of the second problem lies in a 3-dimensional invariant
+    subspace (lucky breakdown at m_used = 3, inside the packed form's steps) while
+    its other right-hand sides run to m = 12: packed and per-unit forms agree bit
+    for bit, the broken-down pair is exact and the others match the oracle."""
+    hosts, probs = build_batch(specs=[(48, 40.0, 30)], nrhs=3)
+    Nb = 1500
+    rng = np.random.default_rng(11)
+    blk = np.diag(rng.uniform(2.0, 5.0, 3)) + np.triu(rng.uniform(-0.3, 0.3, (3, 3)), 1)
+    A = sp.lil_matrix((Nb, Nb))
+    A.setdiag(rng.uniform(1.0, 9.0, Nb))
+    A[:3, :3] = blk
+    A = sp.csr_matrix(A)
+    A.sort_indices()
+    B = rng.standard_normal((3, Nb))
+    B[1, 3:] = 0.0
+    Ad = sk.CSR.from_numpy(A.indptr.astype(np.int32), A.indices.astype(np.int32), A.data)
+    Bt = torch.as_tensor(B, device="cuda")
+    probs.append(sk.BatchProblem(Ad, Bt, torch.zeros_like(Bt), m=12, s=40, seed=9))
+    c = ctx()
+    X, infos = {}, {}
+    for packed in (False, True):
+        X[packed], infos[packed] = _with_tuning(c, 512, 2, packed, lambda: run_batch(probs, f="invsqrt", k=2))
+    for i in range(len(probs)):
+        assert np.array_equal(X[True][i], X[False][i]), i
+    info = infos[True]
+    assert info[1][1].status == 0 and info[1][1].m_used == 3
+    import scipy.linalg as sla
+    truth = np.zeros(Nb)
+    truth[:3] = np.linalg.solve(sla.sqrtm(blk).real, B[1, :3])
+    assert rel(X[True][1][1], truth) < 1e-10
+    for r in (0, 2):
+        assert info[1][r].status == 0 and info[1][r].m_used == 12
+        arn, _ = oracle_run(A, B[r], 12, 2, 40, seed=9)
+        assert rel(X[True][1][r], ometh.sfom_closed(arn, "invsqrt").x) < 1e-10
+    for r in range(3):
+        assert info[0][r].status == 0 and info[0][r].m_used == 30
