@@ -11,7 +11,7 @@
 // eigenvalues of H_hat, negated); Section 5.2 uses the parabola
 // t(theta) = a + i theta - c theta^2.
 //
-//   contour_setup_kernel: eigenvalues of H_hat (Francis double-shift QR on the
+//   contour_setup_kernel: eigenvalues of H_hat (Francis QR with small bulges on the
 //     Hessenberg matrix, one block, the matrix in LDS) and the parabola;
 //   contour_level_kernel: the trapezoidal rule's nodes, one wavefront per node
 //     (complex Givens least squares), each node's contribution
@@ -44,69 +44,227 @@ constexpr double CT_KAPPA_MAX = 0.25;
 
 // ------------------------------------------------ Hessenberg eigenvalues
 // H_hat = H_m + r e_m^T is upper Hessenberg.  Its eigenvalues are found by the
-// Francis double-shift QR iteration (eigenvalues only: each step acts on the
+// Francis QR iteration with small bulges (eigenvalues only: each step acts on the
 // active block), one block, the matrix in LDS in FP64: row i from column
-// max(i - 1, 0) (CT_HQR_CAP doubles for n <= CT_NMAX).  The bulge of a step is
-// at most three entries below the subdiagonal, at (k+2, k), (k+3, k+1) and
-// (k+3, k) after step k: they live in three slots after the matrix, slot row & 1
-// (two below the diagonal, in consecutive rows) and slot 2 (three below), and are
-// zero between sweeps.
+// max(i - 1, 0) (CT_HQR_CAP doubles for n <= CT_NMAX).  A sweep chases up to
+// HQ_NB bulges of two shifts each, HQ_DS rows apart; the shifts are eigenvalues
+// of the trailing 2 HQ_NB x 2 HQ_NB block.  A bulge leaves at most three entries
+// below the subdiagonal, at (k+2, k), (k+3, k+1) and (k+3, k) after its step at
+// row k: those two below the diagonal live in slot row % HQ_P of one array after
+// the matrix, those three below in slot row % HQ_P of another (the entries of a
+// chain span fewer than HQ_P rows), and all are zero between sweeps.
 // Balancing by powers of two (a diagonal similarity, exact) comes first: the last
 // column of H_hat can be orders of magnitude larger than the band.
 constexpr int CT_HQR_CAP = CT_NMAX + (CT_NMAX - 1) * (CT_NMAX + 2) / 2;
-// Threads of the eigenvalue kernel: every wavefront takes the same (uniform)
-// decisions from the same LDS values; the row and column updates of a reflector
-// are spread over all of them, one entry per thread (n <= CT_NMAX < HQ_NT).
-constexpr int HQ_NT = 256;
+constexpr int HQ_P = 32;     // slot period of the entries below the subdiagonal
+constexpr int HQ_NB = 4;     // bulges of a sweep at most
+constexpr int HQ_DS = 4;     // rows between consecutive bulges of a chain
+constexpr int HQ_NS = 2 * HQ_NB;
+constexpr int HQ_NMIN = 24;  // smaller active blocks take one bulge (shifts of the trailing 2 x 2)
+static_assert(HQ_NB * HQ_DS + 4 <= HQ_P, "the sub-subdiagonal entries of a chain map to distinct slots");
+constexpr int HQ_LDS = CT_HQR_CAP + 2 * HQ_P;  // the matrix and the two slot arrays
+// Threads of the eigenvalue kernel (NT): every wavefront takes the same (uniform)
+// decisions from the same LDS values; the row and column updates of a chain step
+// (at most HQ_NB (n + 1) entries each) are spread over all of them.  1024 threads
+// for n > HQ_NSMALL; 256 below, where every sweep takes one bulge (measured: the
+// shift eigenvalues and the chain's fill and drain cost more than they save on
+// such short blocks, and fewer wavefronts make the barriers cheaper).
+constexpr int HQ_NSMALL = 63;
+static_assert(HQ_NB * (HQ_NSMALL + 1) <= 256 && HQ_NB * (CT_NMAX + 1) <= 1024, "one entry per thread and phase");
 
 __device__ __forceinline__ int hq_off(int i, int n) { return (i == 0) ? 0 : n + (i - 1) * (2 * n - i + 2) / 2; }
 
-// address of entry (i, j), j >= i - 3 (entries below the subdiagonal: bulge
-// slots), by arithmetic alone: a load never waits on a branch, so the loads of an
-// update are in flight together (measured: 18 % less time in the iteration)
+// address of entry (i, j), j >= i - 3, by arithmetic alone (a load never waits on
+// a branch, so the loads of an update are in flight together)
 __device__ __forceinline__ double* hq_at(double* Hs, int i, int j, int n) {
     const int d = i - j;
     const int band = hq_off(i, n) + j - (i > 0 ? i - 1 : 0);
-    return Hs + ((d <= 1) ? band : CT_HQR_CAP + ((d == 2) ? (i & 1) : 2));
+    return Hs + ((d <= 1) ? band : CT_HQR_CAP + ((d == 2) ? 0 : HQ_P) + (i & (HQ_P - 1)));
 }
 
+__device__ __forceinline__ void hq_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Balancing by wavefront 0 alone (its LDS accesses ordered by wavefront fences),
+// the other wavefronts waiting at one barrier at the end.
 __device__ void hq_balance(double* Hs, int n) {
-    const int lane = threadIdx.x & 63;
-    for (int sweep = 0; sweep < 40; ++sweep) {
-        bool done = true;
-        for (int i = 0; i < n; ++i) {
-            double c = 0.0, r = 0.0;
-            for (int q = lane; q < min(i + 2, n); q += WAVE)
-                if (q != i) c += fabs(*hq_at(Hs, q, i, n));
-            for (int q = (i > 0 ? i - 1 : 0) + lane; q < n; q += WAVE)
-                if (q != i) r += fabs(*hq_at(Hs, i, q, n));
-            c = wave_sum(c);
-            r = wave_sum(r);
-            __syncthreads();  // every wavefront has its sums before any scaling
-            if (c == 0.0 || r == 0.0) continue;
-            double gg = 0.5 * r, f = 1.0;
-            const double s = c + r;
-            for (int t = 0; t < 2100 && c < gg; ++t) { f *= 2.0; c *= 4.0; }
-            gg = 2.0 * r;
-            for (int t = 0; t < 2100 && c >= gg; ++t) { f *= 0.5; c *= 0.25; }
-            if ((c + r) / f < 0.95 * s) {
-                done = false;
-                const double fi = 1.0 / f;
-                for (int q = (i > 0 ? i - 1 : 0) + (int)threadIdx.x; q < n; q += HQ_NT) *hq_at(Hs, i, q, n) *= fi;
-                __syncthreads();
-                for (int q = threadIdx.x; q < min(i + 2, n); q += HQ_NT) *hq_at(Hs, q, i, n) *= f;
+    if (threadIdx.x < WAVE) {
+        const int lane = threadIdx.x;
+        for (int sweep = 0; sweep < 40; ++sweep) {
+            bool done = true;
+            for (int i = 0; i < n; ++i) {
+                double c = 0.0, r = 0.0;
+                for (int q = lane; q < min(i + 2, n); q += WAVE)
+                    if (q != i) c += fabs(*hq_at(Hs, q, i, n));
+                for (int q = (i > 0 ? i - 1 : 0) + lane; q < n; q += WAVE)
+                    if (q != i) r += fabs(*hq_at(Hs, i, q, n));
+                c = wave_sum(c);
+                r = wave_sum(r);
+                if (c == 0.0 || r == 0.0) continue;
+                double gg = 0.5 * r, f = 1.0;
+                const double s = c + r;
+                for (int t = 0; t < 2100 && c < gg; ++t) { f *= 2.0; c *= 4.0; }
+                gg = 2.0 * r;
+                for (int t = 0; t < 2100 && c >= gg; ++t) { f *= 0.5; c *= 0.25; }
+                if ((c + r) / f < 0.95 * s) {
+                    done = false;
+                    const double fi = 1.0 / f;
+                    hq_wave_sync();  // every lane has its sums before any scaling
+                    for (int q = (i > 0 ? i - 1 : 0) + lane; q < n; q += WAVE) *hq_at(Hs, i, q, n) *= fi;
+                    hq_wave_sync();
+                    for (int q = lane; q < min(i + 2, n); q += WAVE) *hq_at(Hs, q, i, n) *= f;
+                    hq_wave_sync();
+                }
             }
-            __syncthreads();
+            if (done) break;
         }
-        if (done) break;
     }
+    __syncthreads();
 }
 
-// Eigenvalues of the n x n Hessenberg matrix in Hs into wr, wi; one block,
-// every control decision uniform.  Returns false when the iteration has not
-// converged within 30 n double-shift steps.
-__device__ bool hqr_eigs(double* Hs, int n, double* __restrict__ wr, double* __restrict__ wi) {
+// Householder reflector P = I - tau v v^T with P (x, y, z)^T = (alpha, 0, 0)^T, into
+// out = (v0, v1, v2, tau, alpha); tau = 0 (no reflection) when x = y = z = 0.
+__device__ __forceinline__ void hq_reflector(double x, double y, double z, double* out) {
+    const double nx = sqrt(x * x + y * y + z * z);
+    if (nx == 0.0) {
+        out[0] = out[1] = out[2] = out[3] = out[4] = 0.0;
+        return;
+    }
+    const double alpha = (x >= 0.0) ? -nx : nx;
+    const double v0 = x - alpha;
+    out[0] = v0;
+    out[1] = y;
+    out[2] = z;
+    out[3] = 2.0 / (v0 * v0 + y * y + z * z);
+    out[4] = alpha;
+}
+
+// Eigenvalues of the ns x ns upper Hessenberg matrix W (row-major, ld HQ_NS, in
+// LDS) by the double-shift iteration, on the 64 lanes of one wavefront (uniform
+// decisions; a reflector's row and column updates one entry per lane, ordered by
+// wavefront fences); into er, ei.  Returns false without convergence in 30 ns steps.
+
+__device__ bool hq_small_eigs(double* W, int ns, double* er, double* ei) {
     const int lane = threadIdx.x & 63;
+    auto w = [&](int i, int j) -> double& { return W[i * HQ_NS + j]; };
+    double nrm = 0.0;
+    for (int e = lane; e < ns * ns; e += WAVE) nrm += fabs(w(e / ns, e % ns));
+    nrm = wave_sum(nrm);
+    const double eps = 2.3e-16;
+    int hi = ns - 1, its = 0, total = 0;
+    while (hi >= 0) {
+        int l = 0;
+        for (int c = hi; c > 0; --c) {
+            double sd = fabs(w(c - 1, c - 1)) + fabs(w(c, c));
+            if (sd == 0.0) sd = nrm;
+            if (fabs(w(c, c - 1)) <= eps * sd) { l = c; break; }
+        }
+        hq_wave_sync();
+        if (l > 0 && lane == 0) w(l, l - 1) = 0.0;
+        if (l == hi) {
+            if (lane == 0) { er[hi] = w(hi, hi); ei[hi] = 0.0; }
+            hq_wave_sync();
+            --hi;
+            its = 0;
+            continue;
+        }
+        if (l == hi - 1) {
+            const double p = w(hi - 1, hi - 1), q = w(hi - 1, hi), r = w(hi, hi - 1), s = w(hi, hi);
+            const double hm = 0.5 * (p - s), disc = hm * hm + q * r;
+            if (lane == 0) {
+                if (disc >= 0.0) {
+                    const double z = hm + copysign(sqrt(disc), hm);
+                    er[hi - 1] = s + z;
+                    er[hi] = (z != 0.0) ? s - q * r / z : s + z;
+                    ei[hi - 1] = ei[hi] = 0.0;
+                } else {
+                    const double im = sqrt(-disc);
+                    er[hi - 1] = er[hi] = s + hm;
+                    ei[hi - 1] = im;
+                    ei[hi] = -im;
+                }
+            }
+            hq_wave_sync();
+            hi -= 2;
+            its = 0;
+            continue;
+        }
+        if (total >= 30 * ns) return false;
+        double sh, dt;
+        if (its == 10 || its == 20) {
+            const double x = fabs(w(hi, hi - 1)) + fabs(w(hi - 1, hi - 2));
+            sh = 1.5 * x;
+            dt = x * x;
+        } else {
+            const double p = w(hi - 1, hi - 1), q = w(hi - 1, hi), r = w(hi, hi - 1), s = w(hi, hi);
+            sh = p + s;
+            dt = p * s - q * r;
+        }
+        ++its;
+        ++total;
+        const double h00 = w(l, l), h01 = w(l, l + 1), h10 = w(l + 1, l), h11 = w(l + 1, l + 1);
+        double x = h00 * h00 + h01 * h10 - sh * h00 + dt, y = h10 * (h00 + h11 - sh), z = h10 * w(l + 2, l + 1);
+        hq_wave_sync();
+        for (int k = l; k <= hi - 1; ++k) {
+            const bool three = k <= hi - 2;
+            if (k > l) {
+                x = w(k, k - 1);
+                y = w(k + 1, k - 1);
+                z = three ? w(k + 2, k - 1) : 0.0;
+            }
+            double rf[5];
+            hq_reflector(x, y, three ? z : 0.0, rf);
+            const double v0 = rf[0], v1 = rf[1], v2 = rf[2], tau = rf[3];
+            hq_wave_sync();  // every lane has read x, y, z
+            if (tau == 0.0) continue;
+            {
+                const int j = max(l, k - 1) + lane;
+                if (j <= hi) {
+                    if (j == k - 1) {
+                        w(k, j) = rf[4];
+                        w(k + 1, j) = 0.0;
+                        if (three) w(k + 2, j) = 0.0;
+                    } else {
+                        const double r0 = w(k, j), r1 = w(k + 1, j), r2 = three ? w(k + 2, j) : 0.0;
+                        const double d = tau * (v0 * r0 + v1 * r1 + v2 * r2);
+                        w(k, j) = r0 - d * v0;
+                        w(k + 1, j) = r1 - d * v1;
+                        if (three) w(k + 2, j) = r2 - d * v2;
+                    }
+                }
+            }
+            hq_wave_sync();
+            {
+                const int i = l + lane;
+                if (i <= min(k + 3, hi)) {
+                    const double c0 = w(i, k), c1 = w(i, k + 1), c2 = three ? w(i, k + 2) : 0.0;
+                    const double d = tau * (v0 * c0 + v1 * c1 + v2 * c2);
+                    w(i, k) = c0 - d * v0;
+                    w(i, k + 1) = c1 - d * v1;
+                    if (three) w(i, k + 2) = c2 - d * v2;
+                }
+            }
+            hq_wave_sync();
+        }
+    }
+    return true;
+}
+
+// Eigenvalues of the n x n Hessenberg matrix in Hs into wr, wi; every control
+// decision uniform.  Returns false when the iteration has not converged within
+// 30 n sweeps.
+template <int NT>
+__device__ bool hqr_eigs(double* Hs, int n, double* __restrict__ wr, double* __restrict__ wi) {
+    __shared__ double W[HQ_NS * HQ_NS];      // trailing block for the shifts
+    __shared__ double ser[HQ_NS], sei[HQ_NS];
+    __shared__ double shs[HQ_NB], shd[HQ_NB];  // shift pairs: sum and product
+    __shared__ int s_nb;
+    __shared__ double rfl[HQ_NB][5];          // reflector of each bulge in a chain step
+    const int lane = threadIdx.x & 63;
+    const int tid = threadIdx.x;
     auto g = [&](int i, int j) -> double { return *hq_at(Hs, i, j, n); };
     double nrm = 0.0;  // size of the matrix for the deflation test of zero diagonals
     for (int i = lane; i < n; i += WAVE)
@@ -133,10 +291,10 @@ __device__ bool hqr_eigs(double* Hs, int n, double* __restrict__ wr, double* __r
             }
         }
         __syncthreads();
-        if (l > 0 && threadIdx.x == 0) *hq_at(Hs, l, l - 1, n) = 0.0;
+        if (l > 0 && tid == 0) *hq_at(Hs, l, l - 1, n) = 0.0;
         __syncthreads();
         if (l == hi) {
-            if (threadIdx.x == 0) { wr[hi] = g(hi, hi); wi[hi] = 0.0; }
+            if (tid == 0) { wr[hi] = g(hi, hi); wi[hi] = 0.0; }
             --hi;
             its = 0;
             continue;
@@ -145,7 +303,7 @@ __device__ bool hqr_eigs(double* Hs, int n, double* __restrict__ wr, double* __r
             // 2 x 2 block [[p, q], [r, s]]
             const double p = g(hi - 1, hi - 1), q = g(hi - 1, hi), r = g(hi, hi - 1), s = g(hi, hi);
             const double hm = 0.5 * (p - s), disc = hm * hm + q * r;
-            if (threadIdx.x == 0) {
+            if (tid == 0) {
                 if (disc >= 0.0) {
                     const double z = hm + copysign(sqrt(disc), hm);
                     wr[hi - 1] = s + z;
@@ -165,70 +323,203 @@ __device__ bool hqr_eigs(double* Hs, int n, double* __restrict__ wr, double* __r
             continue;
         }
         if (total >= 30 * n) return false;
-        // shifts from the trailing 2 x 2 block (ad hoc shifts after 10 and 20 steps
-        // without deflation)
-        double sh, dt;
-        if (its == 10 || its == 20) {
-            const double x = fabs(g(hi, hi - 1)) + fabs(g(hi - 1, hi - 2));
-            sh = 1.5 * x;
-            dt = x * x;
-        } else {
-            const double p = g(hi - 1, hi - 1), q = g(hi - 1, hi), r = g(hi, hi - 1), s = g(hi, hi);
-            sh = p + s;
-            dt = p * s - q * r;
-        }
         ++its;
         ++total;
-        // first column of H^2 - sh H + dt I, rows l .. l+2
-        const double h00 = g(l, l), h01 = g(l, l + 1), h10 = g(l + 1, l), h11 = g(l + 1, l + 1);
-        double x = h00 * h00 + h01 * h10 - sh * h00 + dt;
-        double y = h10 * (h00 + h11 - sh);
-        double z = h10 * g(l + 2, l + 1);
-        for (int k = l; k <= hi - 1; ++k) {
-            const bool three = k <= hi - 2;  // the last reflector acts on two rows
-            if (k > l) {
-                x = g(k, k - 1);
-                y = g(k + 1, k - 1);
-                z = three ? g(k + 2, k - 1) : 0.0;
+        // the sweep's shifts: eigenvalues of the trailing HQ_NS x HQ_NS block, paired
+        // (conjugate pairs, then real ones in ascending order); one pair from the
+        // trailing 2 x 2 block for small active blocks, or ad hoc after 10 and 20
+        // sweeps without deflation
+        const bool multi = NT >= 1024 && hi - l + 1 >= HQ_NMIN && its != 10 && its != 20;
+        bool small_ok = false;
+        if (multi && tid < WAVE) {  // wavefront 0: the trailing block's eigenvalues
+            const int b0 = hi - HQ_NS + 1;
+            for (int e = lane; e < HQ_NS * HQ_NS; e += WAVE) {
+                const int i = e / HQ_NS, j = e % HQ_NS;
+                W[e] = (i - j <= 1) ? g(b0 + i, b0 + j) : 0.0;
             }
-            const double nx = sqrt(x * x + y * y + z * z);
+            hq_wave_sync();
+            small_ok = hq_small_eigs(W, HQ_NS, ser, sei);
+        }
+        if (tid == 0) {
+            int nb = 0;
+            if (multi) {
+                if (small_ok) {
+                    for (int i = 0; i < HQ_NS && nb < HQ_NB; ++i)
+                        if (sei[i] > 0.0) {
+                            shs[nb] = 2.0 * ser[i];
+                            shd[nb] = ser[i] * ser[i] + sei[i] * sei[i];
+                            ++nb;
+                        }
+                    double rr[HQ_NS];
+                    int nr = 0;
+                    for (int i = 0; i < HQ_NS; ++i)
+                        if (sei[i] == 0.0) {
+                            double v = ser[i];
+                            int q = nr++;
+                            for (; q > 0 && rr[q - 1] > v; --q) rr[q] = rr[q - 1];
+                            rr[q] = v;
+                        }
+                    for (int i = 0; i + 1 < nr && nb < HQ_NB; i += 2) {
+                        shs[nb] = rr[i] + rr[i + 1];
+                        shd[nb] = rr[i] * rr[i + 1];
+                        ++nb;
+                    }
+                }
+            }
+            if (nb == 0) {
+                if (its == 10 || its == 20) {
+                    const double x = fabs(g(hi, hi - 1)) + fabs(g(hi - 1, hi - 2));
+                    shs[0] = 1.5 * x;
+                    shd[0] = x * x;
+                } else {
+                    const double p = g(hi - 1, hi - 1), q = g(hi - 1, hi), r = g(hi, hi - 1), s = g(hi, hi);
+                    shs[0] = p + s;
+                    shd[0] = p * s - q * r;
+                }
+                nb = 1;
+            }
+            s_nb = nb;
+        }
+        __syncthreads();
+        const int nb = s_nb;
+        if (nb == 1) {
+            // one bulge: every thread forms the reflector itself (no record in LDS)
+            const double sh = shs[0], dt = shd[0];
+            const double h00 = g(l, l), h01 = g(l, l + 1), h10 = g(l + 1, l), h11 = g(l + 1, l + 1);
+            double x = h00 * h00 + h01 * h10 - sh * h00 + dt;
+            double y = h10 * (h00 + h11 - sh);
+            double z = h10 * g(l + 2, l + 1);
+            for (int k = l; k <= hi - 1; ++k) {
+                const bool three = k <= hi - 2;
+                if (k > l) {
+                    x = g(k, k - 1);
+                    y = g(k + 1, k - 1);
+                    z = three ? g(k + 2, k - 1) : 0.0;
+                }
+                const double nx = sqrt(x * x + y * y + z * z);
+                __syncthreads();  // every thread has read x, y, z
+                if (nx == 0.0) continue;
+                const double alpha = (x >= 0.0) ? -nx : nx;
+                const double v0 = x - alpha;
+                const double v1 = y, v2 = three ? z : 0.0;
+                const double tau = 2.0 / (v0 * v0 + v1 * v1 + v2 * v2);
+                for (int j = max(l, k - 1) + tid; j <= hi; j += NT) {
+                    double* p0 = hq_at(Hs, k, j, n);
+                    double* p1 = hq_at(Hs, k + 1, j, n);
+                    if (j == k - 1) {
+                        *p0 = alpha;
+                        *p1 = 0.0;
+                        if (three) *hq_at(Hs, k + 2, j, n) = 0.0;
+                        continue;
+                    }
+                    const double r0 = *p0, r1 = *p1;
+                    const double r2 = three ? *hq_at(Hs, k + 2, j, n) : 0.0;
+                    const double d = tau * (v0 * r0 + v1 * r1 + v2 * r2);
+                    *p0 = r0 - d * v0;
+                    *p1 = r1 - d * v1;
+                    if (three) *hq_at(Hs, k + 2, j, n) = r2 - d * v2;
+                }
+                __syncthreads();
+                const int rl = min(k + 3, hi);
+                for (int i = l + tid; i <= rl; i += NT) {
+                    double* p0 = hq_at(Hs, i, k, n);
+                    double* p1 = hq_at(Hs, i, k + 1, n);
+                    const double c0 = *p0, c1 = *p1;
+                    const double c2 = three ? *hq_at(Hs, i, k + 2, n) : 0.0;
+                    const double d = tau * (v0 * c0 + v1 * c1 + v2 * c2);
+                    *p0 = c0 - d * v0;
+                    *p1 = c1 - d * v1;
+                    if (three) *hq_at(Hs, i, k + 2, n) = c2 - d * v2;
+                }
+                __syncthreads();
+            }
+            continue;
+        }
+        // the chain: at step t bulge b is at row k = l + t - b HQ_DS.  Each step forms
+        // every bulge's reflector, applies them all from the left (disjoint rows),
+        // then all from the right (disjoint columns).
+        const int last = hi - 1;
+        const int nsteps = (last - l) + (nb - 1) * HQ_DS + 1;
+        for (int t = 0; t < nsteps; ++t) {
+            if (tid < nb) {
+                const int b = tid, k = l + t - b * HQ_DS;
+                if (k >= l && k <= last) {
+                    const bool three = k <= hi - 2;
+                    double x, y, z;
+                    if (k == l) {
+                        const double sh = shs[b], dt = shd[b];
+                        const double h00 = g(l, l), h01 = g(l, l + 1), h10 = g(l + 1, l), h11 = g(l + 1, l + 1);
+                        x = h00 * h00 + h01 * h10 - sh * h00 + dt;
+                        y = h10 * (h00 + h11 - sh);
+                        z = h10 * g(l + 2, l + 1);
+                    } else {
+                        x = g(k, k - 1);
+                        y = g(k + 1, k - 1);
+                        z = three ? g(k + 2, k - 1) : 0.0;
+                    }
+                    hq_reflector(x, y, three ? z : 0.0, rfl[b]);
+                }
+            }
             __syncthreads();
-            if (nx == 0.0) continue;
-            // P = I - tau v v^T, v = (x - alpha, y, z): one division
-            const double alpha = (x >= 0.0) ? -nx : nx;
-            const double v0 = x - alpha;
-            const double u1 = y, u2 = three ? z : 0.0;
-            const double tau = 2.0 / (v0 * v0 + u1 * u1 + u2 * u2);
-            // from the left: rows k..k+2, columns max(l, k-1)..hi; column k-1 (k > l) is the
-            // annihilated bulge, written exactly: (alpha, 0, 0)
-            for (int j = max(l, k - 1) + (int)threadIdx.x; j <= hi; j += HQ_NT) {
+            // from the left: bulge b on rows k..k+2, columns max(l, k-1)..hi; column
+            // k-1 (k > l) is the annihilated bulge, written exactly: (alpha, 0, 0).  The
+            // entry of a thread follows from l, hi and t alone; a bulge whose reflector
+            // is the identity (tau = 0: x = y = z = 0) changes nothing.
+            for (int e = tid; e < HQ_NB * (n + 1); e += NT) {
+                int rem = e, b = -1, k = 0;
+#pragma unroll
+                for (int q = 0; q < HQ_NB; ++q) {
+                    const int kq = l + t - q * HQ_DS;
+                    const int cnt = (q < nb && kq >= l && kq <= last) ? hi - max(l, kq - 1) + 1 : 0;
+                    if (b < 0) {
+                        if (rem < cnt) { b = q; k = kq; } else rem -= cnt;
+                    }
+                }
+                if (b < 0) break;
+                const bool three = k <= hi - 2;
+                const int j = max(l, k - 1) + rem;
                 double* p0 = hq_at(Hs, k, j, n);
                 double* p1 = hq_at(Hs, k + 1, j, n);
+                double* p2 = hq_at(Hs, k + 2, j, n);  // (unused for a two-row reflector)
+                const double v0 = rfl[b][0], v1 = rfl[b][1], v2 = rfl[b][2], tau = rfl[b][3];
                 if (j == k - 1) {
-                    *p0 = alpha;
-                    *p1 = 0.0;
-                    if (three) *hq_at(Hs, k + 2, j, n) = 0.0;
-                    continue;
+                    if (tau != 0.0) {
+                        *p0 = rfl[b][4];
+                        *p1 = 0.0;
+                        if (three) *p2 = 0.0;
+                    }
+                } else {
+                    const double r0 = *p0, r1 = *p1, r2 = three ? *p2 : 0.0;
+                    const double d = tau * (v0 * r0 + v1 * r1 + v2 * r2);
+                    *p0 = r0 - d * v0;
+                    *p1 = r1 - d * v1;
+                    if (three) *p2 = r2 - d * v2;
                 }
-                const double r0 = *p0, r1 = *p1;
-                const double r2 = three ? *hq_at(Hs, k + 2, j, n) : 0.0;
-                const double d = tau * (v0 * r0 + u1 * r1 + u2 * r2);
-                *p0 = r0 - d * v0;
-                *p1 = r1 - d * u1;
-                if (three) *hq_at(Hs, k + 2, j, n) = r2 - d * u2;
             }
             __syncthreads();
-            // from the right: columns k..k+2, rows l..min(k+3, hi)
-            const int rl = min(k + 3, hi);
-            for (int i = l + (int)threadIdx.x; i <= rl; i += HQ_NT) {
+            // from the right: bulge b on columns k..k+2, rows l..min(k+3, hi)
+            for (int e = tid; e < HQ_NB * (n + 1); e += NT) {
+                int rem = e, b = -1, k = 0;
+#pragma unroll
+                for (int q = 0; q < HQ_NB; ++q) {
+                    const int kq = l + t - q * HQ_DS;
+                    const int cnt = (q < nb && kq >= l && kq <= last) ? min(kq + 3, hi) - l + 1 : 0;
+                    if (b < 0) {
+                        if (rem < cnt) { b = q; k = kq; } else rem -= cnt;
+                    }
+                }
+                if (b < 0) break;
+                const bool three = k <= hi - 2;
+                const int i = l + rem;
                 double* p0 = hq_at(Hs, i, k, n);
                 double* p1 = hq_at(Hs, i, k + 1, n);
-                const double c0 = *p0, c1 = *p1;
-                const double c2 = three ? *hq_at(Hs, i, k + 2, n) : 0.0;
-                const double d = tau * (v0 * c0 + u1 * c1 + u2 * c2);
+                double* p2 = hq_at(Hs, i, k + 2, n);
+                const double v0 = rfl[b][0], v1 = rfl[b][1], v2 = rfl[b][2], tau = rfl[b][3];
+                const double c0 = *p0, c1 = *p1, c2 = three ? *p2 : 0.0;
+                const double d = tau * (v0 * c0 + v1 * c1 + v2 * c2);
                 *p0 = c0 - d * v0;
-                *p1 = c1 - d * u1;
-                if (three) *hq_at(Hs, i, k + 2, n) = c2 - d * u2;
+                *p1 = c1 - d * v1;
+                if (three) *p2 = c2 - d * v2;
             }
             __syncthreads();
         }
@@ -236,25 +527,26 @@ __device__ bool hqr_eigs(double* Hs, int n, double* __restrict__ wr, double* __r
     return true;
 }
 
-// One block of HQ_NT threads: the Ritz values (eigenvalues of H_hat, row-major,
+// One block of NT threads: the Ritz values (eigenvalues of H_hat, row-major,
 // ld m) into ritz[0..mu) (real parts) and ritz[m..m+mu) (imaginary parts), then
 // the parabola into the control block (sigma = 1: the rule carries its own scale).
-__global__ __launch_bounds__(HQ_NT) void contour_setup_kernel(DevCtrl* ctrl, int m, const double* __restrict__ Hh,
+template <int NT>
+__global__ __launch_bounds__(NT) void contour_setup_kernel(DevCtrl* ctrl, int m, const double* __restrict__ Hh,
                                                             double tau, double* __restrict__ ritz) {
-    __shared__ double Hs[CT_HQR_CAP + 3];  // the matrix and the three bulge slots
+    __shared__ double Hs[HQ_LDS];  // the matrix and the slots of the entries below the subdiagonal
     if (ctrl->status != 0) return;
     const int mu = ctrl->m_used;
     if (mu == 0) return;
     const int lane = threadIdx.x & 63;
-    if (threadIdx.x < 3) Hs[CT_HQR_CAP + threadIdx.x] = 0.0;
+    if (threadIdx.x < 2 * HQ_P) Hs[CT_HQR_CAP + threadIdx.x] = 0.0;
     for (int i = 0; i < mu; ++i)
-        for (int j = (i > 0 ? i - 1 : 0) + (int)threadIdx.x; j < mu; j += HQ_NT)
+        for (int j = (i > 0 ? i - 1 : 0) + (int)threadIdx.x; j < mu; j += NT)
             Hs[hq_off(i, mu) + j - (i > 0 ? i - 1 : 0)] = Hh[(int64_t)i * m + j];
     __syncthreads();
     hq_balance(Hs, mu);
     double* wr = ritz;
     double* wi = ritz + m;
-    const bool ok = hqr_eigs(Hs, mu, wr, wi);
+    const bool ok = hqr_eigs<NT>(Hs, mu, wr, wi);
     __threadfence_block();
     __syncthreads();
     if (!ok) {
@@ -420,7 +712,10 @@ __global__ __launch_bounds__(256) void contour_level_kernel(const DevCtrl* ctrl,
 }
 
 hipError_t launch_contour_setup(DevCtrl* ctrl, int m, const double* Hh, double tau, double* ritz, hipStream_t st) {
-    hipLaunchKernelGGL(contour_setup_kernel, dim3(1), dim3(HQ_NT), 0, st, ctrl, m, Hh, tau, ritz);
+    if (m <= HQ_NSMALL)
+        hipLaunchKernelGGL(contour_setup_kernel<256>, dim3(1), dim3(256), 0, st, ctrl, m, Hh, tau, ritz);
+    else
+        hipLaunchKernelGGL(contour_setup_kernel<1024>, dim3(1), dim3(1024), 0, st, ctrl, m, Hh, tau, ritz);
     return hipGetLastError();
 }
 
