@@ -1281,28 +1281,53 @@ __global__ __launch_bounds__(1024) void sell_scan_sums_kernel(const int32_t* sl_
     if (threadIdx.x == 0) bsum[blockIdx.x] = (int64_t)t;
 }
 
-// exclusive scan of the block sums (one block, sequential per thread then across)
+// Exclusive prefix sum of one value per thread over a block of 1024 threads
+// (integers: exact in any order), and the block total.  Scans within each
+// wavefront by shuffles, then across the 16 wavefront totals.
+__device__ __forceinline__ int64_t block_exclusive_scan_1024(int64_t v, int64_t* wsum, int64_t* total) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    int64_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[wid] = x;
+    __syncthreads();
+    if (wid == 0) {
+        int64_t w = (lane < 16) ? wsum[lane] : 0;
+#pragma unroll
+        for (int off = 1; off < 16; off <<= 1) {
+            const int64_t y = __shfl_up(w, off, 64);
+            if (lane >= off) w += y;
+        }
+        if (lane < 16) wsum[16 + lane] = w;  // inclusive scan of the wavefront totals
+    }
+    __syncthreads();
+    *total = wsum[16 + 15];
+    return ((wid > 0) ? wsum[16 + wid - 1] : 0) + x - v;
+}
+
+// exclusive scan of the block sums (one block: a sequential sum per thread, then
+// the block scan)
 __global__ __launch_bounds__(1024) void sell_scan_top_kernel(int64_t* bsum, int64_t nb, int64_t capacity,
                                                              DevCtrl* ctrl, DictBuf* dict, int use_dict) {
-    __shared__ int64_t part[1024];
+    __shared__ int64_t wsum[32];
     __shared__ int sh_ok;
     __shared__ int wcnt[16];
     const int64_t per = (nb + 1023) / 1024;
     const int64_t i0 = threadIdx.x * per, i1 = min(nb, i0 + per);
     int64_t t = 0;
     for (int64_t i = i0; i < i1; ++i) t += bsum[i];
-    part[threadIdx.x] = t;
-    __syncthreads();
+    int64_t total = 0;
+    int64_t run = block_exclusive_scan_1024(t, wsum, &total);
     if (threadIdx.x == 0) {
-        int64_t run = 0;
-        for (int i = 0; i < 1024; ++i) { const int64_t v = part[i]; part[i] = run; run += v; }
-        ctrl->sell_total = run;
-        ctrl->sell_ok = (run <= capacity) ? 1 : 0;
+        ctrl->sell_total = total;
+        ctrl->sell_ok = (total <= capacity) ? 1 : 0;
         ctrl->col16 = ctrl->col_wide ? 0 : 1;
-        sh_ok = (run <= capacity) ? 1 : 0;
+        sh_ok = (total <= capacity) ? 1 : 0;
     }
     __syncthreads();
-    int64_t run = part[threadIdx.x];
     for (int64_t i = i0; i < i1; ++i) { const int64_t v = bsum[i]; bsum[i] = run; run += v; }
     // value table: the occupied slots of the value set numbered in slot order
     const bool use = use_dict && sh_ok && !ctrl->dict_over && ctrl->ndict <= DICT_MAX;
@@ -1325,23 +1350,18 @@ __global__ __launch_bounds__(1024) void sell_scan_top_kernel(int64_t* bsum, int6
 // sl_ptr = exclusive prefix of 64 * sl_len (block-local scan plus block offset)
 __global__ __launch_bounds__(1024) void sell_scan_apply_kernel(const int32_t* sl_len, int64_t nslices,
                                                                const int64_t* boff, int64_t* sl_ptr) {
-    __shared__ int64_t part[1024];
+    __shared__ int64_t wsum[32];
     constexpr int PER = SCAN_CH / 1024;
     const int64_t base = (int64_t)blockIdx.x * SCAN_CH + (int64_t)threadIdx.x * PER;
     int64_t loc[PER];
     int64_t t = 0;
+#pragma unroll
     for (int i = 0; i < PER; ++i) {
         loc[i] = (base + i < nslices) ? 64 * (int64_t)sl_len[base + i] : 0;
         t += loc[i];
     }
-    part[threadIdx.x] = t;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int64_t run = boff[blockIdx.x];
-        for (int i = 0; i < 1024; ++i) { const int64_t v = part[i]; part[i] = run; run += v; }
-    }
-    __syncthreads();
-    int64_t run = part[threadIdx.x];
+    int64_t total = 0;
+    int64_t run = boff[blockIdx.x] + block_exclusive_scan_1024(t, wsum, &total);
     for (int i = 0; i < PER; ++i) {
         if (base + i < nslices) sl_ptr[base + i] = run;
         run += loc[i];
